@@ -1,0 +1,232 @@
+"""CPU oracle for the DPSNN cortical-grid hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It is a plain, slow C
+implementation (oracle/dpsnn_oracle.c) written from the paper and bound here
+with ctypes; it shares no code with the HIP library.
+
+Parameters are passed as a plain dict whose keys are the field names of
+``orc_params`` (pairs are ``[excitatory, inhibitory]``).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liborc.so")
+
+MIRROR32 = 0
+EXACT64 = 1
+WEIGHT_DTYPES = {"f32": 0, "f16": 1, "i8": 2}
+
+_PAIR = C.c_double * 2
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("grid_w", C.c_int32), ("grid_h", C.c_int32), ("K", C.c_int32),
+        ("K_out", C.c_int32), ("frac_exc", C.c_double), ("frac_local", _PAIR),
+        ("lambda_", C.c_double), ("torus", C.c_int32), ("d_min", C.c_int32),
+        ("d_max", C.c_int32), ("dt_ms", C.c_double), ("weight_dtype", C.c_int32),
+        ("acc_bits", C.c_int32), ("q_frac_bits", C.c_int32),
+        ("J_mean", _PAIR), ("J_sd", _PAIR), ("nu_ext_hz", _PAIR),
+        ("Jext_mean", _PAIR), ("Jext_sd", _PAIR), ("tau_m", _PAIR), ("E", _PAIR),
+        ("V_th", _PAIR), ("V_r", _PAIR), ("tau_arp", _PAIR), ("alpha_c", _PAIR),
+        ("tau_c", _PAIR), ("gc", _PAIR), ("I_const", _PAIR),
+        ("rate_bin_steps", C.c_int32),
+    ]
+
+
+def to_struct(params: dict) -> OrcParams:
+    s = OrcParams()
+    for name, ctype in OrcParams._fields_:
+        key = "lambda" if name == "lambda_" else name
+        v = params[key]
+        if key == "weight_dtype" and isinstance(v, str):
+            v = WEIGHT_DTYPES[v]
+        if ctype is _PAIR:
+            setattr(s, name, _PAIR(float(v[0]), float(v[1])))
+        elif ctype is C.c_double:
+            setattr(s, name, float(v))
+        else:
+            setattr(s, name, int(v))
+    return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            _build.build()
+        L = C.CDLL(_LIBPATH)
+        P = C.POINTER
+        L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        L.orc_philox4x32_10.restype = None
+        L.orc_normal_quantile.argtypes = [C.c_double]
+        L.orc_normal_quantile.restype = C.c_double
+        L.orc_f64_to_f16.argtypes = [C.c_double]
+        L.orc_f64_to_f16.restype = C.c_uint16
+        L.orc_f16_to_f64.argtypes = [C.c_uint16]
+        L.orc_f16_to_f64.restype = C.c_double
+        L.orc_create.argtypes = [P(OrcParams), C.c_uint64, C.c_int32, C.c_int32, P(C.c_int32)]
+        L.orc_create.restype = C.c_void_p
+        L.orc_free.argtypes = [C.c_void_p]
+        L.orc_free.restype = None
+        for f in ("orc_n_neurons", "orc_time"):
+            getattr(L, f).argtypes = [C.c_void_p]
+            getattr(L, f).restype = C.c_int64
+        for f in ("orc_n_slots", "orc_status"):
+            getattr(L, f).argtypes = [C.c_void_p]
+            getattr(L, f).restype = C.c_int32
+        L.orc_table.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64]
+        L.orc_table.restype = C.c_int64
+        L.orc_gen_row.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
+        L.orc_gen_row.restype = C.c_int32
+        L.orc_ext_input.argtypes = [C.c_void_p, C.c_int64, C.c_int64,
+                                    P(C.c_int64), P(C.c_double)]
+        L.orc_ext_input.restype = C.c_int32
+        L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_step.restype = C.c_int32
+        L.orc_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_get_state.restype = C.c_int32
+        L.orc_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_state.restype = C.c_int32
+        L.orc_get_ring.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_get_ring.restype = C.c_int32
+        L.orc_spikes.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.orc_spikes.restype = C.c_int64
+        L.orc_rates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        L.orc_rates.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def normal_quantile(p: float) -> float:
+    return lib().orc_normal_quantile(float(p))
+
+
+def f64_to_f16_bits(x: float) -> int:
+    return int(lib().orc_f64_to_f16(float(x)))
+
+
+def f16_bits_to_f64(h: int) -> float:
+    return float(lib().orc_f16_to_f64(int(h)))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class Oracle:
+    """One simulated network on the CPU (see oracle/dpsnn_oracle.h)."""
+
+    def __init__(self, params: dict, seed: int, mode: int = MIRROR32,
+                 store_rows: bool = True):
+        self.params = dict(params)
+        self._s = to_struct(params)
+        err = C.c_int32(0)
+        h = lib().orc_create(C.byref(self._s), C.c_uint64(seed), mode,
+                             1 if store_rows else 0, C.byref(err))
+        if not h:
+            raise ValueError(f"orc_create failed ({err.value})")
+        self._h = h
+        self.seed = seed
+        self.mode = mode
+        self.N = int(lib().orc_n_neurons(h))
+        self.D = int(lib().orc_n_slots(h))
+        self.M = int(params["grid_w"]) * int(params["grid_h"])
+        self.n_del = int(params["d_max"]) - int(params["d_min"]) + 1
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().orc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def t(self) -> int:
+        return int(lib().orc_time(self._h))
+
+    @property
+    def status(self) -> int:
+        return int(lib().orc_status(self._h))
+
+    def step(self, n: int) -> int:
+        return int(lib().orc_step(self._h, int(n)))
+
+    def table(self, name: str, dtype) -> np.ndarray:
+        nb = lib().orc_table(self._h, name.encode(), None, 0)
+        if nb < 0:
+            raise KeyError(name)
+        out = np.zeros(nb // np.dtype(dtype).itemsize, dtype=dtype)
+        lib().orc_table(self._h, name.encode(), _ptr(out), nb)
+        return out
+
+    def gen_row(self, s: int):
+        Ko = int(self.params["K_out"])
+        tgt = np.zeros(Ko, np.int32)
+        dl = np.zeros(Ko, np.uint8)
+        wi = np.zeros(Ko, np.uint16)
+        doff = np.zeros(self.n_del + 1, np.uint16)
+        rc = lib().orc_gen_row(self._h, int(s), _ptr(tgt), _ptr(dl), _ptr(wi), _ptr(doff))
+        if rc != 0:
+            raise ValueError(rc)
+        return tgt, dl, wi, doff
+
+    def ext_input(self, i: int, t: int):
+        fs = C.c_int64(0)
+        ds = C.c_double(0.0)
+        k = lib().orc_ext_input(self._h, int(i), int(t), C.byref(fs), C.byref(ds))
+        return int(k), int(fs.value), float(ds.value)
+
+    def state(self):
+        V = np.zeros(self.N)
+        c = np.zeros(self.N)
+        r = np.zeros(self.N, np.int32)
+        lib().orc_get_state(self._h, _ptr(V), _ptr(c), _ptr(r))
+        return V, c, r
+
+    def set_state(self, V=None, c=None, ref=None):
+        V = None if V is None else np.ascontiguousarray(V, np.float64)
+        c = None if c is None else np.ascontiguousarray(c, np.float64)
+        ref = None if ref is None else np.ascontiguousarray(ref, np.int32)
+        lib().orc_set_state(self._h, _ptr(V), _ptr(c), _ptr(ref))
+
+    def ring(self) -> np.ndarray:
+        if self.mode == MIRROR32:
+            out = np.zeros(self.D * self.N, np.int64)
+            lib().orc_get_ring(self._h, _ptr(out), None)
+        else:
+            out = np.zeros(self.D * self.N, np.float64)
+            lib().orc_get_ring(self._h, None, _ptr(out))
+        return out.reshape(self.D, self.N)
+
+    def spikes(self):
+        n = lib().orc_spikes(self._h, None, None, 0)
+        st = np.zeros(n, np.int32)
+        ids = np.zeros(n, np.int32)
+        lib().orc_spikes(self._h, _ptr(st), _ptr(ids), n)
+        return st, ids
+
+    def rates(self) -> np.ndarray:
+        nb = lib().orc_rates(self._h, None, 0)
+        out = np.zeros((nb, self.M, 2), np.uint32)
+        lib().orc_rates(self._h, _ptr(out), nb)
+        return out

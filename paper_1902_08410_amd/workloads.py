@@ -1,0 +1,73 @@
+"""Parameter sets of the synthetic workloads (plain data, no arithmetic).
+
+Both the HIP library binding and the CPU oracle take these dicts; the keys
+are the fields of the C parameter structs, pairs are [excitatory,
+inhibitory].  Units: mV, ms, Hz, inter-module distance units for lambda.
+
+Neuron constants follow Table S1 of the paper (tau_m 20/10 ms, E = 0,
+V_theta = 20 mV, V_r = 15 mV, tau_arp 2/1 ms, alpha_c = 1 mV,
+g_c/C_m = 0.02 nS/pF = 0.02 1/ms, no adaptation for inhibitory neurons).
+The network structure of the workloads is a fixed 80/20 split, out-degree
+1000 with half the synapses local, exponential remote connectivity (Eq. 1)
+on a torus, delays of 1-20 steps of 0.1 ms, and Gaussian efficacies
+N(0.5, 0.1) mV from excitatory and N(-2.0, 0.4) mV from inhibitory sources.
+"""
+import copy
+
+# Slow-wave (SWA) regime: strong adaptation, tau_c = 500 ms.
+_SWA = dict(
+    grid_w=2, grid_h=2, K=1250, K_out=1000, frac_exc=0.8,
+    frac_local=[0.5, 0.5], torus=1, d_min=1, d_max=20, dt_ms=0.1,
+    weight_dtype="f32", acc_bits=32, q_frac_bits=16,
+    J_mean=[0.5, -2.0], J_sd=[0.1, 0.4],
+    nu_ext_hz=[1000.0, 1000.0], Jext_mean=[0.86, 1.12], Jext_sd=[0.172, 0.224],
+    tau_m=[20.0, 10.0], E=[0.0, 0.0], V_th=[20.0, 20.0], V_r=[15.0, 15.0],
+    tau_arp=[2.0, 1.0], alpha_c=[1.0, 0.0], tau_c=[500.0, 500.0],
+    gc=[0.02, 0.0], I_const=[0.0, 0.0], rate_bin_steps=50,
+)
+_SWA["lambda"] = 1.0
+
+
+def swa(**over) -> dict:
+    p = copy.deepcopy(_SWA)
+    p.update(over)
+    return p
+
+
+def aw(**over) -> dict:
+    """Asynchronous-wake regime: adaptation x0.1 and a higher external rate."""
+    p = swa(gc=[0.002, 0.0], nu_ext_hz=[1500.0, 1500.0])
+    p.update(over)
+    return p
+
+
+def grid(w: int, h: int, regime: str = "swa", **over) -> dict:
+    base = swa if regime == "swa" else aw
+    return base(grid_w=w, grid_h=h, **over)
+
+
+def tiny(w: int = 2, h: int = 2, K: int = 16, K_out: int = 8, **over) -> dict:
+    """Small grids for exhaustive checks (brute-force delivery, rasters)."""
+    p = swa(grid_w=w, grid_h=h, K=K, K_out=K_out, d_max=5)
+    p.update(over)
+    return p
+
+
+# Named configurations: (params, seeds, steps)
+CONFIGS = {
+    # 2x2 grid, 5000 neurons, FP32 weights, SWA, 2 s
+    "c1": dict(params=[swa()], seeds=[1, 2, 3, 4, 5], steps=20000),
+    # 24x24 grid, 720k neurons, FP32 weights, SWA and AW, 10 s
+    "c2": dict(params=[grid(24, 24, "swa"), grid(24, 24, "aw")], seeds=[1, 2, 3],
+               steps=100000),
+    # 48x48 grid, 2.88M neurons, lambda sweep, FP32/FP16/int8
+    "c3": dict(params=[grid(48, 48, r, **{"lambda": lam, "weight_dtype": wd})
+                       for r in ("swa", "aw") for lam in (0.5, 1.0, 2.0, 4.0)
+                       for wd in ("f32", "f16", "i8")],
+               seeds=[1, 2, 3, 4, 5], steps=50000),
+    # 96x96 grid, 11.52M neurons, int8 weights, int64 ring with Q = 32
+    "c5": dict(params=[grid(96, 96, r, **{"lambda": 2.0, "weight_dtype": "i8",
+                                          "acc_bits": 64, "q_frac_bits": 32})
+                       for r in ("swa", "aw")],
+               seeds=[1], steps=20000),
+}

@@ -1,0 +1,511 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against the paper's equations in closed form, a
+library routine (rocRAND, SciPy, NumPy), a hand-worked value stored under
+tests/golden/ with its derivation, or a brute-force recomputation on a tiny
+network.  All run on the CPU.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1902_08410_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+HELP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "helpers")
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10
+def test_philox_known_answer():
+    for line in open(os.path.join(GOLD, "philox_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        assert O.philox4x32_10(w[0:4], w[4:6]) == w[6:10]
+
+
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists(
+            "/opt/rocm/include/rocrand/rocrand_kernel.h"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    exe = str(tmp_path_factory.mktemp("rocrand") / "philox")
+    subprocess.run([hipcc, "-O1", "-o", exe, os.path.join(HELP, "rocrand_philox.cpp")],
+                   check=True, capture_output=True)
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_philox):
+    rng = np.random.default_rng(12345)
+    cases = []
+    for _ in range(2000):
+        c = rng.integers(0, 2**32, size=4, dtype=np.uint64)
+        c[1] = c[1] % (2**30)        # the offset interface holds 62 bits
+        k = rng.integers(0, 2**32, size=2, dtype=np.uint64)
+        cases.append([int(x) for x in c] + [int(x) for x in k])
+    # the counter layouts the method uses: (source, synapse, 0, SYN),
+    # (neuron/4, step, 0, EXT), (neuron, step, 0, EXTJ | block << 8), INIT
+    for s in (0, 1, 4999, 719999):
+        for j in (0, 1, 499, 500, 999):
+            cases.append([s, j, 0, 1, 1, 0])
+        cases.append([s, 0, 0, 4, 7, 0])
+        cases.append([s // 4, 123456, 0, 2, 2, 0])
+        cases.append([s, 123456, 0, 3 | (1 << 8), 3, 0])
+    inp = "\n".join(" ".join(str(x) for x in cs) for cs in cases) + "\n"
+    out = subprocess.run([rocrand_philox], input=inp, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    for cs, line in zip(cases, out):
+        ref = [int(x) for x in line.split()]
+        assert O.philox4x32_10(cs[0:4], cs[4:6]) == ref, cs
+
+
+# --------------------------------------------------------------------------
+# Host tables
+def _net(**over):
+    p = W.tiny(**over)
+    return O.Oracle(p, 1)
+
+
+def test_normal_quantile_matches_scipy():
+    from scipy.special import ndtri
+    o = _net(J_mean=[0.0, 0.0], J_sd=[1.0, 1.0])
+    z = o.table("wt64_0", np.float64)
+    ref = ndtri((np.arange(65536) + 0.5) / 65536.0)
+    assert np.max(np.abs(z - ref)) < 1e-14
+    # the midpoint grid is symmetric, so the table is exactly antisymmetric
+    assert np.array_equal(z[::-1], -z)
+    # a few off-grid probabilities through the exported routine
+    for p in (1e-6, 0.025, 0.3, 0.5 + 1e-9, 0.975, 1 - 1e-7):
+        assert abs(O.normal_quantile(p) - ndtri(p)) < 1e-12 * max(1.0, abs(ndtri(p)))
+
+
+def test_f16_rounding_matches_numpy():
+    rng = np.random.default_rng(3)
+    xs = list(rng.normal(0.5, 0.1, 2000)) + list(rng.normal(-2.0, 0.4, 2000))
+    xs += list(rng.uniform(-70000, 70000, 500)) + list(rng.uniform(-1e-4, 1e-4, 500))
+    # exact ties between neighbouring half values, normal and subnormal
+    for e in (-20, -15, -14, -3, 0, 5, 14):
+        for m in (1024, 1025, 1500, 2046, 2047):
+            xs.append((m + 0.5) * 2.0 ** (e - 10))
+            xs.append(-(m + 0.5) * 2.0 ** (e - 10))
+    xs += [0.0, -0.0, 65504.0, 65519.99, 65520.0, 6.0e-8, 2.0 ** -24, 2.0 ** -25,
+           3 * 2.0 ** -26]
+    for x in xs:
+        ref = int(np.array(x, np.float64).astype(np.float16).view(np.uint16))
+        assert O.f64_to_f16_bits(x) == ref, x
+        if (ref & 0x7C00) != 0x7C00:
+            assert O.f16_bits_to_f64(ref) == float(np.array(ref, np.uint16).view(np.float16))
+
+
+def test_poisson_thresholds_match_scipy():
+    from scipy.stats import poisson
+    for nu in (300.0, 1000.0, 1500.0, 8000.0):
+        o = _net(nu_ext_hz=[nu, nu / 2])
+        for q, rate in ((0, nu), (1, nu / 2)):
+            thr = o.table(f"pois_thr_{q}", np.uint32).astype(np.float64)
+            mean = rate * 0.1e-3
+            ref = np.floor(poisson.cdf(np.arange(len(thr)), mean) * 2.0**32)
+            assert len(thr) >= 3
+            assert np.max(np.abs(thr - ref)) <= 1.0
+            # the first threshold left out is the one that saturates 2^32
+            nxt = poisson.cdf(len(thr), mean) * 2.0**32
+            assert nxt >= 2.0**32 - 2.0 or len(thr) == 16
+
+
+def test_torus_offsets_match_hand_worked_2x2():
+    rows = [l.split() for l in open(os.path.join(GOLD, "torus_2x2_lambda1.txt"))
+            if not l.startswith("#") and l.strip()]
+    o = O.Oracle(W.swa(), 1, store_rows=False)
+    xy = o.table("off_xy", np.int32).reshape(-1, 2)
+    thr = o.table("off_thr", np.uint32).astype(np.float64) / 2.0**32
+    cdf = np.concatenate([thr, [1.0]])
+    prob = np.diff(np.concatenate([[0.0], cdf]))
+    assert len(rows) == len(xy) == 3
+    for (ox, oy, pr), (x, y), pp in zip(rows, xy, prob):
+        assert (int(ox), int(oy)) == (x, y)
+        assert abs(float(pr) - pp) < 2e-8
+
+
+def test_torus_offsets_follow_eq1_on_larger_grid():
+    lam = 1.7
+    o = O.Oracle(W.grid(7, 5, **{"lambda": lam}), 1, store_rows=False)
+    xy = o.table("off_xy", np.int32).reshape(-1, 2)
+    thr = o.table("off_thr", np.uint32).astype(np.float64) / 2.0**32
+    prob = np.diff(np.concatenate([[0.0], thr, [1.0]]))
+    dx = np.minimum(xy[:, 0], 7 - xy[:, 0])
+    dy = np.minimum(xy[:, 1], 5 - xy[:, 1])
+    d = np.sqrt(dx**2 + dy**2)
+    # ratios between offsets follow exp(-(d1 - d2)/lambda) (Eq. 1)
+    ref = prob[0]
+    for k in range(len(prob)):
+        assert abs(prob[k] / ref - math.exp(-(d[k] - d[0]) / lam)) < 1e-7
+    assert abs(prob.sum() - 1.0) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Connectivity rows
+def test_rows_structure_local_count_no_autapse_sorted():
+    p = W.tiny(w=3, h=3, K=40, K_out=30, d_max=7, frac_local=[0.5, 0.8])
+    o = O.Oracle(p, 11, store_rows=False)
+    K, Kexc = 40, 32
+    for s in range(o.N):
+        tgt, dl, wi, doff = o.gen_row(s)
+        q = 0 if (s % K) < Kexc else 1
+        nloc = round(p["frac_local"][q] * 30)
+        assert np.all((tgt >= 0) & (tgt < o.N))
+        assert not np.any(tgt == s)
+        assert np.sum(tgt // K == s // K) == nloc
+        assert doff[0] == 0 and doff[-1] == 30 and np.all(np.diff(doff.astype(int)) >= 0)
+        for k in range(o.n_del):
+            assert np.all(dl[doff[k]:doff[k + 1]] == 1 + k)
+            # stable: local draws (drawn first) precede remote ones
+            loc = (tgt[doff[k]:doff[k + 1]] // K) == s // K
+            assert not np.any(np.diff(loc.astype(int)) > 0)
+
+
+def test_rows_statistics_delays_targets_weights():
+    from scipy.stats import chi2
+    p = W.swa()                   # 2x2 torus, K = 1250, K_out = 1000
+    o = O.Oracle(p, 5, store_rows=False)
+    K = 1250
+    dcount = np.zeros(20)
+    offc = np.zeros(3)
+    wsum = [0.0, 0.0]
+    wsq = [0.0, 0.0]
+    wn = [0, 0]
+    widx_hist = np.zeros(16)
+    loc_t = np.zeros(K)
+    wt = [o.table("wt64_0", np.float64), o.table("wt64_1", np.float64)]
+    for s in list(range(0, 5000, 7)):
+        tgt, dl, wi, doff = o.gen_row(s)
+        q = 0 if (s % K) < 1000 else 1
+        dcount += np.bincount(dl.astype(int) - 1, minlength=20)
+        ms = s // K
+        xs, ys = ms % 2, ms // 2
+        mt = tgt // K
+        rem = mt != ms
+        ox = (mt[rem] % 2 - xs) % 2
+        oy = (mt[rem] // 2 - ys) % 2
+        offc += np.bincount(oy * 2 + ox - 1, minlength=3)
+        loc_t += np.bincount(tgt[~rem] % K, minlength=K)
+        w = wt[q][wi]
+        wsum[q] += w.sum()
+        wsq[q] += (w**2).sum()
+        wn[q] += len(w)
+        widx_hist += np.bincount(wi >> 12, minlength=16)
+    # delays uniform on 1..20
+    e = dcount.sum() / 20
+    assert chi2.sf(((dcount - e) ** 2 / e).sum(), 19) > 1e-4
+    # remote modules follow the hand-worked Eq. 1 probabilities
+    gold = [0.37581837, 0.37581837, 0.24836326]
+    e = offc.sum() * np.array(gold)
+    assert chi2.sf(((offc - e) ** 2 / e).sum(), 2) > 1e-4
+    # efficacy indices uniform
+    e = widx_hist.sum() / 16
+    assert chi2.sf(((widx_hist - e) ** 2 / e).sum(), 15) > 1e-4
+    # efficacies: Gaussian mean and SD within 4 standard errors
+    for q, (mu, sd) in enumerate(((0.5, 0.1), (-2.0, 0.4))):
+        m = wsum[q] / wn[q]
+        v = wsq[q] / wn[q] - m * m
+        assert abs(m - mu) < 4 * sd / math.sqrt(wn[q])
+        assert abs(math.sqrt(v) - sd) < 4 * sd / math.sqrt(2 * wn[q]) + 1e-3 * sd
+
+
+# --------------------------------------------------------------------------
+# Neuron dynamics, Eq. 2
+def _quiet(**over):
+    """A network with no recurrent and no external input."""
+    base = dict(K=10, K_out=0, nu_ext_hz=[0.0, 0.0])
+    base.update(over)
+    return W.tiny(**base)
+
+
+@pytest.mark.parametrize("mode", [O.EXACT64, O.MIRROR32])
+def test_uncoupled_decay_matches_closed_form(mode):
+    p = _quiet(tau_c=[500.0, 300.0], gc=[0.02, 0.0], E=[-3.0, 2.5])
+    o = O.Oracle(p, 2, mode=mode)
+    rng = np.random.default_rng(0)
+    V0 = rng.uniform(-5.0, 19.0, o.N)
+    c0 = rng.uniform(0.0, 8.0, o.N)
+    o.set_state(V0, c0, np.zeros(o.N, np.int32))
+    pop = np.where((np.arange(o.N) % 10) < 8, 0, 1)
+    tau_m = np.array(p["tau_m"])[pop]
+    tau_c = np.array(p["tau_c"])[pop]
+    gc = np.array(p["gc"])[pop]
+    done = 0
+    for n in (1, 7, 100, 2000, 20000):
+        o.step(n - done)
+        done = n
+        t = n * 0.1
+        cn = c0 * np.exp(-t / tau_c)
+        E = np.array(p["E"])[pop]
+        Vn = (E + (V0 - E) * np.exp(-t / tau_m)
+              - gc * c0 * (np.exp(-t / tau_c) - np.exp(-t / tau_m)) / (1 / tau_m - 1 / tau_c))
+        V, c, r = o.state()
+        scale = np.abs(V0) + np.abs(c0) + 1.0
+        tol = 1e-11 if mode == O.EXACT64 else 2e-7 * (1 + n) ** 0.5 * 4
+        assert np.max(np.abs(V - Vn) / scale) < tol, n
+        assert np.max(np.abs(c - cn) / scale) < tol, n
+        assert np.all(r == 0)
+    st, _ = o.spikes()
+    assert len(st) == 0
+
+
+@pytest.mark.parametrize("mode", [O.EXACT64, O.MIRROR32])
+def test_fI_curve_without_adaptation(mode):
+    """ISI under constant drive I: mu = E + I tau_m; after the spike n_arp
+    refractory steps, then the first m with mu + (V_r - mu) e^{-m dt/tau_m} >
+    V_th, i.e. m = floor((tau_m/dt) ln((mu - V_r)/(mu - V_th))) + 1."""
+    for I in (1.03, 1.2, 1.77, 3.0, 0.999999):
+        for q, tau_m, n_arp in ((0, 20.0, 20), (1, 10.0, 10)):
+            Iq = I * 20.0 / tau_m            # same mu for both pops
+            p = _quiet(gc=[0.0, 0.0], alpha_c=[0.0, 0.0], I_const=[Iq, Iq])
+            o = O.Oracle(p, 4, mode=mode)
+            o.step(6000)
+            st, ids = o.spikes()
+            mu = Iq * tau_m
+            sel = [st[ids == i] for i in range(o.N) if ((i % 10) < 8) == (q == 0)]
+            if mu <= 20.0:
+                assert all(len(s) == 0 for s in sel)
+                continue
+            x = (tau_m / 0.1) * math.log((mu - 15.0) / (mu - 20.0))
+            expect = n_arp + int(math.floor(x)) + 1
+            for s in sel:
+                isi = np.diff(s)
+                assert len(isi) >= 3
+                if abs(x - round(x)) > 1e-6:
+                    assert np.all(isi == expect), (I, q, isi[:5], expect)
+                else:
+                    assert np.all(np.abs(isi - expect) <= 1)
+
+
+def _sfa_orbit_isis(I, gc, alpha, tau_c, tau_m=20.0, dt=0.1, n_arp=20,
+                    Vth=20.0, Vr=15.0, jmax=40000):
+    """Periodic orbit of Eq. 2 with adaptation under constant drive, in
+    steps.  For a period T = n_arp + m the fatigue right after a spike is
+    c+ = alpha / (1 - e^{-T dt/tau_c}); it decays through the refractory
+    period to c_a, then V rises from V_r along the closed-form solution of
+    Eq. 2,  V_j = mu + (V_r - mu) e^{-j dt/tau_m}
+                  - g c_a (e^{-j dt/tau_c} - e^{-j dt/tau_m}) / (1/tau_m - 1/tau_c),
+    and the next spike is at the first j with V_j > V_th: f(m) = that j.
+    f does not increase with m, so m* = the largest m with f(m) >= m is
+    found by bisection; the orbit has period n_arp + m* (f(m*) = m*) or
+    alternates between that and one step more.  Returns (T*, exact)."""
+    mu = I * tau_m
+    a, b = 1.0 / tau_m, 1.0 / tau_c
+    j = np.arange(1, jmax + 1)
+
+    def f(m):
+        T = n_arp + m
+        cplus = alpha / (1.0 - math.exp(-T * dt / tau_c))
+        ca = cplus * math.exp(-n_arp * dt / tau_c)
+        Vj = mu + (Vr - mu) * np.exp(-j * dt * a) - gc * ca * (
+            np.exp(-j * dt * b) - np.exp(-j * dt * a)) / (a - b)
+        above = np.nonzero(Vj > Vth)[0]
+        return int(above[0]) + 1 if len(above) else jmax + 1
+
+    lo, hi = 1, jmax
+    assert f(lo) >= lo and f(hi) < hi
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if f(mid) >= mid:
+            lo = mid
+        else:
+            hi = mid
+    return n_arp + lo, f(lo) == lo
+
+
+@pytest.mark.parametrize("mode", [O.EXACT64, O.MIRROR32])
+def test_adaptation_steady_state_orbit(mode):
+    I, gc, alpha, tau_c = 1.25, 0.02, 1.0, 500.0
+    T, exact = _sfa_orbit_isis(I, gc, alpha, tau_c)
+    p = _quiet(K=5, frac_exc=0.8, gc=[gc, 0.0], alpha_c=[alpha, 0.0],
+               tau_c=[tau_c, tau_c], I_const=[I, 0.0])
+    o = O.Oracle(p, 9, mode=mode)
+    o.step(60000)
+    st, ids = o.spikes()
+    for i in range(o.N):
+        if (i % 5) >= 4:
+            # zero-drive inhibitory neurons never fire
+            assert len(st[ids == i]) == 0
+            continue
+        s = st[ids == i]
+        late = np.diff(s[s > 40000])
+        assert len(late) > 3
+        allowed = {T} if exact else {T, T + 1}
+        assert set(late.tolist()) <= allowed, (late[:8], T, exact)
+    # without adaptation the same drive fires far faster: the coupling matters
+    T0 = 20 + int(math.floor(200 * math.log((25.0 - 15.0) / (25.0 - 20.0)))) + 1
+    assert T > T0 + 20
+
+
+@pytest.mark.parametrize("mode", [O.EXACT64, O.MIRROR32])
+def test_external_drive_campbell(mode):
+    """Free membrane driven by the external Poisson input only: with lam =
+    nu dt events per step of efficacy J ~ N(mu_J, sd_J), the stationary
+    V = sum_k P_m^k X_k has mean lam mu_J / (1 - P_m) and variance
+    lam (mu_J^2 + sd_J^2) / (1 - P_m^2) (Campbell's theorem, discrete)."""
+    mu_J, sd_J, nu = 0.86, 0.5, 1000.0
+    p = _quiet(K=100, V_th=[1e9, 1e9], nu_ext_hz=[nu, nu],
+               Jext_mean=[mu_J, mu_J], Jext_sd=[sd_J, sd_J], gc=[0.0, 0.0])
+    o = O.Oracle(p, 21, mode=mode)
+    o.set_state(np.full(o.N, 17.0), np.zeros(o.N), np.zeros(o.N, np.int32))
+    o.step(2000)
+    samples = []
+    exc = (np.arange(o.N) % 100) < 80
+    for _ in range(100):
+        o.step(400)
+        V, _, _ = o.state()
+        samples.append(V[exc])
+    S = np.array(samples)
+    lam = nu * 0.1e-3
+    Pm = math.exp(-0.1 / 20.0)
+    mean_ref = lam * mu_J / (1 - Pm)
+    var_ref = lam * (mu_J**2 + sd_J**2) / (1 - Pm * Pm)
+    n_eff = S.size
+    assert abs(S.mean() - mean_ref) < 5 * math.sqrt(var_ref / n_eff)
+    assert abs(S.var() / var_ref - 1.0) < 5 * math.sqrt(2.0 / n_eff) + 0.002
+    # dropping the efficacy spread would lower the variance by a third
+    assert (mu_J**2 + sd_J**2) / mu_J**2 > 1.3
+
+
+def test_external_counts_are_poisson():
+    from scipy.stats import chi2, poisson
+    o = _net(nu_ext_hz=[1500.0, 1500.0])
+    ks = np.array([o.ext_input(i, t)[0] for i in range(o.N) for t in range(0, 40000, 13)])
+    mean = 1500.0 * 0.1e-3
+    obs = np.bincount(ks, minlength=4)[:4].astype(float)
+    obs[3] = (ks >= 3).sum()
+    exp = len(ks) * np.array([poisson.pmf(0, mean), poisson.pmf(1, mean),
+                              poisson.pmf(2, mean), poisson.sf(2, mean)])
+    assert chi2.sf(((obs - exp) ** 2 / exp).sum(), 3) > 1e-4
+
+
+def test_initial_state_uniform_below_threshold():
+    o = O.Oracle(W.swa(), 1, store_rows=False)
+    V, c, r = o.state()
+    assert np.all(V >= 0.0) and np.all(V < 20.0)
+    assert abs(V.mean() - 10.0) < 4 * 20 / math.sqrt(12 * len(V))
+    assert np.all(c == 0) and np.all(r == 0)
+
+
+@pytest.mark.parametrize("mode", [O.EXACT64, O.MIRROR32])
+def test_threshold_is_strict(mode):
+    """A spike needs V to exceed V_th (Sec. 2.2).  With the resting level at
+    the threshold, a neuron at rest or relaxing towards it never fires."""
+    p = _quiet(E=[20.0, 20.0], gc=[0.0, 0.0])
+    o = O.Oracle(p, 6, mode=mode)
+    V0 = np.where(np.arange(o.N) % 2 == 0, 20.0, 19.0)
+    o.set_state(V0, np.zeros(o.N), np.zeros(o.N, np.int32))
+    o.step(30000)
+    V, _, _ = o.state()
+    assert len(o.spikes()[0]) == 0
+    assert np.all(V[0::2] == 20.0) and np.all(V <= 20.0)
+    # a resting level a hair above the threshold does fire
+    q = _quiet(E=[20.001, 20.001], gc=[0.0, 0.0])
+    o2 = O.Oracle(q, 6, mode=mode)
+    o2.set_state(np.full(o2.N, 20.0), np.zeros(o2.N), np.zeros(o2.N, np.int32))
+    o2.step(10)
+    assert len(o2.spikes()[0]) == o2.N
+
+
+def test_external_draws_are_independent():
+    """Counts of different neurons and efficacies of different events of one
+    neuron must be independent draws."""
+    nu, sd = 8000.0, 0.5
+    o = _net(K=40, nu_ext_hz=[nu, nu], Jext_mean=[1.0, 1.0], Jext_sd=[sd, sd])
+    lam = nu * 0.1e-3
+    both, n_pairs, sums2 = 0, 0, []
+    for t in range(0, 3000):
+        ks = [o.ext_input(i, t) for i in range(o.N)]
+        for i in range(0, o.N - 1):
+            n_pairs += 1
+            both += (ks[i][0] > 0) and (ks[i + 1][0] > 0)
+        sums2 += [d for (k, _, d) in ks if k == 2]
+    p1 = 1 - math.exp(-lam)
+    assert abs(both / n_pairs - p1 * p1) < 5 * math.sqrt(p1 * p1 / n_pairs)
+    v = np.var(sums2)
+    assert abs(v / (2 * sd * sd) - 1.0) < 5 * math.sqrt(2.0 / len(sums2)) + 0.01
+
+
+def test_mirror32_tracks_exact64():
+    """Both precisions take the same random draws; before the first spike
+    that differs, their membrane potentials agree to binary32 rounding."""
+    p = W.tiny(w=2, h=2, K=50, K_out=40, nu_ext_hz=[3000.0, 3000.0])
+    a = O.Oracle(p, 17, mode=O.MIRROR32)
+    b = O.Oracle(p, 17, mode=O.EXACT64)
+    compared = 0
+    for t in range(300):
+        a.step(1)
+        b.step(1)
+        sa, sb = a.spikes(), b.spikes()
+        if len(sa[0]) != len(sb[0]) or not (np.array_equal(sa[0], sb[0]) and
+                                            np.array_equal(sa[1], sb[1])):
+            break
+        Va, ca, _ = a.state()
+        Vb, cb, _ = b.state()
+        assert np.max(np.abs(Va - Vb)) < 1e-3, t
+        assert np.max(np.abs(ca - cb)) < 1e-4, t
+        compared += 1
+    assert compared > 20 and len(a.spikes()[0]) > 10
+
+
+# --------------------------------------------------------------------------
+# Delivery: brute-force dense recomputation of every ring slot
+@pytest.mark.parametrize("w,h,wd", [(2, 2, "f32"), (3, 3, "f32"), (3, 2, "f16"),
+                                    (2, 3, "i8")])
+def test_delivery_matches_dense_bruteforce(w, h, wd):
+    p = W.tiny(w=w, h=h, K=16, K_out=8, d_max=5, weight_dtype=wd,
+               nu_ext_hz=[4000.0, 4000.0], Jext_mean=[1.5, 1.5], Jext_sd=[0.3, 0.3])
+    o = O.Oracle(p, 31)
+    N, D, K = o.N, o.D, 16
+    wfix = [o.table("wfix_0", np.int64), o.table("wfix_1", np.int64)]
+    w64 = [o.table("wt64_0", np.float64), o.table("wt64_1", np.float64)]
+    # fixed point with Q = 16 fractional bits carries the efficacy in mV to
+    # within the weight format's own rounding
+    fmt_err = {"f32": 1e-6, "f16": 2e-3, "i8": 2.5 / 254}[wd]
+    for q in (0, 1):
+        err = np.abs(wfix[q] / 2.0**16 - w64[q])
+        assert np.max(err) <= fmt_err * np.max(np.abs(w64[q])) + 2.0**-17
+    dense = np.zeros((6, N, N), np.int64)      # [delay][post][pre]
+    for s in range(N):
+        tgt, dl, wi, _ = o.gen_row(s)
+        q = 0 if (s % K) < 13 else 1
+        for a, d, i in zip(tgt, dl, wi):
+            dense[d, a, s] += wfix[q][i]
+    spikes = []
+    for t in range(200):
+        o.step(1)
+        st, ids = o.spikes()
+        vec = np.zeros(N, np.int64)
+        vec[ids[st == t]] = 1
+        spikes.append(vec)
+        ring = o.ring()
+        for tp in range(t + 1, t + D + 1):
+            exp = np.zeros(N, np.int64)
+            for d in range(max(1, tp - t), 6):
+                if tp - d >= 0:
+                    exp += dense[d] @ spikes[tp - d]
+            assert np.array_equal(ring[tp % D], exp), (t, tp)
+    assert sum(v.sum() for v in spikes) > 50
+
+
+def test_rates_are_binned_spike_counts():
+    p = W.tiny(w=3, h=2, K=20, K_out=10, rate_bin_steps=7,
+               nu_ext_hz=[3000.0, 3000.0], Jext_mean=[1.5, 1.5])
+    o = O.Oracle(p, 8)
+    o.step(300)
+    st, ids = o.spikes()
+    r = o.rates()
+    ref = np.zeros_like(r)
+    for t, i in zip(st, ids):
+        ref[t // 7, i // 20, 0 if (i % 20) < 16 else 1] += 1
+    assert r.shape[0] == (300 + 6) // 7
+    assert np.array_equal(r, ref) and len(st) > 0
