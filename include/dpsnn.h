@@ -1,0 +1,200 @@
+/*
+ * dpsnn.h -- C-ABI of libdpsnn, the MI355X (gfx950) hot path of the
+ * cortical-grid spiking simulation of Pastorelli et al., "Scaling of a
+ * large-scale simulation of synchronous slow-wave and asynchronous
+ * awake-like activity of a cortical model with long-range
+ * interconnections" (Front. Syst. Neurosci. 2019).
+ *
+ * The network (Sec. 2.2): a W x H grid of modules of K point-like neurons,
+ * a fraction frac_exc excitatory with spike-frequency adaptation, the rest
+ * inhibitory; every neuron projects K_out synapses, a fixed share inside
+ * its own module and the rest to other modules chosen with probability
+ * proportional to exp(-d / lambda) (Eq. 1); Gaussian efficacies; integer
+ * delays; an external Poisson drive generated on the fly.  The neuron is
+ * the LIF neuron with adaptation of Eq. 2 with the constants of Table S1.
+ *
+ * One step of dt advances every neuron (Eq. 2, exact propagator), collects
+ * the spikes, and pushes each spike along its synapse row into per-target
+ * input slots indexed by the arrival step (the per-delay input queues of
+ * Sec. 2.1.1, steps 3-4).  Inputs are summed in fixed point, so the order
+ * in which concurrent additions land cannot change any result.
+ *
+ * Conventions for every entry point:
+ *  - return 0 on success or a negative DPSNN_E_* code;
+ *  - pointers named host_* or documented as host memory are plain host
+ *    buffers owned by the caller; the handle owns all device memory and
+ *    dpsnn_free releases it;
+ *  - a handle is used by one host thread at a time;
+ *  - work is enqueued on the handle's stream (dpsnn_set_stream); calls that
+ *    return data synchronise that stream first.
+ */
+#ifndef DPSNN_H
+#define DPSNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPSNN_ABI_VERSION 1u
+
+/* Error codes. */
+#define DPSNN_OK 0
+#define DPSNN_E_INVAL (-1)         /* invalid argument or parameter set      */
+#define DPSNN_E_NOMEM (-2)         /* device or host allocation failed       */
+#define DPSNN_E_DEVICE (-3)        /* a HIP runtime call failed              */
+#define DPSNN_E_RANGE (-4)         /* fixed-point bound violated at build    */
+#define DPSNN_E_SPIKELOG_FULL (-5) /* spike log overflowed; spikes were lost */
+#define DPSNN_E_STATE (-6)         /* call not valid in the handle's state   */
+#define DPSNN_E_RATES_FULL (-7)    /* rate bins would be overwritten         */
+
+/* Stored synaptic efficacy formats. */
+#define DPSNN_W_F32 0
+#define DPSNN_W_F16 1
+#define DPSNN_W_I8 2 /* int8 code times a per-(module, source pop) scale */
+
+/*
+ * Parameters of one network (plain data, copied at build).  Pairs are
+ * [excitatory, inhibitory]: J_* by source population, everything else by
+ * the population of the neuron itself.  Units: mV, ms, Hz; lambda in
+ * inter-module distance units.  Defaults in brackets are those of the
+ * paper's Table S1 / the benchmark workloads.
+ */
+typedef struct dpsnn_params {
+  uint32_t abi_version;    /* must be DPSNN_ABI_VERSION                     */
+  int32_t grid_w, grid_h;  /* modules per row / column                      */
+  int32_t K;               /* neurons per module [1250]                     */
+  int32_t K_out;           /* recurrent out-degree, <= 4096 [1000]          */
+  double frac_exc;         /* excitatory share of a module [0.8]            */
+  double frac_local[2];    /* share of a source's synapses kept local [0.5] */
+  double lambda;           /* decay length of Eq. 1 [1]                     */
+  int32_t torus;           /* must be 1: periodic grid                      */
+  int32_t d_min, d_max;    /* delays in steps, 1 <= d_min <= d_max,
+                              d_max - d_min < 64 [1, 20]                    */
+  double dt_ms;            /* step [0.1]                                    */
+  int32_t weight_dtype;    /* DPSNN_W_*                                     */
+  int32_t acc_bits;        /* 32 or 64: fixed-point input slot width        */
+  int32_t q_frac_bits;     /* fractional bits Q of the fixed point [16]     */
+  double J_mean[2], J_sd[2];           /* recurrent efficacy [0.5, -2.0] /
+                                          [0.1, 0.4]                        */
+  double nu_ext_hz[2];                 /* external Poisson rate [1000]      */
+  double Jext_mean[2], Jext_sd[2];     /* external efficacy                 */
+  double tau_m[2], E[2], V_th[2], V_r[2], tau_arp[2]; /* Eq. 2, Table S1    */
+  double alpha_c[2], tau_c[2];         /* adaptation increment and decay    */
+  double gc[2];                        /* g_c / C_m in 1/ms [0.02, 0]       */
+  double I_const[2];                   /* constant drive, mV/ms [0]         */
+  int32_t rate_bin_steps;              /* steps per rate bin [50 = 5 ms]    */
+  int64_t spike_log_cap;               /* device spike-log entries; 0 = off */
+  int64_t rate_bins_cap;               /* device rate bins kept [>= 1]      */
+} dpsnn_params;
+
+typedef struct dpsnn_stats {
+  int64_t t;              /* steps simulated                               */
+  int64_t n_neurons;      /* neurons                                       */
+  int64_t n_modules;      /* modules                                       */
+  int64_t n_synapses;     /* recurrent synapses = n_neurons * K_out        */
+  int64_t n_spikes;       /* spikes emitted so far                         */
+  int64_t n_events;       /* recurrent synaptic events = n_spikes * K_out  */
+  double build_ms;        /* wall time of dpsnn_build                      */
+  int64_t bytes_rows;     /* device bytes of the synapse rows              */
+  int64_t bytes_state;    /* device bytes of neuron state and input slots  */
+  int64_t bytes_total;    /* all device bytes owned by the handle          */
+  int32_t lds_bytes;      /* LDS per workgroup of the step kernel          */
+  int32_t reserved;
+} dpsnn_stats;
+
+typedef struct dpsnn_net dpsnn_net; /* opaque handle */
+
+/* Device memory hook: the allocator used by later dpsnn_build calls in
+ * this process (NULL restores hipMalloc/hipFree).  alloc returns device
+ * memory of at least `bytes` bytes aligned to 256 B, or NULL. */
+typedef void* (*dpsnn_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*dpsnn_free_fn)(void* ptr, void* ctx);
+int dpsnn_set_allocator(dpsnn_alloc_fn alloc, dpsnn_free_fn release, void* ctx);
+
+/*
+ * Build a network on the current HIP device: validates p, computes the host
+ * tables in binary64 (propagators of Eq. 2, Poisson count thresholds,
+ * Eq. 1 offset thresholds, efficacy quantile tables), allocates device
+ * memory, generates every synapse row on the device from the counter-based
+ * generator keyed by `seed`, and sets the initial state.  Blocks until
+ * done.  Errors: INVAL (bad p or out == NULL), NOMEM, DEVICE, RANGE.
+ */
+int dpsnn_build(const dpsnn_params* p, uint64_t seed, dpsnn_net** out);
+
+/* Stream on which later work of this handle is enqueued (a hipStream_t;
+ * NULL = the default stream). */
+int dpsnn_set_stream(dpsnn_net* net, void* hip_stream);
+
+/*
+ * Enqueue n_steps steps of dt (Eq. 2 update of every neuron with its
+ * input slot and external drive, spike collection, delivery of the spikes
+ * along their rows into the input slots, 5 ms population counts, spike
+ * log).  Asynchronous: returns once enqueued.  Errors: INVAL (n_steps < 0),
+ * RATES_FULL (the steps would overwrite rate bins not yet read; nothing is
+ * enqueued), DEVICE.
+ */
+int dpsnn_step(dpsnn_net* net, int64_t n_steps);
+
+/* Wait for the handle's stream.  Returns SPIKELOG_FULL once if the spike
+ * log overflowed since the last check. */
+int dpsnn_sync(dpsnn_net* net);
+
+/*
+ * Drain the device spike log into host_step[] / host_id[] (each of
+ * capacity `cap`), sorted by (step, neuron id).  *n_out = number of logged
+ * spikes.  With cap < *n_out nothing is copied or drained (query with
+ * cap = 0).  Synchronises.  Errors: INVAL, SPIKELOG_FULL (the log
+ * overflowed: what was kept is still returned and drained), DEVICE.
+ */
+int dpsnn_read_spikes(dpsnn_net* net, int32_t* host_step, int32_t* host_id,
+                      int64_t cap, int64_t* n_out);
+
+/*
+ * Drain the completed population-count bins (Sec. 2.3: firing rates per
+ * sub-population in bins of rate_bin_steps): host_counts is
+ * [bins][modules][2] uint32 with capacity cap_bins bins; *n_bins = bins
+ * available.  With cap_bins < *n_bins nothing is copied or drained.
+ * Synchronises.
+ */
+int dpsnn_read_rates(dpsnn_net* net, uint32_t* host_counts, int64_t cap_bins,
+                     int64_t* n_bins);
+
+/* Counters and sizes (synchronises). */
+int dpsnn_stats_get(dpsnn_net* net, dpsnn_stats* out);
+
+void dpsnn_free(dpsnn_net* net);
+const char* dpsnn_strerror(int code);
+
+/* ---- inspection entry points (tests and tools; synchronise) ---------- */
+
+/* Neuron state: V and c as binary32, ref (remaining refractory steps) as
+ * uint8; each host array holds n_neurons entries (any may be NULL). */
+int dpsnn_read_state(dpsnn_net* net, float* host_V, float* host_c,
+                     uint8_t* host_ref);
+int dpsnn_write_state(dpsnn_net* net, const float* host_V,
+                      const float* host_c, const uint8_t* host_ref);
+
+/* Input slots: D = d_max + 1 slots of n_neurons fixed-point values,
+ * slot-major, as int64 whatever the device width. */
+int dpsnn_read_slots(dpsnn_net* net, int64_t* host_slots);
+
+/* Synapse rows first..first+count-1 (Eq. 1 targets, stored efficacies,
+ * delay offsets): host_tgt int32 [count][K_out]; host_w [count][K_out] of
+ * the stored format (float / binary16 bits / int8 code); host_doff uint16
+ * [count][d_max - d_min + 2] with doff[k] = first position of delay
+ * d_min + k.  Any pointer may be NULL. */
+int dpsnn_read_rows(dpsnn_net* net, int64_t first, int64_t count,
+                    int32_t* host_tgt, void* host_w, uint16_t* host_doff);
+
+/* Host table computed from p without any device (named arrays, see the
+ * library source); returns the size in bytes, or a negative code. */
+int64_t dpsnn_host_table(const dpsnn_params* p, const char* name, void* out,
+                         int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPSNN_H */

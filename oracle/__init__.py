@@ -100,6 +100,10 @@ def lib():
         L.orc_set_state.restype = C.c_int32
         L.orc_get_ring.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_get_ring.restype = C.c_int32
+        L.orc_set_ring.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_ring.restype = C.c_int32
+        L.orc_set_time.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_set_time.restype = C.c_int32
         L.orc_spikes.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
         L.orc_spikes.restype = C.c_int64
         L.orc_rates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
@@ -217,6 +221,19 @@ class Oracle:
             out = np.zeros(self.D * self.N, np.float64)
             lib().orc_get_ring(self._h, None, _ptr(out))
         return out.reshape(self.D, self.N)
+
+    def set_ring(self, ring):
+        if self.mode == MIRROR32:
+            r = np.ascontiguousarray(ring, np.int64).reshape(-1)
+            assert r.size == self.D * self.N
+            lib().orc_set_ring(self._h, _ptr(r), None)
+        else:
+            r = np.ascontiguousarray(ring, np.float64).reshape(-1)
+            assert r.size == self.D * self.N
+            lib().orc_set_ring(self._h, None, _ptr(r))
+
+    def set_time(self, t: int):
+        lib().orc_set_time(self._h, int(t))
 
     def spikes(self):
         n = lib().orc_spikes(self._h, None, None, 0)

@@ -761,6 +761,24 @@ int32_t orc_get_ring(const orc_net* n, int64_t* ring_fix, double* ring_f64) {
   return ORC_OK;
 }
 
+int32_t orc_set_ring(orc_net* n, const int64_t* ring_fix, const double* ring_f64) {
+  size_t cnt = (size_t)n->D * (size_t)n->N;
+  if (n->mode == ORC_MIRROR32) {
+    if (!ring_fix) return ORC_E_INVAL;
+    memcpy(n->ring_fix, ring_fix, cnt * sizeof(int64_t));
+  } else {
+    if (!ring_f64) return ORC_E_INVAL;
+    memcpy(n->ring64, ring_f64, cnt * sizeof(double));
+  }
+  return ORC_OK;
+}
+
+int32_t orc_set_time(orc_net* n, int64_t t) {
+  if (t < 0) return ORC_E_INVAL;
+  n->t = t;
+  return ORC_OK;
+}
+
 int64_t orc_spikes(const orc_net* n, int32_t* step, int32_t* id, int64_t cap) {
   int64_t m = n->n_sp < cap ? n->n_sp : cap;
   if (step) memcpy(step, n->sp_t, sizeof(int32_t) * (size_t)(m > 0 ? m : 0));

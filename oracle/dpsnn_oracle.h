@@ -127,6 +127,10 @@ int32_t  orc_get_state(const orc_net* n, double* V, double* c, int32_t* ref);
 int32_t  orc_set_state(orc_net* n, const double* V, const double* c,
                        const int32_t* ref);
 int32_t  orc_get_ring(const orc_net* n, int64_t* ring_fix, double* ring_f64);
+int32_t  orc_set_ring(orc_net* n, const int64_t* ring_fix, const double* ring_f64);
+/* Move the step counter (state restored from elsewhere, e.g. to re-run
+ * one step of a longer simulation). */
+int32_t  orc_set_time(orc_net* n, int64_t t);
 
 /* Spikes since creation as (step, id) in the order they were emitted
  * (step-major, id ascending). Returns the count; copies min(count, cap). */

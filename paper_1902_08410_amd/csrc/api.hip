@@ -1,0 +1,477 @@
+// C-ABI of libdpsnn (declared in include/dpsnn.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <vector>
+
+#include "dpsnn_internal.h"
+
+namespace dpsnn {
+std::vector<int64_t> fix_table(const dpsnn_params& p, const HostTables& T, int q);
+}
+
+using namespace dpsnn;
+
+namespace {
+
+dpsnn_alloc_fn g_alloc = nullptr;
+dpsnn_free_fn g_free = nullptr;
+void* g_ctx = nullptr;
+
+#define HIP_OK(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) return DPSNN_E_DEVICE; \
+  } while (0)
+
+void* dev_alloc(dpsnn_net* n, size_t bytes) {
+  bytes = (bytes + 255) / 256 * 256;
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (n->free_fn) {
+    p = g_alloc ? g_alloc(bytes, n->alloc_ctx) : nullptr;
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    n->blocks.push_back(p);
+    n->bytes_total += (int64_t)bytes;
+  }
+  return p;
+}
+
+void release_all(dpsnn_net* n) {
+  for (void* p : n->blocks) {
+    if (n->free_fn)
+      n->free_fn(p, n->alloc_ctx);
+    else
+      (void)hipFree(p);
+  }
+  n->blocks.clear();
+}
+
+int acc_bytes(const dpsnn_params& p) { return p.acc_bits == 32 ? 4 : 8; }
+int w_bytes(const dpsnn_params& p) {
+  return p.weight_dtype == DPSNN_W_F32 ? 4 : p.weight_dtype == DPSNN_W_F16 ? 2 : 1;
+}
+
+int build_impl(dpsnn_net* n) {
+  const dpsnn_params& p = n->p;
+  HostTables& T = n->T;
+  int rc = compute_tables(p, T);
+  if (rc != DPSNN_OK) return rc;
+  HIP_OK(hipGetDevice(&n->device));
+  const hipStream_t st = n->stream;
+  const int64_t N = T.N, Np = T.N_pad, M = T.M;
+  const int ab = acc_bytes(p), wb = w_bytes(p);
+
+  // ---- device memory
+  int32_t* tgt = (int32_t*)dev_alloc(n, (size_t)N * T.row_stride * 4);
+  void* w = dev_alloc(n, (size_t)N * T.row_stride * wb);
+  uint16_t* doff = (uint16_t*)dev_alloc(n, (size_t)N * T.doff_stride * 2);
+  n->bytes_rows = (int64_t)N * T.row_stride * (4 + wb) + (int64_t)N * T.doff_stride * 2;
+  float* V = (float*)dev_alloc(n, (size_t)Np * 4);
+  float* c = (float*)dev_alloc(n, (size_t)Np * 4);
+  uint8_t* ref = (uint8_t*)dev_alloc(n, (size_t)Np);
+  void* slots = dev_alloc(n, (size_t)T.D * Np * ab);
+  n->bytes_state = Np * 9 + (int64_t)T.D * Np * ab;
+  int2* log = (int2*)dev_alloc(n, (size_t)std::max<int64_t>(p.spike_log_cap, 1) * 8);
+  unsigned long long* counters = (unsigned long long*)dev_alloc(n, 256);
+  unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p.rate_bins_cap * M * 2 * 4);
+  const size_t n_off = T.off_xy.size() / 2;
+  uint32_t* off_thr = (uint32_t*)dev_alloc(n, std::max<size_t>(T.off_thr.size(), 1) * 4);
+  int32_t* off_xy = (int32_t*)dev_alloc(n, std::max<size_t>(T.off_xy.size(), 2) * 4);
+  void* wtab[2];
+  for (int q = 0; q < 2; ++q) wtab[q] = dev_alloc(n, (size_t)kQuantN * wb);
+  void* jx = dev_alloc(n, (size_t)2 * kQuantN * ab);
+  int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * 2 * 8);
+  if (!tgt || !w || !doff || !V || !c || !ref || !slots || !log || !counters || !rates ||
+      !off_thr || !off_xy || !wtab[0] || !wtab[1] || !jx || !sfix)
+    return DPSNN_E_NOMEM;
+
+  // ---- tables
+  if (!T.off_thr.empty())
+    HIP_OK(hipMemcpyAsync(off_thr, T.off_thr.data(), T.off_thr.size() * 4, hipMemcpyHostToDevice, st));
+  if (!T.off_xy.empty())
+    HIP_OK(hipMemcpyAsync(off_xy, T.off_xy.data(), T.off_xy.size() * 4, hipMemcpyHostToDevice, st));
+  for (int q = 0; q < 2; ++q) {
+    const void* src = p.weight_dtype == DPSNN_W_F32 ? (const void*)T.wt32[q].data()
+                      : p.weight_dtype == DPSNN_W_F16 ? (const void*)T.wt16[q].data()
+                                                      : (const void*)T.wq8[q].data();
+    HIP_OK(hipMemcpyAsync(wtab[q], src, (size_t)kQuantN * wb, hipMemcpyHostToDevice, st));
+  }
+  std::vector<unsigned char> jxh((size_t)2 * kQuantN * ab);
+  for (int q = 0; q < 2; ++q)
+    for (int i = 0; i < kQuantN; ++i) {
+      const int64_t v = T.jxfix[q][i];
+      if (ab == 4) {
+        const int32_t v32 = (int32_t)v;
+        memcpy(&jxh[((size_t)q * kQuantN + i) * 4], &v32, 4);
+      } else {
+        memcpy(&jxh[((size_t)q * kQuantN + i) * 8], &v, 8);
+      }
+    }
+  HIP_OK(hipMemcpyAsync(jx, jxh.data(), jxh.size(), hipMemcpyHostToDevice, st));
+  // int8 scale per (module, source pop); modules of one network share the
+  // parameters, hence the scale of their population table
+  std::vector<int64_t> sf((size_t)M * 2);
+  for (int64_t m = 0; m < M; ++m) {
+    sf[2 * m] = T.s8fix[0];
+    sf[2 * m + 1] = T.s8fix[1];
+  }
+  HIP_OK(hipMemcpyAsync(sfix, sf.data(), sf.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemsetAsync(slots, 0, (size_t)T.D * Np * ab, st));
+  HIP_OK(hipMemsetAsync(counters, 0, 256, st));
+  HIP_OK(hipMemsetAsync(rates, 0, (size_t)p.rate_bins_cap * M * 2 * 4, st));
+
+  // ---- initial state and rows
+  InitArgs ia{};
+  ia.N = N;
+  ia.N_pad = Np;
+  ia.K = p.K;
+  ia.K_exc = T.K_exc;
+  ia.key0 = (uint32_t)n->seed;
+  ia.key1 = (uint32_t)(n->seed >> 32);
+  for (int q = 0; q < 2; ++q) {
+    ia.E[q] = (float)p.E[q];
+    ia.Vth[q] = (float)p.V_th[q];
+  }
+  ia.V = V;
+  ia.c = c;
+  ia.ref = ref;
+  HIP_OK(launch_init(ia, st));
+
+  GenArgs ga{};
+  ga.N = N;
+  ga.K = p.K;
+  ga.K_exc = T.K_exc;
+  ga.K_out = p.K_out;
+  ga.row_stride = T.row_stride;
+  ga.doff_stride = T.doff_stride;
+  ga.n_del = T.n_del;
+  ga.d_min = p.d_min;
+  ga.W = p.grid_w;
+  ga.H = p.grid_h;
+  ga.n_off = (int32_t)n_off;
+  ga.n_local[0] = T.n_local[0];
+  ga.n_local[1] = T.n_local[1];
+  ga.key0 = ia.key0;
+  ga.key1 = ia.key1;
+  ga.off_thr = off_thr;
+  ga.off_xy = off_xy;
+  ga.wtab[0] = wtab[0];
+  ga.wtab[1] = wtab[1];
+  ga.tgt = tgt;
+  ga.w = w;
+  ga.doff = doff;
+  // int32 input slots: check at build that no step can leave the range.
+  // The per-step sum at a neuron is bounded by the sum of |fixed-point
+  // efficacy| over its incoming synapses plus the largest external sum.
+  unsigned long long* absum = nullptr;
+  int64_t* wfix_dev = nullptr;
+  if (p.acc_bits == 32 && p.K_out > 0) {
+    absum = (unsigned long long*)dev_alloc(n, (size_t)N * 8 + 256);
+    wfix_dev = (int64_t*)dev_alloc(n, (size_t)2 * kQuantN * 8);
+    if (!absum || !wfix_dev) return DPSNN_E_NOMEM;
+    std::vector<int64_t> wf((size_t)2 * kQuantN);
+    for (int q = 0; q < 2; ++q) {
+      std::vector<int64_t> t = fix_table(p, T, q);
+      std::copy(t.begin(), t.end(), wf.begin() + (size_t)q * kQuantN);
+    }
+    HIP_OK(hipMemcpyAsync(wfix_dev, wf.data(), wf.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemsetAsync(absum, 0, (size_t)N * 8 + 256, st));
+    ga.absum = absum;
+    ga.wfix_tab[0] = wfix_dev;
+    ga.wfix_tab[1] = wfix_dev + kQuantN;
+  }
+  if (p.K_out > 0) HIP_OK(launch_gen(ga, p.weight_dtype, st));
+  if (absum) {
+    HIP_OK(launch_absum_max(absum, N, absum + N, st));
+    unsigned long long mx = 0;
+    HIP_OK(hipMemcpyAsync(&mx, absum + N, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if ((double)mx + (double)T.ext_bound >= 2147483647.0) return DPSNN_E_RANGE;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+
+  // ---- step arguments
+  StepArgs& a = n->sa;
+  memset(&a, 0, sizeof(a));
+  a.N = N;
+  a.N_pad = Np;
+  a.K = p.K;
+  a.K_exc = T.K_exc;
+  a.K_out = p.K_out;
+  a.row_stride = T.row_stride;
+  a.doff_stride = T.doff_stride;
+  a.D = T.D;
+  a.n_del = T.n_del;
+  a.d_min = p.d_min;
+  a.M = (int32_t)M;
+  a.rate_bin_steps = p.rate_bin_steps;
+  a.rate_bins_cap = (int32_t)p.rate_bins_cap;
+  a.key0 = ia.key0;
+  a.key1 = ia.key1;
+  for (int q = 0; q < 2; ++q) {
+    a.Pm[q] = T.prop32[q][0];
+    a.Pc[q] = T.prop32[q][1];
+    a.PVc[q] = T.prop32[q][2];
+    a.Iterm[q] = T.prop32[q][3];
+    a.E[q] = (float)p.E[q];
+    a.Vth[q] = (float)p.V_th[q];
+    a.Vr[q] = (float)p.V_r[q];
+    a.alpha[q] = (float)p.alpha_c[q];
+    a.n_arp[q] = T.n_arp[q];
+    a.n_pois[q] = T.n_pois[q];
+    for (int x = 0; x < kMaxPois; ++x) a.pois[q][x] = T.pois[q][x];
+  }
+  a.inv2q = ldexpf(1.0f, -p.q_frac_bits);
+  a.two_q = ldexpf(1.0f, p.q_frac_bits);
+  a.spike_log_cap = p.spike_log_cap;
+  a.V = V;
+  a.c = c;
+  a.ref = ref;
+  a.slots = slots;
+  a.tgt = tgt;
+  a.w = w;
+  a.doff = doff;
+  a.jxfix = jx;
+  a.sfix = sfix;
+  a.log = log;
+  a.log_count = counters;
+  a.rates = rates;
+  a.n_spikes = counters + 1;
+  n->d_counters = counters;
+  return DPSNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpsnn_set_allocator(dpsnn_alloc_fn alloc, dpsnn_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr)) return DPSNN_E_INVAL;
+  g_alloc = alloc;
+  g_free = release;
+  g_ctx = ctx;
+  return DPSNN_OK;
+}
+
+int dpsnn_build(const dpsnn_params* p, uint64_t seed, dpsnn_net** out) {
+  if (!p || !out) return DPSNN_E_INVAL;
+  *out = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<dpsnn_net> n(new dpsnn_net());
+  n->p = *p;
+  n->seed = seed;
+  n->free_fn = g_free;
+  n->alloc_ctx = g_ctx;
+  const int rc = build_impl(n.get());
+  if (rc != DPSNN_OK) {
+    (void)hipStreamSynchronize(n->stream);
+    release_all(n.get());
+    return rc;
+  }
+  n->build_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = n.release();
+  return DPSNN_OK;
+}
+
+int dpsnn_set_stream(dpsnn_net* n, void* s) {
+  if (!n) return DPSNN_E_INVAL;
+  n->stream = (hipStream_t)s;
+  return DPSNN_OK;
+}
+
+int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
+  if (!n || n_steps < 0) return DPSNN_E_INVAL;
+  if (n_steps == 0) return DPSNN_OK;
+  if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
+  const int64_t last_bin = (n->t + n_steps - 1) / n->p.rate_bin_steps;
+  if (last_bin - n->rate_first + 1 > n->p.rate_bins_cap) return DPSNN_E_RATES_FULL;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    if (launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, (uint32_t)(n->t + k), n->stream) !=
+        hipSuccess)
+      return DPSNN_E_DEVICE;
+  }
+  n->t += n_steps;
+  return DPSNN_OK;
+}
+
+int dpsnn_sync(dpsnn_net* n) {
+  if (!n) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  unsigned long long cnt = 0;
+  HIP_OK(hipMemcpy(&cnt, n->d_counters, 8, hipMemcpyDeviceToHost));
+  if ((int64_t)cnt > n->p.spike_log_cap) return DPSNN_E_SPIKELOG_FULL;
+  return DPSNN_OK;
+}
+
+int dpsnn_read_spikes(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_t cap,
+                      int64_t* n_out) {
+  if (!n || !n_out || cap < 0) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  unsigned long long cnt = 0;
+  HIP_OK(hipMemcpy(&cnt, n->d_counters, 8, hipMemcpyDeviceToHost));
+  const bool overflow = (int64_t)cnt > n->p.spike_log_cap;
+  const int64_t have = std::min<int64_t>((int64_t)cnt, n->p.spike_log_cap);
+  *n_out = have;
+  if (cap < have || (have > 0 && (!host_step || !host_id))) return DPSNN_OK;
+  std::vector<int2> buf((size_t)have);
+  if (have > 0)
+    HIP_OK(hipMemcpy(buf.data(), n->sa.log, (size_t)have * 8, hipMemcpyDeviceToHost));
+  std::sort(buf.begin(), buf.end(), [](const int2& a, const int2& b) {
+    return a.x != b.x ? a.x < b.x : a.y < b.y;
+  });
+  for (int64_t k = 0; k < have; ++k) {
+    host_step[k] = buf[k].x;
+    host_id[k] = buf[k].y;
+  }
+  HIP_OK(hipMemsetAsync(n->d_counters, 0, 8, n->stream));
+  HIP_OK(hipStreamSynchronize(n->stream));
+  return overflow ? DPSNN_E_SPIKELOG_FULL : DPSNN_OK;
+}
+
+int dpsnn_read_rates(dpsnn_net* n, uint32_t* host_counts, int64_t cap_bins, int64_t* n_bins) {
+  if (!n || !n_bins || cap_bins < 0) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const int64_t done = n->t / n->p.rate_bin_steps;
+  const int64_t nb = done - n->rate_first;
+  *n_bins = nb;
+  if (nb <= 0 || cap_bins < nb || !host_counts) return DPSNN_OK;
+  const int64_t per = (int64_t)n->T.M * 2;
+  const int64_t cap = n->p.rate_bins_cap;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t src = (n->rate_first + b) % cap;
+    HIP_OK(hipMemcpy(host_counts + b * per, n->sa.rates + src * per, (size_t)per * 4,
+                     hipMemcpyDeviceToHost));
+    HIP_OK(hipMemsetAsync(n->sa.rates + src * per, 0, (size_t)per * 4, n->stream));
+  }
+  HIP_OK(hipStreamSynchronize(n->stream));
+  n->rate_first = done;
+  return DPSNN_OK;
+}
+
+int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
+  if (!n || !out) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  unsigned long long ns = 0;
+  HIP_OK(hipMemcpy(&ns, n->d_counters + 1, 8, hipMemcpyDeviceToHost));
+  memset(out, 0, sizeof(*out));
+  out->t = n->t;
+  out->n_neurons = n->T.N;
+  out->n_modules = n->T.M;
+  out->n_synapses = n->T.N * n->p.K_out;
+  out->n_spikes = (int64_t)ns;
+  out->n_events = (int64_t)ns * n->p.K_out;
+  out->build_ms = n->build_ms;
+  out->bytes_rows = n->bytes_rows;
+  out->bytes_state = n->bytes_state;
+  out->bytes_total = n->bytes_total;
+  out->lds_bytes = 1024 * 4 + 16;
+  return DPSNN_OK;
+}
+
+void dpsnn_free(dpsnn_net* n) {
+  if (!n) return;
+  (void)hipStreamSynchronize(n->stream);
+  release_all(n);
+  delete n;
+}
+
+const char* dpsnn_strerror(int code) {
+  switch (code) {
+    case DPSNN_OK: return "ok";
+    case DPSNN_E_INVAL: return "invalid argument";
+    case DPSNN_E_NOMEM: return "out of memory";
+    case DPSNN_E_DEVICE: return "HIP runtime error";
+    case DPSNN_E_RANGE: return "fixed-point range exceeded";
+    case DPSNN_E_SPIKELOG_FULL: return "spike log full";
+    case DPSNN_E_STATE: return "invalid state";
+    case DPSNN_E_RATES_FULL: return "rate bins full";
+    default: return "unknown error";
+  }
+}
+
+int dpsnn_read_state(dpsnn_net* n, float* V, float* c, uint8_t* ref) {
+  if (!n) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const size_t N = (size_t)n->T.N;
+  if (V) HIP_OK(hipMemcpy(V, n->sa.V, N * 4, hipMemcpyDeviceToHost));
+  if (c) HIP_OK(hipMemcpy(c, n->sa.c, N * 4, hipMemcpyDeviceToHost));
+  if (ref) HIP_OK(hipMemcpy(ref, n->sa.ref, N, hipMemcpyDeviceToHost));
+  return DPSNN_OK;
+}
+
+int dpsnn_write_state(dpsnn_net* n, const float* V, const float* c, const uint8_t* ref) {
+  if (!n) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const size_t N = (size_t)n->T.N;
+  if (V) HIP_OK(hipMemcpy(n->sa.V, V, N * 4, hipMemcpyHostToDevice));
+  if (c) HIP_OK(hipMemcpy(n->sa.c, c, N * 4, hipMemcpyHostToDevice));
+  if (ref) HIP_OK(hipMemcpy(n->sa.ref, ref, N, hipMemcpyHostToDevice));
+  return DPSNN_OK;
+}
+
+int dpsnn_read_slots(dpsnn_net* n, int64_t* host_slots) {
+  if (!n || !host_slots) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const int64_t N = n->T.N, Np = n->T.N_pad;
+  const int ab = acc_bytes(n->p);
+  std::vector<unsigned char> buf((size_t)n->T.D * Np * ab);
+  HIP_OK(hipMemcpy(buf.data(), n->sa.slots, buf.size(), hipMemcpyDeviceToHost));
+  for (int64_t s = 0; s < n->T.D; ++s)
+    for (int64_t i = 0; i < N; ++i) {
+      const size_t at = (size_t)(s * Np + i);
+      if (ab == 4) {
+        int32_t v;
+        memcpy(&v, &buf[at * 4], 4);
+        host_slots[s * N + i] = v;
+      } else {
+        int64_t v;
+        memcpy(&v, &buf[at * 8], 8);
+        host_slots[s * N + i] = v;
+      }
+    }
+  return DPSNN_OK;
+}
+
+int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tgt, void* host_w,
+                    uint16_t* host_doff) {
+  if (!n || first < 0 || count < 0 || first + count > n->T.N) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const int Ko = n->p.K_out, rs = n->T.row_stride, ds = n->T.doff_stride;
+  const int wb = w_bytes(n->p);
+  if (host_tgt && Ko > 0)
+    HIP_OK(hipMemcpy2D(host_tgt, (size_t)Ko * 4, n->sa.tgt + first * rs, (size_t)rs * 4,
+                       (size_t)Ko * 4, (size_t)count, hipMemcpyDeviceToHost));
+  if (host_w && Ko > 0)
+    HIP_OK(hipMemcpy2D(host_w, (size_t)Ko * wb,
+                       static_cast<const unsigned char*>(n->sa.w) + (size_t)first * rs * wb,
+                       (size_t)rs * wb, (size_t)Ko * wb, (size_t)count, hipMemcpyDeviceToHost));
+  if (host_doff)
+    HIP_OK(hipMemcpy2D(host_doff, (size_t)(n->T.n_del + 1) * 2, n->sa.doff + first * ds,
+                       (size_t)ds * 2, (size_t)(n->T.n_del + 1) * 2, (size_t)count,
+                       hipMemcpyDeviceToHost));
+  return DPSNN_OK;
+}
+
+int64_t dpsnn_host_table(const dpsnn_params* p, const char* name, void* out, int64_t cap) {
+  if (!p || !name) return DPSNN_E_INVAL;
+  HostTables T;
+  const int rc = compute_tables(*p, T);
+  if (rc != DPSNN_OK) return rc;
+  if (!strcmp(name, "wfix_0") || !strcmp(name, "wfix_1")) {
+    std::vector<int64_t> v = fix_table(*p, T, name[5] - '0');
+    const int64_t bytes = (int64_t)v.size() * 8;
+    if (out && cap >= bytes) memcpy(out, v.data(), (size_t)bytes);
+    return bytes;
+  }
+  return host_table(T, name, out, cap);
+}
+
+}  // extern "C"

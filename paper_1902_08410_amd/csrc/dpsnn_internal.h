@@ -1,0 +1,136 @@
+// Internal declarations of libdpsnn: host tables, the handle, kernel
+// arguments and launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "dpsnn.h"
+
+namespace dpsnn {
+
+constexpr int kQuantN = 65536;  // entries of each efficacy quantile table
+constexpr int kMaxPois = 16;    // Poisson count thresholds per population
+constexpr int kMaxDelays = 64;  // distinct delays handled by one wavefront
+constexpr int kMaxKout = 4096;
+
+// Everything dpsnn_build derives from the parameters on the host, in
+// binary64 first and rounded once to the width the device uses.
+struct HostTables {
+  int64_t N = 0;          // neurons
+  int64_t N_pad = 0;      // neurons rounded up to the step kernel's tile
+  int32_t M = 0;          // modules
+  int32_t K_exc = 0;      // excitatory neurons per module
+  int32_t n_local[2] = {0, 0};
+  int32_t D = 0;          // input slots = d_max + 1
+  int32_t n_del = 0;      // distinct delays
+  int32_t row_stride = 0; // K_out rounded up to a multiple of 4
+  int32_t doff_stride = 0;
+  int32_t n_arp[2] = {0, 0};
+
+  double prop64[2][4];    // Pm, Pc, PVc, Iterm
+  float prop32[2][4];
+
+  int32_t n_pois[2] = {0, 0};
+  uint32_t pois[2][kMaxPois];
+
+  std::vector<uint32_t> off_thr;  // M - 2 cumulative thresholds
+  std::vector<int32_t> off_xy;    // (ox, oy) per offset, M - 1 offsets
+
+  std::vector<double> wt64[2];    // recurrent efficacy by source pop
+  std::vector<float> wt32[2];
+  std::vector<uint16_t> wt16[2];
+  std::vector<int8_t> wq8[2];
+  float s8[2] = {1.f, 1.f};
+  int64_t s8fix[2] = {0, 0};
+  std::vector<double> jx64[2];    // external efficacy by target pop
+  std::vector<float> jx32[2];
+  std::vector<int64_t> jxfix[2];
+  int64_t ext_bound = 0;          // largest |external sum| of one step
+};
+
+int validate(const dpsnn_params& p);
+int compute_tables(const dpsnn_params& p, HostTables& T);
+int64_t host_table(const HostTables& T, const char* name, void* out, int64_t cap);
+
+// Arguments of the step kernel (passed by value).
+struct StepArgs {
+  int64_t N, N_pad;
+  int32_t K, K_exc, K_out, row_stride, doff_stride, D, n_del, d_min, M;
+  int32_t rate_bin_steps, rate_bins_cap;
+  uint32_t key0, key1;
+  float Pm[2], Pc[2], PVc[2], Iterm[2], E[2], Vth[2], Vr[2], alpha[2];
+  int32_t n_arp[2];
+  int32_t n_pois[2];
+  uint32_t pois[2][kMaxPois];
+  float inv2q, two_q;
+  int64_t spike_log_cap;
+  float* V;
+  float* c;
+  uint8_t* ref;
+  void* slots;
+  const int32_t* tgt;
+  const void* w;
+  const uint16_t* doff;
+  const void* jxfix;
+  const int64_t* sfix;  // [M][2], int8 format only
+  int2* log;
+  unsigned long long* log_count;
+  unsigned int* rates;
+  unsigned long long* n_spikes;
+};
+
+struct GenArgs {
+  int64_t N;
+  int32_t K, K_exc, K_out, row_stride, doff_stride, n_del, d_min;
+  int32_t W, H, n_off;
+  int32_t n_local[2];
+  uint32_t key0, key1;
+  const uint32_t* off_thr;
+  const int32_t* off_xy;
+  const void* wtab[2];     // stored-format table by source pop
+  int32_t* tgt;
+  void* w;
+  uint16_t* doff;
+  // fixed-point in-weight sums for the int32 range check (may be null)
+  unsigned long long* absum;
+  const int64_t* wfix_tab[2];
+};
+
+struct InitArgs {
+  int64_t N, N_pad;
+  int32_t K, K_exc;
+  uint32_t key0, key1;
+  float E[2], Vth[2];
+  float* V;
+  float* c;
+  uint8_t* ref;
+};
+
+hipError_t launch_gen(const GenArgs& a, int wdt, hipStream_t s);
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, uint32_t t,
+                       hipStream_t s);
+hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
+                            unsigned long long* out, hipStream_t s);
+
+}  // namespace dpsnn
+
+// The opaque handle of the C-ABI.
+struct dpsnn_net {
+  dpsnn_params p;
+  uint64_t seed = 0;
+  dpsnn::HostTables T;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  dpsnn_free_fn free_fn = nullptr;
+  void* alloc_ctx = nullptr;
+  std::vector<void*> blocks;   // every device allocation of this handle
+  int64_t bytes_total = 0, bytes_rows = 0, bytes_state = 0;
+  double build_ms = 0.0;
+  int64_t t = 0;
+  int64_t rate_first = 0;      // first rate bin not yet drained
+  dpsnn::StepArgs sa;
+  unsigned long long* d_counters = nullptr;  // [0] log_count, [1] n_spikes
+};

@@ -1,0 +1,311 @@
+"""Python binding of libdpsnn (include/dpsnn.h): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels; this module
+converts parameter dicts to the C struct, passes PyTorch's current HIP
+stream and (optionally) PyTorch's caching allocator to the library, and
+copies results into NumPy arrays.  There is no fallback: if libdpsnn.so is
+missing the import of the library fails loudly.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libdpsnn.so")
+
+ABI_VERSION = 1
+W_F32, W_F16, W_I8 = 0, 1, 2
+WEIGHT_DTYPES = {"f32": W_F32, "f16": W_F16, "i8": W_I8}
+ERRORS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "RANGE",
+          -5: "SPIKELOG_FULL", -6: "STATE", -7: "RATES_FULL"}
+
+_PAIR = C.c_double * 2
+
+
+class DpsnnParams(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("grid_w", C.c_int32), ("grid_h", C.c_int32),
+        ("K", C.c_int32), ("K_out", C.c_int32), ("frac_exc", C.c_double),
+        ("frac_local", _PAIR), ("lambda_", C.c_double), ("torus", C.c_int32),
+        ("d_min", C.c_int32), ("d_max", C.c_int32), ("dt_ms", C.c_double),
+        ("weight_dtype", C.c_int32), ("acc_bits", C.c_int32), ("q_frac_bits", C.c_int32),
+        ("J_mean", _PAIR), ("J_sd", _PAIR), ("nu_ext_hz", _PAIR), ("Jext_mean", _PAIR),
+        ("Jext_sd", _PAIR), ("tau_m", _PAIR), ("E", _PAIR), ("V_th", _PAIR),
+        ("V_r", _PAIR), ("tau_arp", _PAIR), ("alpha_c", _PAIR), ("tau_c", _PAIR),
+        ("gc", _PAIR), ("I_const", _PAIR), ("rate_bin_steps", C.c_int32),
+        ("spike_log_cap", C.c_int64), ("rate_bins_cap", C.c_int64),
+    ]
+
+
+class DpsnnStats(C.Structure):
+    _fields_ = [
+        ("t", C.c_int64), ("n_neurons", C.c_int64), ("n_modules", C.c_int64),
+        ("n_synapses", C.c_int64), ("n_spikes", C.c_int64), ("n_events", C.c_int64),
+        ("build_ms", C.c_double), ("bytes_rows", C.c_int64), ("bytes_state", C.c_int64),
+        ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+DEFAULT_SPIKE_LOG_CAP = 1 << 24
+DEFAULT_RATE_BINS_CAP = 4096
+
+
+def to_struct(params: dict) -> DpsnnParams:
+    s = DpsnnParams()
+    s.abi_version = ABI_VERSION
+    for name, ctype in DpsnnParams._fields_:
+        if name == "abi_version":
+            continue
+        key = "lambda" if name == "lambda_" else name
+        if key == "spike_log_cap":
+            v = params.get(key, DEFAULT_SPIKE_LOG_CAP)
+        elif key == "rate_bins_cap":
+            v = params.get(key, DEFAULT_RATE_BINS_CAP)
+        else:
+            v = params[key]
+        if key == "weight_dtype" and isinstance(v, str):
+            v = WEIGHT_DTYPES[v]
+        if ctype is _PAIR:
+            setattr(s, name, _PAIR(float(v[0]), float(v[1])))
+        elif ctype is C.c_double:
+            setattr(s, name, float(v))
+        else:
+            setattr(s, name, int(v))
+    return s
+
+
+class DpsnnError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {ERRORS.get(code, code)} ({code})")
+        self.code = code
+
+
+_lib = None
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def lib():
+    """The loaded libdpsnn.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with "
+                              "paper_1902_08410_amd.build.build()")
+        L = C.CDLL(LIBPATH)
+        P, V = C.POINTER, C.c_void_p
+        sig = {
+            "dpsnn_set_allocator": ([_ALLOC, _FREE, V], C.c_int),
+            "dpsnn_build": ([P(DpsnnParams), C.c_uint64, P(V)], C.c_int),
+            "dpsnn_set_stream": ([V, V], C.c_int),
+            "dpsnn_step": ([V, C.c_int64], C.c_int),
+            "dpsnn_sync": ([V], C.c_int),
+            "dpsnn_read_spikes": ([V, V, V, C.c_int64, P(C.c_int64)], C.c_int),
+            "dpsnn_read_rates": ([V, V, C.c_int64, P(C.c_int64)], C.c_int),
+            "dpsnn_stats_get": ([V, P(DpsnnStats)], C.c_int),
+            "dpsnn_free": ([V], None),
+            "dpsnn_strerror": ([C.c_int], C.c_char_p),
+            "dpsnn_read_state": ([V, V, V, V], C.c_int),
+            "dpsnn_write_state": ([V, V, V, V], C.c_int),
+            "dpsnn_read_slots": ([V, V], C.c_int),
+            "dpsnn_read_rows": ([V, C.c_int64, C.c_int64, V, V, V], C.c_int),
+            "dpsnn_host_table": ([P(DpsnnParams), C.c_char_p, V, C.c_int64], C.c_int64),
+        }
+        for fn, (args, res) in sig.items():
+            f = getattr(L, fn)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step",
+           "dpsnn_sync", "dpsnn_read_spikes", "dpsnn_read_rates", "dpsnn_stats_get",
+           "dpsnn_free", "dpsnn_strerror", "dpsnn_read_state", "dpsnn_write_state",
+           "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table"]
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise DpsnnError(fn, rc)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---- torch as device-memory and stream provider --------------------------
+class _TorchAllocator:
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.live = {}
+        self.alloc_cb = _ALLOC(self._alloc)
+        self.free_cb = _FREE(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, ptr, ctx):
+        self.live.pop(int(ptr) if ptr else 0, None)
+
+
+_torch_alloc = None
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route later builds' device allocations through torch's allocator."""
+    global _torch_alloc
+    if enable:
+        if _torch_alloc is None:
+            _torch_alloc = _TorchAllocator()
+        _check("dpsnn_set_allocator",
+               lib().dpsnn_set_allocator(_torch_alloc.alloc_cb, _torch_alloc.free_cb, None))
+    else:
+        _check("dpsnn_set_allocator", lib().dpsnn_set_allocator(
+            C.cast(None, _ALLOC), C.cast(None, _FREE), None))
+
+
+def current_torch_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Net:
+    """A built network (owns the C handle)."""
+
+    def __init__(self, handle, params: dict, seed: int):
+        self.h = handle
+        self.params = dict(params)
+        self.seed = seed
+        st = self.stats()
+        self.N = int(st["n_neurons"])
+        self.M = int(st["n_modules"])
+        self.D = int(params["d_max"]) + 1
+        self.n_del = int(params["d_max"]) - int(params["d_min"]) + 1
+
+    def stats(self) -> dict:
+        return dpsnn_stats_get(self)
+
+    def close(self):
+        if self.h:
+            lib().dpsnn_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dpsnn_build(params: dict, seed: int, stream=None, torch_memory: bool = True) -> Net:
+    if torch_memory:
+        use_torch_allocator(True)
+    s = to_struct(params)
+    h = C.c_void_p()
+    _check("dpsnn_build", lib().dpsnn_build(C.byref(s), C.c_uint64(seed), C.byref(h)))
+    net = Net(h, params, seed)
+    dpsnn_set_stream(net, current_torch_stream() if stream is None else stream)
+    return net
+
+
+def dpsnn_set_stream(net: Net, stream) -> None:
+    _check("dpsnn_set_stream", lib().dpsnn_set_stream(net.h, C.c_void_p(int(stream or 0))))
+
+
+def dpsnn_step(net: Net, n_steps: int) -> None:
+    _check("dpsnn_step", lib().dpsnn_step(net.h, int(n_steps)))
+
+
+def dpsnn_sync(net: Net) -> int:
+    return int(lib().dpsnn_sync(net.h))
+
+
+def dpsnn_read_spikes(net: Net):
+    n = C.c_int64(0)
+    rc = lib().dpsnn_read_spikes(net.h, None, None, 0, C.byref(n))
+    if rc not in (0, -5):
+        _check("dpsnn_read_spikes", rc)
+    st = np.zeros(n.value, np.int32)
+    ids = np.zeros(n.value, np.int32)
+    rc = lib().dpsnn_read_spikes(net.h, _ptr(st), _ptr(ids), n.value, C.byref(n))
+    _check("dpsnn_read_spikes", rc)
+    return st, ids
+
+
+def dpsnn_read_rates(net: Net) -> np.ndarray:
+    nb = C.c_int64(0)
+    _check("dpsnn_read_rates", lib().dpsnn_read_rates(net.h, None, 0, C.byref(nb)))
+    out = np.zeros((max(nb.value, 0), net.M, 2), np.uint32)
+    if nb.value > 0:
+        _check("dpsnn_read_rates",
+               lib().dpsnn_read_rates(net.h, _ptr(out), nb.value, C.byref(nb)))
+    return out
+
+
+def dpsnn_stats_get(net: Net) -> dict:
+    s = DpsnnStats()
+    _check("dpsnn_stats_get", lib().dpsnn_stats_get(net.h, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in DpsnnStats._fields_}
+
+
+def dpsnn_free(net: Net) -> None:
+    net.close()
+
+
+def dpsnn_strerror(code: int) -> str:
+    return lib().dpsnn_strerror(int(code)).decode()
+
+
+def dpsnn_read_state(net: Net):
+    V = np.zeros(net.N, np.float32)
+    c = np.zeros(net.N, np.float32)
+    r = np.zeros(net.N, np.uint8)
+    _check("dpsnn_read_state", lib().dpsnn_read_state(net.h, _ptr(V), _ptr(c), _ptr(r)))
+    return V, c, r
+
+
+def dpsnn_write_state(net: Net, V=None, c=None, ref=None) -> None:
+    V = None if V is None else np.ascontiguousarray(V, np.float32)
+    c = None if c is None else np.ascontiguousarray(c, np.float32)
+    ref = None if ref is None else np.ascontiguousarray(ref, np.uint8)
+    _check("dpsnn_write_state", lib().dpsnn_write_state(net.h, _ptr(V), _ptr(c), _ptr(ref)))
+
+
+def dpsnn_read_slots(net: Net) -> np.ndarray:
+    out = np.zeros((net.D, net.N), np.int64)
+    _check("dpsnn_read_slots", lib().dpsnn_read_slots(net.h, _ptr(out)))
+    return out
+
+
+_W_NP = {W_F32: np.float32, W_F16: np.uint16, W_I8: np.int8}
+
+
+def dpsnn_read_rows(net: Net, first: int, count: int):
+    Ko = int(net.params["K_out"])
+    wd = net.params["weight_dtype"]
+    wd = WEIGHT_DTYPES[wd] if isinstance(wd, str) else int(wd)
+    tgt = np.zeros((count, Ko), np.int32)
+    w = np.zeros((count, Ko), _W_NP[wd])
+    doff = np.zeros((count, net.n_del + 1), np.uint16)
+    _check("dpsnn_read_rows",
+           lib().dpsnn_read_rows(net.h, int(first), int(count), _ptr(tgt), _ptr(w), _ptr(doff)))
+    return tgt, w, doff
+
+
+def dpsnn_host_table(params: dict, name: str, dtype) -> np.ndarray:
+    s = to_struct(params)
+    nb = lib().dpsnn_host_table(C.byref(s), name.encode(), None, 0)
+    if nb < 0:
+        raise DpsnnError("dpsnn_host_table", int(nb))
+    out = np.zeros(nb // np.dtype(dtype).itemsize, dtype)
+    lib().dpsnn_host_table(C.byref(s), name.encode(), _ptr(out), nb)
+    return out

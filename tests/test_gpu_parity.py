@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+The binary32-weight path must reproduce the oracle's MIRROR32 spike rasters,
+neuron state and fixed-point input slots bit for bit; the binary16 and int8
+paths are bit-exact against the oracle run with the same stored formats.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1902_08410_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_08410_amd import dpsnn
+    dpsnn.lib()
+    return dpsnn
+
+
+def _pair(p, seed, store_rows=True, **over):
+    from paper_1902_08410_amd import dpsnn
+    q = dict(p)
+    q.setdefault("spike_log_cap", 1 << 22)
+    q.setdefault("rate_bins_cap", 4096)
+    q.update(over)
+    net = dpsnn.dpsnn_build(q, seed)
+    orc = O.Oracle(q, seed, store_rows=store_rows)
+    return net, orc
+
+
+def _compare_rows(L, net, orc, rows, wd):
+    tgt, w, doff = L.dpsnn_read_rows(net, rows[0], len(rows)) if len(rows) and \
+        rows == list(range(rows[0], rows[0] + len(rows))) else (None, None, None)
+    tabs = {"f32": [orc.table(f"wt32_{q}", np.float32) for q in (0, 1)],
+            "f16": [orc.table(f"wt16_{q}", np.uint16) for q in (0, 1)],
+            "i8": [orc.table(f"wq8_{q}", np.int8) for q in (0, 1)]}[wd]
+    K = int(orc.params["K"])
+    Kexc = round(orc.params["frac_exc"] * K)
+    for k, s in enumerate(rows):
+        if tgt is None:
+            t1, w1, d1 = L.dpsnn_read_rows(net, s, 1)
+            t1, w1, d1 = t1[0], w1[0], d1[0]
+        else:
+            t1, w1, d1 = tgt[k], w[k], doff[k]
+        ot, od, ow, oo = orc.gen_row(s)
+        q = 0 if (s % K) < Kexc else 1
+        assert np.array_equal(t1, ot), s
+        assert np.array_equal(d1, oo), s
+        assert w1.tobytes() == tabs[q][ow].tobytes(), s
+
+
+@pytest.mark.parametrize("case", ["c1_f32", "tiny_f16", "tiny_i8", "ragged_3x3",
+                                  "odd_7x5", "delays64", "single_delay"])
+def test_rows_bitwise_equal(L, case):
+    p = {"c1_f32": W.swa(),
+         "tiny_f16": W.tiny(w=3, h=2, K=40, K_out=30, weight_dtype="f16"),
+         "tiny_i8": W.tiny(w=2, h=3, K=40, K_out=30, weight_dtype="i8"),
+         "ragged_3x3": W.tiny(w=3, h=3, K=47, K_out=37, d_max=11),
+         "odd_7x5": W.grid(7, 5, "swa", K=60, K_out=130, **{"lambda": 1.7}),
+         "delays64": W.tiny(w=2, h=2, K=50, K_out=300, d_min=1, d_max=64),
+         "single_delay": W.tiny(w=2, h=2, K=50, K_out=40, d_min=3, d_max=3)}[case]
+    _say("rows", case)
+    net, orc = _pair(p, 7, store_rows=False)
+    rows = list(range(net.N)) if net.N <= 5000 else list(range(0, net.N, 3))
+    _compare_rows(L, net, orc, list(range(net.N)) if net.N <= 5000 else rows,
+                  p["weight_dtype"])
+    net.close()
+
+
+def test_initial_state_equal(L):
+    _say("initial state c1")
+    net, orc = _pair(W.swa(), 3, store_rows=False)
+    V, c, r = L.dpsnn_read_state(net)
+    oV, oc, orr = orc.state()
+    assert np.array_equal(V.astype(np.float64), oV)
+    assert np.all(c == 0) and np.all(r == 0)
+    net.close()
+
+
+def _compare_state(L, net, orc, what=""):
+    V, c, r = L.dpsnn_read_state(net)
+    oV, oc, orr = orc.state()
+    assert np.array_equal(V.astype(np.float64), oV), what
+    assert np.array_equal(c.astype(np.float64), oc), what
+    assert np.array_equal(r.astype(np.int32), orr), what
+
+
+def _compare_all(L, net, orc, what=""):
+    st, ids = L.dpsnn_read_spikes(net)
+    ost, oids = orc.spikes()
+    assert len(st) == len(ost), (what, len(st), len(ost))
+    assert np.array_equal(st, ost) and np.array_equal(ids, oids), what
+    _compare_state(L, net, orc, what)
+    assert np.array_equal(L.dpsnn_read_slots(net), orc.ring()), what
+    return len(st)
+
+
+def test_uncoupled_trace_bit_exact(L):
+    p = W.tiny(w=2, h=2, K=300, K_out=0, nu_ext_hz=[3000.0, 2500.0],
+               Jext_mean=[1.0, 1.2], Jext_sd=[0.4, 0.3])
+    _say("uncoupled", p["K"])
+    net, orc = _pair(p, 11)
+    total = 0
+    for k in range(10):
+        L.dpsnn_step(net, 200)
+        orc.step(200)
+        _compare_state(L, net, orc, k)
+    st, ids = L.dpsnn_read_spikes(net)
+    ost, oids = orc.spikes()
+    assert np.array_equal(st, ost) and np.array_equal(ids, oids)
+    assert len(st) > 100
+    net.close()
+
+
+RASTER_CASES = {
+    "tiny_f32_acc32": W.tiny(w=3, h=3, K=60, K_out=50, nu_ext_hz=[3500.0, 3500.0]),
+    "tiny_f16_acc32": W.tiny(w=2, h=3, K=60, K_out=50, weight_dtype="f16",
+                             nu_ext_hz=[3500.0, 3500.0]),
+    "tiny_i8_acc32": W.tiny(w=3, h=2, K=60, K_out=50, weight_dtype="i8",
+                            nu_ext_hz=[3500.0, 3500.0]),
+    "tiny_f32_acc64": W.tiny(w=2, h=2, K=70, K_out=60, acc_bits=64, q_frac_bits=32,
+                             nu_ext_hz=[3500.0, 3500.0]),
+    "tiny_i8_acc64": W.tiny(w=3, h=3, K=50, K_out=40, weight_dtype="i8", acc_bits=64,
+                            q_frac_bits=32, nu_ext_hz=[3500.0, 3500.0]),
+    "mid_f32_local_only_1x1": W.tiny(w=1, h=1, K=900, K_out=100, frac_local=[1.0, 1.0],
+                                     nu_ext_hz=[1200.0, 1200.0]),
+    "mid_f32_strong_adapt": W.tiny(w=2, h=2, K=500, K_out=200, tau_c=[5.0, 5.0],
+                                   gc=[0.5, 0.0], alpha_c=[3.0, 0.0],
+                                   nu_ext_hz=[3000.0, 3000.0]),
+    "const_drive": W.tiny(w=2, h=2, K=30, K_out=20, I_const=[1.3, 2.1],
+                          nu_ext_hz=[0.0, 0.0]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(RASTER_CASES))
+def test_raster_bit_exact(L, case):
+    p = RASTER_CASES[case]
+    _say("raster", case)
+    net, orc = _pair(p, 5)
+    n = 0
+    for k in range(4):
+        L.dpsnn_step(net, 500)
+        orc.step(500)
+        n += _compare_all(L, net, orc, (case, k))
+    assert n > 50
+    assert np.array_equal(L.dpsnn_read_rates(net), orc.rates()[: 2000 // p["rate_bin_steps"]])
+    assert orc.status == 0
+    net.close()
+
+
+def test_raster_bit_exact_c1_two_seconds(L):
+    """Config 1: 2x2 grid, 5000 neurons, FP32 weights, SWA, 2 s = 20000 steps."""
+    _say("c1 2 s")
+    net, orc = _pair(W.swa(), 1)
+    total = 0
+    for k in range(4):
+        L.dpsnn_step(net, 5000)
+        orc.step(5000)
+        total += _compare_all(L, net, orc, k)
+    assert total > 10000
+    st = net.stats()
+    assert st["n_spikes"] == total and st["n_events"] == total * 1000
+    net.close()
+
+
+def test_c2_full_size_start_and_teacher_forced_step(L):
+    """Config 2 at full size (24x24, 720k neurons, 0.72G synapses) in the
+    benchmark's launch configuration: sampled rows, the first 30 steps
+    bit-exact, then after 2000 more steps one step re-run by the oracle from
+    the GPU's state, slots and time."""
+    p = W.grid(24, 24, "swa")
+    _say("c2 build")
+    net, orc = _pair(p, 1, store_rows=False)
+    rng = np.random.default_rng(0)
+    rows = sorted(rng.choice(net.N, 300, replace=False).tolist())
+    _compare_rows(L, net, orc, rows, "f32")
+    _say("c2 first 30 steps")
+    L.dpsnn_step(net, 30)
+    orc.step(30)
+    _compare_all(L, net, orc, "c2 start")
+    _say("c2 2000 steps + teacher forced step")
+    L.dpsnn_step(net, 2000)
+    L.dpsnn_read_spikes(net)
+    V, c, r = L.dpsnn_read_state(net)
+    slots = L.dpsnn_read_slots(net)
+    orc2 = O.Oracle(p, 1, store_rows=False)
+    orc2.set_state(V.astype(np.float64), c.astype(np.float64), r.astype(np.int32))
+    orc2.set_ring(slots)
+    orc2.set_time(2030)
+    L.dpsnn_step(net, 1)
+    orc2.step(1)
+    st, ids = L.dpsnn_read_spikes(net)
+    ost, oids = orc2.spikes()
+    assert np.array_equal(st, ost) and np.array_equal(ids, oids)
+    assert len(st) > 0
+    _compare_state(L, net, orc2, "teacher forced")
+    assert np.array_equal(L.dpsnn_read_slots(net), orc2.ring())
+    net.close()
+
+
+def test_rerun_and_chunking_identical(L):
+    p = W.tiny(w=3, h=3, K=80, K_out=60, nu_ext_hz=[3000.0, 3000.0])
+    _say("determinism")
+    from paper_1902_08410_amd import dpsnn
+    a = dpsnn.dpsnn_build(dict(p, rate_bins_cap=64), 9)
+    b = dpsnn.dpsnn_build(dict(p, rate_bins_cap=64), 9)
+    dpsnn.dpsnn_step(a, 1000)
+    for _ in range(10):
+        dpsnn.dpsnn_step(b, 100)
+    sa, sb = dpsnn.dpsnn_read_spikes(a), dpsnn.dpsnn_read_spikes(b)
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])
+    assert np.array_equal(dpsnn.dpsnn_read_slots(a), dpsnn.dpsnn_read_slots(b))
+    a.close()
+    b.close()
+
+
+def test_error_paths(L):
+    from paper_1902_08410_amd import dpsnn
+    p = W.tiny(w=2, h=2, K=40, K_out=20, nu_ext_hz=[5000.0, 5000.0])
+    _say("errors")
+    net = dpsnn.dpsnn_build(dict(p, rate_bins_cap=2, spike_log_cap=10), 1)
+    with pytest.raises(dpsnn.DpsnnError) as e:
+        dpsnn.dpsnn_step(net, 101)              # needs 3 bins of 50 steps
+    assert e.value.code == -7
+    dpsnn.dpsnn_step(net, 100)
+    assert dpsnn.dpsnn_sync(net) == -5          # more than 10 spikes
+    with pytest.raises(dpsnn.DpsnnError) as e:
+        dpsnn.dpsnn_read_spikes(net)
+    assert e.value.code == -5
+    assert dpsnn.dpsnn_read_rates(net).shape[0] == 2
+    dpsnn.dpsnn_step(net, 100)                  # bins drained: room again
+    with pytest.raises(dpsnn.DpsnnError) as e:
+        dpsnn.dpsnn_step(net, -1)
+    assert e.value.code == -1
+    net.close()

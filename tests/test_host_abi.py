@@ -1,0 +1,111 @@
+"""Host-side checks of libdpsnn that need no GPU: the shared library loads
+and exports every entry point include/dpsnn.h declares, its host tables are
+bitwise equal to the oracle's (computed independently from the same
+definitions), and invalid parameter sets are rejected."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1902_08410_amd import dpsnn as L
+from paper_1902_08410_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dpsnn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpsnn_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTS) == names
+
+
+def test_strerror_names_codes():
+    assert L.dpsnn_strerror(0) == "ok"
+    assert "spike log" in L.dpsnn_strerror(-5)
+    assert L.dpsnn_strerror(-99) == "unknown error"
+
+
+TABLES = [("prop_f64", np.float64), ("prop_f32", np.float32), ("n_arp", np.int32),
+          ("pois_thr_0", np.uint32), ("pois_thr_1", np.uint32), ("off_thr", np.uint32),
+          ("off_xy", np.int32), ("s8", np.float32), ("s8fix", np.int64)]
+for _q in (0, 1):
+    TABLES += [(f"wt64_{_q}", np.float64), (f"wt32_{_q}", np.float32),
+               (f"wt16_{_q}", np.uint16), (f"wq8_{_q}", np.int8), (f"wfix_{_q}", np.int64),
+               (f"jx64_{_q}", np.float64), (f"jx32_{_q}", np.float32),
+               (f"jxfix_{_q}", np.int64)]
+
+PARAM_SETS = {
+    "c1_swa": W.swa(),
+    "c2_aw": W.grid(24, 24, "aw"),
+    "c3_f16_l05": W.grid(48, 48, "swa", **{"lambda": 0.5, "weight_dtype": "f16"}),
+    "c3_i8_l4": W.grid(48, 48, "aw", **{"lambda": 4.0, "weight_dtype": "i8"}),
+    "c5_i8_q32": W.grid(96, 96, "swa", **{"lambda": 2.0, "weight_dtype": "i8",
+                                          "acc_bits": 64, "q_frac_bits": 32}),
+    "tiny_3x2": W.tiny(w=3, h=2, K=16, K_out=8, tau_c=[300.0, 300.0], I_const=[0.5, 0.2]),
+    "odd_7x5": W.grid(7, 5, "swa", **{"lambda": 1.7, "J_sd": [0.3, 0.9]}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PARAM_SETS))
+def test_host_tables_bitwise_equal_to_oracle(name):
+    p = PARAM_SETS[name]
+    o = O.Oracle(p, 1, store_rows=False) if p["grid_w"] * p["grid_h"] <= 64 else None
+    if o is None:
+        # tables do not depend on the network size beyond the grid: build the
+        # oracle's tables on a network with the same grid and K = 4
+        o = O.Oracle(dict(p, K=5, K_out=4, frac_local=[0.5, 0.5]), 1, store_rows=False)
+    for tname, dt in TABLES:
+        a = L.dpsnn_host_table(p, tname, dt)
+        b = o.table(tname, dt)
+        if tname.startswith(("wfix", "jxfix")) and p["acc_bits"] == 32:
+            assert np.all(np.abs(a) < 2**31)
+        assert a.dtype == b.dtype and a.shape == b.shape, tname
+        assert a.tobytes() == b.tobytes(), (name, tname)
+
+
+def test_f16_table_matches_numpy_rounding():
+    p = W.grid(4, 4, "swa", weight_dtype="f16", J_sd=[0.7, 1.3])
+    for q in (0, 1):
+        w64 = L.dpsnn_host_table(p, f"wt64_{q}", np.float64)
+        h = L.dpsnn_host_table(p, f"wt16_{q}", np.uint16)
+        assert np.array_equal(h, w64.astype(np.float16).view(np.uint16))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(torus=0), dict(d_min=0), dict(d_max=0), dict(d_min=1, d_max=65),
+    {"lambda": 0.0}, {"lambda": -1.0}, dict(grid_w=1, grid_h=1), dict(K=3),
+    dict(K_out=5000), dict(acc_bits=16), dict(q_frac_bits=31), dict(weight_dtype=3),
+    dict(rate_bin_steps=0), dict(rate_bins_cap=0), dict(spike_log_cap=-1),
+    dict(dt_ms=0.0), dict(tau_m=[0.0, 10.0]), dict(frac_exc=1.5),
+    dict(frac_local=[1.2, 0.5]), dict(tau_arp=[30.0, 1.0]),
+])
+def test_invalid_parameters_rejected(bad):
+    p = W.swa(rate_bins_cap=16, spike_log_cap=16)
+    p.update(bad)
+    with pytest.raises(L.DpsnnError) as e:
+        L.dpsnn_host_table(p, "prop_f64", np.float64)
+    assert e.value.code == -1
+
+
+def test_single_module_valid_when_all_local():
+    p = W.swa(grid_w=1, grid_h=1, frac_local=[1.0, 1.0])
+    assert len(L.dpsnn_host_table(p, "prop_f64", np.float64)) == 8
+    assert len(L.dpsnn_host_table(p, "off_xy", np.int32)) == 0
+
+
+def test_abi_version_checked():
+    s = L.to_struct(W.swa())
+    s.abi_version = 99
+    import ctypes as C
+    assert L.lib().dpsnn_host_table(C.byref(s), b"prop_f64", None, 0) == -1
