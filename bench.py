@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--dt-steps", type=int, default=10000, help="dt steps per bench step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--autotune", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
@@ -92,41 +93,44 @@ def main():
         from paper_1902_08410_amd import build as libbuild
         libbuild.build()
     torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
     S = args.dt_steps
-    total_bins = (args.warmup + args.steps) * S // 50 + 2
+    total_bins = (args.warmup + args.steps) * S // 50 + 200   # + autotune probes
     regimes = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
     nets = {}
     build_ms = {}
-    for name, p in regimes.items():
-        p.update(spike_log_cap=0, rate_bins_cap=total_bins)
-        nets[name] = dpsnn.dpsnn_build(p, 1)
-        build_ms[name] = nets[name].stats()["build_ms"]
-
-    for _ in range(args.warmup):
-        for net in nets.values():
-            dpsnn.dpsnn_step(net, S)
-    torch.cuda.synchronize()
-    sp0 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
-
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        for net in nets.values():
-            dpsnn.dpsnn_step(net, S)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    sched = {}
+    with torch.cuda.stream(stream):
+        for name, p in regimes.items():
+            p.update(spike_log_cap=0, rate_bins_cap=total_bins)
+            nets[name] = dpsnn.dpsnn_build(p, 1)
+            build_ms[name] = nets[name].stats()["build_ms"]
+        for _ in range(args.warmup):
+            for net in nets.values():
+                dpsnn.dpsnn_step(net, S)
+        for name, net in nets.items():
+            sched[name] = dpsnn.dpsnn_autotune(net, 1000) if args.autotune else \
+                net.stats()["reserved"]
+        torch.cuda.synchronize()
+        sp0 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            for net in nets.values():
+                dpsnn.dpsnn_step(net, S)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
 
     sp1 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
     spikes = {k: sp1[k] - sp0[k] for k in nets}
     events = sum(spikes.values()) * K_OUT
     value = events / wall
-    n_launch = args.steps * S * len(nets)
+    n_launch = args.steps * S * len(nets)   # steps of dt (one launch sequence each)
     N = nets["swa"].N
     p0 = regimes["swa"]
     Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
@@ -169,7 +173,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_step (neuron update + spike delivery, one launch per dt)",
+            "kernel": "one step of dt (k_neuron + k_deliver, or fused k_step)",
             "bytes_per_neuron_step": Bn,
             "bytes_per_event": Be,
             "avg_launch_us": launch_ms * 1e3,
@@ -180,6 +184,7 @@ def main():
                            "events_per_s": spikes[k] * K_OUT / wall,
                            "build_ms": build_ms[k]} for k in nets},
         "gpu_ms_timed": gpu_ms,
+        "schedule": {k: ("split" if v == 1 else "fused") for k, v in sched.items()},
     }
     print(json.dumps(out), flush=True)
 

@@ -50,6 +50,12 @@ extern "C" {
 #define DPSNN_E_STATE (-6)         /* call not valid in the handle's state   */
 #define DPSNN_E_RATES_FULL (-7)    /* rate bins would be overwritten         */
 
+/* Step schedules (results are bit-identical; only speed differs). */
+#define DPSNN_SCHED_FUSED 0 /* one kernel per step; a tile delivers its own
+                               spikes (small networks) */
+#define DPSNN_SCHED_SPLIT 1 /* neuron kernel, then a delivery kernel that
+                               spreads the spiking rows over the whole GPU */
+
 /* Stored synaptic efficacy formats. */
 #define DPSNN_W_F32 0
 #define DPSNN_W_F16 1
@@ -67,6 +73,7 @@ typedef struct dpsnn_params {
   int32_t grid_w, grid_h;  /* modules per row / column                      */
   int32_t K;               /* neurons per module [1250]                     */
   int32_t K_out;           /* recurrent out-degree, <= 4096 [1000]          */
+                           /* (network size W*H*K <= 2^26 neurons)          */
   double frac_exc;         /* excitatory share of a module [0.8]            */
   double frac_local[2];    /* share of a source's synapses kept local [0.5] */
   double lambda;           /* decay length of Eq. 1 [1]                     */
@@ -138,8 +145,23 @@ int dpsnn_set_stream(dpsnn_net* net, void* hip_stream);
  */
 int dpsnn_step(dpsnn_net* net, int64_t n_steps);
 
-/* Wait for the handle's stream.  Returns SPIKELOG_FULL once if the spike
- * log overflowed since the last check. */
+/* Choose the step schedule (DPSNN_SCHED_*).  SPLIT needs at most 16000
+ * tiles of 1024 neurons (else INVAL). */
+int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
+
+/* Steps captured per HIP graph replay (0 disables graphs; graphs are only
+ * used on a non-default stream).  Default 128. */
+int dpsnn_set_graph_steps(dpsnn_net* net, int64_t steps);
+
+/*
+ * Time probe_steps real steps with each available schedule (they advance
+ * the simulation; results do not depend on the schedule) and keep the
+ * fastest; *chosen (may be NULL) receives it.  Synchronises.
+ */
+int dpsnn_autotune(dpsnn_net* net, int64_t probe_steps, int32_t* chosen);
+
+/* Wait for the handle's stream.  Returns SPIKELOG_FULL if the spike log
+ * overflowed since it was last drained. */
 int dpsnn_sync(dpsnn_net* net);
 
 /*

@@ -433,8 +433,9 @@ int32_t orc_gen_row(const orc_net* n, int64_t s, int32_t* tgt, uint8_t* delay,
 /* External Poisson input (Sec. 2.1 "no memory structure associated with
  * external synapses": counts and efficacies generated on the fly).  The
  * count of neuron i at step t comes from word (i mod 4) of the draw
- * (i / 4, t, EXT); efficacy e uses 16 bits of the draw (i, t, EXTJ, e / 8):
- * word (e mod 8) / 2, high half for even e, low half for odd e. */
+ * (i / 4, t, EXT).  Efficacy e of the neuron uses 16 bits of the draw
+ * (i / 4, t, EXTJ | (e / 2) << 8): word (i mod 4), high half for even e,
+ * low half for odd e. */
 int32_t orc_ext_input(const orc_net* n, int64_t i, int64_t t, int64_t* fix_sum,
                       double* f64_sum) {
   if (i < 0 || i >= n->N || t < 0) return ORC_E_INVAL;
@@ -449,9 +450,10 @@ int32_t orc_ext_input(const orc_net* n, int64_t i, int64_t t, int64_t* fix_sum,
   double ds = 0.0;
   uint32_t v[4];
   for (int e = 0; e < k; e++) {
-    if ((e & 7) == 0)
-      draw(n, (uint32_t)i, (uint32_t)t, ORC_TAG_EXTJ | ((uint32_t)(e >> 3) << 8), v);
-    uint32_t word = v[(e & 7) >> 1];
+    if ((e & 1) == 0)
+      draw(n, (uint32_t)(i >> 2), (uint32_t)t,
+           ORC_TAG_EXTJ | ((uint32_t)(e >> 1) << 8), v);
+    uint32_t word = v[i & 3];
     uint32_t idx = (e & 1) ? (word & 0xFFFFu) : (word >> 16);
     fs += n->jxfix[q][idx];
     ds += n->jx64[q][idx];

@@ -78,8 +78,11 @@ int build_impl(dpsnn_net* n) {
   uint8_t* ref = (uint8_t*)dev_alloc(n, (size_t)Np);
   void* slots = dev_alloc(n, (size_t)T.D * Np * ab);
   n->bytes_state = Np * 9 + (int64_t)T.D * Np * ab;
+  const int64_t n_tiles = Np / 1024;
+  int32_t* spk = (int32_t*)dev_alloc(n, (size_t)Np * 4);
+  int32_t* blk_cnt = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
   int2* log = (int2*)dev_alloc(n, (size_t)std::max<int64_t>(p.spike_log_cap, 1) * 8);
-  unsigned long long* counters = (unsigned long long*)dev_alloc(n, 256);
+  unsigned char* ctl = (unsigned char*)dev_alloc(n, 256);
   unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p.rate_bins_cap * M * 2 * 4);
   const size_t n_off = T.off_xy.size() / 2;
   uint32_t* off_thr = (uint32_t*)dev_alloc(n, std::max<size_t>(T.off_thr.size(), 1) * 4);
@@ -88,8 +91,8 @@ int build_impl(dpsnn_net* n) {
   for (int q = 0; q < 2; ++q) wtab[q] = dev_alloc(n, (size_t)kQuantN * wb);
   void* jx = dev_alloc(n, (size_t)2 * kQuantN * ab);
   int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * 2 * 8);
-  if (!tgt || !w || !doff || !V || !c || !ref || !slots || !log || !counters || !rates ||
-      !off_thr || !off_xy || !wtab[0] || !wtab[1] || !jx || !sfix)
+  if (!tgt || !w || !doff || !V || !c || !ref || !slots || !spk || !blk_cnt || !log || !ctl ||
+      !rates || !off_thr || !off_xy || !wtab[0] || !wtab[1] || !jx || !sfix)
     return DPSNN_E_NOMEM;
 
   // ---- tables
@@ -124,7 +127,8 @@ int build_impl(dpsnn_net* n) {
   }
   HIP_OK(hipMemcpyAsync(sfix, sf.data(), sf.size() * 8, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemsetAsync(slots, 0, (size_t)T.D * Np * ab, st));
-  HIP_OK(hipMemsetAsync(counters, 0, 256, st));
+  HIP_OK(hipMemsetAsync(ctl, 0, 256, st));
+  HIP_OK(hipMemsetAsync(blk_cnt, 0, (size_t)n_tiles * 4, st));
   HIP_OK(hipMemsetAsync(rates, 0, (size_t)p.rate_bins_cap * M * 2 * 4, st));
 
   // ---- initial state and rows
@@ -206,11 +210,12 @@ int build_impl(dpsnn_net* n) {
   a.K_exc = T.K_exc;
   a.K_out = p.K_out;
   a.row_stride = T.row_stride;
-  a.doff_stride = T.doff_stride;
   a.D = T.D;
   a.n_del = T.n_del;
   a.d_min = p.d_min;
   a.M = (int32_t)M;
+  a.n_tiles = (int32_t)n_tiles;
+  a.deliver_blocks = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, n_tiles));
   a.rate_bin_steps = p.rate_bin_steps;
   a.rate_bins_cap = (int32_t)p.rate_bins_cap;
   a.key0 = ia.key0;
@@ -237,14 +242,19 @@ int build_impl(dpsnn_net* n) {
   a.slots = slots;
   a.tgt = tgt;
   a.w = w;
-  a.doff = doff;
   a.jxfix = jx;
   a.sfix = sfix;
+  a.spk = spk;
+  a.blk_cnt = blk_cnt;
   a.log = log;
-  a.log_count = counters;
+  a.log_base = reinterpret_cast<unsigned long long*>(ctl);
+  a.n_spikes = reinterpret_cast<unsigned long long*>(ctl + 16);
+  a.t_base = reinterpret_cast<uint32_t*>(ctl + 32);
   a.rates = rates;
-  a.n_spikes = counters + 1;
-  n->d_counters = counters;
+  n->doff = doff;
+  n->ctl = ctl;
+  n->split_ok = n_tiles <= kMaxSplitTiles;
+  n->sched = (n->split_ok && N >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
   return DPSNN_OK;
 }
 
@@ -287,18 +297,129 @@ int dpsnn_set_stream(dpsnn_net* n, void* s) {
   return DPSNN_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+void drop_graph(dpsnn_net* n) {
+  if (n->graph) (void)hipGraphExecDestroy(n->graph);
+  n->graph = nullptr;
+  n->graph_K = 0;
+  n->graph_sched = -1;
+  n->graph_stream = nullptr;
+}
+
+// Capture graph_steps steps of the current schedule followed by the step
+// counter update; replays then need no host work per step.
+int ensure_graph(dpsnn_net* n) {
+  if (n->graph && n->graph_sched == n->sched && n->graph_stream == n->stream &&
+      n->graph_K == n->graph_steps)
+    return DPSNN_OK;
+  drop_graph(n);
+  hipGraph_t g = nullptr;
+  HIP_OK(hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal));
+  bool ok = true;
+  for (int64_t k = 0; k < n->graph_steps && ok; ++k)
+    ok = launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, n->sched, (uint32_t)k,
+                     n->stream) == hipSuccess;
+  if (ok) ok = launch_tick(n->sa, (uint32_t)n->graph_steps, 0, n->stream) == hipSuccess;
+  const hipError_t e = hipStreamEndCapture(n->stream, &g);
+  if (!ok || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return DPSNN_E_DEVICE;
+  }
+  hipGraphExec_t ge = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return DPSNN_E_DEVICE;
+  n->graph = ge;
+  n->graph_K = (int)n->graph_steps;
+  n->graph_sched = n->sched;
+  n->graph_stream = n->stream;
+  return DPSNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpsnn_set_schedule(dpsnn_net* n, int32_t sched) {
+  if (!n || (sched != DPSNN_SCHED_FUSED && sched != DPSNN_SCHED_SPLIT)) return DPSNN_E_INVAL;
+  if (sched == DPSNN_SCHED_SPLIT && !n->split_ok) return DPSNN_E_INVAL;
+  n->sched = sched;
+  return DPSNN_OK;
+}
+
+int dpsnn_set_graph_steps(dpsnn_net* n, int64_t steps) {
+  if (!n || steps < 0 || steps > 100000) return DPSNN_E_INVAL;
+  n->graph_steps = steps;
+  return DPSNN_OK;
+}
+
 int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
   if (!n || n_steps < 0) return DPSNN_E_INVAL;
   if (n_steps == 0) return DPSNN_OK;
   if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
   const int64_t last_bin = (n->t + n_steps - 1) / n->p.rate_bin_steps;
   if (last_bin - n->rate_first + 1 > n->p.rate_bins_cap) return DPSNN_E_RATES_FULL;
-  for (int64_t k = 0; k < n_steps; ++k) {
-    if (launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, (uint32_t)(n->t + k), n->stream) !=
-        hipSuccess)
-      return DPSNN_E_DEVICE;
+  // the fused schedule advances both spike-log bases: align them after split
+  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
+    HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
+  n->last_sched = n->sched;
+  int64_t done = 0;
+  if (n->stream && n->graph_steps > 0 && n_steps >= n->graph_steps) {
+    const int rc = ensure_graph(n);
+    if (rc != DPSNN_OK) return rc;
+    while (n_steps - done >= n->graph_K) {
+      HIP_OK(hipGraphLaunch(n->graph, n->stream));
+      done += n->graph_K;
+    }
+  }
+  const int64_t rest = n_steps - done;
+  if (rest > 0) {
+    for (int64_t k = 0; k < rest; ++k)
+      HIP_OK(launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, n->sched, (uint32_t)k,
+                         n->stream));
+    HIP_OK(launch_tick(n->sa, (uint32_t)rest, 0, n->stream));
   }
   n->t += n_steps;
+  return DPSNN_OK;
+}
+
+int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
+  if (!n || probe_steps < 1) return DPSNN_E_INVAL;
+  const int cands[2] = {DPSNN_SCHED_FUSED, DPSNN_SCHED_SPLIT};
+  float best_ms = -1.f;
+  int best = n->sched;
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  int rc = DPSNN_OK;
+  for (int c : cands) {
+    if (c == DPSNN_SCHED_SPLIT && !n->split_ok) continue;
+    n->sched = c;
+    // one untimed pass builds the graph and warms the caches
+    if ((rc = dpsnn_step(n, probe_steps)) != DPSNN_OK) break;
+    if (hipEventRecord(e0, n->stream) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
+    if ((rc = dpsnn_step(n, probe_steps)) != DPSNN_OK) break;
+    if (hipEventRecord(e1, n->stream) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best_ms < 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  n->sched = best;
+  if (chosen) *chosen = best;
+  return rc;
+}
+
+static int log_count(dpsnn_net* n, unsigned long long* cnt) {
+  HIP_OK(hipMemcpy(cnt, n->sa.log_base + (n->t & 1), 8, hipMemcpyDeviceToHost));
   return DPSNN_OK;
 }
 
@@ -306,7 +427,8 @@ int dpsnn_sync(dpsnn_net* n) {
   if (!n) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
   unsigned long long cnt = 0;
-  HIP_OK(hipMemcpy(&cnt, n->d_counters, 8, hipMemcpyDeviceToHost));
+  const int rc = log_count(n, &cnt);
+  if (rc != DPSNN_OK) return rc;
   if ((int64_t)cnt > n->p.spike_log_cap) return DPSNN_E_SPIKELOG_FULL;
   return DPSNN_OK;
 }
@@ -316,7 +438,8 @@ int dpsnn_read_spikes(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_
   if (!n || !n_out || cap < 0) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
   unsigned long long cnt = 0;
-  HIP_OK(hipMemcpy(&cnt, n->d_counters, 8, hipMemcpyDeviceToHost));
+  const int rc = log_count(n, &cnt);
+  if (rc != DPSNN_OK) return rc;
   const bool overflow = (int64_t)cnt > n->p.spike_log_cap;
   const int64_t have = std::min<int64_t>((int64_t)cnt, n->p.spike_log_cap);
   *n_out = have;
@@ -331,7 +454,7 @@ int dpsnn_read_spikes(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_
     host_step[k] = buf[k].x;
     host_id[k] = buf[k].y;
   }
-  HIP_OK(hipMemsetAsync(n->d_counters, 0, 8, n->stream));
+  HIP_OK(hipMemsetAsync(n->sa.log_base, 0, 16, n->stream));
   HIP_OK(hipStreamSynchronize(n->stream));
   return overflow ? DPSNN_E_SPIKELOG_FULL : DPSNN_OK;
 }
@@ -360,7 +483,7 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   if (!n || !out) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
   unsigned long long ns = 0;
-  HIP_OK(hipMemcpy(&ns, n->d_counters + 1, 8, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&ns, n->sa.n_spikes, 8, hipMemcpyDeviceToHost));
   memset(out, 0, sizeof(*out));
   out->t = n->t;
   out->n_neurons = n->T.N;
@@ -372,13 +495,15 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->bytes_rows = n->bytes_rows;
   out->bytes_state = n->bytes_state;
   out->bytes_total = n->bytes_total;
-  out->lds_bytes = 1024 * 4 + 16;
+  out->lds_bytes = n->sched == DPSNN_SCHED_SPLIT ? n->sa.n_tiles * 4 + 1024 : 1024 * 4 + 16;
+  out->reserved = n->sched;
   return DPSNN_OK;
 }
 
 void dpsnn_free(dpsnn_net* n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->stream);
+  drop_graph(n);
   release_all(n);
   delete n;
 }
@@ -446,15 +571,17 @@ int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tg
   HIP_OK(hipStreamSynchronize(n->stream));
   const int Ko = n->p.K_out, rs = n->T.row_stride, ds = n->T.doff_stride;
   const int wb = w_bytes(n->p);
-  if (host_tgt && Ko > 0)
+  if (host_tgt && Ko > 0) {
     HIP_OK(hipMemcpy2D(host_tgt, (size_t)Ko * 4, n->sa.tgt + first * rs, (size_t)rs * 4,
                        (size_t)Ko * 4, (size_t)count, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < count * Ko; ++k) host_tgt[k] &= kTargetMask;
+  }
   if (host_w && Ko > 0)
     HIP_OK(hipMemcpy2D(host_w, (size_t)Ko * wb,
                        static_cast<const unsigned char*>(n->sa.w) + (size_t)first * rs * wb,
                        (size_t)rs * wb, (size_t)Ko * wb, (size_t)count, hipMemcpyDeviceToHost));
   if (host_doff)
-    HIP_OK(hipMemcpy2D(host_doff, (size_t)(n->T.n_del + 1) * 2, n->sa.doff + first * ds,
+    HIP_OK(hipMemcpy2D(host_doff, (size_t)(n->T.n_del + 1) * 2, n->doff + first * ds,
                        (size_t)ds * 2, (size_t)(n->T.n_del + 1) * 2, (size_t)count,
                        hipMemcpyDeviceToHost));
   return DPSNN_OK;

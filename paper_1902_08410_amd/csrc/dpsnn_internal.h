@@ -14,6 +14,9 @@ constexpr int kQuantN = 65536;  // entries of each efficacy quantile table
 constexpr int kMaxPois = 16;    // Poisson count thresholds per population
 constexpr int kMaxDelays = 64;  // distinct delays handled by one wavefront
 constexpr int kMaxKout = 4096;
+constexpr int kDelayShift = 26;  // target word = target | delay index << 26
+constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
+constexpr int kMaxSplitTiles = 16000;  // LDS prefix of the delivery kernel
 
 // Everything dpsnn_build derives from the parameters on the host, in
 // binary64 first and rounded once to the width the device uses.
@@ -54,10 +57,12 @@ int validate(const dpsnn_params& p);
 int compute_tables(const dpsnn_params& p, HostTables& T);
 int64_t host_table(const HostTables& T, const char* name, void* out, int64_t cap);
 
-// Arguments of the step kernel (passed by value).
+// Arguments of the step kernels (passed by value).
 struct StepArgs {
   int64_t N, N_pad;
-  int32_t K, K_exc, K_out, row_stride, doff_stride, D, n_del, d_min, M;
+  int32_t K, K_exc, K_out, row_stride, D, n_del, d_min, M;
+  int32_t n_tiles;         // neuron tiles of 1024 = N_pad / 1024
+  int32_t deliver_blocks;  // grid of the delivery kernel
   int32_t rate_bin_steps, rate_bins_cap;
   uint32_t key0, key1;
   float Pm[2], Pc[2], PVc[2], Iterm[2], E[2], Vth[2], Vr[2], alpha[2];
@@ -70,15 +75,17 @@ struct StepArgs {
   float* c;
   uint8_t* ref;
   void* slots;
-  const int32_t* tgt;
+  const int32_t* tgt;      // target | delay index << 26
   const void* w;
-  const uint16_t* doff;
   const void* jxfix;
-  const int64_t* sfix;  // [M][2], int8 format only
+  const int64_t* sfix;     // [M][2], int8 format only
+  int32_t* spk;            // [n_tiles][1024] spike ids of the step, per tile
+  int32_t* blk_cnt;        // [n_tiles] spikes per tile
   int2* log;
-  unsigned long long* log_count;
+  unsigned long long* log_base;  // [2]: log entries before step t at [t & 1]
   unsigned int* rates;
   unsigned long long* n_spikes;
+  uint32_t* t_base;        // device step counter
 };
 
 struct GenArgs {
@@ -110,8 +117,9 @@ struct InitArgs {
 
 hipError_t launch_gen(const GenArgs& a, int wdt, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
-hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, uint32_t t,
+hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint32_t t_off,
                        hipStream_t s);
+hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t s);
 hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
                             unsigned long long* out, hipStream_t s);
 
@@ -132,5 +140,14 @@ struct dpsnn_net {
   int64_t t = 0;
   int64_t rate_first = 0;      // first rate bin not yet drained
   dpsnn::StepArgs sa;
-  unsigned long long* d_counters = nullptr;  // [0] log_count, [1] n_spikes
+  uint16_t* doff = nullptr;    // delay offsets of the rows (inspection)
+  unsigned char* ctl = nullptr;  // log bases, spike total, step counter
+  int sched = DPSNN_SCHED_SPLIT;
+  int last_sched = -1;
+  bool split_ok = true;
+  // captured steps: graph_K steps of the current schedule on `stream`
+  hipGraphExec_t graph = nullptr;
+  int graph_K = 0, graph_sched = -1;
+  hipStream_t graph_stream = nullptr;
+  int64_t graph_steps = 128;    // steps per captured graph (0 = no graphs)
 };

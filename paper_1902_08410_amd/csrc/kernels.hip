@@ -1,18 +1,29 @@
 // HIP kernels of libdpsnn for gfx950 (64-lane wavefronts).
 //
-//  k_gen   one wavefront per source row: draws the K_out synapses of the
-//          source from Philox (Eq. 1 targets, uniform delay, quantile-table
-//          efficacy), ranks them stably by delay with wavefront ballots and
-//          writes the delay-sorted row plus its delay offsets.
-//  k_init  initial membrane potentials, fatigue and refractory counters.
-//  k_step  one step of dt for a tile of 1024 neurons (4 per thread): input
-//          slot read-and-clear, external Poisson drive, Eq. 2 update,
-//          threshold, spike compaction in LDS, then the tile's own spikes are
-//          delivered by its four wavefronts, each walking a whole row with
-//          16-byte loads and fixed-point atomics into the target slots.
-//          The step reads only slot t mod D and delivery writes only slots
-//          t+d_min .. t+d_max, so the two phases need no grid-wide sync
-//          inside a step; the kernel boundary orders consecutive steps.
+//  k_gen      one wavefront per source row: draws the K_out synapses of the
+//             source from Philox (Eq. 1 targets, uniform delay, quantile-table
+//             efficacy), ranks them stably by delay with wavefront ballots and
+//             writes the delay-sorted row plus its delay offsets.  The delay
+//             index also rides in the top 6 bits of each target word, so that
+//             delivery needs no lookup.
+//  k_init     initial membrane potentials, fatigue and refractory counters.
+//  k_neuron   one step of dt for a tile of 1024 neurons (4 per thread):
+//             input slot read-and-clear, external Poisson drive, Eq. 2 update,
+//             threshold; the tile's spikes go to its own segment of the spike
+//             list (no global counter).
+//  k_deliver  the tile counts are scanned in LDS by every block; then every
+//             wavefront of the grid takes chunks of 256 synapses of spiking
+//             rows (16-byte loads) and adds the fixed-point efficacies into the
+//             target slots with atomics.  Spreading the chunks over the whole
+//             chip keeps every CU issuing atomics.  Also appends the spike log
+//             and the 5 ms population counts.
+//  k_step     fused schedule for small networks: k_neuron followed by the
+//             delivery of the tile's own spikes by its four wavefronts.
+//
+// A step reads only slot t mod D and delivery writes only slots t+d_min ..
+// t+d_max, so update and delivery of one step need no grid-wide ordering;
+// the kernel boundary orders consecutive steps.  The step index is read on
+// the device (t = *t_base + t_off) so that launches can be captured in a graph.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -123,7 +134,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     const int64_t o = rb + pos;
     const int32_t tg = st_tgt[j];
     const uint16_t wi = st_w[j];
-    a.tgt[o] = tg;
+    a.tgt[o] = tg | (k << kDelayShift);
     if (WDT == DPSNN_W_F32)
       static_cast<float*>(a.w)[o] = static_cast<const float*>(a.wtab[pop])[wi];
     else if (WDT == DPSNN_W_F16)
@@ -173,12 +184,13 @@ __global__ void k_init(InitArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// One step.
+// Fixed-point helpers
 
-// Fixed-point input sum in mV: one rounding of I * 2^-Q to binary32 (an
-// int64 sum below 2^53 converts to binary64 exactly first).
+// Input sum in mV: one rounding of I * 2^-Q to binary32 (an int64 sum below
+// 2^53 converts to binary64 exactly first).
 __device__ __forceinline__ float fix_to_f32(int32_t v) { return (float)v; }
 __device__ __forceinline__ float fix_to_f32(int64_t v) { return (float)(double)v; }
+
 template <typename Acc>
 __device__ __forceinline__ void atomic_add_fix(Acc* p, Acc v);
 template <>
@@ -203,151 +215,272 @@ __device__ __forceinline__ Acc stored_to_fix(const void* w, int64_t o, float two
   }
 }
 
+// ------------------------------------------------------------------------
+// Neuron update of the 4 neurons i0..i0+3 of one thread at step t.  Spiking
+// neurons are appended to the LDS list s_spk (count s_n).
+template <typename Acc>
+__device__ __forceinline__ void update4(const StepArgs& a, int64_t i0, uint32_t t,
+                                        int32_t* s_spk, int* s_n) {
+  const int slot = (int)(t % (uint32_t)a.D);
+  Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
+  Acc I[4];
+  if (sizeof(Acc) == 4) {
+    const int4 v = *reinterpret_cast<const int4*>(sl);
+    I[0] = v.x; I[1] = v.y; I[2] = v.z; I[3] = v.w;
+    *reinterpret_cast<int4*>(sl) = make_int4(0, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      I[j] = sl[j];
+      sl[j] = 0;
+    }
+  }
+  const float4 V4 = *reinterpret_cast<const float4*>(a.V + i0);
+  const float4 c4 = *reinterpret_cast<const float4*>(a.c + i0);
+  const uint32_t r4 = *reinterpret_cast<const uint32_t*>(a.ref + i0);
+  float Vv[4] = {V4.x, V4.y, V4.z, V4.w};
+  float cv[4] = {c4.x, c4.y, c4.z, c4.w};
+
+  // external Poisson drive generated on the fly: counts from word j of
+  // (i0/4, t, EXT); efficacies 2b and 2b+1 of neuron j from word j of
+  // (i0/4, t, EXTJ | b << 8), high half then low half
+  const uint32_t g = (uint32_t)(i0 >> 2);
+  const uint4 u = philox10(make_uint4(g, t, 0u, kTagExt), a.key0, a.key1);
+  const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
+  const int64_t m0 = i0 / a.K;
+  const int l0 = (int)(i0 - m0 * a.K);
+  int q[4], k[4];
+  int kmax = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int lj = l0 + j;
+    if (lj >= a.K) lj -= a.K;
+    q[j] = lj < a.K_exc ? 0 : 1;
+    int kk = 0;
+    for (int x = 0; x < a.n_pois[q[j]]; ++x) kk += uu[j] >= a.pois[q[j]][x] ? 1 : 0;
+    k[j] = kk;
+    kmax = kk > kmax ? kk : kmax;
+  }
+  const Acc* jx = static_cast<const Acc*>(a.jxfix);
+  for (int b = 0; 2 * b < kmax; ++b) {
+    const uint4 v = philox10(make_uint4(g, t, 0u, kTagExtJ | ((uint32_t)b << 8)), a.key0, a.key1);
+    const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (2 * b < k[j]) I[j] += jx[q[j] * kQuantN + (vv[j] >> 16)];
+      if (2 * b + 1 < k[j]) I[j] += jx[q[j] * kQuantN + (vv[j] & 0xFFFFu)];
+    }
+  }
+
+  uint32_t r_out = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int qq = q[j];
+    uint32_t rj = (r4 >> (8 * j)) & 0xFFu;
+    if (i0 + j < a.N) {
+      const float dv = fix_to_f32(I[j]) * a.inv2q;
+      float Vj = Vv[j], cj = cv[j];
+      bool spk = false;
+      if (rj > 0) {
+        rj -= 1;
+        cj = cj * a.Pc[qq];
+      } else {
+        float vv = Vj - a.E[qq];
+        vv = vv * a.Pm[qq];
+        vv = a.E[qq] + vv;
+        const float cc = cj * a.PVc[qq];
+        vv = vv - cc;
+        vv = vv + a.Iterm[qq];
+        vv = vv + dv;
+        cj = cj * a.Pc[qq];
+        if (vv > a.Vth[qq]) {
+          spk = true;
+          vv = a.Vr[qq];
+          cj = cj + a.alpha[qq];
+          rj = (uint32_t)a.n_arp[qq];
+        }
+        Vj = vv;
+      }
+      Vv[j] = Vj;
+      cv[j] = cj;
+      if (spk) {
+        const int pos = atomicAdd(s_n, 1);
+        s_spk[pos] = (int32_t)(i0 + j);
+      }
+    }
+    r_out |= rj << (8 * j);
+  }
+  *reinterpret_cast<float4*>(a.V + i0) = make_float4(Vv[0], Vv[1], Vv[2], Vv[3]);
+  *reinterpret_cast<float4*>(a.c + i0) = make_float4(cv[0], cv[1], cv[2], cv[3]);
+  *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
+}
+
+// 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.
 template <typename Acc, int WDT>
-__device__ __forceinline__ void deliver_row(const StepArgs& a, int32_t s, uint32_t t,
-                                            int lane) {
+__device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int p0,
+                                              uint32_t t, int lane) {
   const int64_t rb = (int64_t)s * a.row_stride;
-  const int32_t* trow = a.tgt + rb;
-  const uint16_t* drow = a.doff + (int64_t)s * a.doff_stride;
   int64_t scale = 0;
   if (WDT == DPSNN_W_I8) {
     const int32_t ms = s / a.K;
     const int q = (s - ms * a.K) < a.K_exc ? 0 : 1;
     scale = a.sfix[2 * ms + q];
   }
+  const int p = p0 + lane * 4;
+  if (p >= a.K_out) return;
+  const int4 tg = *reinterpret_cast<const int4*>(a.tgt + rb + p);
+  const int tv[4] = {tg.x, tg.y, tg.z, tg.w};
+  Acc wv[4];
+  if (WDT == DPSNN_W_F32) {
+    const float4 w4 = *reinterpret_cast<const float4*>(static_cast<const float*>(a.w) + rb + p);
+    wv[0] = (Acc)__builtin_rintf(w4.x * a.two_q);
+    wv[1] = (Acc)__builtin_rintf(w4.y * a.two_q);
+    wv[2] = (Acc)__builtin_rintf(w4.z * a.two_q);
+    wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
+  }
   const int slot0 = (int)((t + (uint32_t)a.d_min) % (uint32_t)a.D);
   Acc* slots = static_cast<Acc*>(a.slots);
-  for (int p0 = lane * 4; p0 < a.K_out; p0 += 256) {
-    const int4 tg = *reinterpret_cast<const int4*>(trow + p0);
-    const int tv[4] = {tg.x, tg.y, tg.z, tg.w};
-    int kd[4] = {0, 0, 0, 0};
-    for (int x = 1; x < a.n_del; ++x) {
-      const int b = drow[x];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) kd[q] += (p0 + q >= b) ? 1 : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (p0 + q < a.K_out) {
-        int sl = slot0 + kd[q];
-        if (sl >= a.D) sl -= a.D;
-        const Acc v = stored_to_fix<Acc, WDT>(a.w, rb + p0 + q, a.two_q, scale);
-        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + tv[q], v);
-      }
+  for (int j = 0; j < 4; ++j) {
+    if (p + j < a.K_out) {
+      int sl = slot0 + (int)((uint32_t)tv[j] >> kDelayShift);
+      if (sl >= a.D) sl -= a.D;
+      const int32_t target = tv[j] & kTargetMask;
+      atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
     }
   }
 }
 
+__device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint32_t t,
+                                             unsigned long long pos) {
+  if (pos < (unsigned long long)a.spike_log_cap) a.log[pos] = make_int2((int)t, id);
+  const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
+  const int32_t mod = id / a.K;
+  const int q = (id - mod * a.K) < a.K_exc ? 0 : 1;
+  atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * 2 + q], 1u);
+}
+
+// ------------------------------------------------------------------------
+// Split schedule: neuron kernel, then the delivery kernel.
+template <typename Acc>
+__global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
+  __shared__ int32_t s_spk[1024];
+  __shared__ int s_n;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  const uint32_t t = a.t_base[0] + t_off;
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
+  if (i0 < a.N) update4<Acc>(a, i0, t, s_spk, &s_n);
+  __syncthreads();
+  const int n = s_n;
+  int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
+  for (int k = tid; k < n; k += 256) out[k] = s_spk[k];
+  if (tid == 0) a.blk_cnt[blockIdx.x] = n;
+}
+
 template <typename Acc, int WDT>
-__global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t) {
+__global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
+  extern __shared__ int32_t s_pref[];  // inclusive prefix of the tile counts
+  __shared__ int32_t s_part[256];
+  const int tid = threadIdx.x;
+  const int nb = a.n_tiles;
+  const uint32_t t = a.t_base[0] + t_off;
+  // block-wide scan: each thread sums a contiguous run of tile counts
+  const int per = (nb + 255) / 256;
+  const int lo = tid * per;
+  const int hi = lo + per < nb ? lo + per : nb;
+  int run = 0;
+  for (int b = lo; b < hi; ++b) run += a.blk_cnt[b];
+  s_part[tid] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? s_part[tid - off] : 0;
+    __syncthreads();
+    s_part[tid] += v;
+    __syncthreads();
+  }
+  int acc = s_part[tid] - run;
+  for (int b = lo; b < hi; ++b) {
+    acc += a.blk_cnt[b];
+    s_pref[b] = acc;
+  }
+  __syncthreads();
+  const int n_spk = s_part[255];
+  const unsigned long long log0 = a.log_base[t & 1];
+  if (blockIdx.x == 0 && tid == 0) {
+    a.log_base[(t + 1) & 1] = log0 + (unsigned long long)n_spk;
+    a.n_spikes[0] += (unsigned long long)n_spk;
+  }
+  const int cpr = (a.K_out + 255) / 256;  // chunks per row
+  const int64_t items = (int64_t)n_spk * cpr;
+  const int lane = tid & 63;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (tid >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t it = wid; it < items; it += nw) {
+    const int sidx = (int)(it / cpr);
+    const int chunk = (int)(it - (int64_t)sidx * cpr);
+    // tile holding spike number sidx: first b with s_pref[b] > sidx
+    int l = 0, h = nb - 1;
+    while (l < h) {
+      const int mid = (l + h) >> 1;
+      if (s_pref[mid] > sidx)
+        h = mid;
+      else
+        l = mid + 1;
+    }
+    const int first = l ? s_pref[l - 1] : 0;
+    const int32_t s = __builtin_amdgcn_readfirstlane(a.spk[(int64_t)l * 1024 + (sidx - first)]);
+    if (chunk == 0 && lane == 0) record_spike(a, s, t, log0 + (unsigned long long)sidx);
+    deliver_chunk<Acc, WDT>(a, s, chunk * 256, t, lane);
+  }
+}
+
+// Fused schedule (small networks): the tile's own spikes are delivered by
+// its four wavefronts right after the update.
+template <typename Acc, int WDT>
+__global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
   __shared__ int s_n;
   __shared__ unsigned long long s_logbase;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
   __syncthreads();
-
+  const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
-  const int slot = (int)(t % (uint32_t)a.D);
-  if (i0 < a.N) {
-    Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
-    Acc I[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      I[j] = sl[j];
-      sl[j] = 0;
-    }
-    float4 V4 = *reinterpret_cast<const float4*>(a.V + i0);
-    float4 c4 = *reinterpret_cast<const float4*>(a.c + i0);
-    uint32_t r4 = *reinterpret_cast<const uint32_t*>(a.ref + i0);
-    float Vv[4] = {V4.x, V4.y, V4.z, V4.w};
-    float cv[4] = {c4.x, c4.y, c4.z, c4.w};
-    const uint4 u = philox10(make_uint4((uint32_t)(i0 >> 2), t, 0u, kTagExt), a.key0, a.key1);
-    const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
-    const int64_t m0 = i0 / a.K;
-    const int l0 = (int)(i0 - m0 * a.K);
-    uint32_t r_out = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t i = i0 + j;
-      int lj = l0 + j;
-      if (lj >= a.K) lj -= a.K;
-      const int q = lj < a.K_exc ? 0 : 1;
-      uint32_t rj = (r4 >> (8 * j)) & 0xFFu;
-      if (i < a.N) {
-        // external Poisson drive generated on the fly
-        int k = 0;
-        for (int x = 0; x < a.n_pois[q]; ++x) k += uu[j] >= a.pois[q][x] ? 1 : 0;
-        Acc sum = I[j];
-        if (k > 0) {
-          uint4 v = make_uint4(0, 0, 0, 0);
-          for (int e = 0; e < k; ++e) {
-            if ((e & 7) == 0)
-              v = philox10(make_uint4((uint32_t)i, t, 0u, kTagExtJ | ((uint32_t)(e >> 3) << 8)),
-                           a.key0, a.key1);
-            const int wsel = (e & 7) >> 1;
-            const uint32_t word = wsel == 0 ? v.x : wsel == 1 ? v.y : wsel == 2 ? v.z : v.w;
-            const uint32_t idx = (e & 1) ? (word & 0xFFFFu) : (word >> 16);
-            sum += static_cast<const Acc*>(a.jxfix)[q * kQuantN + idx];
-          }
-        }
-        const float dv = fix_to_f32(sum) * a.inv2q;
-        float Vj = Vv[j], cj = cv[j];
-        bool spk = false;
-        if (rj > 0) {
-          rj -= 1;
-          cj = cj * a.Pc[q];
-        } else {
-          float vv = Vj - a.E[q];
-          vv = vv * a.Pm[q];
-          vv = a.E[q] + vv;
-          const float cc = cj * a.PVc[q];
-          vv = vv - cc;
-          vv = vv + a.Iterm[q];
-          vv = vv + dv;
-          cj = cj * a.Pc[q];
-          if (vv > a.Vth[q]) {
-            spk = true;
-            vv = a.Vr[q];
-            cj = cj + a.alpha[q];
-            rj = (uint32_t)a.n_arp[q];
-          }
-          Vj = vv;
-        }
-        Vv[j] = Vj;
-        cv[j] = cj;
-        if (spk) {
-          const int pos = atomicAdd(&s_n, 1);
-          s_spk[pos] = (int32_t)i;
-        }
-      }
-      r_out |= rj << (8 * j);
-    }
-    *reinterpret_cast<float4*>(a.V + i0) = make_float4(Vv[0], Vv[1], Vv[2], Vv[3]);
-    *reinterpret_cast<float4*>(a.c + i0) = make_float4(cv[0], cv[1], cv[2], cv[3]);
-    *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
-  }
+  if (i0 < a.N) update4<Acc>(a, i0, t, s_spk, &s_n);
   __syncthreads();
   const int n = s_n;
   if (n == 0) return;
   if (tid == 0) {
-    s_logbase = atomicAdd(a.log_count, (unsigned long long)n);
+    // both log bases advance together in this schedule
+    s_logbase = atomicAdd(&a.log_base[t & 1], (unsigned long long)n);
+    atomicAdd(&a.log_base[(t + 1) & 1], (unsigned long long)n);
     atomicAdd(a.n_spikes, (unsigned long long)n);
   }
   __syncthreads();
-  const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
-  for (int k = tid; k < n; k += 256) {
-    const int32_t id = s_spk[k];
-    const unsigned long long pos = s_logbase + (unsigned long long)k;
-    if (pos < (unsigned long long)a.spike_log_cap) a.log[pos] = make_int2((int)t, id);
-    const int32_t mod = id / a.K;
-    const int q = (id - mod * a.K) < a.K_exc ? 0 : 1;
-    atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * 2 + q], 1u);
-  }
+  for (int k = tid; k < n; k += 256)
+    record_spike(a, s_spk[k], t, s_logbase + (unsigned long long)k);
   const int lane = tid & 63, wave = tid >> 6;
-  for (int k = wave; k < n; k += 4) {
+  const int cpr = (a.K_out + 255) / 256;
+  for (int it = wave; it < n * cpr; it += 4) {
+    const int k = it / cpr;
     const int32_t s = __builtin_amdgcn_readfirstlane(s_spk[k]);
-    deliver_row<Acc, WDT>(a, s, t, lane);
+    deliver_chunk<Acc, WDT>(a, s, (it - k * cpr) * 256, t, lane);
+  }
+}
+
+// Advance the device step counter after `n` steps; on a switch from the
+// split to the fused schedule, make both spike-log bases current.
+__global__ void k_tick(uint32_t* t_base, uint32_t n, unsigned long long* log_base,
+                       int sync_logs) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint32_t t = t_base[0];
+    if (sync_logs) log_base[(t + 1) & 1] = log_base[t & 1];
+    t_base[0] = t + n;
   }
 }
 
@@ -380,23 +513,49 @@ hipError_t launch_init(const InitArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, uint32_t t, hipStream_t st) {
-  const dim3 grid((unsigned)(a.N_pad / 1024)), block(256);
-  if (acc_bits == 32) {
-    if (wdt == DPSNN_W_F32)
-      hipLaunchKernelGGL((k_step<int32_t, DPSNN_W_F32>), grid, block, 0, st, a, t);
-    else if (wdt == DPSNN_W_F16)
-      hipLaunchKernelGGL((k_step<int32_t, DPSNN_W_F16>), grid, block, 0, st, a, t);
+template <typename Acc>
+static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
+  const dim3 tiles((unsigned)a.n_tiles), block(256);
+  hipLaunchKernelGGL(k_neuron<Acc>, tiles, block, 0, st, a, t_off);
+  const size_t lds = (size_t)a.n_tiles * 4;
+  const dim3 grid((unsigned)a.deliver_blocks);
+  if (wdt == DPSNN_W_F32)
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
+  else if (wdt == DPSNN_W_F16)
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
+  else
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
+}
+
+template <typename Acc>
+static void launch_fused(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
+  const dim3 tiles((unsigned)a.n_tiles), block(256);
+  if (wdt == DPSNN_W_F32)
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F32>), tiles, block, 0, st, a, t_off);
+  else if (wdt == DPSNN_W_F16)
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F16>), tiles, block, 0, st, a, t_off);
+  else
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_I8>), tiles, block, 0, st, a, t_off);
+}
+
+hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint32_t t_off,
+                       hipStream_t st) {
+  if (sched == DPSNN_SCHED_SPLIT) {
+    if (acc_bits == 32)
+      launch_split<int32_t>(a, wdt, t_off, st);
     else
-      hipLaunchKernelGGL((k_step<int32_t, DPSNN_W_I8>), grid, block, 0, st, a, t);
+      launch_split<int64_t>(a, wdt, t_off, st);
   } else {
-    if (wdt == DPSNN_W_F32)
-      hipLaunchKernelGGL((k_step<int64_t, DPSNN_W_F32>), grid, block, 0, st, a, t);
-    else if (wdt == DPSNN_W_F16)
-      hipLaunchKernelGGL((k_step<int64_t, DPSNN_W_F16>), grid, block, 0, st, a, t);
+    if (acc_bits == 32)
+      launch_fused<int32_t>(a, wdt, t_off, st);
     else
-      hipLaunchKernelGGL((k_step<int64_t, DPSNN_W_I8>), grid, block, 0, st, a, t);
+      launch_fused<int64_t>(a, wdt, t_off, st);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, a.t_base, n, a.log_base, sync_logs);
   return hipGetLastError();
 }
 

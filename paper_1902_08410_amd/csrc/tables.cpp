@@ -77,7 +77,7 @@ int validate(const dpsnn_params& p) {
   if (p.grid_w < 1 || p.grid_h < 1 || p.K < 4 || p.K_out < 0 || p.K_out > kMaxKout)
     return DPSNN_E_INVAL;
   const int64_t N = (int64_t)p.grid_w * p.grid_h * p.K;
-  if (N > (1ll << 31) - 4096) return DPSNN_E_INVAL;
+  if (N > (int64_t)kTargetMask) return DPSNN_E_INVAL;  // target field of a row word
   if (!(p.frac_exc >= 0 && p.frac_exc <= 1)) return DPSNN_E_INVAL;
   for (int q = 0; q < 2; ++q) {
     if (!(p.frac_local[q] >= 0 && p.frac_local[q] <= 1)) return DPSNN_E_INVAL;

@@ -111,6 +111,9 @@ def lib():
             "dpsnn_read_slots": ([V, V], C.c_int),
             "dpsnn_read_rows": ([V, C.c_int64, C.c_int64, V, V, V], C.c_int),
             "dpsnn_host_table": ([P(DpsnnParams), C.c_char_p, V, C.c_int64], C.c_int64),
+            "dpsnn_set_schedule": ([V, C.c_int32], C.c_int),
+            "dpsnn_set_graph_steps": ([V, C.c_int64], C.c_int),
+            "dpsnn_autotune": ([V, C.c_int64, P(C.c_int32)], C.c_int),
         }
         for fn, (args, res) in sig.items():
             f = getattr(L, fn)
@@ -123,7 +126,9 @@ def lib():
 EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step",
            "dpsnn_sync", "dpsnn_read_spikes", "dpsnn_read_rates", "dpsnn_stats_get",
            "dpsnn_free", "dpsnn_strerror", "dpsnn_read_state", "dpsnn_write_state",
-           "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table"]
+           "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
+           "dpsnn_set_graph_steps", "dpsnn_autotune"]
+SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
 def _check(fn, rc):
@@ -223,6 +228,20 @@ def dpsnn_set_stream(net: Net, stream) -> None:
 
 def dpsnn_step(net: Net, n_steps: int) -> None:
     _check("dpsnn_step", lib().dpsnn_step(net.h, int(n_steps)))
+
+
+def dpsnn_set_schedule(net: Net, sched: int) -> None:
+    _check("dpsnn_set_schedule", lib().dpsnn_set_schedule(net.h, int(sched)))
+
+
+def dpsnn_set_graph_steps(net: Net, steps: int) -> None:
+    _check("dpsnn_set_graph_steps", lib().dpsnn_set_graph_steps(net.h, int(steps)))
+
+
+def dpsnn_autotune(net: Net, probe_steps: int) -> int:
+    chosen = C.c_int32(-1)
+    _check("dpsnn_autotune", lib().dpsnn_autotune(net.h, int(probe_steps), C.byref(chosen)))
+    return int(chosen.value)
 
 
 def dpsnn_sync(net: Net) -> int:

@@ -98,9 +98,17 @@ def _compare_state(L, net, orc, what=""):
     assert np.array_equal(r.astype(np.int32), orr), what
 
 
+def _new_oracle_spikes(orc):
+    """Oracle spikes emitted since the previous call (the GPU log drains)."""
+    st, ids = orc.spikes()
+    k = getattr(orc, "_seen", 0)
+    orc._seen = len(st)
+    return st[k:], ids[k:]
+
+
 def _compare_all(L, net, orc, what=""):
     st, ids = L.dpsnn_read_spikes(net)
-    ost, oids = orc.spikes()
+    ost, oids = _new_oracle_spikes(orc)
     assert len(st) == len(ost), (what, len(st), len(ost))
     assert np.array_equal(st, ost) and np.array_equal(ids, oids), what
     _compare_state(L, net, orc, what)
@@ -145,11 +153,13 @@ RASTER_CASES = {
 }
 
 
+@pytest.mark.parametrize("sched", [0, 1])
 @pytest.mark.parametrize("case", sorted(RASTER_CASES))
-def test_raster_bit_exact(L, case):
+def test_raster_bit_exact(L, case, sched):
     p = RASTER_CASES[case]
-    _say("raster", case)
+    _say("raster", case, "schedule", sched)
     net, orc = _pair(p, 5)
+    L.dpsnn_set_schedule(net, sched)
     n = 0
     for k in range(4):
         L.dpsnn_step(net, 500)
@@ -203,7 +213,7 @@ def test_c2_full_size_start_and_teacher_forced_step(L):
     L.dpsnn_step(net, 1)
     orc2.step(1)
     st, ids = L.dpsnn_read_spikes(net)
-    ost, oids = orc2.spikes()
+    ost, oids = _new_oracle_spikes(orc2)
     assert np.array_equal(st, ost) and np.array_equal(ids, oids)
     assert len(st) > 0
     _compare_state(L, net, orc2, "teacher forced")
@@ -246,3 +256,44 @@ def test_error_paths(L):
         dpsnn.dpsnn_step(net, -1)
     assert e.value.code == -1
     net.close()
+
+
+def test_graph_replay_and_schedule_switching(L):
+    """Steps replayed from captured HIP graphs on a non-default stream, with
+    the schedule switched between chunks, stay bit-exact."""
+    import torch
+    p = W.tiny(w=3, h=3, K=120, K_out=90, nu_ext_hz=[3000.0, 3000.0])
+    _say("graphs + schedule switching")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        net, orc = _pair(p, 13)
+        L.dpsnn_set_graph_steps(net, 64)
+        total = 0
+        for k, (sched, n) in enumerate([(1, 300), (0, 257), (1, 64), (0, 1), (1, 700),
+                                        (0, 130), (0, 128)]):
+            L.dpsnn_set_schedule(net, sched)
+            L.dpsnn_step(net, n)
+            orc.step(n)
+            total += _compare_all(L, net, orc, ("chunk", k, sched))
+        assert total > 200
+        chosen = L.dpsnn_autotune(net, 200)
+        orc.step(800)
+        assert chosen in (0, 1)
+        _compare_all(L, net, orc, "after autotune")
+        net.close()
+
+
+def test_c1_graph_stream_two_seconds(L):
+    """Config 1 for 2 s on a non-default stream with graph replay."""
+    import torch
+    _say("c1 graphs")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        net, orc = _pair(W.swa(), 2)
+        for sched in (1, 0):
+            L.dpsnn_set_schedule(net, sched)
+            for k in range(2):
+                L.dpsnn_step(net, 5000)
+                orc.step(5000)
+                _compare_all(L, net, orc, (sched, k))
+        net.close()

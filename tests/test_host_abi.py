@@ -89,6 +89,7 @@ def test_f16_table_matches_numpy_rounding():
     dict(rate_bin_steps=0), dict(rate_bins_cap=0), dict(spike_log_cap=-1),
     dict(dt_ms=0.0), dict(tau_m=[0.0, 10.0]), dict(frac_exc=1.5),
     dict(frac_local=[1.2, 0.5]), dict(tau_arp=[30.0, 1.0]),
+    dict(grid_w=64, grid_h=64, K=20000, K_out=10),   # more than 2^26 neurons
 ])
 def test_invalid_parameters_rejected(bad):
     p = W.swa(rate_bins_cap=16, spike_log_cap=16)
