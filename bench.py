@@ -44,6 +44,66 @@ def bytes_per_event(p) -> float:
     return 4 + wb + 2 * acc
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1902_08410_amd", "csrc", "kernels.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "c2_24x24_traffic.json")
+
+
+def kernels_sha256() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def recorded_traffic():
+    """Per-launch HBM bytes of the kernels from the committed counter runs,
+    or None if the kernel source changed since they were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get("kernels_sha256") == kernels_sha256() else None
+
+
+def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, out_json):
+    """Fold rocprofv3 CSV output (kernel trace/stats and FETCH_SIZE / WRITE_SIZE
+    passes of this benchmark, plus the same counters for a 256 MiB copy) into
+    per-launch figures: medians over the last 2000 dispatches of each kernel."""
+    import csv
+    import glob
+    import statistics
+
+    def one(d, pat):
+        f = glob.glob(os.path.join(d, pat))
+        return list(csv.DictReader(open(f[0]))) if f else []
+
+    known_kib = 256 * 1024
+    cf = [float(r["Counter_Value"]) for r in one(cal_fetch_dir, "*counter_collection.csv")
+          if "copyBuffer" in r["Kernel_Name"]]
+    cw = [float(r["Counter_Value"]) for r in one(cal_write_dir, "*counter_collection.csv")
+          if "copyBuffer" in r["Kernel_Name"]]
+    f_fetch = known_kib / statistics.mean(cf)
+    f_write = known_kib / statistics.mean(cw)
+    rec = {"kernels_sha256": kernels_sha256(), "fetch_scale": f_fetch, "write_scale": f_write,
+           "kernels": {}}
+    fe = one(fetch_dir, "*counter_collection.csv")
+    wr = one(write_dir, "*counter_collection.csv")
+    tr = one(kt_dir, "*kernel_trace.csv")
+    for name in ("k_neuron", "k_deliver", "k_step"):
+        a = [float(r["Counter_Value"]) for r in fe if name in r["Kernel_Name"]][-2000:]
+        b = [float(r["Counter_Value"]) for r in wr if name in r["Kernel_Name"]][-2000:]
+        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr
+             if name in r["Kernel_Name"]][-4000:]
+        if not a or not b:
+            continue
+        fetch_b = statistics.median(a) * 1024 * f_fetch
+        write_b = statistics.median(b) * 1024 * f_write
+        rec["kernels"][name] = {"fetch_bytes": fetch_b, "write_bytes": write_b,
+                                "bytes_per_launch": fetch_b + write_b,
+                                "median_duration_us": statistics.median(d) / 1e3 if d else None,
+                                "dispatches": len(a)}
+    json.dump(rec, open(out_json, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(params, gpu_net, dpsnn, steps: int, budget_s: float):
     """The oracle (single thread) re-running a post-transient window of the
     same workload from the GPU's state: events/s of the CPU implementation."""
@@ -71,6 +131,10 @@ def cpu_baseline(params, gpu_net, dpsnn, steps: int, budget_s: float):
             "cpu": platform.processor() or platform.machine()}
 
 
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,7 +144,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only copy 256 MiB device-to-device three times (counter calibration)")
+    ap.add_argument("--summarize-rocprof", nargs=6, metavar=("KT", "FETCH", "WRITE",
+                    "CAL_FETCH", "CAL_WRITE", "OUT_JSON"),
+                    help="fold rocprofv3 CSV directories into per-launch traffic figures")
+    ap.add_argument("--profile-steps", type=int, default=2000,
+                    help="steps timed per kernel with events for the roofline")
+    ap.add_argument("--variants", type=int, default=1, help="also time FP16 and int8 weights")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        summarize_rocprof(*args.summarize_rocprof)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
@@ -93,9 +168,17 @@ def main():
         from paper_1902_08410_amd import build as libbuild
         libbuild.build()
     torch.cuda.set_device(0)
+    if args.calibrate:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
     S = args.dt_steps
-    total_bins = (args.warmup + args.steps) * S // 50 + 200   # + autotune probes
+    total_bins = (args.warmup + args.steps) * S // 50 + 400   # + autotune/profile steps
     regimes = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
     nets = {}
     build_ms = {}
@@ -105,6 +188,7 @@ def main():
             p.update(spike_log_cap=0, rate_bins_cap=total_bins)
             nets[name] = dpsnn.dpsnn_build(p, 1)
             build_ms[name] = nets[name].stats()["build_ms"]
+            progress(f"built {name}: {build_ms[name]:.0f} ms")
         for _ in range(args.warmup):
             for net in nets.values():
                 dpsnn.dpsnn_step(net, S)
@@ -112,35 +196,76 @@ def main():
             sched[name] = dpsnn.dpsnn_autotune(net, 1000) if args.autotune else \
                 net.stats()["reserved"]
         torch.cuda.synchronize()
+        progress("warmup done")
         sp0 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0.record(stream)
-        for _ in range(args.steps):
+        for k in range(args.steps):
             for net in nets.values():
                 dpsnn.dpsnn_step(net, S)
+            if k % 5 == 4:
+                progress(f"enqueued timed step {k + 1}")
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         gpu_ms = ev0.elapsed_time(ev1)
+        sp1 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
+        # per-kernel times over further real steps (events around each kernel)
+        progress("timed region done")
+        prof = {}
+        for name, net in nets.items():
+            if args.profile_steps <= 0:
+                continue
+            dpsnn.dpsnn_set_schedule(net, dpsnn.SCHED_SPLIT)
+            s_a = net.stats()["n_spikes"]
+            upd_ms, del_ms = dpsnn.dpsnn_profile_steps(net, args.profile_steps)
+            prof[name] = (upd_ms, del_ms, (net.stats()["n_spikes"] - s_a) * K_OUT)
+        # the same workload with binary16 and int8 stored efficacies
+        variants = {}
+        if args.variants:
+            for wd in ("f16", "i8"):
+                for reg in ("swa", "aw"):
+                    q = dict(regimes[reg], weight_dtype=wd)
+                    vn = dpsnn.dpsnn_build(q, 1)
+                    dpsnn.dpsnn_step(vn, S)
+                    torch.cuda.synchronize()
+                    v0 = vn.stats()["n_spikes"]
+                    ta = time.perf_counter()
+                    dpsnn.dpsnn_step(vn, 2 * S)
+                    torch.cuda.synchronize()
+                    tb = time.perf_counter()
+                    ev = (vn.stats()["n_spikes"] - v0) * K_OUT
+                    variants[f"{wd}_{reg}"] = {"events_per_s": ev / (tb - ta),
+                                               "rate_hz": ev / K_OUT / vn.N / (2 * S * 1e-4)}
+                    vn.close()
+                    progress(f"variant {wd} {reg} done")
 
-    sp1 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
     spikes = {k: sp1[k] - sp0[k] for k in nets}
     events = sum(spikes.values()) * K_OUT
     value = events / wall
-    n_launch = args.steps * S * len(nets)   # steps of dt (one launch sequence each)
+    n_launch = args.steps * S * len(nets)   # steps of dt
     N = nets["swa"].N
     p0 = regimes["swa"]
     Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
-    ev_per_launch = events / n_launch
-    alg_bytes = N * Bn + ev_per_launch * Be
-    launch_ms = gpu_ms / n_launch
-    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     sim_s = args.steps * S * 0.1e-3
     rates = {k: spikes[k] / N / sim_s for k in nets}
-
+    # dominant kernel: the delivery kernel (most of the step time)
+    n_prof = max(1, args.profile_steps * len(nets))
+    del_ms = sum(v[1] for v in prof.values())
+    upd_ms = sum(v[0] for v in prof.values())
+    prof_events = sum(v[2] for v in prof.values())
+    del_us = del_ms * 1e3 / n_prof
+    upd_us = upd_ms * 1e3 / n_prof
+    ev_per_launch = prof_events / n_prof
+    alg_del = ev_per_launch * Be
+    achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
+    traffic = None
+    rec = recorded_traffic()
+    if rec and "k_deliver" in rec["kernels"]:
+        traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"]
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(regimes["swa"], nets["swa"], dpsnn, 400, args.cpu_budget)
@@ -171,13 +296,20 @@ def main():
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "one step of dt (k_neuron + k_deliver, or fused k_step)",
-            "bytes_per_neuron_step": Bn,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic,
+            "kernel": "k_deliver (spike delivery, fixed-point atomics into input slots)",
             "bytes_per_event": Be,
-            "avg_launch_us": launch_ms * 1e3,
             "events_per_launch": ev_per_launch,
+            "algorithmic_bytes_per_launch": alg_del,
+            "avg_launch_us": del_us,
+            "atomic_rate_G_per_s": ev_per_launch / del_us / 1e3 if del_us > 0 else None,
+            "atomic_ceiling_G_per_s": 27.0,
+            "update_kernel": {"kernel": "k_neuron", "avg_launch_us": upd_us,
+                              "algorithmic_bytes_per_launch": N * Bn,
+                              "achieved_GB_s": N * Bn / (upd_us * 1e-6) / 1e9 if upd_us else None,
+                              "bytes_per_neuron_step": Bn},
+            "step_us": gpu_ms * 1e3 / n_launch,
         },
         "cpu_baseline": cpu,
         "per_regime": {k: {"spikes": spikes[k], "rate_hz": rates[k],
@@ -185,6 +317,7 @@ def main():
                            "build_ms": build_ms[k]} for k in nets},
         "gpu_ms_timed": gpu_ms,
         "schedule": {k: ("split" if v == 1 else "fused") for k, v in sched.items()},
+        "weight_variants": variants,
     }
     print(json.dumps(out), flush=True)
 

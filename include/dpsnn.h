@@ -160,6 +160,15 @@ int dpsnn_set_graph_steps(dpsnn_net* net, int64_t steps);
  */
 int dpsnn_autotune(dpsnn_net* net, int64_t probe_steps, int32_t* chosen);
 
+/*
+ * Run n_steps real steps with HIP events around each kernel and return the
+ * summed kernel times in host_ms[0] (neuron update; the whole step for the
+ * fused schedule) and host_ms[1] (delivery).  The per-block timing of the
+ * execution flow the paper uses to guide optimisation (Sec. 2.1.1, Fig. 1
+ * caption).  No graphs; synchronises.
+ */
+int dpsnn_profile_steps(dpsnn_net* net, int64_t n_steps, double* host_ms);
+
 /* Wait for the handle's stream.  Returns SPIKELOG_FULL if the spike log
  * overflowed since it was last drained. */
 int dpsnn_sync(dpsnn_net* net);

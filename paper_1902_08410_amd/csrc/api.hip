@@ -418,6 +418,54 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   return rc;
 }
 
+int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
+  if (!n || n_steps < 1 || !host_ms) return DPSNN_E_INVAL;
+  if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
+  const int64_t last_bin = (n->t + n_steps - 1) / n->p.rate_bin_steps;
+  if (last_bin - n->rate_first + 1 > n->p.rate_bins_cap) return DPSNN_E_RATES_FULL;
+  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
+    HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
+  n->last_sched = n->sched;
+  std::vector<hipEvent_t> ev((size_t)3 * n_steps);
+  for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+  int rc = DPSNN_OK;
+  for (int64_t k = 0; k < n_steps && rc == DPSNN_OK; ++k) {
+    hipEvent_t* e = &ev[(size_t)3 * k];
+    if (hipEventRecord(e[0], n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
+    if (n->sched == DPSNN_SCHED_SPLIT) {
+      if (launch_phase(n->sa, n->p.weight_dtype, n->p.acc_bits, 0, (uint32_t)k, n->stream) !=
+              hipSuccess ||
+          hipEventRecord(e[1], n->stream) != hipSuccess ||
+          launch_phase(n->sa, n->p.weight_dtype, n->p.acc_bits, 1, (uint32_t)k, n->stream) !=
+              hipSuccess)
+        rc = DPSNN_E_DEVICE;
+    } else {
+      if (launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, n->sched, (uint32_t)k,
+                      n->stream) != hipSuccess ||
+          hipEventRecord(e[1], n->stream) != hipSuccess)
+        rc = DPSNN_E_DEVICE;
+    }
+    if (hipEventRecord(e[2], n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
+  }
+  if (rc == DPSNN_OK && launch_tick(n->sa, (uint32_t)n_steps, 0, n->stream) != hipSuccess)
+    rc = DPSNN_E_DEVICE;
+  if (rc == DPSNN_OK && hipStreamSynchronize(n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
+  double t0 = 0.0, t1 = 0.0;
+  for (int64_t k = 0; k < n_steps && rc == DPSNN_OK; ++k) {
+    float a = 0.f, b = 0.f;
+    (void)hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+    (void)hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+    t0 += a;
+    t1 += b;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc != DPSNN_OK) return rc;
+  n->t += n_steps;
+  host_ms[0] = t0;
+  host_ms[1] = t1;
+  return DPSNN_OK;
+}
+
 static int log_count(dpsnn_net* n, unsigned long long* cnt) {
   HIP_OK(hipMemcpy(cnt, n->sa.log_base + (n->t & 1), 8, hipMemcpyDeviceToHost));
   return DPSNN_OK;

@@ -120,6 +120,8 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint32_t t_off,
                        hipStream_t s);
 hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t s);
+hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uint32_t t_off,
+                        hipStream_t s);
 hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
                             unsigned long long* out, hipStream_t s);
 

@@ -554,6 +554,35 @@ hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint
   return hipGetLastError();
 }
 
+// One phase of the split schedule on its own (0 = neuron update, 1 = delivery).
+hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uint32_t t_off,
+                        hipStream_t st) {
+  const dim3 tiles((unsigned)a.n_tiles), block(256);
+  const dim3 grid((unsigned)a.deliver_blocks);
+  const size_t lds = (size_t)a.n_tiles * 4;
+  if (phase == 0) {
+    if (acc_bits == 32)
+      hipLaunchKernelGGL(k_neuron<int32_t>, tiles, block, 0, st, a, t_off);
+    else
+      hipLaunchKernelGGL(k_neuron<int64_t>, tiles, block, 0, st, a, t_off);
+  } else if (acc_bits == 32) {
+    if (wdt == DPSNN_W_F32)
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
+    else if (wdt == DPSNN_W_F16)
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
+    else
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
+  } else {
+    if (wdt == DPSNN_W_F32)
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
+    else if (wdt == DPSNN_W_F16)
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
+    else
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, a.t_base, n, a.log_base, sync_logs);
   return hipGetLastError();

@@ -114,6 +114,7 @@ def lib():
             "dpsnn_set_schedule": ([V, C.c_int32], C.c_int),
             "dpsnn_set_graph_steps": ([V, C.c_int64], C.c_int),
             "dpsnn_autotune": ([V, C.c_int64, P(C.c_int32)], C.c_int),
+            "dpsnn_profile_steps": ([V, C.c_int64, V], C.c_int),
         }
         for fn, (args, res) in sig.items():
             f = getattr(L, fn)
@@ -127,7 +128,7 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_sync", "dpsnn_read_spikes", "dpsnn_read_rates", "dpsnn_stats_get",
            "dpsnn_free", "dpsnn_strerror", "dpsnn_read_state", "dpsnn_write_state",
            "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
-           "dpsnn_set_graph_steps", "dpsnn_autotune"]
+           "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -242,6 +243,13 @@ def dpsnn_autotune(net: Net, probe_steps: int) -> int:
     chosen = C.c_int32(-1)
     _check("dpsnn_autotune", lib().dpsnn_autotune(net.h, int(probe_steps), C.byref(chosen)))
     return int(chosen.value)
+
+
+def dpsnn_profile_steps(net: Net, n_steps: int):
+    """(update_ms, delivery_ms) summed over n_steps real steps."""
+    ms = np.zeros(2, np.float64)
+    _check("dpsnn_profile_steps", lib().dpsnn_profile_steps(net.h, int(n_steps), _ptr(ms)))
+    return float(ms[0]), float(ms[1])
 
 
 def dpsnn_sync(net: Net) -> int:
