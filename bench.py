@@ -194,7 +194,7 @@ def main():
                 dpsnn.dpsnn_step(net, S)
         for name, net in nets.items():
             sched[name] = dpsnn.dpsnn_autotune(net, 1000) if args.autotune else \
-                net.stats()["reserved"]
+                net.stats()["schedule"]
         torch.cuda.synchronize()
         progress("warmup done")
         sp0 = {k: n.stats()["n_spikes"] for k, n in nets.items()}

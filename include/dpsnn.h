@@ -108,7 +108,11 @@ typedef struct dpsnn_stats {
   int64_t bytes_rows;     /* device bytes of the synapse rows              */
   int64_t bytes_state;    /* device bytes of neuron state and input slots  */
   int64_t bytes_total;    /* all device bytes owned by the handle          */
-  int32_t lds_bytes;      /* LDS per workgroup of the step kernel          */
+  int32_t lds_bytes;      /* LDS per workgroup of the step kernels         */
+  int32_t schedule;       /* current DPSNN_SCHED_*                         */
+  int64_t n_index;        /* entries of the inspection arrays: the global
+                             index space of all networks (see below)      */
+  int32_t n_nets;         /* networks in the handle                        */
   int32_t reserved;
 } dpsnn_stats;
 
@@ -130,6 +134,24 @@ int dpsnn_set_allocator(dpsnn_alloc_fn alloc, dpsnn_free_fn release, void* ctx);
  * done.  Errors: INVAL (bad p or out == NULL), NOMEM, DEVICE, RANGE.
  */
 int dpsnn_build(const dpsnn_params* p, uint64_t seed, dpsnn_net** out);
+
+/*
+ * Build several independent networks in one handle (batched sweep): they
+ * advance together, one set of launches per step for all of them, and each
+ * reproduces its own dpsnn_build run bit for bit.  p[k] and seeds[k]
+ * describe network k; K_out, d_min, d_max, dt_ms, weight_dtype, acc_bits,
+ * q_frac_bits and rate_bin_steps must agree, and the buffer capacities
+ * (spike_log_cap, rate_bins_cap) of p[0] apply to the handle.  Networks
+ * are laid end to end in one global index space, each padded to a multiple
+ * of 1024 neurons (dpsnn_net_info); spike ids, rows, state and slots use
+ * global indices, rate bins use global module indices.
+ */
+int dpsnn_build_batch(const dpsnn_params* p, const uint64_t* seeds, int32_t n_nets,
+                      dpsnn_net** out);
+
+/* Where network k of a handle lives in the global index spaces. */
+int dpsnn_net_info(dpsnn_net* net, int32_t k, int64_t* base, int64_t* n_neurons,
+                   int64_t* module_base, int64_t* n_modules);
 
 /* Stream on which later work of this handle is enqueued (a hipStream_t;
  * NULL = the default stream). */
@@ -202,13 +224,14 @@ const char* dpsnn_strerror(int code);
 /* ---- inspection entry points (tests and tools; synchronise) ---------- */
 
 /* Neuron state: V and c as binary32, ref (remaining refractory steps) as
- * uint8; each host array holds n_neurons entries (any may be NULL). */
+ * uint8; each host array holds stats.n_index entries (= n_neurons for a
+ * single network; any pointer may be NULL). */
 int dpsnn_read_state(dpsnn_net* net, float* host_V, float* host_c,
                      uint8_t* host_ref);
 int dpsnn_write_state(dpsnn_net* net, const float* host_V,
                       const float* host_c, const uint8_t* host_ref);
 
-/* Input slots: D = d_max + 1 slots of n_neurons fixed-point values,
+/* Input slots: D = d_max + 1 slots of stats.n_index fixed-point values,
  * slot-major, as int64 whatever the device width. */
 int dpsnn_read_slots(dpsnn_net* net, int64_t* host_slots);
 

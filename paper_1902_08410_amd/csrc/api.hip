@@ -58,191 +58,252 @@ int w_bytes(const dpsnn_params& p) {
   return p.weight_dtype == DPSNN_W_F32 ? 4 : p.weight_dtype == DPSNN_W_F16 ? 2 : 1;
 }
 
+// Parameters shared by every network of a batch (the step kernels use one
+// value for all of them).
+bool same_structure(const dpsnn_params& a, const dpsnn_params& b) {
+  return a.K_out == b.K_out && a.d_min == b.d_min && a.d_max == b.d_max &&
+         a.weight_dtype == b.weight_dtype && a.acc_bits == b.acc_bits &&
+         a.q_frac_bits == b.q_frac_bits && a.rate_bin_steps == b.rate_bin_steps &&
+         a.dt_ms == b.dt_ms;
+}
+
 int build_impl(dpsnn_net* n) {
-  const dpsnn_params& p = n->p;
-  HostTables& T = n->T;
-  int rc = compute_tables(p, T);
-  if (rc != DPSNN_OK) return rc;
+  const int nn = (int)n->p.size();
+  const dpsnn_params& p0 = n->p[0];
+  n->T.resize(nn);
+  for (int k = 0; k < nn; ++k) {
+    const int rc = compute_tables(n->p[k], n->T[k]);
+    if (rc != DPSNN_OK) return rc;
+    if (!same_structure(p0, n->p[k])) return DPSNN_E_INVAL;
+  }
   HIP_OK(hipGetDevice(&n->device));
   const hipStream_t st = n->stream;
-  const int64_t N = T.N, Np = T.N_pad, M = T.M;
-  const int ab = acc_bytes(p), wb = w_bytes(p);
+  const HostTables& T0 = n->T[0];
+  // global index space: networks end to end, each padded to whole tiles
+  n->base.resize(nn);
+  n->mbase.resize(nn);
+  int64_t gi = 0, gm = 0;
+  for (int k = 0; k < nn; ++k) {
+    n->base[k] = gi;
+    n->mbase[k] = gm;
+    gi += n->T[k].N_pad;
+    gm += n->T[k].M;
+    n->N_total += n->T[k].N;
+  }
+  n->N_pad = gi;
+  n->N_index = n->base[nn - 1] + n->T[nn - 1].N;
+  n->M_total = (int32_t)gm;
+  if (n->N_pad > (int64_t)kTargetMask) return DPSNN_E_INVAL;
+  const int64_t Np = n->N_pad, M = gm;
+  const int ab = acc_bytes(p0), wb = w_bytes(p0);
+  const int rs = T0.row_stride;
+  n->doff_stride = T0.doff_stride;
+  const int ds = T0.doff_stride;
 
   // ---- device memory
-  int32_t* tgt = (int32_t*)dev_alloc(n, (size_t)N * T.row_stride * 4);
-  void* w = dev_alloc(n, (size_t)N * T.row_stride * wb);
-  uint16_t* doff = (uint16_t*)dev_alloc(n, (size_t)N * T.doff_stride * 2);
-  n->bytes_rows = (int64_t)N * T.row_stride * (4 + wb) + (int64_t)N * T.doff_stride * 2;
+  int32_t* tgt = (int32_t*)dev_alloc(n, (size_t)Np * rs * 4);
+  void* w = dev_alloc(n, (size_t)Np * rs * wb);
+  uint16_t* doff = (uint16_t*)dev_alloc(n, (size_t)Np * ds * 2);
+  n->bytes_rows = Np * rs * (4 + wb) + Np * ds * 2;
   float* V = (float*)dev_alloc(n, (size_t)Np * 4);
   float* c = (float*)dev_alloc(n, (size_t)Np * 4);
   uint8_t* ref = (uint8_t*)dev_alloc(n, (size_t)Np);
-  void* slots = dev_alloc(n, (size_t)T.D * Np * ab);
-  n->bytes_state = Np * 9 + (int64_t)T.D * Np * ab;
+  void* slots = dev_alloc(n, (size_t)T0.D * Np * ab);
+  n->bytes_state = Np * 9 + (int64_t)T0.D * Np * ab;
   const int64_t n_tiles = Np / 1024;
   int32_t* spk = (int32_t*)dev_alloc(n, (size_t)Np * 4);
   int32_t* blk_cnt = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
-  int2* log = (int2*)dev_alloc(n, (size_t)std::max<int64_t>(p.spike_log_cap, 1) * 8);
+  int32_t* tile_net = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
+  NetDev* nets = (NetDev*)dev_alloc(n, sizeof(NetDev) * nn);
+  int2* log = (int2*)dev_alloc(n, (size_t)std::max<int64_t>(p0.spike_log_cap, 1) * 8);
   unsigned char* ctl = (unsigned char*)dev_alloc(n, 256);
-  unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p.rate_bins_cap * M * 2 * 4);
-  const size_t n_off = T.off_xy.size() / 2;
-  uint32_t* off_thr = (uint32_t*)dev_alloc(n, std::max<size_t>(T.off_thr.size(), 1) * 4);
-  int32_t* off_xy = (int32_t*)dev_alloc(n, std::max<size_t>(T.off_xy.size(), 2) * 4);
-  void* wtab[2];
-  for (int q = 0; q < 2; ++q) wtab[q] = dev_alloc(n, (size_t)kQuantN * wb);
-  void* jx = dev_alloc(n, (size_t)2 * kQuantN * ab);
+  unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p0.rate_bins_cap * M * 2 * 4);
   int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * 2 * 8);
-  if (!tgt || !w || !doff || !V || !c || !ref || !slots || !spk || !blk_cnt || !log || !ctl ||
-      !rates || !off_thr || !off_xy || !wtab[0] || !wtab[1] || !jx || !sfix)
+  if (!tgt || !w || !doff || !V || !c || !ref || !slots || !spk || !blk_cnt || !tile_net ||
+      !nets || !log || !ctl || !rates || !sfix)
     return DPSNN_E_NOMEM;
-
-  // ---- tables
-  if (!T.off_thr.empty())
-    HIP_OK(hipMemcpyAsync(off_thr, T.off_thr.data(), T.off_thr.size() * 4, hipMemcpyHostToDevice, st));
-  if (!T.off_xy.empty())
-    HIP_OK(hipMemcpyAsync(off_xy, T.off_xy.data(), T.off_xy.size() * 4, hipMemcpyHostToDevice, st));
-  for (int q = 0; q < 2; ++q) {
-    const void* src = p.weight_dtype == DPSNN_W_F32 ? (const void*)T.wt32[q].data()
-                      : p.weight_dtype == DPSNN_W_F16 ? (const void*)T.wt16[q].data()
-                                                      : (const void*)T.wq8[q].data();
-    HIP_OK(hipMemcpyAsync(wtab[q], src, (size_t)kQuantN * wb, hipMemcpyHostToDevice, st));
-  }
-  std::vector<unsigned char> jxh((size_t)2 * kQuantN * ab);
-  for (int q = 0; q < 2; ++q)
-    for (int i = 0; i < kQuantN; ++i) {
-      const int64_t v = T.jxfix[q][i];
-      if (ab == 4) {
-        const int32_t v32 = (int32_t)v;
-        memcpy(&jxh[((size_t)q * kQuantN + i) * 4], &v32, 4);
-      } else {
-        memcpy(&jxh[((size_t)q * kQuantN + i) * 8], &v, 8);
-      }
-    }
-  HIP_OK(hipMemcpyAsync(jx, jxh.data(), jxh.size(), hipMemcpyHostToDevice, st));
-  // int8 scale per (module, source pop); modules of one network share the
-  // parameters, hence the scale of their population table
-  std::vector<int64_t> sf((size_t)M * 2);
-  for (int64_t m = 0; m < M; ++m) {
-    sf[2 * m] = T.s8fix[0];
-    sf[2 * m + 1] = T.s8fix[1];
-  }
-  HIP_OK(hipMemcpyAsync(sfix, sf.data(), sf.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemsetAsync(slots, 0, (size_t)T.D * Np * ab, st));
+  HIP_OK(hipMemsetAsync(slots, 0, (size_t)T0.D * Np * ab, st));
   HIP_OK(hipMemsetAsync(ctl, 0, 256, st));
   HIP_OK(hipMemsetAsync(blk_cnt, 0, (size_t)n_tiles * 4, st));
-  HIP_OK(hipMemsetAsync(rates, 0, (size_t)p.rate_bins_cap * M * 2 * 4, st));
+  HIP_OK(hipMemsetAsync(rates, 0, (size_t)p0.rate_bins_cap * M * 2 * 4, st));
 
-  // ---- initial state and rows
-  InitArgs ia{};
-  ia.N = N;
-  ia.N_pad = Np;
-  ia.K = p.K;
-  ia.K_exc = T.K_exc;
-  ia.key0 = (uint32_t)n->seed;
-  ia.key1 = (uint32_t)(n->seed >> 32);
-  for (int q = 0; q < 2; ++q) {
-    ia.E[q] = (float)p.E[q];
-    ia.Vth[q] = (float)p.V_th[q];
-  }
-  ia.V = V;
-  ia.c = c;
-  ia.ref = ref;
-  HIP_OK(launch_init(ia, st));
-
-  GenArgs ga{};
-  ga.N = N;
-  ga.K = p.K;
-  ga.K_exc = T.K_exc;
-  ga.K_out = p.K_out;
-  ga.row_stride = T.row_stride;
-  ga.doff_stride = T.doff_stride;
-  ga.n_del = T.n_del;
-  ga.d_min = p.d_min;
-  ga.W = p.grid_w;
-  ga.H = p.grid_h;
-  ga.n_off = (int32_t)n_off;
-  ga.n_local[0] = T.n_local[0];
-  ga.n_local[1] = T.n_local[1];
-  ga.key0 = ia.key0;
-  ga.key1 = ia.key1;
-  ga.off_thr = off_thr;
-  ga.off_xy = off_xy;
-  ga.wtab[0] = wtab[0];
-  ga.wtab[1] = wtab[1];
-  ga.tgt = tgt;
-  ga.w = w;
-  ga.doff = doff;
   // int32 input slots: check at build that no step can leave the range.
   // The per-step sum at a neuron is bounded by the sum of |fixed-point
   // efficacy| over its incoming synapses plus the largest external sum.
   unsigned long long* absum = nullptr;
-  int64_t* wfix_dev = nullptr;
-  if (p.acc_bits == 32 && p.K_out > 0) {
-    absum = (unsigned long long*)dev_alloc(n, (size_t)N * 8 + 256);
-    wfix_dev = (int64_t*)dev_alloc(n, (size_t)2 * kQuantN * 8);
-    if (!absum || !wfix_dev) return DPSNN_E_NOMEM;
-    std::vector<int64_t> wf((size_t)2 * kQuantN);
+  int64_t ext_bound = 0;
+  if (p0.acc_bits == 32 && p0.K_out > 0) {
+    absum = (unsigned long long*)dev_alloc(n, (size_t)Np * 8 + 256);
+    if (!absum) return DPSNN_E_NOMEM;
+    HIP_OK(hipMemsetAsync(absum, 0, (size_t)Np * 8 + 256, st));
+  }
+
+  std::vector<NetDev> nd(nn);
+  std::vector<int32_t> tn((size_t)n_tiles);
+  std::vector<int64_t> sf((size_t)M * 2);
+  for (int k = 0; k < nn; ++k) {
+    const dpsnn_params& p = n->p[k];
+    const HostTables& T = n->T[k];
+    const int64_t b = n->base[k];
+    const uint32_t key0 = (uint32_t)n->seed[k], key1 = (uint32_t)(n->seed[k] >> 32);
+    ext_bound = std::max(ext_bound, T.ext_bound);
+    // per-network tables
+    uint32_t* off_thr = (uint32_t*)dev_alloc(n, std::max<size_t>(T.off_thr.size(), 1) * 4);
+    int32_t* off_xy = (int32_t*)dev_alloc(n, std::max<size_t>(T.off_xy.size(), 2) * 4);
+    void* wtab[2];
+    for (int q = 0; q < 2; ++q) wtab[q] = dev_alloc(n, (size_t)kQuantN * wb);
+    void* jx = dev_alloc(n, (size_t)2 * kQuantN * ab);
+    int64_t* wfix_dev = absum ? (int64_t*)dev_alloc(n, (size_t)2 * kQuantN * 8) : nullptr;
+    if (!off_thr || !off_xy || !wtab[0] || !wtab[1] || !jx || (absum && !wfix_dev))
+      return DPSNN_E_NOMEM;
+    if (!T.off_thr.empty())
+      HIP_OK(hipMemcpyAsync(off_thr, T.off_thr.data(), T.off_thr.size() * 4,
+                            hipMemcpyHostToDevice, st));
+    if (!T.off_xy.empty())
+      HIP_OK(hipMemcpyAsync(off_xy, T.off_xy.data(), T.off_xy.size() * 4,
+                            hipMemcpyHostToDevice, st));
     for (int q = 0; q < 2; ++q) {
-      std::vector<int64_t> t = fix_table(p, T, q);
-      std::copy(t.begin(), t.end(), wf.begin() + (size_t)q * kQuantN);
+      const void* src = p.weight_dtype == DPSNN_W_F32 ? (const void*)T.wt32[q].data()
+                        : p.weight_dtype == DPSNN_W_F16 ? (const void*)T.wt16[q].data()
+                                                        : (const void*)T.wq8[q].data();
+      HIP_OK(hipMemcpyAsync(wtab[q], src, (size_t)kQuantN * wb, hipMemcpyHostToDevice, st));
     }
-    HIP_OK(hipMemcpyAsync(wfix_dev, wf.data(), wf.size() * 8, hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemsetAsync(absum, 0, (size_t)N * 8 + 256, st));
+    // host staging buffers must outlive the asynchronous copies: sync below
+    std::vector<unsigned char> jxh((size_t)2 * kQuantN * ab);
+    for (int q = 0; q < 2; ++q)
+      for (int i = 0; i < kQuantN; ++i) {
+        const int64_t v = T.jxfix[q][i];
+        if (ab == 4) {
+          const int32_t v32 = (int32_t)v;
+          memcpy(&jxh[((size_t)q * kQuantN + i) * 4], &v32, 4);
+        } else {
+          memcpy(&jxh[((size_t)q * kQuantN + i) * 8], &v, 8);
+        }
+      }
+    HIP_OK(hipMemcpyAsync(jx, jxh.data(), jxh.size(), hipMemcpyHostToDevice, st));
+    std::vector<int64_t> wf;
+    if (absum) {
+      wf.resize((size_t)2 * kQuantN);
+      for (int q = 0; q < 2; ++q) {
+        std::vector<int64_t> t = fix_table(p, T, q);
+        std::copy(t.begin(), t.end(), wf.begin() + (size_t)q * kQuantN);
+      }
+      HIP_OK(hipMemcpyAsync(wfix_dev, wf.data(), wf.size() * 8, hipMemcpyHostToDevice, st));
+    }
+    // int8 scale per (module, source pop); modules of one network share the
+    // parameters, hence the scale of their population table
+    for (int64_t m = 0; m < T.M; ++m) {
+      sf[2 * (n->mbase[k] + m)] = T.s8fix[0];
+      sf[2 * (n->mbase[k] + m) + 1] = T.s8fix[1];
+    }
+    for (int64_t tl = b / 1024; tl < (b + T.N_pad) / 1024; ++tl) tn[(size_t)tl] = k;
+
+    InitArgs ia{};
+    ia.N = T.N;
+    ia.N_pad = T.N_pad;
+    ia.K = p.K;
+    ia.K_exc = T.K_exc;
+    ia.key0 = key0;
+    ia.key1 = key1;
+    for (int q = 0; q < 2; ++q) {
+      ia.E[q] = (float)p.E[q];
+      ia.Vth[q] = (float)p.V_th[q];
+    }
+    ia.V = V + b;
+    ia.c = c + b;
+    ia.ref = ref + b;
+    HIP_OK(launch_init(ia, st));
+
+    GenArgs ga{};
+    ga.N = T.N;
+    ga.tgt_base = b;
+    ga.K = p.K;
+    ga.K_exc = T.K_exc;
+    ga.K_out = p.K_out;
+    ga.row_stride = rs;
+    ga.doff_stride = ds;
+    ga.n_del = T.n_del;
+    ga.d_min = p.d_min;
+    ga.W = p.grid_w;
+    ga.H = p.grid_h;
+    ga.n_off = (int32_t)(T.off_xy.size() / 2);
+    ga.n_local[0] = T.n_local[0];
+    ga.n_local[1] = T.n_local[1];
+    ga.key0 = key0;
+    ga.key1 = key1;
+    ga.off_thr = off_thr;
+    ga.off_xy = off_xy;
+    ga.wtab[0] = wtab[0];
+    ga.wtab[1] = wtab[1];
+    ga.tgt = tgt + b * rs;
+    ga.w = static_cast<unsigned char*>(w) + (size_t)b * rs * wb;
+    ga.doff = doff + b * ds;
     ga.absum = absum;
     ga.wfix_tab[0] = wfix_dev;
-    ga.wfix_tab[1] = wfix_dev + kQuantN;
-  }
-  if (p.K_out > 0) HIP_OK(launch_gen(ga, p.weight_dtype, st));
-  if (absum) {
-    HIP_OK(launch_absum_max(absum, N, absum + N, st));
-    unsigned long long mx = 0;
-    HIP_OK(hipMemcpyAsync(&mx, absum + N, 8, hipMemcpyDeviceToHost, st));
+    ga.wfix_tab[1] = wfix_dev ? wfix_dev + kQuantN : nullptr;
+    if (p.K_out > 0) HIP_OK(launch_gen(ga, p.weight_dtype, st));
     HIP_OK(hipStreamSynchronize(st));
-    if ((double)mx + (double)T.ext_bound >= 2147483647.0) return DPSNN_E_RANGE;
+
+    NetDev& d = nd[k];
+    d.base = b;
+    d.N = T.N;
+    d.mbase = (int32_t)n->mbase[k];
+    d.K = p.K;
+    d.K_exc = T.K_exc;
+    d.key0 = key0;
+    d.key1 = key1;
+    for (int q = 0; q < 2; ++q) {
+      d.Pm[q] = T.prop32[q][0];
+      d.Pc[q] = T.prop32[q][1];
+      d.PVc[q] = T.prop32[q][2];
+      d.Iterm[q] = T.prop32[q][3];
+      d.E[q] = (float)p.E[q];
+      d.Vth[q] = (float)p.V_th[q];
+      d.Vr[q] = (float)p.V_r[q];
+      d.alpha[q] = (float)p.alpha_c[q];
+      d.n_arp[q] = T.n_arp[q];
+      d.n_pois[q] = T.n_pois[q];
+      for (int x = 0; x < kMaxPois; ++x) d.pois[q][x] = T.pois[q][x];
+    }
+    d.jxfix = jx;
+  }
+  HIP_OK(hipMemcpyAsync(nets, nd.data(), sizeof(NetDev) * nn, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(tile_net, tn.data(), tn.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(sfix, sf.data(), sf.size() * 8, hipMemcpyHostToDevice, st));
+  if (absum) {
+    HIP_OK(launch_absum_max(absum, Np, absum + Np, st));
+    unsigned long long mx = 0;
+    HIP_OK(hipMemcpyAsync(&mx, absum + Np, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if ((double)mx + (double)ext_bound >= 2147483647.0) return DPSNN_E_RANGE;
   }
   HIP_OK(hipStreamSynchronize(st));
 
   // ---- step arguments
   StepArgs& a = n->sa;
   memset(&a, 0, sizeof(a));
-  a.N = N;
   a.N_pad = Np;
-  a.K = p.K;
-  a.K_exc = T.K_exc;
-  a.K_out = p.K_out;
-  a.row_stride = T.row_stride;
-  a.D = T.D;
-  a.n_del = T.n_del;
-  a.d_min = p.d_min;
+  a.K_out = p0.K_out;
+  a.row_stride = rs;
+  a.D = T0.D;
+  a.n_del = T0.n_del;
+  a.d_min = p0.d_min;
   a.M = (int32_t)M;
   a.n_tiles = (int32_t)n_tiles;
   a.deliver_blocks = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, n_tiles));
-  a.rate_bin_steps = p.rate_bin_steps;
-  a.rate_bins_cap = (int32_t)p.rate_bins_cap;
-  a.key0 = ia.key0;
-  a.key1 = ia.key1;
-  for (int q = 0; q < 2; ++q) {
-    a.Pm[q] = T.prop32[q][0];
-    a.Pc[q] = T.prop32[q][1];
-    a.PVc[q] = T.prop32[q][2];
-    a.Iterm[q] = T.prop32[q][3];
-    a.E[q] = (float)p.E[q];
-    a.Vth[q] = (float)p.V_th[q];
-    a.Vr[q] = (float)p.V_r[q];
-    a.alpha[q] = (float)p.alpha_c[q];
-    a.n_arp[q] = T.n_arp[q];
-    a.n_pois[q] = T.n_pois[q];
-    for (int x = 0; x < kMaxPois; ++x) a.pois[q][x] = T.pois[q][x];
-  }
-  a.inv2q = ldexpf(1.0f, -p.q_frac_bits);
-  a.two_q = ldexpf(1.0f, p.q_frac_bits);
-  a.spike_log_cap = p.spike_log_cap;
+  a.rate_bin_steps = p0.rate_bin_steps;
+  a.rate_bins_cap = (int32_t)p0.rate_bins_cap;
+  a.inv2q = ldexpf(1.0f, -p0.q_frac_bits);
+  a.two_q = ldexpf(1.0f, p0.q_frac_bits);
+  a.spike_log_cap = p0.spike_log_cap;
+  a.nets = nets;
+  a.tile_net = tile_net;
   a.V = V;
   a.c = c;
   a.ref = ref;
   a.slots = slots;
   a.tgt = tgt;
   a.w = w;
-  a.jxfix = jx;
   a.sfix = sfix;
   a.spk = spk;
   a.blk_cnt = blk_cnt;
@@ -254,7 +315,29 @@ int build_impl(dpsnn_net* n) {
   n->doff = doff;
   n->ctl = ctl;
   n->split_ok = n_tiles <= kMaxSplitTiles;
-  n->sched = (n->split_ok && N >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
+  n->sched = (n->split_ok && n->N_total >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
+  return DPSNN_OK;
+}
+
+int build_common(const dpsnn_params* p, const uint64_t* seeds, int32_t n_nets,
+                 dpsnn_net** out) {
+  if (!p || !seeds || !out || n_nets < 1) return DPSNN_E_INVAL;
+  *out = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<dpsnn_net> n(new dpsnn_net());
+  n->p.assign(p, p + n_nets);
+  n->seed.assign(seeds, seeds + n_nets);
+  n->free_fn = g_free;
+  n->alloc_ctx = g_ctx;
+  const int rc = build_impl(n.get());
+  if (rc != DPSNN_OK) {
+    (void)hipStreamSynchronize(n->stream);
+    release_all(n.get());
+    return rc;
+  }
+  n->build_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = n.release();
   return DPSNN_OK;
 }
 
@@ -271,23 +354,21 @@ int dpsnn_set_allocator(dpsnn_alloc_fn alloc, dpsnn_free_fn release, void* ctx) 
 }
 
 int dpsnn_build(const dpsnn_params* p, uint64_t seed, dpsnn_net** out) {
-  if (!p || !out) return DPSNN_E_INVAL;
-  *out = nullptr;
-  const auto t0 = std::chrono::steady_clock::now();
-  std::unique_ptr<dpsnn_net> n(new dpsnn_net());
-  n->p = *p;
-  n->seed = seed;
-  n->free_fn = g_free;
-  n->alloc_ctx = g_ctx;
-  const int rc = build_impl(n.get());
-  if (rc != DPSNN_OK) {
-    (void)hipStreamSynchronize(n->stream);
-    release_all(n.get());
-    return rc;
-  }
-  n->build_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  *out = n.release();
+  return build_common(p, &seed, 1, out);
+}
+
+int dpsnn_build_batch(const dpsnn_params* p, const uint64_t* seeds, int32_t n_nets,
+                      dpsnn_net** out) {
+  return build_common(p, seeds, n_nets, out);
+}
+
+int dpsnn_net_info(dpsnn_net* n, int32_t k, int64_t* base, int64_t* n_neurons,
+                   int64_t* module_base, int64_t* n_modules) {
+  if (!n || k < 0 || k >= (int32_t)n->p.size()) return DPSNN_E_INVAL;
+  if (base) *base = n->base[k];
+  if (n_neurons) *n_neurons = n->T[k].N;
+  if (module_base) *module_base = n->mbase[k];
+  if (n_modules) *n_modules = n->T[k].M;
   return DPSNN_OK;
 }
 
@@ -320,7 +401,7 @@ int ensure_graph(dpsnn_net* n) {
   HIP_OK(hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal));
   bool ok = true;
   for (int64_t k = 0; k < n->graph_steps && ok; ++k)
-    ok = launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, n->sched, (uint32_t)k,
+    ok = launch_step(n->sa, n->p[0].weight_dtype, n->p[0].acc_bits, n->sched, (uint32_t)k,
                      n->stream) == hipSuccess;
   if (ok) ok = launch_tick(n->sa, (uint32_t)n->graph_steps, 0, n->stream) == hipSuccess;
   const hipError_t e = hipStreamEndCapture(n->stream, &g);
@@ -360,8 +441,8 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
   if (!n || n_steps < 0) return DPSNN_E_INVAL;
   if (n_steps == 0) return DPSNN_OK;
   if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
-  const int64_t last_bin = (n->t + n_steps - 1) / n->p.rate_bin_steps;
-  if (last_bin - n->rate_first + 1 > n->p.rate_bins_cap) return DPSNN_E_RATES_FULL;
+  const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
+  if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
   // the fused schedule advances both spike-log bases: align them after split
   if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
     HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
@@ -378,7 +459,7 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
   const int64_t rest = n_steps - done;
   if (rest > 0) {
     for (int64_t k = 0; k < rest; ++k)
-      HIP_OK(launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, n->sched, (uint32_t)k,
+      HIP_OK(launch_step(n->sa, n->p[0].weight_dtype, n->p[0].acc_bits, n->sched, (uint32_t)k,
                          n->stream));
     HIP_OK(launch_tick(n->sa, (uint32_t)rest, 0, n->stream));
   }
@@ -421,8 +502,8 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
 int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
   if (!n || n_steps < 1 || !host_ms) return DPSNN_E_INVAL;
   if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
-  const int64_t last_bin = (n->t + n_steps - 1) / n->p.rate_bin_steps;
-  if (last_bin - n->rate_first + 1 > n->p.rate_bins_cap) return DPSNN_E_RATES_FULL;
+  const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
+  if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
   if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
     HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
   n->last_sched = n->sched;
@@ -433,14 +514,14 @@ int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
     hipEvent_t* e = &ev[(size_t)3 * k];
     if (hipEventRecord(e[0], n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
     if (n->sched == DPSNN_SCHED_SPLIT) {
-      if (launch_phase(n->sa, n->p.weight_dtype, n->p.acc_bits, 0, (uint32_t)k, n->stream) !=
+      if (launch_phase(n->sa, n->p[0].weight_dtype, n->p[0].acc_bits, 0, (uint32_t)k, n->stream) !=
               hipSuccess ||
           hipEventRecord(e[1], n->stream) != hipSuccess ||
-          launch_phase(n->sa, n->p.weight_dtype, n->p.acc_bits, 1, (uint32_t)k, n->stream) !=
+          launch_phase(n->sa, n->p[0].weight_dtype, n->p[0].acc_bits, 1, (uint32_t)k, n->stream) !=
               hipSuccess)
         rc = DPSNN_E_DEVICE;
     } else {
-      if (launch_step(n->sa, n->p.weight_dtype, n->p.acc_bits, n->sched, (uint32_t)k,
+      if (launch_step(n->sa, n->p[0].weight_dtype, n->p[0].acc_bits, n->sched, (uint32_t)k,
                       n->stream) != hipSuccess ||
           hipEventRecord(e[1], n->stream) != hipSuccess)
         rc = DPSNN_E_DEVICE;
@@ -477,7 +558,7 @@ int dpsnn_sync(dpsnn_net* n) {
   unsigned long long cnt = 0;
   const int rc = log_count(n, &cnt);
   if (rc != DPSNN_OK) return rc;
-  if ((int64_t)cnt > n->p.spike_log_cap) return DPSNN_E_SPIKELOG_FULL;
+  if ((int64_t)cnt > n->p[0].spike_log_cap) return DPSNN_E_SPIKELOG_FULL;
   return DPSNN_OK;
 }
 
@@ -488,8 +569,8 @@ int dpsnn_read_spikes(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_
   unsigned long long cnt = 0;
   const int rc = log_count(n, &cnt);
   if (rc != DPSNN_OK) return rc;
-  const bool overflow = (int64_t)cnt > n->p.spike_log_cap;
-  const int64_t have = std::min<int64_t>((int64_t)cnt, n->p.spike_log_cap);
+  const bool overflow = (int64_t)cnt > n->p[0].spike_log_cap;
+  const int64_t have = std::min<int64_t>((int64_t)cnt, n->p[0].spike_log_cap);
   *n_out = have;
   if (cap < have || (have > 0 && (!host_step || !host_id))) return DPSNN_OK;
   std::vector<int2> buf((size_t)have);
@@ -510,12 +591,12 @@ int dpsnn_read_spikes(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_
 int dpsnn_read_rates(dpsnn_net* n, uint32_t* host_counts, int64_t cap_bins, int64_t* n_bins) {
   if (!n || !n_bins || cap_bins < 0) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
-  const int64_t done = n->t / n->p.rate_bin_steps;
+  const int64_t done = n->t / n->p[0].rate_bin_steps;
   const int64_t nb = done - n->rate_first;
   *n_bins = nb;
   if (nb <= 0 || cap_bins < nb || !host_counts) return DPSNN_OK;
-  const int64_t per = (int64_t)n->T.M * 2;
-  const int64_t cap = n->p.rate_bins_cap;
+  const int64_t per = (int64_t)n->M_total * 2;
+  const int64_t cap = n->p[0].rate_bins_cap;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t src = (n->rate_first + b) % cap;
     HIP_OK(hipMemcpy(host_counts + b * per, n->sa.rates + src * per, (size_t)per * 4,
@@ -534,17 +615,19 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   HIP_OK(hipMemcpy(&ns, n->sa.n_spikes, 8, hipMemcpyDeviceToHost));
   memset(out, 0, sizeof(*out));
   out->t = n->t;
-  out->n_neurons = n->T.N;
-  out->n_modules = n->T.M;
-  out->n_synapses = n->T.N * n->p.K_out;
+  out->n_neurons = n->N_total;
+  out->n_modules = n->M_total;
+  out->n_synapses = n->N_total * n->p[0].K_out;
   out->n_spikes = (int64_t)ns;
-  out->n_events = (int64_t)ns * n->p.K_out;
+  out->n_events = (int64_t)ns * n->p[0].K_out;
   out->build_ms = n->build_ms;
   out->bytes_rows = n->bytes_rows;
   out->bytes_state = n->bytes_state;
   out->bytes_total = n->bytes_total;
   out->lds_bytes = n->sched == DPSNN_SCHED_SPLIT ? n->sa.n_tiles * 4 + 1024 : 1024 * 4 + 16;
-  out->reserved = n->sched;
+  out->schedule = n->sched;
+  out->n_index = n->N_index;
+  out->n_nets = (int32_t)n->p.size();
   return DPSNN_OK;
 }
 
@@ -573,7 +656,7 @@ const char* dpsnn_strerror(int code) {
 int dpsnn_read_state(dpsnn_net* n, float* V, float* c, uint8_t* ref) {
   if (!n) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
-  const size_t N = (size_t)n->T.N;
+  const size_t N = (size_t)n->N_index;
   if (V) HIP_OK(hipMemcpy(V, n->sa.V, N * 4, hipMemcpyDeviceToHost));
   if (c) HIP_OK(hipMemcpy(c, n->sa.c, N * 4, hipMemcpyDeviceToHost));
   if (ref) HIP_OK(hipMemcpy(ref, n->sa.ref, N, hipMemcpyDeviceToHost));
@@ -583,7 +666,7 @@ int dpsnn_read_state(dpsnn_net* n, float* V, float* c, uint8_t* ref) {
 int dpsnn_write_state(dpsnn_net* n, const float* V, const float* c, const uint8_t* ref) {
   if (!n) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
-  const size_t N = (size_t)n->T.N;
+  const size_t N = (size_t)n->N_index;
   if (V) HIP_OK(hipMemcpy(n->sa.V, V, N * 4, hipMemcpyHostToDevice));
   if (c) HIP_OK(hipMemcpy(n->sa.c, c, N * 4, hipMemcpyHostToDevice));
   if (ref) HIP_OK(hipMemcpy(n->sa.ref, ref, N, hipMemcpyHostToDevice));
@@ -593,11 +676,11 @@ int dpsnn_write_state(dpsnn_net* n, const float* V, const float* c, const uint8_
 int dpsnn_read_slots(dpsnn_net* n, int64_t* host_slots) {
   if (!n || !host_slots) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
-  const int64_t N = n->T.N, Np = n->T.N_pad;
-  const int ab = acc_bytes(n->p);
-  std::vector<unsigned char> buf((size_t)n->T.D * Np * ab);
+  const int64_t N = n->N_index, Np = n->N_pad;
+  const int ab = acc_bytes(n->p[0]);
+  std::vector<unsigned char> buf((size_t)n->T[0].D * Np * ab);
   HIP_OK(hipMemcpy(buf.data(), n->sa.slots, buf.size(), hipMemcpyDeviceToHost));
-  for (int64_t s = 0; s < n->T.D; ++s)
+  for (int64_t s = 0; s < n->T[0].D; ++s)
     for (int64_t i = 0; i < N; ++i) {
       const size_t at = (size_t)(s * Np + i);
       if (ab == 4) {
@@ -615,10 +698,10 @@ int dpsnn_read_slots(dpsnn_net* n, int64_t* host_slots) {
 
 int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tgt, void* host_w,
                     uint16_t* host_doff) {
-  if (!n || first < 0 || count < 0 || first + count > n->T.N) return DPSNN_E_INVAL;
+  if (!n || first < 0 || count < 0 || first + count > n->N_index) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
-  const int Ko = n->p.K_out, rs = n->T.row_stride, ds = n->T.doff_stride;
-  const int wb = w_bytes(n->p);
+  const int Ko = n->p[0].K_out, rs = n->T[0].row_stride, ds = n->doff_stride;
+  const int wb = w_bytes(n->p[0]);
   if (host_tgt && Ko > 0) {
     HIP_OK(hipMemcpy2D(host_tgt, (size_t)Ko * 4, n->sa.tgt + first * rs, (size_t)rs * 4,
                        (size_t)Ko * 4, (size_t)count, hipMemcpyDeviceToHost));
@@ -629,8 +712,8 @@ int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tg
                        static_cast<const unsigned char*>(n->sa.w) + (size_t)first * rs * wb,
                        (size_t)rs * wb, (size_t)Ko * wb, (size_t)count, hipMemcpyDeviceToHost));
   if (host_doff)
-    HIP_OK(hipMemcpy2D(host_doff, (size_t)(n->T.n_del + 1) * 2, n->doff + first * ds,
-                       (size_t)ds * 2, (size_t)(n->T.n_del + 1) * 2, (size_t)count,
+    HIP_OK(hipMemcpy2D(host_doff, (size_t)(n->T[0].n_del + 1) * 2, n->doff + first * ds,
+                       (size_t)ds * 2, (size_t)(n->T[0].n_del + 1) * 2, (size_t)count,
                        hipMemcpyDeviceToHost));
   return DPSNN_OK;
 }

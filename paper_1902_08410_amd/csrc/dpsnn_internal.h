@@ -57,28 +57,41 @@ int validate(const dpsnn_params& p);
 int compute_tables(const dpsnn_params& p, HostTables& T);
 int64_t host_table(const HostTables& T, const char* name, void* out, int64_t cap);
 
-// Arguments of the step kernels (passed by value).
-struct StepArgs {
-  int64_t N, N_pad;
-  int32_t K, K_exc, K_out, row_stride, D, n_del, d_min, M;
-  int32_t n_tiles;         // neuron tiles of 1024 = N_pad / 1024
-  int32_t deliver_blocks;  // grid of the delivery kernel
-  int32_t rate_bin_steps, rate_bins_cap;
-  uint32_t key0, key1;
+// Per-network constants, one entry per network of a handle (a batch of one
+// for dpsnn_build).  Networks are laid end to end in one global index space,
+// each padded to whole 1024-neuron tiles, so every tile belongs to exactly
+// one network and the step kernels read these fields with uniform loads.
+struct NetDev {
+  int64_t base;             // global index of the network's neuron 0
+  int64_t N;                // neurons of the network
+  int32_t mbase;            // global index of the network's module 0
+  int32_t K, K_exc;         // neurons and excitatory neurons per module
+  uint32_t key0, key1;      // Philox key (the network's seed)
   float Pm[2], Pc[2], PVc[2], Iterm[2], E[2], Vth[2], Vr[2], alpha[2];
   int32_t n_arp[2];
   int32_t n_pois[2];
   uint32_t pois[2][kMaxPois];
+  const void* jxfix;        // [2][65536] external fixed-point efficacies
+};
+
+// Arguments of the step kernels (passed by value).
+struct StepArgs {
+  int64_t N_pad;           // size of the global index space
+  int32_t K_out, row_stride, D, n_del, d_min, M;  // M: modules of all networks
+  int32_t n_tiles;         // neuron tiles of 1024 = N_pad / 1024
+  int32_t deliver_blocks;  // grid of the delivery kernel
+  int32_t rate_bin_steps, rate_bins_cap;
   float inv2q, two_q;
   int64_t spike_log_cap;
+  const NetDev* nets;
+  const int32_t* tile_net;  // [n_tiles] network of each tile
   float* V;
   float* c;
   uint8_t* ref;
   void* slots;
-  const int32_t* tgt;      // target | delay index << 26
+  const int32_t* tgt;      // global target | delay index << 26
   const void* w;
-  const void* jxfix;
-  const int64_t* sfix;     // [M][2], int8 format only
+  const int64_t* sfix;     // [M][2] int8 scale in fixed point (int8 format)
   int32_t* spk;            // [n_tiles][1024] spike ids of the step, per tile
   int32_t* blk_cnt;        // [n_tiles] spikes per tile
   int2* log;
@@ -90,6 +103,7 @@ struct StepArgs {
 
 struct GenArgs {
   int64_t N;
+  int64_t tgt_base;        // global index of the network's neuron 0
   int32_t K, K_exc, K_out, row_stride, doff_stride, n_del, d_min;
   int32_t W, H, n_off;
   int32_t n_local[2];
@@ -129,9 +143,13 @@ hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
 
 // The opaque handle of the C-ABI.
 struct dpsnn_net {
-  dpsnn_params p;
-  uint64_t seed = 0;
-  dpsnn::HostTables T;
+  std::vector<dpsnn_params> p;       // one per network; p[0] holds the
+                                     // parameters shared by the batch
+  std::vector<uint64_t> seed;
+  std::vector<dpsnn::HostTables> T;
+  std::vector<int64_t> base, mbase;  // global neuron / module offsets
+  int64_t N_total = 0, N_index = 0, N_pad = 0;
+  int32_t M_total = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   dpsnn_free_fn free_fn = nullptr;
@@ -143,6 +161,7 @@ struct dpsnn_net {
   int64_t rate_first = 0;      // first rate bin not yet drained
   dpsnn::StepArgs sa;
   uint16_t* doff = nullptr;    // delay offsets of the rows (inspection)
+  int32_t doff_stride = 0;
   unsigned char* ctl = nullptr;  // log bases, spike total, step counter
   int sched = DPSNN_SCHED_SPLIT;
   int last_sched = -1;

@@ -134,7 +134,8 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     const int64_t o = rb + pos;
     const int32_t tg = st_tgt[j];
     const uint16_t wi = st_w[j];
-    a.tgt[o] = tg | (k << kDelayShift);
+    const int32_t gt = tg + (int32_t)a.tgt_base;  // global target index
+    a.tgt[o] = gt | (k << kDelayShift);
     if (WDT == DPSNN_W_F32)
       static_cast<float*>(a.w)[o] = static_cast<const float*>(a.wtab[pop])[wi];
     else if (WDT == DPSNN_W_F16)
@@ -143,7 +144,7 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
       static_cast<int8_t*>(a.w)[o] = static_cast<const int8_t*>(a.wtab[pop])[wi];
     if (a.absum) {
       const int64_t f = a.wfix_tab[pop][wi];
-      atomicAdd(&a.absum[tg], (unsigned long long)(f < 0 ? -f : f));
+      atomicAdd(&a.absum[gt], (unsigned long long)(f < 0 ? -f : f));
     }
   }
   for (int j = Ko + lane; j < a.row_stride; j += 64) {
@@ -216,11 +217,13 @@ __device__ __forceinline__ Acc stored_to_fix(const void* w, int64_t o, float two
 }
 
 // ------------------------------------------------------------------------
-// Neuron update of the 4 neurons i0..i0+3 of one thread at step t.  Spiking
-// neurons are appended to the LDS list s_spk (count s_n).
+// Neuron update of the 4 neurons i0..i0+3 (global indices) of one thread at
+// step t; nd is the tile's network.  Spiking neurons are appended to the LDS
+// list s_spk (count s_n).  Counters of the random draws use the network's
+// own neuron indices, so a network in a batch draws what it draws alone.
 template <typename Acc>
-__device__ __forceinline__ void update4(const StepArgs& a, int64_t i0, uint32_t t,
-                                        int32_t* s_spk, int* s_n) {
+__device__ __forceinline__ void update4(const StepArgs& a, const NetDev& nd, int64_t i0,
+                                        uint32_t t, int32_t* s_spk, int* s_n) {
   const int slot = (int)(t % (uint32_t)a.D);
   Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
   Acc I[4];
@@ -242,28 +245,29 @@ __device__ __forceinline__ void update4(const StepArgs& a, int64_t i0, uint32_t 
   float cv[4] = {c4.x, c4.y, c4.z, c4.w};
 
   // external Poisson drive generated on the fly: counts from word j of
-  // (i0/4, t, EXT); efficacies 2b and 2b+1 of neuron j from word j of
-  // (i0/4, t, EXTJ | b << 8), high half then low half
-  const uint32_t g = (uint32_t)(i0 >> 2);
-  const uint4 u = philox10(make_uint4(g, t, 0u, kTagExt), a.key0, a.key1);
+  // (il0/4, t, EXT); efficacies 2b and 2b+1 of neuron j from word j of
+  // (il0/4, t, EXTJ | b << 8), high half then low half
+  const int64_t il0 = i0 - nd.base;  // network-local index, a multiple of 4
+  const uint32_t g = (uint32_t)(il0 >> 2);
+  const uint4 u = philox10(make_uint4(g, t, 0u, kTagExt), nd.key0, nd.key1);
   const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
-  const int64_t m0 = i0 / a.K;
-  const int l0 = (int)(i0 - m0 * a.K);
+  const int64_t m0 = il0 / nd.K;
+  const int l0 = (int)(il0 - m0 * nd.K);
   int q[4], k[4];
   int kmax = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
-    if (lj >= a.K) lj -= a.K;
-    q[j] = lj < a.K_exc ? 0 : 1;
+    if (lj >= nd.K) lj -= nd.K;
+    q[j] = lj < nd.K_exc ? 0 : 1;
     int kk = 0;
-    for (int x = 0; x < a.n_pois[q[j]]; ++x) kk += uu[j] >= a.pois[q[j]][x] ? 1 : 0;
+    for (int x = 0; x < nd.n_pois[q[j]]; ++x) kk += uu[j] >= nd.pois[q[j]][x] ? 1 : 0;
     k[j] = kk;
     kmax = kk > kmax ? kk : kmax;
   }
-  const Acc* jx = static_cast<const Acc*>(a.jxfix);
+  const Acc* jx = static_cast<const Acc*>(nd.jxfix);
   for (int b = 0; 2 * b < kmax; ++b) {
-    const uint4 v = philox10(make_uint4(g, t, 0u, kTagExtJ | ((uint32_t)b << 8)), a.key0, a.key1);
+    const uint4 v = philox10(make_uint4(g, t, 0u, kTagExtJ | ((uint32_t)b << 8)), nd.key0, nd.key1);
     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -277,27 +281,27 @@ __device__ __forceinline__ void update4(const StepArgs& a, int64_t i0, uint32_t 
   for (int j = 0; j < 4; ++j) {
     const int qq = q[j];
     uint32_t rj = (r4 >> (8 * j)) & 0xFFu;
-    if (i0 + j < a.N) {
+    if (il0 + j < nd.N) {
       const float dv = fix_to_f32(I[j]) * a.inv2q;
       float Vj = Vv[j], cj = cv[j];
       bool spk = false;
       if (rj > 0) {
         rj -= 1;
-        cj = cj * a.Pc[qq];
+        cj = cj * nd.Pc[qq];
       } else {
-        float vv = Vj - a.E[qq];
-        vv = vv * a.Pm[qq];
-        vv = a.E[qq] + vv;
-        const float cc = cj * a.PVc[qq];
+        float vv = Vj - nd.E[qq];
+        vv = vv * nd.Pm[qq];
+        vv = nd.E[qq] + vv;
+        const float cc = cj * nd.PVc[qq];
         vv = vv - cc;
-        vv = vv + a.Iterm[qq];
+        vv = vv + nd.Iterm[qq];
         vv = vv + dv;
-        cj = cj * a.Pc[qq];
-        if (vv > a.Vth[qq]) {
+        cj = cj * nd.Pc[qq];
+        if (vv > nd.Vth[qq]) {
           spk = true;
-          vv = a.Vr[qq];
-          cj = cj + a.alpha[qq];
-          rj = (uint32_t)a.n_arp[qq];
+          vv = nd.Vr[qq];
+          cj = cj + nd.alpha[qq];
+          rj = (uint32_t)nd.n_arp[qq];
         }
         Vj = vv;
       }
@@ -315,6 +319,16 @@ __device__ __forceinline__ void update4(const StepArgs& a, int64_t i0, uint32_t 
   *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
 }
 
+// Global module and population of a (global) neuron id.
+__device__ __forceinline__ void module_pop(const StepArgs& a, int32_t id, int32_t* mod,
+                                           int* pop) {
+  const NetDev& nd = a.nets[a.tile_net[id >> 10]];
+  const int32_t local = id - (int32_t)nd.base;
+  const int32_t m = local / nd.K;
+  *mod = nd.mbase + m;
+  *pop = (local - m * nd.K) < nd.K_exc ? 0 : 1;
+}
+
 // 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.
 template <typename Acc, int WDT>
 __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int p0,
@@ -322,8 +336,9 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
   const int64_t rb = (int64_t)s * a.row_stride;
   int64_t scale = 0;
   if (WDT == DPSNN_W_I8) {
-    const int32_t ms = s / a.K;
-    const int q = (s - ms * a.K) < a.K_exc ? 0 : 1;
+    int32_t ms;
+    int q;
+    module_pop(a, s, &ms, &q);
     scale = a.sfix[2 * ms + q];
   }
   const int p = p0 + lane * 4;
@@ -358,8 +373,9 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
                                              unsigned long long pos) {
   if (pos < (unsigned long long)a.spike_log_cap) a.log[pos] = make_int2((int)t, id);
   const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
-  const int32_t mod = id / a.K;
-  const int q = (id - mod * a.K) < a.K_exc ? 0 : 1;
+  int32_t mod;
+  int q;
+  module_pop(a, id, &mod, &q);
   atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * 2 + q], 1u);
 }
 
@@ -374,7 +390,8 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   __syncthreads();
   const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
-  if (i0 < a.N) update4<Acc>(a, i0, t, s_spk, &s_n);
+  const NetDev& nd = a.nets[a.tile_net[blockIdx.x]];
+  update4<Acc>(a, nd, i0, t, s_spk, &s_n);
   __syncthreads();
   const int n = s_n;
   int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
@@ -451,7 +468,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   __syncthreads();
   const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
-  if (i0 < a.N) update4<Acc>(a, i0, t, s_spk, &s_n);
+  const NetDev& nd = a.nets[a.tile_net[blockIdx.x]];
+  update4<Acc>(a, nd, i0, t, s_spk, &s_n);
   __syncthreads();
   const int n = s_n;
   if (n == 0) return;

@@ -43,7 +43,8 @@ class DpsnnStats(C.Structure):
         ("t", C.c_int64), ("n_neurons", C.c_int64), ("n_modules", C.c_int64),
         ("n_synapses", C.c_int64), ("n_spikes", C.c_int64), ("n_events", C.c_int64),
         ("build_ms", C.c_double), ("bytes_rows", C.c_int64), ("bytes_state", C.c_int64),
-        ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("reserved", C.c_int32),
+        ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("schedule", C.c_int32),
+        ("n_index", C.c_int64), ("n_nets", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -115,6 +116,9 @@ def lib():
             "dpsnn_set_graph_steps": ([V, C.c_int64], C.c_int),
             "dpsnn_autotune": ([V, C.c_int64, P(C.c_int32)], C.c_int),
             "dpsnn_profile_steps": ([V, C.c_int64, V], C.c_int),
+            "dpsnn_build_batch": ([P(DpsnnParams), P(C.c_uint64), C.c_int32, P(V)], C.c_int),
+            "dpsnn_net_info": ([V, C.c_int32, P(C.c_int64), P(C.c_int64), P(C.c_int64),
+                                P(C.c_int64)], C.c_int),
         }
         for fn, (args, res) in sig.items():
             f = getattr(L, fn)
@@ -128,7 +132,8 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_sync", "dpsnn_read_spikes", "dpsnn_read_rates", "dpsnn_stats_get",
            "dpsnn_free", "dpsnn_strerror", "dpsnn_read_state", "dpsnn_write_state",
            "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
-           "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps"]
+           "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps",
+           "dpsnn_build_batch", "dpsnn_net_info"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -185,17 +190,22 @@ def current_torch_stream():
 
 
 class Net:
-    """A built network (owns the C handle)."""
+    """A built handle (one network, or a batch of networks)."""
 
-    def __init__(self, handle, params: dict, seed: int):
+    def __init__(self, handle, params, seed):
         self.h = handle
-        self.params = dict(params)
-        self.seed = seed
+        plist = params if isinstance(params, (list, tuple)) else [params]
+        self.params_list = [dict(p) for p in plist]
+        self.params = self.params_list[0]
+        self.seeds = list(seed) if isinstance(seed, (list, tuple)) else [seed]
+        self.seed = self.seeds[0]
         st = self.stats()
-        self.N = int(st["n_neurons"])
+        self.n_neurons = int(st["n_neurons"])
+        self.N = int(st["n_index"])          # entries of the inspection arrays
         self.M = int(st["n_modules"])
-        self.D = int(params["d_max"]) + 1
-        self.n_del = int(params["d_max"]) - int(params["d_min"]) + 1
+        self.n_nets = int(st["n_nets"])
+        self.D = int(self.params["d_max"]) + 1
+        self.n_del = int(self.params["d_max"]) - int(self.params["d_min"]) + 1
 
     def stats(self) -> dict:
         return dpsnn_stats_get(self)
@@ -221,6 +231,26 @@ def dpsnn_build(params: dict, seed: int, stream=None, torch_memory: bool = True)
     net = Net(h, params, seed)
     dpsnn_set_stream(net, current_torch_stream() if stream is None else stream)
     return net
+
+
+def dpsnn_build_batch(params_list, seeds, stream=None, torch_memory: bool = True) -> Net:
+    if torch_memory:
+        use_torch_allocator(True)
+    n = len(params_list)
+    arr = (DpsnnParams * n)(*[to_struct(p) for p in params_list])
+    sd = (C.c_uint64 * n)(*[int(s) for s in seeds])
+    h = C.c_void_p()
+    _check("dpsnn_build_batch", lib().dpsnn_build_batch(arr, sd, n, C.byref(h)))
+    net = Net(h, list(params_list), list(seeds))
+    dpsnn_set_stream(net, current_torch_stream() if stream is None else stream)
+    return net
+
+
+def dpsnn_net_info(net: Net, k: int) -> dict:
+    v = [C.c_int64(0) for _ in range(4)]
+    _check("dpsnn_net_info", lib().dpsnn_net_info(net.h, int(k), *[C.byref(x) for x in v]))
+    return {"base": v[0].value, "n_neurons": v[1].value, "module_base": v[2].value,
+            "n_modules": v[3].value}
 
 
 def dpsnn_set_stream(net: Net, stream) -> None:

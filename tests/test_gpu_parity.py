@@ -297,3 +297,78 @@ def test_c1_graph_stream_two_seconds(L):
                 orc.step(5000)
                 _compare_all(L, net, orc, (sched, k))
         net.close()
+
+
+BATCH = [
+    (W.tiny(w=2, h=2, K=60, K_out=40, nu_ext_hz=[3500.0, 3500.0]), 101),
+    (W.tiny(w=3, h=2, K=60, K_out=40, gc=[0.002, 0.0], nu_ext_hz=[4000.0, 3000.0],
+            **{"lambda": 2.0}), 202),
+    (W.tiny(w=1, h=3, K=50, K_out=40, tau_c=[300.0, 300.0], Jext_mean=[1.0, 1.3],
+            nu_ext_hz=[3000.0, 3500.0]), 303),
+]
+
+
+def _split_spikes(L, net, st, ids):
+    out = []
+    for k in range(net.n_nets):
+        info = L.dpsnn_net_info(net, k)
+        sel = (ids >= info["base"]) & (ids < info["base"] + info["n_neurons"])
+        out.append((st[sel], ids[sel] - info["base"], info))
+    return out
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+def test_batch_matches_oracle_per_network(L, sched):
+    """Networks of different sizes, parameters and seeds advanced together
+    in one handle each reproduce their own oracle run bit for bit."""
+    _say("batch vs oracle", sched)
+    params = [dict(p, spike_log_cap=1 << 20, rate_bins_cap=256) for p, _ in BATCH]
+    seeds = [s for _, s in BATCH]
+    net = L.dpsnn_build_batch(params, seeds)
+    L.dpsnn_set_schedule(net, sched)
+    orcs = [O.Oracle(p, s) for p, s in zip(params, seeds)]
+    L.dpsnn_step(net, 1500)
+    for o in orcs:
+        o.step(1500)
+    st, ids = L.dpsnn_read_spikes(net)
+    V, c, r = L.dpsnn_read_state(net)
+    slots = L.dpsnn_read_slots(net)
+    rates = L.dpsnn_read_rates(net)
+    total = 0
+    for (s_k, i_k, info), o in zip(_split_spikes(L, net, st, ids), orcs):
+        ost, oids = o.spikes()
+        assert np.array_equal(s_k, ost) and np.array_equal(i_k, oids)
+        b, n = info["base"], info["n_neurons"]
+        oV, oc, orr = o.state()
+        assert np.array_equal(V[b:b + n].astype(np.float64), oV)
+        assert np.array_equal(c[b:b + n].astype(np.float64), oc)
+        assert np.array_equal(r[b:b + n].astype(np.int32), orr)
+        assert np.array_equal(slots[:, b:b + n], o.ring())
+        mb, m = info["module_base"], info["n_modules"]
+        assert np.array_equal(rates[:, mb:mb + m, :], o.rates()[:rates.shape[0]])
+        total += len(ost)
+    assert total > 300 and len(st) == total
+    net.close()
+
+
+def test_batch_matches_solo_runs(L):
+    """A batch of larger networks (uneven sizes, adaptation and lambda
+    swept) against each network built and run alone on the GPU."""
+    _say("batch vs solo")
+    plist = [W.grid(4, 4, "swa", **{"gc": [0.02, 0.0], "lambda": 1.0, "weight_dtype": "f16"}),
+             W.grid(2, 6, "swa", **{"gc": [0.002, 0.0], "lambda": 2.0, "weight_dtype": "f16"}),
+             W.grid(3, 3, "swa", **{"gc": [0.0063, 0.0], "lambda": 2.0, "weight_dtype": "f16"})]
+    plist = [dict(p, spike_log_cap=1 << 22, rate_bins_cap=256) for p in plist]
+    seeds = [11, 12, 13]
+    net = L.dpsnn_build_batch(plist, seeds)
+    L.dpsnn_step(net, 3000)
+    st, ids = L.dpsnn_read_spikes(net)
+    parts = _split_spikes(L, net, st, ids)
+    for (s_k, i_k, info), p, sd in zip(parts, plist, seeds):
+        solo = L.dpsnn_build(p, sd)
+        L.dpsnn_step(solo, 3000)
+        ss, si = L.dpsnn_read_spikes(solo)
+        assert np.array_equal(s_k, ss) and np.array_equal(i_k, si)
+        assert len(ss) > 1000
+        solo.close()
+    net.close()
