@@ -1,13 +1,18 @@
 """Benchmark: synaptic events per second on one MI355X.
 
-Workload (the configuration the metric is quoted on): a 24x24 grid of
-modules of 1250 LIF-SFA neurons (720k neurons, 0.72G synapses, out-degree
-1000, half local, Eq. 1 remote connectivity with lambda = 1 on a torus,
-delays 1-20 steps of 0.1 ms), FP32 efficacies, int32 fixed-point input
-slots; one slow-wave (SWA) and one asynchronous-wake (AW) network advance
-side by side.  One benchmark step = 1 s of biological time (10 000 steps
-of dt) of both networks.  Inputs are synthetic and seeded; the networks are
-built (connectivity generated on the device) before the timed region.
+Default workload (the configuration the metric is quoted on): a 24x24 grid
+of modules of 1250 LIF-SFA neurons (720k neurons, 0.72G synapses,
+out-degree 1000, half local, Eq. 1 remote connectivity with lambda = 1 on a
+torus, delays 1-20 steps of 0.1 ms), FP32 efficacies, int32 fixed-point
+input slots; one slow-wave (SWA) and one asynchronous-wake (AW) network
+advance side by side.  One benchmark step = 1 s of biological time (10 000
+steps of dt) of both networks.  Inputs are synthetic and seeded; the
+networks are built (connectivity generated on the device) before the timed
+region.
+
+Other workloads: --workload c4 (64 networks of 4x4 to 16x16 modules in one
+batched handle, FP16 efficacies), --workload c5 (96x96 modules, 11.52M
+neurons, int8 efficacies, int64 slots).
 
 Prints one JSON line.
 """
@@ -135,12 +140,51 @@ def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def build_workload(name, dpsnn, workloads, total_bins):
+    """Handles of the workload: {label: (handle, params of its first net)}."""
+    if name == "c2":
+        regs = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
+    elif name == "c5":
+        regs = {"swa": workloads.c5("swa"), "aw": workloads.c5("aw")}
+    else:
+        regs = None
+    nets = {}
+    if regs is not None:
+        for label, p in regs.items():
+            p.update(spike_log_cap=0, rate_bins_cap=total_bins)
+            nets[label] = (dpsnn.dpsnn_build(p, 1), p)
+            progress(f"built {label}: {nets[label][0].stats()['build_ms']:.0f} ms")
+    else:
+        plist, seeds = workloads.sweep_c4()
+        for p in plist:
+            p.update(spike_log_cap=0, rate_bins_cap=total_bins)
+        nets["sweep"] = (dpsnn.dpsnn_build_batch(plist, seeds), plist[0])
+        progress(f"built sweep of {len(plist)}: {nets['sweep'][0].stats()['build_ms']:.0f} ms")
+    return nets
+
+
+DESCRIPTIONS = {
+    "c2": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
+           "SWA + AW networks, FP32 efficacies, int32 fixed-point slots"),
+    "c4": ("batched sweep: 64 networks of 4x4..16x16 modules (9.5M neurons, 9.5G synapses), "
+           "g_c log-uniform 0.002-0.02, lambda 1 or 2, FP16 efficacies, int32 slots, "
+           "one handle"),
+    "c5": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
+           "SWA + AW networks, int8 efficacies with per-module scale, int64 fixed-point "
+           "slots (Q = 32)"),
+}
+DTYPES = {"c2": "f32", "c4": "f16", "c5": "i8"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed steps of 1 s biological")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 10 for c2, 2 for c4/c5)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dt-steps", type=int, default=10000, help="dt steps per bench step")
+    ap.add_argument("--dt-steps", type=int, default=None,
+                    help="dt steps per bench step (default 10000 = 1 s; 2000 for c4/c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--autotune", type=int, default=1)
@@ -151,7 +195,8 @@ def main():
                     help="fold rocprofv3 CSV directories into per-launch traffic figures")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps timed per kernel with events for the roofline")
-    ap.add_argument("--variants", type=int, default=1, help="also time FP16 and int8 weights")
+    ap.add_argument("--variants", type=int, default=1,
+                    help="c2: also time FP16 and int8 efficacies")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof)
@@ -160,6 +205,11 @@ def main():
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    wl = args.workload
+    steps = args.steps if args.steps is not None else (10 if wl == "c2" else 2)
+    S = args.dt_steps if args.dt_steps is not None else (10000 if wl == "c2" else 2000)
+    if wl != "c2":
+        args.profile_steps = min(args.profile_steps, 200)
 
     import torch
     from paper_1902_08410_amd import dpsnn, workloads
@@ -177,58 +227,49 @@ def main():
         print(json.dumps({"calibration_copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
         return
     stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
-    S = args.dt_steps
-    total_bins = (args.warmup + args.steps) * S // 50 + 400   # + autotune/profile steps
-    regimes = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
-    nets = {}
-    build_ms = {}
+    total_bins = (args.warmup + steps) * S // 50 + 400   # + autotune/profile steps
     sched = {}
+    variants = {}
     with torch.cuda.stream(stream):
-        for name, p in regimes.items():
-            p.update(spike_log_cap=0, rate_bins_cap=total_bins)
-            nets[name] = dpsnn.dpsnn_build(p, 1)
-            build_ms[name] = nets[name].stats()["build_ms"]
-            progress(f"built {name}: {build_ms[name]:.0f} ms")
+        nets = build_workload(wl, dpsnn, workloads, total_bins)
         for _ in range(args.warmup):
-            for net in nets.values():
-                dpsnn.dpsnn_step(net, S)
-        for name, net in nets.items():
-            sched[name] = dpsnn.dpsnn_autotune(net, 1000) if args.autotune else \
-                net.stats()["schedule"]
+            for h, _ in nets.values():
+                dpsnn.dpsnn_step(h, S)
+        for name, (h, _) in nets.items():
+            sched[name] = (dpsnn.dpsnn_autotune(h, min(1000, S // 2)) if args.autotune
+                           else h.stats()["schedule"])
         torch.cuda.synchronize()
         progress("warmup done")
-        sp0 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
+        sp0 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0.record(stream)
-        for k in range(args.steps):
-            for net in nets.values():
-                dpsnn.dpsnn_step(net, S)
-            if k % 5 == 4:
-                progress(f"enqueued timed step {k + 1}")
+        for k in range(steps):
+            for h, _ in nets.values():
+                dpsnn.dpsnn_step(h, S)
+            progress(f"enqueued timed step {k + 1}")
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         gpu_ms = ev0.elapsed_time(ev1)
-        sp1 = {k: n.stats()["n_spikes"] for k, n in nets.items()}
-        # per-kernel times over further real steps (events around each kernel)
+        sp1 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
         progress("timed region done")
+        # per-kernel times over further real steps (events around each kernel)
         prof = {}
-        for name, net in nets.items():
+        for name, (h, _) in nets.items():
             if args.profile_steps <= 0:
                 continue
-            dpsnn.dpsnn_set_schedule(net, dpsnn.SCHED_SPLIT)
-            s_a = net.stats()["n_spikes"]
-            upd_ms, del_ms = dpsnn.dpsnn_profile_steps(net, args.profile_steps)
-            prof[name] = (upd_ms, del_ms, (net.stats()["n_spikes"] - s_a) * K_OUT)
-        # the same workload with binary16 and int8 stored efficacies
-        variants = {}
-        if args.variants:
+            dpsnn.dpsnn_set_schedule(h, dpsnn.SCHED_SPLIT)
+            s_a = h.stats()["n_spikes"]
+            upd_ms, del_ms = dpsnn.dpsnn_profile_steps(h, args.profile_steps)
+            prof[name] = (upd_ms, del_ms, (h.stats()["n_spikes"] - s_a) * K_OUT)
+        progress("kernel timing done")
+        if wl == "c2" and args.variants:
             for wd in ("f16", "i8"):
                 for reg in ("swa", "aw"):
-                    q = dict(regimes[reg], weight_dtype=wd)
+                    q = dict(nets[reg][1], weight_dtype=wd)
                     vn = dpsnn.dpsnn_build(q, 1)
                     dpsnn.dpsnn_step(vn, S)
                     torch.cuda.synchronize()
@@ -246,14 +287,13 @@ def main():
     spikes = {k: sp1[k] - sp0[k] for k in nets}
     events = sum(spikes.values()) * K_OUT
     value = events / wall
-    n_launch = args.steps * S * len(nets)   # steps of dt
-    N = nets["swa"].N
-    p0 = regimes["swa"]
+    n_steps_all = steps * S * len(nets)
+    p0 = next(iter(nets.values()))[1]
     Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
-    sim_s = args.steps * S * 0.1e-3
-    rates = {k: spikes[k] / N / sim_s for k in nets}
-    # dominant kernel: the delivery kernel (most of the step time)
-    n_prof = max(1, args.profile_steps * len(nets))
+    neurons = {k: h.stats()["n_neurons"] for k, (h, _) in nets.items()}
+    sim_s = steps * S * 0.1e-3
+    rates = {k: spikes[k] / neurons[k] / sim_s for k in nets}
+    n_prof = max(1, args.profile_steps * len(prof))
     del_ms = sum(v[1] for v in prof.values())
     upd_ms = sum(v[0] for v in prof.values())
     prof_events = sum(v[2] for v in prof.values())
@@ -262,34 +302,33 @@ def main():
     ev_per_launch = prof_events / n_prof
     alg_del = ev_per_launch * Be
     achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
+    n_mean = sum(neurons.values()) / len(neurons)
     traffic = None
-    rec = recorded_traffic()
+    rec = recorded_traffic() if wl == "c2" else None
     if rec and "k_deliver" in rec["kernels"]:
         traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"]
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(regimes["swa"], nets["swa"], dpsnn, 400, args.cpu_budget)
+    if wl == "c2" and not args.no_cpu_baseline:
+        cpu = cpu_baseline(nets["swa"][1], nets["swa"][0], dpsnn, 400, args.cpu_budget)
 
     out = {
         "metric": "synaptic events/sec on 1 MI355X (SWA & AW), FP16/int8 vs FP32 weights",
         "value": value,
         "unit": "synaptic events/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": wall * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPES[wl],
         "data": "synthetic",
         "config": {
-            "workload": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G "
-                         "synapses), lambda 1, SWA + AW networks, FP32 efficacies, "
-                         "int32 fixed-point slots"),
-            "bench_step": f"{S} steps of dt = 0.1 ms (1 s biological) of each network",
-            "neurons_per_network": N,
-            "networks": list(nets),
+            "workload": DESCRIPTIONS[wl],
+            "bench_step": f"{S} steps of dt = 0.1 ms ({S * 1e-4:g} s biological) of every network",
+            "neurons": neurons,
+            "handles": list(nets),
         },
         "roofline": {
             "bound": "hbm",
@@ -306,17 +345,18 @@ def main():
             "atomic_rate_G_per_s": ev_per_launch / del_us / 1e3 if del_us > 0 else None,
             "atomic_ceiling_G_per_s": 27.0,
             "update_kernel": {"kernel": "k_neuron", "avg_launch_us": upd_us,
-                              "algorithmic_bytes_per_launch": N * Bn,
-                              "achieved_GB_s": N * Bn / (upd_us * 1e-6) / 1e9 if upd_us else None,
+                              "algorithmic_bytes_per_launch": n_mean * Bn,
+                              "achieved_GB_s": n_mean * Bn / (upd_us * 1e-6) / 1e9
+                              if upd_us else None,
                               "bytes_per_neuron_step": Bn},
-            "step_us": gpu_ms * 1e3 / n_launch,
+            "step_us": gpu_ms * 1e3 / (n_steps_all / max(1, len(nets))) / max(1, len(nets)),
         },
         "cpu_baseline": cpu,
-        "per_regime": {k: {"spikes": spikes[k], "rate_hz": rates[k],
+        "per_handle": {k: {"spikes": spikes[k], "rate_hz": rates[k],
                            "events_per_s": spikes[k] * K_OUT / wall,
-                           "build_ms": build_ms[k]} for k in nets},
+                           "build_ms": nets[k][0].stats()["build_ms"],
+                           "schedule": "split" if sched[k] == 1 else "fused"} for k in nets},
         "gpu_ms_timed": gpu_ms,
-        "schedule": {k: ("split" if v == 1 else "fused") for k, v in sched.items()},
         "weight_variants": variants,
     }
     print(json.dumps(out), flush=True)

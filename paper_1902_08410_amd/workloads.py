@@ -71,3 +71,23 @@ CONFIGS = {
                        for r in ("swa", "aw")],
                seeds=[1], steps=20000),
 }
+
+
+def sweep_c4(n: int = 64, seed: int = 1):
+    """Batched sweep: n networks, grids uniform in {4x4, 8x8, 12x12, 16x16}
+    modules, adaptation g_c/C_m log-uniform on [0.002, 0.02] 1/ms (AW to
+    SWA), lambda in {1, 2}, binary16 efficacies.  Returns (params, seeds)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sides = rng.choice([4, 8, 12, 16], size=n)
+    gcs = np.exp(rng.uniform(np.log(0.002), np.log(0.02), size=n))
+    lams = rng.choice([1.0, 2.0], size=n)
+    params = [swa(grid_w=int(s), grid_h=int(s), gc=[float(g), 0.0], weight_dtype="f16",
+                  **{"lambda": float(lam)}) for s, g, lam in zip(sides, gcs, lams)]
+    return params, list(range(1, n + 1))
+
+
+def c5(regime: str) -> dict:
+    """96x96 grid (11.52M neurons), lambda = 2, int8 efficacies, int64 slots."""
+    return grid(96, 96, regime, **{"lambda": 2.0, "weight_dtype": "i8",
+                                   "acc_bits": 64, "q_frac_bits": 32})

@@ -1,0 +1,123 @@
+"""Error of the binary32 / binary16 / int8 efficacy paths against the binary64
+oracle (EXACT64 mode: unrounded efficacies, binary64 sums and state).
+
+Long runs: config 1 (2x2 grid of 1250-neuron modules), SWA and AW, seeds
+1-5, 2 s each; statistics after a 0.5 s transient are compared with the
+oracle's, stored in tests/golden/fp64_stats_c1.json (written by
+tests/golden/make_fp64_stats.py from the oracle only):
+  - mean excitatory and inhibitory rates within max(5 %, 2 sigma_seed),
+  - burst (population up-state) frequency within max(10 %, 2 sigma_seed),
+  - per-neuron rate distribution: KS distance within max(0.05, the largest
+    seed-to-seed KS distance of the binary64 runs).
+Short horizon: membrane potentials of every neuron at every step, before
+the first spike that differs from the binary64 run.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1902_08410_amd import analysis
+from paper_1902_08410_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp64_stats_c1.json")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_08410_amd import dpsnn
+    dpsnn.lib()
+    return dpsnn
+
+
+def _regime(r):
+    return W.swa() if r == "swa" else W.aw()
+
+
+@pytest.mark.parametrize("wd", ["f32", "f16", "i8"])
+def test_long_run_statistics_vs_fp64(L, wd):
+    gold = json.load(open(GOLD))
+    steps, seeds = gold["steps"], gold["seeds"]
+    jobs = [(r, s) for r in ("swa", "aw") for s in seeds]
+    _say("precision long runs", wd)
+    plist = [dict(_regime(r), weight_dtype=wd, spike_log_cap=1 << 24, rate_bins_cap=512)
+             for r, _ in jobs]
+    net = L.dpsnn_build_batch(plist, [s for _, s in jobs])
+    L.dpsnn_step(net, steps)
+    st, ids = L.dpsnn_read_spikes(net)
+    rates = L.dpsnn_read_rates(net)
+    got = {"swa": {}, "aw": {}}
+    for k, (r, s) in enumerate(jobs):
+        info = L.dpsnn_net_info(net, k)
+        b, n = info["base"], info["n_neurons"]
+        mb, m = info["module_base"], info["n_modules"]
+        sel = (ids >= b) & (ids < b + n)
+        p = plist[k]
+        got[r][s] = analysis.summary(rates[:, mb:mb + m, :], st[sel], ids[sel] - b, n,
+                                     p["K"], round(p["frac_exc"] * p["K"]),
+                                     p["rate_bin_steps"] * p["dt_ms"], p["dt_ms"], steps)
+    net.close()
+    report = {}
+    for r in ("swa", "aw"):
+        ref = [gold["runs"][r][str(s)] for s in seeds]
+        mine = [got[r][s] for s in seeds]
+        for key, rel in (("rate_exc_hz", 0.05), ("rate_inh_hz", 0.05), ("burst_freq_hz", 0.10)):
+            a = np.array([x[key] for x in ref])
+            b = np.array([x[key] for x in mine])
+            tol = max(rel * a.mean(), 2 * a.std(ddof=1))
+            report[(r, key)] = (b.mean(), a.mean(), tol)
+            assert abs(b.mean() - a.mean()) <= tol, (wd, r, key, b.mean(), a.mean(), tol)
+        ha = [np.array(x["count_hist"]) for x in ref]
+        hb = [np.array(x["count_hist"]) for x in mine]
+        seed_ks = max(analysis.ks_from_hists(ha[i], ha[j])
+                      for i in range(len(ha)) for j in range(i + 1, len(ha)))
+        pool = lambda hs: sum(np.pad(h, (0, 4000 - len(h))) for h in hs)  # noqa: E731
+        ks = analysis.ks_from_hists(pool(hb), pool(ha))
+        report[(r, "ks")] = (ks, 0.0, max(0.05, seed_ks))
+        assert ks <= max(0.05, seed_ks), (wd, r, ks, seed_ks)
+    for k, v in report.items():
+        print(f"[precision {wd}] {k[0]} {k[1]}: gpu {v[0]:.4f} fp64 {v[1]:.4f} tol {v[2]:.4f}",
+              flush=True)
+
+
+@pytest.mark.parametrize("wd", ["f32", "f16", "i8"])
+def test_short_horizon_membrane_error_vs_fp64(L, wd):
+    """Max and RMS |V - V_fp64| over all neurons at each step until the first
+    spike raster difference (config 1, SWA, seed 1)."""
+    p = dict(W.swa(), weight_dtype=wd, spike_log_cap=1 << 20, rate_bins_cap=64)
+    _say("short horizon", wd)
+    net = L.dpsnn_build(p, 1)
+    ref = O.Oracle(p, 1, mode=O.EXACT64)
+    worst, rms, steps_ok = 0.0, 0.0, 0
+    bound = {"f32": 2e-3, "f16": 5e-2, "i8": 0.5}[wd]
+    for t in range(200):
+        L.dpsnn_step(net, 1)
+        ref.step(1)
+        st, ids = L.dpsnn_read_spikes(net)
+        ost, oids = ref.spikes()
+        ost, oids = ost[ost == t], oids[ost == t]
+        if len(ids) != len(oids) or not np.array_equal(ids, oids):
+            break
+        V, _, _ = L.dpsnn_read_state(net)
+        oV, _, _ = ref.state()
+        d = np.abs(V.astype(np.float64) - oV)
+        worst = max(worst, float(d.max()))
+        rms = max(rms, float(np.sqrt((d * d).mean())))
+        steps_ok += 1
+    net.close()
+    print(f"[precision {wd}] short horizon: {steps_ok} steps before the first raster "
+          f"difference, max |dV| {worst:.3e} mV, max RMS {rms:.3e} mV", flush=True)
+    assert steps_ok >= 3
+    assert worst < bound
