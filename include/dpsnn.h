@@ -17,7 +17,13 @@
  * the spikes, and pushes each spike along its synapse row into per-target
  * input slots indexed by the arrival step (the per-delay input queues of
  * Sec. 2.1.1, steps 3-4).  Inputs are summed in fixed point, so the order
- * in which concurrent additions land cannot change any result.
+ * in which concurrent additions land cannot change any result.  Rows are
+ * stored sorted by target, so the events of a spike to one 1024-neuron tile
+ * are contiguous: delivery reserves room for each such run in the tile's
+ * inbox with one atomic and appends the events; in the next step the tile
+ * moves them into its per-slot queues, and sums the queue of the current
+ * slot when it reaches it.  Events that find a queue full are added into
+ * the slot directly.
  *
  * Conventions for every entry point:
  *  - return 0 on success or a negative DPSNN_E_* code;
@@ -38,7 +44,7 @@
 extern "C" {
 #endif
 
-#define DPSNN_ABI_VERSION 1u
+#define DPSNN_ABI_VERSION 2u
 
 /* Error codes. */
 #define DPSNN_OK 0
@@ -95,6 +101,14 @@ typedef struct dpsnn_params {
   int32_t rate_bin_steps;              /* steps per rate bin [50 = 5 ms]    */
   int64_t spike_log_cap;               /* device spike-log entries; 0 = off */
   int64_t rate_bins_cap;               /* device rate bins kept [>= 1]      */
+  int32_t queue_cap;                   /* entries of each per-(tile, slot)
+                                          input queue; each tile's inbox per
+                                          step holds twice as many.  0 =
+                                          default (4096, less if the queues
+                                          would pass 16 GiB), -1 = no queues
+                                          (every event is an atomic add into
+                                          its slot), else 1 .. 2^20.  Results
+                                          do not depend on it.              */
 } dpsnn_params;
 
 typedef struct dpsnn_stats {
@@ -113,7 +127,7 @@ typedef struct dpsnn_stats {
   int64_t n_index;        /* entries of the inspection arrays: the global
                              index space of all networks (see below)      */
   int32_t n_nets;         /* networks in the handle                        */
-  int32_t reserved;
+  int32_t queue_cap;      /* entries per input queue in use (0 = none)   */
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */
@@ -232,16 +246,17 @@ int dpsnn_write_state(dpsnn_net* net, const float* host_V,
                       const float* host_c, const uint8_t* host_ref);
 
 /* Input slots: D = d_max + 1 slots of stats.n_index fixed-point values,
- * slot-major, as int64 whatever the device width. */
+ * slot-major, as int64 whatever the device width.  Pending local-queue
+ * entries are folded into the slots first (the sums are unchanged). */
 int dpsnn_read_slots(dpsnn_net* net, int64_t* host_slots);
 
 /* Synapse rows first..first+count-1 (Eq. 1 targets, stored efficacies,
- * delay offsets): host_tgt int32 [count][K_out]; host_w [count][K_out] of
- * the stored format (float / binary16 bits / int8 code); host_doff uint16
- * [count][d_max - d_min + 2] with doff[k] = first position of delay
- * d_min + k.  Any pointer may be NULL. */
+ * delays), each sorted by (target, delay, draw index j): host_tgt int32
+ * [count][K_out]; host_w [count][K_out] of the stored format (float /
+ * binary16 bits / int8 code); host_dk uint8 [count][K_out] = delay - d_min.
+ * Any pointer may be NULL. */
 int dpsnn_read_rows(dpsnn_net* net, int64_t first, int64_t count,
-                    int32_t* host_tgt, void* host_w, uint16_t* host_doff);
+                    int32_t* host_tgt, void* host_w, uint8_t* host_dk);
 
 /* Host table computed from p without any device (named arrays, see the
  * library source); returns the size in bytes, or a negative code. */

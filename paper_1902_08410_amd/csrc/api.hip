@@ -97,14 +97,11 @@ int build_impl(dpsnn_net* n) {
   const int64_t Np = n->N_pad, M = gm;
   const int ab = acc_bytes(p0), wb = w_bytes(p0);
   const int rs = T0.row_stride;
-  n->doff_stride = T0.doff_stride;
-  const int ds = T0.doff_stride;
 
   // ---- device memory
   int32_t* tgt = (int32_t*)dev_alloc(n, (size_t)Np * rs * 4);
   void* w = dev_alloc(n, (size_t)Np * rs * wb);
-  uint16_t* doff = (uint16_t*)dev_alloc(n, (size_t)Np * ds * 2);
-  n->bytes_rows = Np * rs * (4 + wb) + Np * ds * 2;
+  n->bytes_rows = Np * rs * (4 + wb);
   float* V = (float*)dev_alloc(n, (size_t)Np * 4);
   float* c = (float*)dev_alloc(n, (size_t)Np * 4);
   uint8_t* ref = (uint8_t*)dev_alloc(n, (size_t)Np);
@@ -119,7 +116,7 @@ int build_impl(dpsnn_net* n) {
   unsigned char* ctl = (unsigned char*)dev_alloc(n, 256);
   unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p0.rate_bins_cap * M * 2 * 4);
   int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * 2 * 8);
-  if (!tgt || !w || !doff || !V || !c || !ref || !slots || !spk || !blk_cnt || !tile_net ||
+  if (!tgt || !w || !V || !c || !ref || !slots || !spk || !blk_cnt || !tile_net ||
       !nets || !log || !ctl || !rates || !sfix)
     return DPSNN_E_NOMEM;
   HIP_OK(hipMemsetAsync(slots, 0, (size_t)T0.D * Np * ab, st));
@@ -221,7 +218,6 @@ int build_impl(dpsnn_net* n) {
     ga.K_exc = T.K_exc;
     ga.K_out = p.K_out;
     ga.row_stride = rs;
-    ga.doff_stride = ds;
     ga.n_del = T.n_del;
     ga.d_min = p.d_min;
     ga.W = p.grid_w;
@@ -237,7 +233,6 @@ int build_impl(dpsnn_net* n) {
     ga.wtab[1] = wtab[1];
     ga.tgt = tgt + b * rs;
     ga.w = static_cast<unsigned char*>(w) + (size_t)b * rs * wb;
-    ga.doff = doff + b * ds;
     ga.absum = absum;
     ga.wfix_tab[0] = wfix_dev;
     ga.wfix_tab[1] = wfix_dev ? wfix_dev + kQuantN : nullptr;
@@ -312,8 +307,37 @@ int build_impl(dpsnn_net* n) {
   a.n_spikes = reinterpret_cast<unsigned long long*>(ctl + 16);
   a.t_base = reinterpret_cast<uint32_t*>(ctl + 32);
   a.rates = rates;
-  n->doff = doff;
   n->ctl = ctl;
+
+  // event queues: per tile an inbox for each step parity (2 x cap entries)
+  // and one queue per slot (cap entries); none for more than 128 slots; the
+  // default capacity shrinks so that the queues stay within 16 GiB
+  int64_t qcap = p0.queue_cap == 0 ? kQueueDefaultCap
+                 : p0.queue_cap < 0 ? 0 : p0.queue_cap;
+  if (p0.K_out == 0 || T0.D > kQueueMaxSlots) qcap = 0;
+  const int64_t per_cap = (int64_t)n_tiles * (T0.D + 4) * (ab == 4 ? 8 : 16);  // bytes per unit of cap
+  if (p0.queue_cap == 0 && qcap > 0) {
+    const int64_t budget = (int64_t)16 << 30;
+    qcap = std::min(qcap, budget / std::max<int64_t>(per_cap, 1));
+    if (qcap < 64) qcap = 0;
+  }
+  if (qcap > 0) {
+    a.q_cap = (int32_t)qcap;
+    a.in_cap = (int32_t)(2 * qcap);
+    const size_t eb = ab == 4 ? sizeof(QEntry<int32_t>) : sizeof(QEntry<int64_t>);
+    const size_t n_in = (size_t)2 * n_tiles * a.in_cap;
+    const size_t n_q = (size_t)n_tiles * T0.D * qcap;
+    a.in_cnt = (uint32_t*)dev_alloc(n, (size_t)2 * n_tiles * kInboxStride * 4);
+    a.in_q = dev_alloc(n, n_in * eb);
+    a.q_cnt = (uint32_t*)dev_alloc(n, (size_t)n_tiles * T0.D * 4);
+    a.q_q = dev_alloc(n, n_q * eb);
+    if (!a.in_cnt || !a.in_q || !a.q_cnt || !a.q_q) return DPSNN_E_NOMEM;
+    HIP_OK(hipMemsetAsync(a.in_cnt, 0, (size_t)2 * n_tiles * kInboxStride * 4, st));
+    HIP_OK(hipMemsetAsync(a.q_cnt, 0, (size_t)n_tiles * T0.D * 4, st));
+    HIP_OK(hipStreamSynchronize(st));
+    n->bytes_state += (int64_t)((n_in + n_q) * eb) +
+                      (2 * n_tiles * kInboxStride + n_tiles * T0.D) * 4;
+  }
   n->split_ok = n_tiles <= kMaxSplitTiles;
   n->sched = (n->split_ok && n->N_total >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
   return DPSNN_OK;
@@ -624,10 +648,16 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->bytes_rows = n->bytes_rows;
   out->bytes_state = n->bytes_state;
   out->bytes_total = n->bytes_total;
-  out->lds_bytes = n->sched == DPSNN_SCHED_SPLIT ? n->sa.n_tiles * 4 + 1024 : 1024 * 4 + 16;
+  {
+    const int ab = acc_bytes(n->p[0]);
+    out->lds_bytes = n->sched == DPSNN_SCHED_SPLIT
+                         ? n->sa.n_tiles * 4 + 1024 + 4 * 256 * 4
+                         : 1024 * 4 + 1024 * ab + kQueueMaxSlots * 4 + 4 * 256 * 4 + 16;
+  }
   out->schedule = n->sched;
   out->n_index = n->N_index;
   out->n_nets = (int32_t)n->p.size();
+  out->queue_cap = n->sa.q_cap;
   return DPSNN_OK;
 }
 
@@ -675,6 +705,7 @@ int dpsnn_write_state(dpsnn_net* n, const float* V, const float* c, const uint8_
 
 int dpsnn_read_slots(dpsnn_net* n, int64_t* host_slots) {
   if (!n || !host_slots) return DPSNN_E_INVAL;
+  HIP_OK(launch_drain(n->sa, n->p[0].acc_bits, (uint32_t)n->t, n->stream));
   HIP_OK(hipStreamSynchronize(n->stream));
   const int64_t N = n->N_index, Np = n->N_pad;
   const int ab = acc_bytes(n->p[0]);
@@ -697,24 +728,24 @@ int dpsnn_read_slots(dpsnn_net* n, int64_t* host_slots) {
 }
 
 int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tgt, void* host_w,
-                    uint16_t* host_doff) {
+                    uint8_t* host_dk) {
   if (!n || first < 0 || count < 0 || first + count > n->N_index) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
-  const int Ko = n->p[0].K_out, rs = n->T[0].row_stride, ds = n->doff_stride;
+  const int Ko = n->p[0].K_out, rs = n->T[0].row_stride;
   const int wb = w_bytes(n->p[0]);
-  if (host_tgt && Ko > 0) {
-    HIP_OK(hipMemcpy2D(host_tgt, (size_t)Ko * 4, n->sa.tgt + first * rs, (size_t)rs * 4,
+  if ((host_tgt || host_dk) && Ko > 0 && count > 0) {
+    std::vector<int32_t> words((size_t)count * Ko);
+    HIP_OK(hipMemcpy2D(words.data(), (size_t)Ko * 4, n->sa.tgt + first * rs, (size_t)rs * 4,
                        (size_t)Ko * 4, (size_t)count, hipMemcpyDeviceToHost));
-    for (int64_t k = 0; k < count * Ko; ++k) host_tgt[k] &= kTargetMask;
+    for (size_t k = 0; k < words.size(); ++k) {
+      if (host_tgt) host_tgt[k] = words[k] & kTargetMask;
+      if (host_dk) host_dk[k] = (uint8_t)((uint32_t)words[k] >> kDelayShift);
+    }
   }
-  if (host_w && Ko > 0)
+  if (host_w && Ko > 0 && count > 0)
     HIP_OK(hipMemcpy2D(host_w, (size_t)Ko * wb,
                        static_cast<const unsigned char*>(n->sa.w) + (size_t)first * rs * wb,
                        (size_t)rs * wb, (size_t)Ko * wb, (size_t)count, hipMemcpyDeviceToHost));
-  if (host_doff)
-    HIP_OK(hipMemcpy2D(host_doff, (size_t)(n->T[0].n_del + 1) * 2, n->doff + first * ds,
-                       (size_t)ds * 2, (size_t)(n->T[0].n_del + 1) * 2, (size_t)count,
-                       hipMemcpyDeviceToHost));
   return DPSNN_OK;
 }
 

@@ -17,6 +17,25 @@ constexpr int kMaxKout = 4096;
 constexpr int kDelayShift = 26;  // target word = target | delay index << 26
 constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
 constexpr int kMaxSplitTiles = 16000;  // LDS prefix of the delivery kernel
+constexpr int kQueueMaxSlots = 128;   // input queues need D <= 128 slots
+constexpr int kQueueDefaultCap = 4096; // entries per (tile, slot) queue
+constexpr int kInboxStride = 16;       // inbox counters 64 bytes apart
+constexpr int kStage = 2048;           // LDS staging of a tile's routed events
+
+// Queue entry: one 8-byte (int32 slots) or 16-byte (int64) word.
+template <typename Acc>
+struct QEntry;
+template <>
+struct __attribute__((aligned(8))) QEntry<int32_t> {
+  uint32_t x;
+  int32_t w;
+};
+template <>
+struct __attribute__((aligned(16))) QEntry<int64_t> {
+  uint32_t x;
+  uint32_t pad;
+  int64_t w;
+};
 
 // Everything dpsnn_build derives from the parameters on the host, in
 // binary64 first and rounded once to the width the device uses.
@@ -29,7 +48,6 @@ struct HostTables {
   int32_t D = 0;          // input slots = d_max + 1
   int32_t n_del = 0;      // distinct delays
   int32_t row_stride = 0; // K_out rounded up to a multiple of 4
-  int32_t doff_stride = 0;
   int32_t n_arp[2] = {0, 0};
 
   double prop64[2][4];    // Pm, Pc, PVc, Iterm
@@ -99,12 +117,24 @@ struct StepArgs {
   unsigned int* rates;
   unsigned long long* n_spikes;
   uint32_t* t_base;        // device step counter
+  // Event queues (q_cap = 0: none; every event is then an atomic add into
+  // its slot).  Delivery appends each event to the inbox of its target tile
+  // for the step (parity t & 1); in the next step the tile moves its inbox
+  // into its own per-slot queues and sums the queue of the current slot.
+  // An entry (QEntry) holds in-tile index | delay index << 10 and the
+  // fixed-point efficacy.  Events that find a queue full are added into the
+  // slot.
+  int32_t q_cap, in_cap;
+  uint32_t* in_cnt;        // [2][n_tiles * kInboxStride] (may exceed in_cap)
+  void* in_q;              // [2][n_tiles][in_cap] entries
+  uint32_t* q_cnt;         // [n_tiles][D], written by the owning tile only
+  void* q_q;               // [n_tiles][D][q_cap] entries
 };
 
 struct GenArgs {
   int64_t N;
   int64_t tgt_base;        // global index of the network's neuron 0
-  int32_t K, K_exc, K_out, row_stride, doff_stride, n_del, d_min;
+  int32_t K, K_exc, K_out, row_stride, n_del, d_min;
   int32_t W, H, n_off;
   int32_t n_local[2];
   uint32_t key0, key1;
@@ -113,7 +143,6 @@ struct GenArgs {
   const void* wtab[2];     // stored-format table by source pop
   int32_t* tgt;
   void* w;
-  uint16_t* doff;
   // fixed-point in-weight sums for the int32 range check (may be null)
   unsigned long long* absum;
   const int64_t* wfix_tab[2];
@@ -136,6 +165,9 @@ hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint
 hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t s);
 hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uint32_t t_off,
                         hipStream_t s);
+// Fold every pending queue entry into its slot and empty the queues; t is
+// the number of steps taken.
+hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t s);
 hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
                             unsigned long long* out, hipStream_t s);
 
@@ -160,8 +192,6 @@ struct dpsnn_net {
   int64_t t = 0;
   int64_t rate_first = 0;      // first rate bin not yet drained
   dpsnn::StepArgs sa;
-  uint16_t* doff = nullptr;    // delay offsets of the rows (inspection)
-  int32_t doff_stride = 0;
   unsigned char* ctl = nullptr;  // log bases, spike total, step counter
   int sched = DPSNN_SCHED_SPLIT;
   int last_sched = -1;

@@ -19,6 +19,18 @@
 //             and the 5 ms population counts.
 //  k_step     fused schedule for small networks: k_neuron followed by the
 //             delivery of the tile's own spikes by its four wavefronts.
+//  k_drain    folds pending local-queue entries into the slots (inspection).
+//
+// Local-event queues.  Half of a row (the local synapses) targets the
+// source's own module, which spans at most four 1024-neuron tiles.  A
+// wavefront delivering a chunk of 256 synapses groups its local events by
+// (delay, tile) in LDS, reserves room for each group with one atomic on the
+// queue counter of (arrival slot, tile), and appends (in-tile index,
+// fixed-point efficacy) pairs with plain stores.  When a tile consumes a
+// slot it sums that slot's queue into LDS and adds it to the slot value.
+// Events that do not fit a full queue, and all remote events, are atomic
+// adds into the slot.  Every path sums integers, so the result is the same
+// whichever path an event takes.
 //
 // A step reads only slot t mod D and delivery writes only slots t+d_min ..
 // t+d_max, so update and delivery of one step need no grid-wide ordering;
@@ -33,10 +45,25 @@
 namespace dpsnn {
 
 // ------------------------------------------------------------------------
+// LDS written by some lanes of a wavefront and read by others: the hardware
+// performs one wavefront's LDS operations in order, so only the compiler
+// must not move them across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------------
 // Connectivity generation
+__host__ __device__ inline int gen_pow2(int Ko) {
+  int P = 64;
+  while (P < Ko) P <<= 1;
+  return P;
+}
 __host__ __device__ inline int gen_stage_bytes(int Ko) {
-  // tgt (4) + efficacy index (2) + rank (2) + delay index (1) per synapse
-  return ((9 * Ko + 15) / 16) * 16 + 64 * 4;
+  // sort keys (8 per slot of the power-of-two sort) + efficacy index (2)
+  return gen_pow2(Ko) * 8 + ((2 * Ko + 15) / 16) * 16;
 }
 
 template <int WDT>
@@ -46,94 +73,74 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
   const int wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
   const int64_t s = (int64_t)blockIdx.x * wpb + wave;
-  const bool active = s < a.N;
+  if (s >= a.N) return;  // whole wavefronts only: no block barrier below
   const int Ko = a.K_out;
+  const int P = gen_pow2(Ko);
 
   unsigned char* base = smem + (size_t)wave * gen_stage_bytes(Ko);
-  int32_t* st_tgt = reinterpret_cast<int32_t*>(base);
-  uint16_t* st_w = reinterpret_cast<uint16_t*>(st_tgt + Ko);
-  uint16_t* st_rank = st_w + Ko;
-  uint8_t* st_del = reinterpret_cast<uint8_t*>(st_rank + Ko);
-  uint32_t* st_off = reinterpret_cast<uint32_t*>(base + ((9 * Ko + 15) / 16) * 16);
+  uint64_t* st_key = reinterpret_cast<uint64_t*>(base);
+  uint16_t* st_w = reinterpret_cast<uint16_t*>(base + (size_t)P * 8);
 
-  const int32_t ls = active ? (int32_t)(s % a.K) : 0;
-  const int32_t ms = active ? (int32_t)(s / a.K) : 0;
+  const int32_t ls = (int32_t)(s % a.K);
+  const int32_t ms = (int32_t)(s / a.K);
   const int pop = ls < a.K_exc ? 0 : 1;
   const int xs = ms % a.W, ys = ms / a.W;
-  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
 
-  uint32_t cnt = 0;  // lane x: synapses with delay index x seen so far
-  if (active) {
-    for (int j0 = 0; j0 < Ko; j0 += 64) {
-      const int j = j0 + lane;
-      int k = -1;
-      int32_t tg = 0;
-      uint16_t wi = 0;
-      if (j < Ko) {
-        const uint4 u = philox10(make_uint4((uint32_t)s, (uint32_t)j, 0u, kTagSyn),
-                                 a.key0, a.key1);
-        if (j < a.n_local[pop]) {
-          const uint32_t r = scale32(u.x, (uint32_t)(a.K - 1));
-          tg = ms * a.K + (int32_t)(r + (r >= (uint32_t)ls ? 1u : 0u));
-        } else {
-          int lo = 0, hi = a.n_off - 1;  // first threshold above u.x
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (a.off_thr[mid] <= u.x)
-              lo = mid + 1;
-            else
-              hi = mid;
-          }
-          int xt = xs + a.off_xy[2 * lo];
-          int yt = ys + a.off_xy[2 * lo + 1];
-          if (xt >= a.W) xt -= a.W;
-          if (yt >= a.H) yt -= a.H;
-          tg = (yt * a.W + xt) * a.K + (int32_t)scale32(u.y, (uint32_t)a.K);
+  // draw synapse j: sort key = target << 18 | delay index << 12 | j
+  for (int j = lane; j < P; j += 64) {
+    uint64_t key = ~0ull;
+    if (j < Ko) {
+      const uint4 u = philox10(make_uint4((uint32_t)s, (uint32_t)j, 0u, kTagSyn),
+                               a.key0, a.key1);
+      int32_t tg;
+      if (j < a.n_local[pop]) {
+        const uint32_t r = scale32(u.x, (uint32_t)(a.K - 1));
+        tg = ms * a.K + (int32_t)(r + (r >= (uint32_t)ls ? 1u : 0u));
+      } else {
+        int lo = 0, hi = a.n_off - 1;  // first threshold above u.x
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (a.off_thr[mid] <= u.x)
+            lo = mid + 1;
+          else
+            hi = mid;
         }
-        k = (int)scale32(u.z, (uint32_t)a.n_del);
-        wi = (uint16_t)(u.w >> 16);
+        int xt = xs + a.off_xy[2 * lo];
+        int yt = ys + a.off_xy[2 * lo + 1];
+        if (xt >= a.W) xt -= a.W;
+        if (yt >= a.H) yt -= a.H;
+        tg = (yt * a.W + xt) * a.K + (int32_t)scale32(u.y, (uint32_t)a.K);
       }
-      // stable rank among equal delays: earlier chunks, then lower lanes
-      const uint32_t before = cnt;
-      uint32_t in_chunk = 0;
-      for (int x = 0; x < a.n_del; ++x) {
-        const uint64_t m = __ballot(k == x);
-        if (lane == x) cnt += (uint32_t)__popcll(m);
-        if (k == x) in_chunk = (uint32_t)__popcll(m & below);
-      }
-      const uint32_t prev = __shfl(before, k < 0 ? 0 : k);
-      if (j < Ko) {
-        st_tgt[j] = tg;
-        st_w[j] = wi;
-        st_del[j] = (uint8_t)k;
-        st_rank[j] = (uint16_t)(prev + in_chunk);
-      }
+      const uint32_t k = scale32(u.z, (uint32_t)a.n_del);
+      st_w[j] = (uint16_t)(u.w >> 16);
+      key = ((uint64_t)(uint32_t)tg << 18) | ((uint64_t)k << 12) | (uint64_t)j;
     }
-    // exclusive scan of the per-delay counts across lanes
-    uint32_t incl = cnt;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t v = __shfl_up(incl, off);
-      if (lane >= off) incl += v;
-    }
-    const uint32_t excl = incl - cnt;
-    if (lane < a.n_del) {
-      st_off[lane] = excl;
-      a.doff[s * a.doff_stride + lane] = (uint16_t)excl;
-    }
-    if (lane == 0) a.doff[s * a.doff_stride + a.n_del] = (uint16_t)Ko;
-    for (int x = a.n_del + 1 + lane; x < a.doff_stride; x += 64)
-      a.doff[s * a.doff_stride + x] = 0;
+    st_key[j] = key;
   }
-  __syncthreads();
-  if (!active) return;
+  wave_lds_sync();
+  // bitonic sort of the P keys, ascending (padding keys sort last); the
+  // keys are distinct, so the order is that of (target, delay, j)
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int q = lane; q < P / 2; q += 64) {
+        const int lo = 2 * q - (q & (stride - 1));
+        const int hi = lo + stride;
+        const uint64_t x = st_key[lo], y = st_key[hi];
+        if ((x > y) == ((lo & size) == 0)) {
+          st_key[lo] = y;
+          st_key[hi] = x;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
   const int64_t rb = s * a.row_stride;
-  for (int j = lane; j < Ko; j += 64) {
-    const int k = st_del[j];
-    const uint32_t pos = st_off[k] + st_rank[j];
-    if (pos >= (uint32_t)Ko) continue;  // unreachable: ranks stay inside the row
+  for (int pos = lane; pos < Ko; pos += 64) {
+    const uint64_t key = st_key[pos];
+    const int32_t tg = (int32_t)(key >> 18);
+    const int k = (int)((key >> 12) & 63u);
+    const uint16_t wi = st_w[key & 4095u];
     const int64_t o = rb + pos;
-    const int32_t tg = st_tgt[j];
-    const uint16_t wi = st_w[j];
     const int32_t gt = tg + (int32_t)a.tgt_base;  // global target index
     a.tgt[o] = gt | (k << kDelayShift);
     if (WDT == DPSNN_W_F32)
@@ -216,33 +223,195 @@ __device__ __forceinline__ Acc stored_to_fix(const void* w, int64_t o, float two
   }
 }
 
+template <typename Acc>
+__device__ __forceinline__ void lds_add(Acc* p, Acc v);
+template <>
+__device__ __forceinline__ void lds_add<int32_t>(int32_t* p, int32_t v) {
+  atomicAdd(p, v);
+}
+template <>
+__device__ __forceinline__ void lds_add<int64_t>(int64_t* p, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+
+// LDS of the queue consumer of one tile.
+template <typename Acc>
+struct QueueLds {
+  Acc in[1024];             // input sums of the tile's neurons
+  Acc sw[kStage];           // routed events, grouped by slot
+  uint16_t sx[kStage];
+  uint8_t ss[kStage];
+  uint32_t qc[kQueueMaxSlots];    // queue counts before this step
+  uint32_t cnew[kQueueMaxSlots];  // events routed to each slot now
+  uint32_t off[kQueueMaxSlots];   // their first staging position
+};
+
+// Event queues of one tile at step t (all threads of the block call it).
+// The inbox filled by the delivery of step t-1 is routed: events arriving
+// now are summed into L.in; the others are grouped by arrival slot in LDS
+// and appended to the tile's per-slot queues as one contiguous run per slot
+// (past the staging space or a full queue they are added into the slot).
+// The queue of slot t mod D is summed into L.in and emptied.  Entries are
+// loaded kQBatch per thread at a time before any is used, so that their
+// memory latency is paid once per batch.
+constexpr int kQBatch = 8;
+
+template <typename Acc>
+__device__ __forceinline__ void consume_queues(const StepArgs& a, int tile, uint32_t t,
+                                               QueueLds<Acc>& L) {
+  const int D = a.D;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int cur = (int)(t % (uint32_t)D);
+  const uint32_t par = (t - 1u) & 1u;
+  const int64_t ic = ((int64_t)par * a.n_tiles + tile) * kInboxStride;
+  const uint32_t got = a.in_cnt[ic];
+  const uint32_t qn = a.q_cnt[(int64_t)tile * D + cur];
+  const uint32_t n_in = got < (uint32_t)a.in_cap ? got : (uint32_t)a.in_cap;
+  const uint32_t n_cur = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
+  for (int k = tid; k < 1024; k += nth) L.in[k] = 0;
+  for (int k = tid; k < D; k += nth) {
+    L.qc[k] = a.q_cnt[(int64_t)tile * D + k];
+    L.cnew[k] = 0;
+  }
+  __syncthreads();
+  if (tid == 0) a.in_cnt[ic] = 0;
+  Acc* slots = static_cast<Acc*>(a.slots);
+  const QEntry<Acc>* qq = static_cast<const QEntry<Acc>*>(a.q_q);
+  const QEntry<Acc>* iq = static_cast<const QEntry<Acc>*>(a.in_q);
+  const int64_t qb = (int64_t)tile * D * a.q_cap;
+  const int64_t qc = qb + (int64_t)cur * a.q_cap;
+  const int64_t ib = ((int64_t)par * a.n_tiles + tile) * a.in_cap;
+  const uint32_t n_max = n_cur > n_in ? n_cur : n_in;
+  // events of the inbox are kept in registers between the passes (at most
+  // kQBatch per thread; larger inboxes take more rounds of the whole scheme)
+  for (uint32_t r0 = 0; r0 < n_max; r0 += (uint32_t)nth * kQBatch) {
+    QEntry<Acc> ce[kQBatch], ie[kQBatch];
+    int sl[kQBatch];
+    uint32_t rk[kQBatch];
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      const uint32_t e = r0 + (uint32_t)(u * nth + tid);
+      ce[u].x = 0xFFFFFFFFu;
+      ie[u].x = 0xFFFFFFFFu;
+      if (e < n_cur) ce[u] = qq[qc + e];
+      if (e < n_in) ie[u] = iq[ib + e];
+    }
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      if (ce[u].x != 0xFFFFFFFFu) lds_add<Acc>(&L.in[ce[u].x & 1023u], ce[u].w);
+      sl[u] = -1;
+      if (ie[u].x != 0xFFFFFFFFu) {
+        const uint32_t x = ie[u].x;
+        const int dk = (int)(x >> 10) < a.n_del ? (int)(x >> 10) : a.n_del - 1;
+        const int off = a.d_min + dk - 1;  // arrival in off steps: 0 .. D - 2
+        if (off == 0) {
+          lds_add<Acc>(&L.in[x & 1023u], ie[u].w);
+        } else {
+          int s2 = cur + off;
+          if (s2 >= D) s2 -= D;
+          sl[u] = s2;
+          rk[u] = atomicAdd(&L.cnew[s2], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {  // exclusive scan of the per-slot counts (D <= 128)
+      const uint32_t c0 = 2 * tid < D ? L.cnew[2 * tid] : 0u;
+      const uint32_t c1 = 2 * tid + 1 < D ? L.cnew[2 * tid + 1] : 0u;
+      uint32_t v = c0 + c1;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t w = __shfl_up(v, o);
+        if (tid >= o) v += w;
+      }
+      const uint32_t ex = v - c0 - c1;
+      if (2 * tid < D) L.off[2 * tid] = ex;
+      if (2 * tid + 1 < D) L.off[2 * tid + 1] = ex + c0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      if (sl[u] < 0) continue;
+      const uint32_t sp = L.off[sl[u]] + rk[u];
+      const uint32_t idx = ie[u].x & 1023u;
+      if (sp < (uint32_t)kStage) {
+        L.sx[sp] = (uint16_t)idx;
+        L.ss[sp] = (uint8_t)sl[u];
+        L.sw[sp] = ie[u].w;
+      } else {
+        atomic_add_fix<Acc>(slots + (int64_t)sl[u] * a.N_pad + (int64_t)tile * 1024 + idx,
+                            ie[u].w);
+      }
+    }
+    __syncthreads();
+    uint32_t total = 0;
+    if (D > 0) total = L.off[D - 1] + L.cnew[D - 1];
+    const uint32_t staged = total < (uint32_t)kStage ? total : (uint32_t)kStage;
+    QEntry<Acc>* qw = static_cast<QEntry<Acc>*>(a.q_q);
+    for (uint32_t e = tid; e < staged; e += nth) {
+      const int s2 = L.ss[e];
+      const uint32_t gpos = L.qc[s2] + (e - L.off[s2]);
+      if (gpos < (uint32_t)a.q_cap) {
+        QEntry<Acc> q;
+        q.x = L.sx[e];
+        q.w = L.sw[e];
+        if (sizeof(QEntry<Acc>) == 16) reinterpret_cast<uint32_t*>(&q)[1] = 0u;
+        qw[qb + (int64_t)s2 * a.q_cap + gpos] = q;
+      } else {
+        atomic_add_fix<Acc>(slots + (int64_t)s2 * a.N_pad + (int64_t)tile * 1024 + L.sx[e],
+                            L.sw[e]);
+      }
+    }
+    __syncthreads();
+    // queue counts after this round: staged events only (the rest went to
+    // the slots); the current queue is empty
+    for (int k = tid; k < D; k += nth) {
+      const uint32_t o = L.off[k], c = L.cnew[k];
+      const uint32_t st = o >= (uint32_t)kStage ? 0u : (o + c <= (uint32_t)kStage ? c : kStage - o);
+      L.qc[k] = k == cur ? 0u : L.qc[k] + st;
+      L.cnew[k] = 0;
+    }
+    __syncthreads();
+  }
+  for (int k = tid; k < D; k += nth) a.q_cnt[(int64_t)tile * D + k] = k == cur ? 0u : L.qc[k];
+}
+
 // ------------------------------------------------------------------------
 // Neuron update of the 4 neurons i0..i0+3 (global indices) of one thread at
-// step t; nd is the tile's network.  Spiking neurons are appended to the LDS
-// list s_spk (count s_n).  Counters of the random draws use the network's
-// own neuron indices, so a network in a batch draws what it draws alone.
+// step t; nd is the tile's network.  neuron_load reads and clears the input
+// slot, reads the state and adds the external drive; neuron_finish adds the
+// queued inputs (s_in, may be null), integrates Eq. 2 and appends spiking
+// neurons to the LDS list s_spk (count s_n).  Counters of the random draws
+// use the network's own neuron indices, so a network in a batch draws what
+// it draws alone.
 template <typename Acc>
-__device__ __forceinline__ void update4(const StepArgs& a, const NetDev& nd, int64_t i0,
-                                        uint32_t t, int32_t* s_spk, int* s_n) {
+struct NeuronRegs {
+  Acc I[4];
+  float V[4], c[4];
+  uint32_t r4;
+};
+
+template <typename Acc>
+__device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd, int64_t i0,
+                                            uint32_t t, NeuronRegs<Acc>& R) {
   const int slot = (int)(t % (uint32_t)a.D);
   Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
-  Acc I[4];
   if (sizeof(Acc) == 4) {
     const int4 v = *reinterpret_cast<const int4*>(sl);
-    I[0] = v.x; I[1] = v.y; I[2] = v.z; I[3] = v.w;
+    R.I[0] = v.x; R.I[1] = v.y; R.I[2] = v.z; R.I[3] = v.w;
     *reinterpret_cast<int4*>(sl) = make_int4(0, 0, 0, 0);
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      I[j] = sl[j];
+      R.I[j] = sl[j];
       sl[j] = 0;
     }
   }
   const float4 V4 = *reinterpret_cast<const float4*>(a.V + i0);
   const float4 c4 = *reinterpret_cast<const float4*>(a.c + i0);
-  const uint32_t r4 = *reinterpret_cast<const uint32_t*>(a.ref + i0);
-  float Vv[4] = {V4.x, V4.y, V4.z, V4.w};
-  float cv[4] = {c4.x, c4.y, c4.z, c4.w};
+  R.r4 = *reinterpret_cast<const uint32_t*>(a.ref + i0);
+  R.V[0] = V4.x; R.V[1] = V4.y; R.V[2] = V4.z; R.V[3] = V4.w;
+  R.c[0] = c4.x; R.c[1] = c4.y; R.c[2] = c4.z; R.c[3] = c4.w;
 
   // external Poisson drive generated on the fly: counts from word j of
   // (il0/4, t, EXT); efficacies 2b and 2b+1 of neuron j from word j of
@@ -271,19 +440,33 @@ __device__ __forceinline__ void update4(const StepArgs& a, const NetDev& nd, int
     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (2 * b < k[j]) I[j] += jx[q[j] * kQuantN + (vv[j] >> 16)];
-      if (2 * b + 1 < k[j]) I[j] += jx[q[j] * kQuantN + (vv[j] & 0xFFFFu)];
+      if (2 * b < k[j]) R.I[j] += jx[q[j] * kQuantN + (vv[j] >> 16)];
+      if (2 * b + 1 < k[j]) R.I[j] += jx[q[j] * kQuantN + (vv[j] & 0xFFFFu)];
     }
   }
+}
 
+template <typename Acc>
+__device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& nd, int64_t i0,
+                                              NeuronRegs<Acc>& R, const Acc* s_in,
+                                              int32_t* s_spk, int* s_n) {
+  if (s_in) {  // this thread's four entries of the tile's queue sums
+#pragma unroll
+    for (int j = 0; j < 4; ++j) R.I[j] += s_in[4 * threadIdx.x + j];
+  }
+  const int64_t il0 = i0 - nd.base;
+  const int64_t m0 = il0 / nd.K;
+  const int l0 = (int)(il0 - m0 * nd.K);
   uint32_t r_out = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int qq = q[j];
-    uint32_t rj = (r4 >> (8 * j)) & 0xFFu;
+    int lj = l0 + j;
+    if (lj >= nd.K) lj -= nd.K;
+    const int qq = lj < nd.K_exc ? 0 : 1;
+    uint32_t rj = (R.r4 >> (8 * j)) & 0xFFu;
     if (il0 + j < nd.N) {
-      const float dv = fix_to_f32(I[j]) * a.inv2q;
-      float Vj = Vv[j], cj = cv[j];
+      const float dv = fix_to_f32(R.I[j]) * a.inv2q;
+      float Vj = R.V[j], cj = R.c[j];
       bool spk = false;
       if (rj > 0) {
         rj -= 1;
@@ -305,8 +488,8 @@ __device__ __forceinline__ void update4(const StepArgs& a, const NetDev& nd, int
         }
         Vj = vv;
       }
-      Vv[j] = Vj;
-      cv[j] = cj;
+      R.V[j] = Vj;
+      R.c[j] = cj;
       if (spk) {
         const int pos = atomicAdd(s_n, 1);
         s_spk[pos] = (int32_t)(i0 + j);
@@ -314,8 +497,8 @@ __device__ __forceinline__ void update4(const StepArgs& a, const NetDev& nd, int
     }
     r_out |= rj << (8 * j);
   }
-  *reinterpret_cast<float4*>(a.V + i0) = make_float4(Vv[0], Vv[1], Vv[2], Vv[3]);
-  *reinterpret_cast<float4*>(a.c + i0) = make_float4(cv[0], cv[1], cv[2], cv[3]);
+  *reinterpret_cast<float4*>(a.V + i0) = make_float4(R.V[0], R.V[1], R.V[2], R.V[3]);
+  *reinterpret_cast<float4*>(a.c + i0) = make_float4(R.c[0], R.c[1], R.c[2], R.c[3]);
   *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
 }
 
@@ -329,10 +512,12 @@ __device__ __forceinline__ void module_pop(const StepArgs& a, int32_t id, int32_
   *pop = (local - m * nd.K) < nd.K_exc ? 0 : 1;
 }
 
-// 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.
+// 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.  s_b is
+// the wavefront's 256-entry LDS scratch.  Every lane of the wavefront takes
+// part, also past the end of the row.
 template <typename Acc, int WDT>
 __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int p0,
-                                              uint32_t t, int lane) {
+                                              uint32_t t, int lane, uint32_t* s_b) {
   const int64_t rb = (int64_t)s * a.row_stride;
   int64_t scale = 0;
   if (WDT == DPSNN_W_I8) {
@@ -342,31 +527,122 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
     scale = a.sfix[2 * ms + q];
   }
   const int p = p0 + lane * 4;
-  if (p >= a.K_out) return;
-  const int4 tg = *reinterpret_cast<const int4*>(a.tgt + rb + p);
-  const int tv[4] = {tg.x, tg.y, tg.z, tg.w};
-  Acc wv[4];
-  if (WDT == DPSNN_W_F32) {
-    const float4 w4 = *reinterpret_cast<const float4*>(static_cast<const float*>(a.w) + rb + p);
-    wv[0] = (Acc)__builtin_rintf(w4.x * a.two_q);
-    wv[1] = (Acc)__builtin_rintf(w4.y * a.two_q);
-    wv[2] = (Acc)__builtin_rintf(w4.z * a.two_q);
-    wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
-  } else {
+  int tv[4] = {0, 0, 0, 0};
+  Acc wv[4] = {0, 0, 0, 0};
+  if (p < a.K_out) {  // rows are padded to a multiple of 4 words
+    const int4 tg = *reinterpret_cast<const int4*>(a.tgt + rb + p);
+    tv[0] = tg.x; tv[1] = tg.y; tv[2] = tg.z; tv[3] = tg.w;
+    if (WDT == DPSNN_W_F32) {
+      const float4 w4 =
+          *reinterpret_cast<const float4*>(static_cast<const float*>(a.w) + rb + p);
+      wv[0] = (Acc)__builtin_rintf(w4.x * a.two_q);
+      wv[1] = (Acc)__builtin_rintf(w4.y * a.two_q);
+      wv[2] = (Acc)__builtin_rintf(w4.z * a.two_q);
+      wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
+      for (int j = 0; j < 4; ++j)
+        wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
+    }
   }
   const int slot0 = (int)((t + (uint32_t)a.d_min) % (uint32_t)a.D);
   Acc* slots = static_cast<Acc*>(a.slots);
+  if (a.q_cap == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (p + j < a.K_out) {
+        int sl = slot0 + (int)((uint32_t)tv[j] >> kDelayShift);
+        if (sl >= a.D) sl -= a.D;
+        const int32_t target = tv[j] & kTargetMask;
+        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+      }
+    }
+    return;
+  }
+  // Rows are sorted by target, so the events to one tile form runs.  The
+  // first event of a run reserves room for the whole run in that tile's
+  // inbox; the others take the following entries.
+  const int end = p0 + 256 < a.K_out ? p0 + 256 : a.K_out;
+  int tl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) tl[j] = p + j < end ? (tv[j] & kTargetMask) >> 10 : -1;
+  int prev = __shfl_up(tl[3], 1);
+  if (lane == 0) prev = -2;
+  bool f[4];
+  f[0] = tl[0] >= 0 && tl[0] != prev;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) f[j] = tl[j] >= 0 && tl[j] != tl[j - 1];
+  // start of the run of each event: the last start at or before it
+  int last = -1, first = 1 << 30;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (p + j < a.K_out) {
-      int sl = slot0 + (int)((uint32_t)tv[j] >> kDelayShift);
-      if (sl >= a.D) sl -= a.D;
-      const int32_t target = tv[j] & kTargetMask;
-      atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+    if (f[j]) {
+      last = p + j;
+      first = first < p + j ? first : p + j;
     }
   }
+  int incl = last;  // max-scan over lanes
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl = incl > v ? incl : v;
+  }
+  int carry = __shfl_up(incl, 1);
+  if (lane == 0) carry = -1;
+  int after = first;  // min-scan over the later lanes
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_down(after, off);
+    if (lane + off < 64) after = after < v ? after : v;
+  }
+  int nxt = __shfl_down(after, 1);
+  if (lane == 63) nxt = 1 << 30;
+  int rs[4];
+  {
+    int c = carry;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (f[j]) c = p + j;
+      rs[j] = c;
+    }
+  }
+  const uint32_t par = t & 1u;
+  // reservations: one returning atomic per run
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (f[j]) {
+      int ne = nxt;
+#pragma unroll
+      for (int k = 3; k > j; --k)
+        if (f[k]) ne = p + k;
+      if (ne > end) ne = end;
+      const uint32_t len = (uint32_t)(ne - (p + j));
+      s_b[p + j - p0] =
+          atomicAdd(&a.in_cnt[((int64_t)par * a.n_tiles + tl[j]) * kInboxStride], len);
+    }
+  }
+  wave_lds_sync();
+  QEntry<Acc>* iq = static_cast<QEntry<Acc>*>(a.in_q);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (tl[j] >= 0) {
+      const uint32_t pos = s_b[rs[j] - p0] + (uint32_t)(p + j - rs[j]);
+      const int32_t target = tv[j] & kTargetMask;
+      const uint32_t dk = (uint32_t)tv[j] >> kDelayShift;
+      if (pos < (uint32_t)a.in_cap) {
+        QEntry<Acc> q;
+        q.x = (uint32_t)(target & 1023) | (dk << 10);
+        q.w = wv[j];
+        if (sizeof(QEntry<Acc>) == 16) reinterpret_cast<uint32_t*>(&q)[1] = 0u;
+        iq[((int64_t)par * a.n_tiles + tl[j]) * a.in_cap + pos] = q;
+      } else {
+        int sl = slot0 + (int)dk;
+        if (sl >= a.D) sl -= a.D;
+        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+      }
+    }
+  }
+  wave_lds_sync();  // s_b is written again by the wavefront's next chunk
 }
 
 __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint32_t t,
@@ -384,14 +660,20 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 template <typename Acc>
 __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
+  __shared__ QueueLds<Acc> s_q;
   __shared__ int s_n;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
-  __syncthreads();
   const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
   const NetDev& nd = a.nets[a.tile_net[blockIdx.x]];
-  update4<Acc>(a, nd, i0, t, s_spk, &s_n);
+  NeuronRegs<Acc> R;
+  neuron_load<Acc>(a, nd, i0, t, R);
+  if (a.q_cap)
+    consume_queues<Acc>(a, blockIdx.x, t, s_q);
+  else
+    __syncthreads();
+  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_q.in : nullptr, s_spk, &s_n);
   __syncthreads();
   const int n = s_n;
   int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
@@ -403,6 +685,7 @@ template <typename Acc, int WDT>
 __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   extern __shared__ int32_t s_pref[];  // inclusive prefix of the tile counts
   __shared__ int32_t s_part[256];
+  __shared__ uint32_t s_b[4][256];
   const int tid = threadIdx.x;
   const int nb = a.n_tiles;
   const uint32_t t = a.t_base[0] + t_off;
@@ -452,7 +735,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
     const int first = l ? s_pref[l - 1] : 0;
     const int32_t s = __builtin_amdgcn_readfirstlane(a.spk[(int64_t)l * 1024 + (sidx - first)]);
     if (chunk == 0 && lane == 0) record_spike(a, s, t, log0 + (unsigned long long)sidx);
-    deliver_chunk<Acc, WDT>(a, s, chunk * 256, t, lane);
+    deliver_chunk<Acc, WDT>(a, s, chunk * 256, t, lane, s_b[tid >> 6]);
   }
 }
 
@@ -461,15 +744,22 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
 template <typename Acc, int WDT>
 __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
+  __shared__ QueueLds<Acc> s_q;
+  __shared__ uint32_t s_b[4][256];
   __shared__ int s_n;
   __shared__ unsigned long long s_logbase;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
-  __syncthreads();
   const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
   const NetDev& nd = a.nets[a.tile_net[blockIdx.x]];
-  update4<Acc>(a, nd, i0, t, s_spk, &s_n);
+  NeuronRegs<Acc> R;
+  neuron_load<Acc>(a, nd, i0, t, R);
+  if (a.q_cap)
+    consume_queues<Acc>(a, blockIdx.x, t, s_q);
+  else
+    __syncthreads();
+  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_q.in : nullptr, s_spk, &s_n);
   __syncthreads();
   const int n = s_n;
   if (n == 0) return;
@@ -487,7 +777,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   for (int it = wave; it < n * cpr; it += 4) {
     const int k = it / cpr;
     const int32_t s = __builtin_amdgcn_readfirstlane(s_spk[k]);
-    deliver_chunk<Acc, WDT>(a, s, (it - k * cpr) * 256, t, lane);
+    deliver_chunk<Acc, WDT>(a, s, (it - k * cpr) * 256, t, lane, s_b[wave]);
   }
 }
 
@@ -500,6 +790,44 @@ __global__ void k_tick(uint32_t* t_base, uint32_t n, unsigned long long* log_bas
     if (sync_logs) log_base[(t + 1) & 1] = log_base[t & 1];
     t_base[0] = t + n;
   }
+}
+
+// Pending queue entries of tile blockIdx.x after t steps added into the
+// slots: the inbox of step t-1 and every per-slot queue; all left empty.
+template <typename Acc>
+__global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
+  const int tile = blockIdx.x;
+  const int D = a.D;
+  Acc* slots = static_cast<Acc*>(a.slots);
+  const uint32_t par = (t - 1u) & 1u;
+  const int64_t ic = ((int64_t)par * a.n_tiles + tile) * kInboxStride;
+  const uint32_t got = a.in_cnt[ic];
+  const uint32_t n_in = got < (uint32_t)a.in_cap ? got : (uint32_t)a.in_cap;
+  const int64_t ib = ((int64_t)par * a.n_tiles + tile) * a.in_cap;
+  const QEntry<Acc>* iq = static_cast<const QEntry<Acc>*>(a.in_q);
+  for (uint32_t e = threadIdx.x; e < n_in; e += blockDim.x) {
+    const QEntry<Acc> q = iq[ib + e];
+    const int dk = (int)(q.x >> 10) < a.n_del ? (int)(q.x >> 10) : a.n_del - 1;
+    // emitted at t - 1, arrives at t - 1 + d_min + dk
+    const int sl = (int)(((uint64_t)t + (uint64_t)(a.d_min + dk) - 1u) % (uint64_t)D);
+    atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + (int64_t)tile * 1024 + (q.x & 1023u),
+                        q.w);
+  }
+  const int64_t qb = (int64_t)tile * D * a.q_cap;
+  const QEntry<Acc>* qq = static_cast<const QEntry<Acc>*>(a.q_q);
+  for (int k = 0; k < D; ++k) {
+    const uint32_t qn = a.q_cnt[(int64_t)tile * D + k];
+    const uint32_t n = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
+    const int64_t qc = qb + (int64_t)k * a.q_cap;
+    for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
+      const QEntry<Acc> q = qq[qc + e];
+      atomic_add_fix<Acc>(slots + (int64_t)k * a.N_pad + (int64_t)tile * 1024 + (q.x & 1023u),
+                          q.w);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.in_cnt[ic] = 0;
+  for (int k = threadIdx.x; k < D; k += blockDim.x) a.q_cnt[(int64_t)tile * D + k] = 0;
 }
 
 // ------------------------------------------------------------------------
@@ -598,6 +926,16 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
     else
       hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t st) {
+  if (a.q_cap == 0 || a.n_tiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)a.n_tiles);
+  if (acc_bits == 32)
+    hipLaunchKernelGGL(k_drain<int32_t>, grid, dim3(256), 0, st, a, t);
+  else
+    hipLaunchKernelGGL(k_drain<int64_t>, grid, dim3(256), 0, st, a, t);
   return hipGetLastError();
 }
 

@@ -97,6 +97,7 @@ int validate(const dpsnn_params& p) {
     return DPSNN_E_INVAL;
   if (p.rate_bin_steps < 1 || p.rate_bins_cap < 1 || p.spike_log_cap < 0)
     return DPSNN_E_INVAL;
+  if (p.queue_cap < -1 || p.queue_cap > (1 << 20)) return DPSNN_E_INVAL;
   const int M = p.grid_w * p.grid_h;
   for (int q = 0; q < 2; ++q) {
     const long nloc = llround(p.frac_local[q] * p.K_out);
@@ -116,7 +117,6 @@ int compute_tables(const dpsnn_params& p, HostTables& T) {
   T.D = p.d_max + 1;
   T.n_del = p.d_max - p.d_min + 1;
   T.row_stride = (p.K_out + 3) / 4 * 4;
-  T.doff_stride = (T.n_del + 1 + 1) / 2 * 2;
   const double two_q = ldexp(1.0, p.q_frac_bits);
 
   for (int q = 0; q < 2; ++q) {

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libdpsnn.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 W_F32, W_F16, W_I8 = 0, 1, 2
 WEIGHT_DTYPES = {"f32": W_F32, "f16": W_F16, "i8": W_I8}
 ERRORS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "RANGE",
@@ -35,6 +35,7 @@ class DpsnnParams(C.Structure):
         ("V_r", _PAIR), ("tau_arp", _PAIR), ("alpha_c", _PAIR), ("tau_c", _PAIR),
         ("gc", _PAIR), ("I_const", _PAIR), ("rate_bin_steps", C.c_int32),
         ("spike_log_cap", C.c_int64), ("rate_bins_cap", C.c_int64),
+        ("queue_cap", C.c_int32),
     ]
 
 
@@ -44,7 +45,7 @@ class DpsnnStats(C.Structure):
         ("n_synapses", C.c_int64), ("n_spikes", C.c_int64), ("n_events", C.c_int64),
         ("build_ms", C.c_double), ("bytes_rows", C.c_int64), ("bytes_state", C.c_int64),
         ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("schedule", C.c_int32),
-        ("n_index", C.c_int64), ("n_nets", C.c_int32), ("reserved", C.c_int32),
+        ("n_index", C.c_int64), ("n_nets", C.c_int32), ("queue_cap", C.c_int32),
     ]
 
 
@@ -63,6 +64,8 @@ def to_struct(params: dict) -> DpsnnParams:
             v = params.get(key, DEFAULT_SPIKE_LOG_CAP)
         elif key == "rate_bins_cap":
             v = params.get(key, DEFAULT_RATE_BINS_CAP)
+        elif key == "queue_cap":
+            v = params.get(key, 0)
         else:
             v = params[key]
         if key == "weight_dtype" and isinstance(v, str):
@@ -347,15 +350,17 @@ _W_NP = {W_F32: np.float32, W_F16: np.uint16, W_I8: np.int8}
 
 
 def dpsnn_read_rows(net: Net, first: int, count: int):
+    """(targets, stored efficacies, delay - d_min) of rows first..first+count-1,
+    each row sorted by (target, delay, draw index)."""
     Ko = int(net.params["K_out"])
     wd = net.params["weight_dtype"]
     wd = WEIGHT_DTYPES[wd] if isinstance(wd, str) else int(wd)
     tgt = np.zeros((count, Ko), np.int32)
     w = np.zeros((count, Ko), _W_NP[wd])
-    doff = np.zeros((count, net.n_del + 1), np.uint16)
+    dk = np.zeros((count, Ko), np.uint8)
     _check("dpsnn_read_rows",
-           lib().dpsnn_read_rows(net.h, int(first), int(count), _ptr(tgt), _ptr(w), _ptr(doff)))
-    return tgt, w, doff
+           lib().dpsnn_read_rows(net.h, int(first), int(count), _ptr(tgt), _ptr(w), _ptr(dk)))
+    return tgt, w, dk
 
 
 def dpsnn_host_table(params: dict, name: str, dtype) -> np.ndarray:

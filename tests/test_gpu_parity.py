@@ -42,24 +42,31 @@ def _pair(p, seed, store_rows=True, **over):
 
 
 def _compare_rows(L, net, orc, rows, wd):
-    tgt, w, doff = L.dpsnn_read_rows(net, rows[0], len(rows)) if len(rows) and \
+    """Rows on the device are sorted by (target, delay, draw index); the
+    oracle's are sorted by delay in draw order.  The same order is taken from
+    the oracle's row by a stable sort, then targets, delays and stored
+    efficacies must agree bit for bit."""
+    tgt, w, dk = L.dpsnn_read_rows(net, rows[0], len(rows)) if len(rows) and \
         rows == list(range(rows[0], rows[0] + len(rows))) else (None, None, None)
     tabs = {"f32": [orc.table(f"wt32_{q}", np.float32) for q in (0, 1)],
             "f16": [orc.table(f"wt16_{q}", np.uint16) for q in (0, 1)],
             "i8": [orc.table(f"wq8_{q}", np.int8) for q in (0, 1)]}[wd]
     K = int(orc.params["K"])
     Kexc = round(orc.params["frac_exc"] * K)
+    d_min = int(orc.params["d_min"])
     for k, s in enumerate(rows):
         if tgt is None:
             t1, w1, d1 = L.dpsnn_read_rows(net, s, 1)
             t1, w1, d1 = t1[0], w1[0], d1[0]
         else:
-            t1, w1, d1 = tgt[k], w[k], doff[k]
+            t1, w1, d1 = tgt[k], w[k], dk[k]
         ot, od, ow, oo = orc.gen_row(s)
+        order = np.lexsort((np.arange(len(ot)), od, ot))
         q = 0 if (s % K) < Kexc else 1
-        assert np.array_equal(t1, ot), s
-        assert np.array_equal(d1, oo), s
-        assert w1.tobytes() == tabs[q][ow].tobytes(), s
+        assert np.array_equal(t1, ot[order]), s
+        assert np.array_equal(d1.astype(np.int64), od[order].astype(np.int64) - d_min), s
+        assert w1.tobytes() == tabs[q][ow[order]].tobytes(), s
+        assert np.all(np.diff(t1.astype(np.int64)) >= 0), s
 
 
 @pytest.mark.parametrize("case", ["c1_f32", "tiny_f16", "tiny_i8", "ragged_3x3",
@@ -371,4 +378,46 @@ def test_batch_matches_solo_runs(L):
         assert np.array_equal(s_k, ss) and np.array_equal(i_k, si)
         assert len(ss) > 1000
         solo.close()
+    net.close()
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+@pytest.mark.parametrize("cap", [-1, 1, 7, 0])
+def test_queue_capacity_bit_exact(L, cap, sched):
+    """Events go through the tile inboxes and per-slot queues, past a full
+    inbox or queue into the slots, or (cap -1) all into the slots: rasters,
+    state and slots stay those of the oracle.  Cases: modules of 1500
+    neurons (three tiles), int8 efficacies with int64 slots (8-byte queue
+    entries), a minimum delay of 3 steps (no event arrives in the step after
+    its spike), modules of 3100 neurons (four tiles and more)."""
+    cases = [W.tiny(w=2, h=2, K=1500, K_out=120, nu_ext_hz=[2600.0, 2600.0]),
+             W.tiny(w=2, h=2, K=1100, K_out=100, weight_dtype="i8", acc_bits=64,
+                    q_frac_bits=32, nu_ext_hz=[2600.0, 2600.0]),
+             W.tiny(w=3, h=2, K=700, K_out=90, d_min=3, d_max=11,
+                    nu_ext_hz=[2600.0, 2600.0]),
+             W.tiny(w=1, h=2, K=3100, K_out=60, nu_ext_hz=[2600.0, 2600.0])]
+    for k, p in enumerate(cases):
+        _say("queue cap", cap, "schedule", sched, "case", k)
+        net, orc = _pair(p, 3, queue_cap=cap)
+        L.dpsnn_set_schedule(net, sched)
+        want = {-1: 0, 0: 4096}.get(cap, cap)
+        assert net.stats()["queue_cap"] == want
+        n = 0
+        for j in range(3):
+            L.dpsnn_step(net, 300)
+            orc.step(300)
+            n += _compare_all(L, net, orc, (cap, sched, k, j))
+        assert n > 200
+        net.close()
+
+
+def test_queues_off_past_128_slots(L):
+    p = W.tiny(w=2, h=2, K=200, K_out=40, d_min=100, d_max=130,
+               nu_ext_hz=[2600.0, 2600.0])
+    _say("131 slots")
+    net, orc = _pair(p, 2)
+    assert net.stats()["queue_cap"] == 0
+    L.dpsnn_step(net, 400)
+    orc.step(400)
+    assert _compare_all(L, net, orc, "131 slots") > 0
     net.close()

@@ -110,3 +110,41 @@ def test_abi_version_checked():
     s.abi_version = 99
     import ctypes as C
     assert L.lib().dpsnn_host_table(C.byref(s), b"prop_f64", None, 0) == -1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Sizes and field offsets of the ctypes structs equal those of the C
+    header (compiled here with the host C compiler)."""
+    import ctypes as C
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = []
+    for cname, py in (("dpsnn_params", L.DpsnnParams), ("dpsnn_stats", L.DpsnnStats)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            cf = "lambda" if f == "lambda_" else f
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {cf}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"dpsnn.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        a, b, v = ln.split()
+        got[(a, b)] = int(v)
+    for cname, py in (("dpsnn_params", L.DpsnnParams), ("dpsnn_stats", L.DpsnnStats)):
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_queue_cap_validated():
+    for cap in (-2, (1 << 20) + 1):
+        with pytest.raises(L.DpsnnError) as e:
+            L.dpsnn_host_table(W.swa(queue_cap=cap), "prop_f64", np.float64)
+        assert e.value.code == -1
+    for cap in (-1, 0, 1, 1 << 20):
+        assert len(L.dpsnn_host_table(W.swa(queue_cap=cap), "prop_f64", np.float64)) == 8
