@@ -135,6 +135,8 @@ int build_impl(dpsnn_net* n) {
     HIP_OK(hipMemsetAsync(absum, 0, (size_t)Np * 8 + 256, st));
   }
 
+  void* jx_all = dev_alloc(n, (size_t)nn * 2 * kQuantN * ab);
+  if (!jx_all) return DPSNN_E_NOMEM;
   std::vector<NetDev> nd(nn);
   std::vector<int32_t> tn((size_t)n_tiles);
   std::vector<int64_t> sf((size_t)M * 2);
@@ -149,9 +151,9 @@ int build_impl(dpsnn_net* n) {
     int32_t* off_xy = (int32_t*)dev_alloc(n, std::max<size_t>(T.off_xy.size(), 2) * 4);
     void* wtab[2];
     for (int q = 0; q < 2; ++q) wtab[q] = dev_alloc(n, (size_t)kQuantN * wb);
-    void* jx = dev_alloc(n, (size_t)2 * kQuantN * ab);
+    void* jx = static_cast<unsigned char*>(jx_all) + (size_t)k * 2 * kQuantN * ab;
     int64_t* wfix_dev = absum ? (int64_t*)dev_alloc(n, (size_t)2 * kQuantN * 8) : nullptr;
-    if (!off_thr || !off_xy || !wtab[0] || !wtab[1] || !jx || (absum && !wfix_dev))
+    if (!off_thr || !off_xy || !wtab[0] || !wtab[1] || (absum && !wfix_dev))
       return DPSNN_E_NOMEM;
     if (!T.off_thr.empty())
       HIP_OK(hipMemcpyAsync(off_thr, T.off_thr.data(), T.off_thr.size() * 4,
@@ -260,7 +262,6 @@ int build_impl(dpsnn_net* n) {
       d.n_pois[q] = T.n_pois[q];
       for (int x = 0; x < kMaxPois; ++x) d.pois[q][x] = T.pois[q][x];
     }
-    d.jxfix = jx;
   }
   HIP_OK(hipMemcpyAsync(nets, nd.data(), sizeof(NetDev) * nn, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(tile_net, tn.data(), tn.size() * 4, hipMemcpyHostToDevice, st));
@@ -293,6 +294,7 @@ int build_impl(dpsnn_net* n) {
   a.spike_log_cap = p0.spike_log_cap;
   a.nets = nets;
   a.tile_net = tile_net;
+  a.jx = jx_all;
   a.V = V;
   a.c = c;
   a.ref = ref;
@@ -324,6 +326,7 @@ int build_impl(dpsnn_net* n) {
   if (qcap > 0) {
     a.q_cap = (int32_t)qcap;
     a.in_cap = (int32_t)(2 * qcap);
+    a.route_blocks = (int32_t)std::min<int64_t>(n_tiles, 4096);
     const size_t eb = ab == 4 ? sizeof(QEntry<int32_t>) : sizeof(QEntry<int64_t>);
     const size_t n_in = (size_t)2 * n_tiles * a.in_cap;
     const size_t n_q = (size_t)n_tiles * T0.D * qcap;

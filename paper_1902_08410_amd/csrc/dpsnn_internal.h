@@ -89,7 +89,6 @@ struct NetDev {
   int32_t n_arp[2];
   int32_t n_pois[2];
   uint32_t pois[2][kMaxPois];
-  const void* jxfix;        // [2][65536] external fixed-point efficacies
 };
 
 // Arguments of the step kernels (passed by value).
@@ -97,12 +96,15 @@ struct StepArgs {
   int64_t N_pad;           // size of the global index space
   int32_t K_out, row_stride, D, n_del, d_min, M;  // M: modules of all networks
   int32_t n_tiles;         // neuron tiles of 1024 = N_pad / 1024
-  int32_t deliver_blocks;  // grid of the delivery kernel
+  int32_t deliver_blocks;  // delivery blocks of the delivery kernel
+  int32_t route_blocks;    // inbox-routing blocks that follow them
   int32_t rate_bin_steps, rate_bins_cap;
   float inv2q, two_q;
   int64_t spike_log_cap;
   const NetDev* nets;
   const int32_t* tile_net;  // [n_tiles] network of each tile
+  const void* jx;          // [networks][2][65536] external fixed-point
+                           // efficacies of the slot width
   float* V;
   float* c;
   uint8_t* ref;

@@ -54,6 +54,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier that orders LDS only: global loads and stores issued
+// before it stay in flight (a full __syncthreads waits for all of them).
+// Used where threads share data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------------
 // Connectivity generation
 __host__ __device__ inline int gen_pow2(int Ko) {
@@ -234,11 +243,61 @@ __device__ __forceinline__ void lds_add<int64_t>(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 
-// LDS of the queue consumer of one tile.
+// Event queues of one tile.  At step t the tile sums the queue of slot
+// t mod D and the events of its inbox of step t-1 that arrive now
+// (gather_now, before the neuron update); the other events of that inbox are
+// moved into the tile's per-slot queues (route_inbox), off the update's
+// path: in the delivery kernel of the same step for the split schedule.
+// Entries are loaded kQBatch per thread at a time before any is used, so
+// that their memory latency is paid once per batch.
+constexpr int kQBatch = 8;
+
 template <typename Acc>
-struct QueueLds {
-  Acc in[1024];             // input sums of the tile's neurons
-  Acc sw[kStage];           // routed events, grouped by slot
+__device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t t, Acc* s_in) {
+  const int D = a.D;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int cur = (int)(t % (uint32_t)D);
+  const uint32_t par = (t - 1u) & 1u;
+  const uint32_t qn = a.q_cnt[(int64_t)tile * D + cur];
+  const uint32_t n_cur = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
+  uint32_t n_in = 0;
+  if (a.d_min == 1) {  // only then can an event of step t-1 arrive at t
+    const uint32_t got = a.in_cnt[((int64_t)par * a.n_tiles + tile) * kInboxStride];
+    n_in = got < (uint32_t)a.in_cap ? got : (uint32_t)a.in_cap;
+  }
+  for (int k = tid; k < 1024; k += nth) s_in[k] = 0;
+  lds_barrier();
+  const QEntry<Acc>* qq =
+      static_cast<const QEntry<Acc>*>(a.q_q) + ((int64_t)tile * D + cur) * a.q_cap;
+  const QEntry<Acc>* iq =
+      static_cast<const QEntry<Acc>*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
+  const uint32_t n_max = n_cur > n_in ? n_cur : n_in;
+  for (uint32_t r0 = 0; r0 < n_max; r0 += (uint32_t)nth * kQBatch) {
+    QEntry<Acc> ce[kQBatch], ie[kQBatch];
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      const uint32_t e = r0 + (uint32_t)(u * nth + tid);
+      ce[u].x = 0xFFFFFFFFu;
+      ie[u].x = 0xFFFFFFFFu;
+      if (e < n_cur) ce[u] = qq[e];
+      if (e < n_in) ie[u] = iq[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      if (ce[u].x != 0xFFFFFFFFu) lds_add<Acc>(&s_in[ce[u].x & 1023u], ce[u].w);
+      if (ie[u].x != 0xFFFFFFFFu && (ie[u].x >> 10) == 0u)  // delay d_min = 1
+        lds_add<Acc>(&s_in[ie[u].x & 1023u], ie[u].w);
+    }
+  }
+  lds_barrier();
+  // every thread has used the count: the current queue is empty now
+  if (tid == 0) a.q_cnt[(int64_t)tile * D + cur] = 0;
+}
+
+// LDS of route_inbox.
+template <typename Acc>
+struct RouteLds {
+  Acc sw[kStage];                 // routed events, grouped by slot
   uint16_t sx[kStage];
   uint8_t ss[kStage];
   uint32_t qc[kQueueMaxSlots];    // queue counts before this step
@@ -246,67 +305,48 @@ struct QueueLds {
   uint32_t off[kQueueMaxSlots];   // their first staging position
 };
 
-// Event queues of one tile at step t (all threads of the block call it).
-// The inbox filled by the delivery of step t-1 is routed: events arriving
-// now are summed into L.in; the others are grouped by arrival slot in LDS
-// and appended to the tile's per-slot queues as one contiguous run per slot
-// (past the staging space or a full queue they are added into the slot).
-// The queue of slot t mod D is summed into L.in and emptied.  Entries are
-// loaded kQBatch per thread at a time before any is used, so that their
-// memory latency is paid once per batch.
-constexpr int kQBatch = 8;
-
+// Moves the events of the inbox of step t-1 that arrive after t into the
+// tile's per-slot queues, one contiguous run per slot (past the staging
+// space or a full queue they are added into the slot), and empties the
+// inbox.  The queue of slot t mod D is neither read nor written.
 template <typename Acc>
-__device__ __forceinline__ void consume_queues(const StepArgs& a, int tile, uint32_t t,
-                                               QueueLds<Acc>& L) {
+__device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_t t,
+                                            RouteLds<Acc>& L) {
   const int D = a.D;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int cur = (int)(t % (uint32_t)D);
   const uint32_t par = (t - 1u) & 1u;
   const int64_t ic = ((int64_t)par * a.n_tiles + tile) * kInboxStride;
   const uint32_t got = a.in_cnt[ic];
-  const uint32_t qn = a.q_cnt[(int64_t)tile * D + cur];
   const uint32_t n_in = got < (uint32_t)a.in_cap ? got : (uint32_t)a.in_cap;
-  const uint32_t n_cur = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
-  for (int k = tid; k < 1024; k += nth) L.in[k] = 0;
   for (int k = tid; k < D; k += nth) {
     L.qc[k] = a.q_cnt[(int64_t)tile * D + k];
     L.cnew[k] = 0;
   }
-  __syncthreads();
-  if (tid == 0) a.in_cnt[ic] = 0;
+  lds_barrier();
   Acc* slots = static_cast<Acc*>(a.slots);
-  const QEntry<Acc>* qq = static_cast<const QEntry<Acc>*>(a.q_q);
-  const QEntry<Acc>* iq = static_cast<const QEntry<Acc>*>(a.in_q);
+  const QEntry<Acc>* iq =
+      static_cast<const QEntry<Acc>*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
+  QEntry<Acc>* qw = static_cast<QEntry<Acc>*>(a.q_q);
   const int64_t qb = (int64_t)tile * D * a.q_cap;
-  const int64_t qc = qb + (int64_t)cur * a.q_cap;
-  const int64_t ib = ((int64_t)par * a.n_tiles + tile) * a.in_cap;
-  const uint32_t n_max = n_cur > n_in ? n_cur : n_in;
-  // events of the inbox are kept in registers between the passes (at most
-  // kQBatch per thread; larger inboxes take more rounds of the whole scheme)
-  for (uint32_t r0 = 0; r0 < n_max; r0 += (uint32_t)nth * kQBatch) {
-    QEntry<Acc> ce[kQBatch], ie[kQBatch];
+  for (uint32_t r0 = 0; r0 < n_in; r0 += (uint32_t)nth * kQBatch) {
+    QEntry<Acc> ie[kQBatch];
     int sl[kQBatch];
     uint32_t rk[kQBatch];
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      ce[u].x = 0xFFFFFFFFu;
       ie[u].x = 0xFFFFFFFFu;
-      if (e < n_cur) ce[u] = qq[qc + e];
-      if (e < n_in) ie[u] = iq[ib + e];
+      if (e < n_in) ie[u] = iq[e];
     }
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
-      if (ce[u].x != 0xFFFFFFFFu) lds_add<Acc>(&L.in[ce[u].x & 1023u], ce[u].w);
       sl[u] = -1;
       if (ie[u].x != 0xFFFFFFFFu) {
         const uint32_t x = ie[u].x;
         const int dk = (int)(x >> 10) < a.n_del ? (int)(x >> 10) : a.n_del - 1;
         const int off = a.d_min + dk - 1;  // arrival in off steps: 0 .. D - 2
-        if (off == 0) {
-          lds_add<Acc>(&L.in[x & 1023u], ie[u].w);
-        } else {
+        if (off > 0) {
           int s2 = cur + off;
           if (s2 >= D) s2 -= D;
           sl[u] = s2;
@@ -314,7 +354,7 @@ __device__ __forceinline__ void consume_queues(const StepArgs& a, int tile, uint
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < 64) {  // exclusive scan of the per-slot counts (D <= 128)
       const uint32_t c0 = 2 * tid < D ? L.cnew[2 * tid] : 0u;
       const uint32_t c1 = 2 * tid + 1 < D ? L.cnew[2 * tid + 1] : 0u;
@@ -328,7 +368,7 @@ __device__ __forceinline__ void consume_queues(const StepArgs& a, int tile, uint
       if (2 * tid < D) L.off[2 * tid] = ex;
       if (2 * tid + 1 < D) L.off[2 * tid + 1] = ex + c0;
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       if (sl[u] < 0) continue;
@@ -343,11 +383,9 @@ __device__ __forceinline__ void consume_queues(const StepArgs& a, int tile, uint
                             ie[u].w);
       }
     }
-    __syncthreads();
-    uint32_t total = 0;
-    if (D > 0) total = L.off[D - 1] + L.cnew[D - 1];
+    lds_barrier();
+    const uint32_t total = L.off[D - 1] + L.cnew[D - 1];
     const uint32_t staged = total < (uint32_t)kStage ? total : (uint32_t)kStage;
-    QEntry<Acc>* qw = static_cast<QEntry<Acc>*>(a.q_q);
     for (uint32_t e = tid; e < staged; e += nth) {
       const int s2 = L.ss[e];
       const uint32_t gpos = L.qc[s2] + (e - L.off[s2]);
@@ -362,18 +400,21 @@ __device__ __forceinline__ void consume_queues(const StepArgs& a, int tile, uint
                             L.sw[e]);
       }
     }
-    __syncthreads();
+    lds_barrier();
     // queue counts after this round: staged events only (the rest went to
-    // the slots); the current queue is empty
+    // the slots)
     for (int k = tid; k < D; k += nth) {
       const uint32_t o = L.off[k], c = L.cnew[k];
       const uint32_t st = o >= (uint32_t)kStage ? 0u : (o + c <= (uint32_t)kStage ? c : kStage - o);
-      L.qc[k] = k == cur ? 0u : L.qc[k] + st;
+      L.qc[k] += st;
       L.cnew[k] = 0;
     }
-    __syncthreads();
+    lds_barrier();
   }
-  for (int k = tid; k < D; k += nth) a.q_cnt[(int64_t)tile * D + k] = k == cur ? 0u : L.qc[k];
+  // every thread has used the inbox count by now
+  if (tid == 0) a.in_cnt[ic] = 0;
+  for (int k = tid; k < D; k += nth)
+    if (k != cur) a.q_cnt[(int64_t)tile * D + k] = L.qc[k];
 }
 
 // ------------------------------------------------------------------------
@@ -392,8 +433,8 @@ struct NeuronRegs {
 };
 
 template <typename Acc>
-__device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd, int64_t i0,
-                                            uint32_t t, NeuronRegs<Acc>& R) {
+__device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd, int net,
+                                            int64_t i0, uint32_t t, NeuronRegs<Acc>& R) {
   const int slot = (int)(t % (uint32_t)a.D);
   Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
   if (sizeof(Acc) == 4) {
@@ -423,26 +464,40 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
   const int64_t m0 = il0 / nd.K;
   const int l0 = (int)(il0 - m0 * nd.K);
   int q[4], k[4];
-  int kmax = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
     q[j] = lj < nd.K_exc ? 0 : 1;
-    int kk = 0;
-    for (int x = 0; x < nd.n_pois[q[j]]; ++x) kk += uu[j] >= nd.pois[q[j]][x] ? 1 : 0;
-    k[j] = kk;
-    kmax = kk > kmax ? kk : kmax;
+    k[j] = 0;
   }
-  const Acc* jx = static_cast<const Acc*>(nd.jxfix);
+  // Poisson counts: thresholds are uniform over the block (scalar loads),
+  // each lane picks its population's
+  const int np0 = nd.n_pois[0], np1 = nd.n_pois[1];
+#pragma unroll
+  for (int x = 0; x < kMaxPois; ++x) {
+    const uint32_t t0 = nd.pois[0][x], t1 = nd.pois[1][x];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool in_range = x < (q[j] ? np1 : np0);
+      if (in_range && uu[j] >= (q[j] ? t1 : t0)) k[j] += 1;
+    }
+  }
+  int kmax = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) kmax = k[j] > kmax ? k[j] : kmax;
+  const Acc* jx = static_cast<const Acc*>(a.jx) + (int64_t)net * 2 * kQuantN;
   for (int b = 0; 2 * b < kmax; ++b) {
     const uint4 v = philox10(make_uint4(g, t, 0u, kTagExtJ | ((uint32_t)b << 8)), nd.key0, nd.key1);
     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+    Acc e0[4], e1[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (2 * b < k[j]) R.I[j] += jx[q[j] * kQuantN + (vv[j] >> 16)];
-      if (2 * b + 1 < k[j]) R.I[j] += jx[q[j] * kQuantN + (vv[j] & 0xFFFFu)];
+    for (int j = 0; j < 4; ++j) {  // issue the table loads before any is used
+      e0[j] = 2 * b < k[j] ? jx[q[j] * kQuantN + (vv[j] >> 16)] : (Acc)0;
+      e1[j] = 2 * b + 1 < k[j] ? jx[q[j] * kQuantN + (vv[j] & 0xFFFFu)] : (Acc)0;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) R.I[j] += e0[j] + e1[j];
   }
 }
 
@@ -457,34 +512,41 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
   const int64_t il0 = i0 - nd.base;
   const int64_t m0 = il0 / nd.K;
   const int l0 = (int)(il0 - m0 * nd.K);
+  // per-population constants: uniform loads, selected per lane
+  const float Pm0 = nd.Pm[0], Pm1 = nd.Pm[1], Pc0 = nd.Pc[0], Pc1 = nd.Pc[1];
+  const float PVc0 = nd.PVc[0], PVc1 = nd.PVc[1], It0 = nd.Iterm[0], It1 = nd.Iterm[1];
+  const float E0 = nd.E[0], E1 = nd.E[1], Vth0 = nd.Vth[0], Vth1 = nd.Vth[1];
+  const float Vr0 = nd.Vr[0], Vr1 = nd.Vr[1], al0 = nd.alpha[0], al1 = nd.alpha[1];
+  const int na0 = nd.n_arp[0], na1 = nd.n_arp[1];
   uint32_t r_out = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
-    const int qq = lj < nd.K_exc ? 0 : 1;
+    const bool inh = lj >= nd.K_exc;
     uint32_t rj = (R.r4 >> (8 * j)) & 0xFFu;
     if (il0 + j < nd.N) {
       const float dv = fix_to_f32(R.I[j]) * a.inv2q;
       float Vj = R.V[j], cj = R.c[j];
+      const float Pc = inh ? Pc1 : Pc0, E = inh ? E1 : E0;
       bool spk = false;
       if (rj > 0) {
         rj -= 1;
-        cj = cj * nd.Pc[qq];
+        cj = cj * Pc;
       } else {
-        float vv = Vj - nd.E[qq];
-        vv = vv * nd.Pm[qq];
-        vv = nd.E[qq] + vv;
-        const float cc = cj * nd.PVc[qq];
+        float vv = Vj - E;
+        vv = vv * (inh ? Pm1 : Pm0);
+        vv = E + vv;
+        const float cc = cj * (inh ? PVc1 : PVc0);
         vv = vv - cc;
-        vv = vv + nd.Iterm[qq];
+        vv = vv + (inh ? It1 : It0);
         vv = vv + dv;
-        cj = cj * nd.Pc[qq];
-        if (vv > nd.Vth[qq]) {
+        cj = cj * Pc;
+        if (vv > (inh ? Vth1 : Vth0)) {
           spk = true;
-          vv = nd.Vr[qq];
-          cj = cj + nd.alpha[qq];
-          rj = (uint32_t)nd.n_arp[qq];
+          vv = inh ? Vr1 : Vr0;
+          cj = cj + (inh ? al1 : al0);
+          rj = (uint32_t)(inh ? na1 : na0);
         }
         Vj = vv;
       }
@@ -660,21 +722,22 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 template <typename Acc>
 __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
-  __shared__ QueueLds<Acc> s_q;
+  __shared__ Acc s_in[1024];
   __shared__ int s_n;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
   const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
-  const NetDev& nd = a.nets[a.tile_net[blockIdx.x]];
+  const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
+  const NetDev& nd = a.nets[net];
   NeuronRegs<Acc> R;
-  neuron_load<Acc>(a, nd, i0, t, R);
+  neuron_load<Acc>(a, nd, net, i0, t, R);
   if (a.q_cap)
-    consume_queues<Acc>(a, blockIdx.x, t, s_q);
+    gather_now<Acc>(a, blockIdx.x, t, s_in);
   else
-    __syncthreads();
-  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_q.in : nullptr, s_spk, &s_n);
-  __syncthreads();
+    lds_barrier();
+  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  lds_barrier();
   const int n = s_n;
   int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
   for (int k = tid; k < n; k += 256) out[k] = s_spk[k];
@@ -683,12 +746,22 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
 
 template <typename Acc, int WDT>
 __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
-  extern __shared__ int32_t s_pref[];  // inclusive prefix of the tile counts
+  // delivery blocks: inclusive prefix of the tile counts; routing blocks:
+  // their RouteLds
+  extern __shared__ __align__(16) int32_t s_pref[];
   __shared__ int32_t s_part[256];
   __shared__ uint32_t s_b[4][256];
   const int tid = threadIdx.x;
   const int nb = a.n_tiles;
   const uint32_t t = a.t_base[0] + t_off;
+  if ((int)blockIdx.x >= a.deliver_blocks) {
+    // routing of the inboxes of step t-1, one tile at a time
+    RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_pref);
+    const int nr = (int)gridDim.x - a.deliver_blocks;
+    for (int tile = (int)blockIdx.x - a.deliver_blocks; tile < nb; tile += nr)
+      route_inbox<Acc>(a, tile, t, L);
+    return;
+  }
   // block-wide scan: each thread sums a contiguous run of tile counts
   const int per = (nb + 255) / 256;
   const int lo = tid * per;
@@ -696,19 +769,19 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   int run = 0;
   for (int b = lo; b < hi; ++b) run += a.blk_cnt[b];
   s_part[tid] = run;
-  __syncthreads();
+  lds_barrier();
   for (int off = 1; off < 256; off <<= 1) {
     const int v = tid >= off ? s_part[tid - off] : 0;
-    __syncthreads();
+    lds_barrier();
     s_part[tid] += v;
-    __syncthreads();
+    lds_barrier();
   }
   int acc = s_part[tid] - run;
   for (int b = lo; b < hi; ++b) {
     acc += a.blk_cnt[b];
     s_pref[b] = acc;
   }
-  __syncthreads();
+  lds_barrier();
   const int n_spk = s_part[255];
   const unsigned long long log0 = a.log_base[t & 1];
   if (blockIdx.x == 0 && tid == 0) {
@@ -719,7 +792,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   const int64_t items = (int64_t)n_spk * cpr;
   const int lane = tid & 63;
   const int64_t wid = (int64_t)blockIdx.x * 4 + (tid >> 6);
-  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int64_t nw = (int64_t)a.deliver_blocks * 4;  // delivery wavefronts
   for (int64_t it = wid; it < items; it += nw) {
     const int sidx = (int)(it / cpr);
     const int chunk = (int)(it - (int64_t)sidx * cpr);
@@ -744,7 +817,8 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
 template <typename Acc, int WDT>
 __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
-  __shared__ QueueLds<Acc> s_q;
+  __shared__ Acc s_in[1024];
+  __shared__ RouteLds<Acc> s_route;
   __shared__ uint32_t s_b[4][256];
   __shared__ int s_n;
   __shared__ unsigned long long s_logbase;
@@ -752,15 +826,17 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   if (tid == 0) s_n = 0;
   const uint32_t t = a.t_base[0] + t_off;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
-  const NetDev& nd = a.nets[a.tile_net[blockIdx.x]];
+  const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
+  const NetDev& nd = a.nets[net];
   NeuronRegs<Acc> R;
-  neuron_load<Acc>(a, nd, i0, t, R);
+  neuron_load<Acc>(a, nd, net, i0, t, R);
   if (a.q_cap)
-    consume_queues<Acc>(a, blockIdx.x, t, s_q);
+    gather_now<Acc>(a, blockIdx.x, t, s_in);
   else
-    __syncthreads();
-  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_q.in : nullptr, s_spk, &s_n);
-  __syncthreads();
+    lds_barrier();
+  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  if (a.q_cap) route_inbox<Acc>(a, blockIdx.x, t, s_route);  // has barriers
+  lds_barrier();
   const int n = s_n;
   if (n == 0) return;
   if (tid == 0) {
@@ -769,7 +845,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
     atomicAdd(&a.log_base[(t + 1) & 1], (unsigned long long)n);
     atomicAdd(a.n_spikes, (unsigned long long)n);
   }
-  __syncthreads();
+  lds_barrier();
   for (int k = tid; k < n; k += 256)
     record_spike(a, s_spk[k], t, s_logbase + (unsigned long long)k);
   const int lane = tid & 63, wave = tid >> 6;
@@ -859,12 +935,21 @@ hipError_t launch_init(const InitArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Dynamic LDS of the delivery kernel: the larger of the tile-count prefix
+// and the routing blocks' RouteLds.
+template <typename Acc>
+static size_t deliver_lds(const StepArgs& a) {
+  const size_t pref = (size_t)a.n_tiles * 4;
+  const size_t route = a.route_blocks ? sizeof(RouteLds<Acc>) : 0;
+  return pref > route ? pref : route;
+}
+
 template <typename Acc>
 static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
   hipLaunchKernelGGL(k_neuron<Acc>, tiles, block, 0, st, a, t_off);
-  const size_t lds = (size_t)a.n_tiles * 4;
-  const dim3 grid((unsigned)a.deliver_blocks);
+  const size_t lds = deliver_lds<Acc>(a);
+  const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
   if (wdt == DPSNN_W_F32)
     hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
   else if (wdt == DPSNN_W_F16)
@@ -904,8 +989,8 @@ hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint
 hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uint32_t t_off,
                         hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
-  const dim3 grid((unsigned)a.deliver_blocks);
-  const size_t lds = (size_t)a.n_tiles * 4;
+  const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
+  const size_t lds = acc_bits == 32 ? deliver_lds<int32_t>(a) : deliver_lds<int64_t>(a);
   if (phase == 0) {
     if (acc_bits == 32)
       hipLaunchKernelGGL(k_neuron<int32_t>, tiles, block, 0, st, a, t_off);

@@ -421,3 +421,22 @@ def test_queues_off_past_128_slots(L):
     orc.step(400)
     assert _compare_all(L, net, orc, "131 slots") > 0
     net.close()
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+def test_more_work_items_than_delivery_wavefronts(L, sched):
+    """A 4x4 grid driven hard enough that about a third of the steps have
+    more (spike, chunk) work items than the delivery kernel has wavefronts,
+    with the inbox-routing blocks present: rasters, state and slots equal
+    the oracle's."""
+    p = W.tiny(w=4, h=4, K=700, K_out=1000, nu_ext_hz=[60000.0, 60000.0])
+    _say("many work items, schedule", sched)
+    net, orc = _pair(p, 4)
+    L.dpsnn_set_schedule(net, sched)
+    n = 0
+    for j in range(3):
+        L.dpsnn_step(net, 100)
+        orc.step(100)
+        n += _compare_all(L, net, orc, ("many items", sched, j))
+    assert n > 50000
+    net.close()
