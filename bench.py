@@ -337,14 +337,15 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic,
-            "kernel": "k_deliver (spike delivery, fixed-point atomics into input slots)",
+            "kernel": "k_deliver (spike delivery: one inbox reservation per target-tile run, "
+                      "plus the inbox routers)",
             "bytes_per_event": Be,
             "events_per_launch": ev_per_launch,
             "algorithmic_bytes_per_launch": alg_del,
             "avg_launch_us": del_us,
-            "atomic_rate_G_per_s": ev_per_launch / del_us / 1e3 if del_us > 0 else None,
-            "atomic_ceiling_G_per_s": 27.0,
-            "update_kernel": {"kernel": "k_neuron", "avg_launch_us": upd_us,
+            "events_per_s_in_kernel": ev_per_launch / (del_us * 1e-6) if del_us > 0 else None,
+            "update_kernel": {"kernel": "k_neuron (update, with the queued-input gather)",
+                              "avg_launch_us": upd_us,
                               "algorithmic_bytes_per_launch": n_mean * Bn,
                               "achieved_GB_s": n_mean * Bn / (upd_us * 1e-6) / 1e9
                               if upd_us else None,
@@ -355,7 +356,9 @@ def main():
         "per_handle": {k: {"spikes": spikes[k], "rate_hz": rates[k],
                            "events_per_s": spikes[k] * K_OUT / wall,
                            "build_ms": nets[k][0].stats()["build_ms"],
-                           "schedule": "split" if sched[k] == 1 else "fused"} for k in nets},
+                           "schedule": "split" if sched[k] == 1 else "fused",
+                           "deliver_blocks": nets[k][0].stats()["deliver_blocks"]}
+                       for k in nets},
         "gpu_ms_timed": gpu_ms,
         "weight_variants": variants,
     }

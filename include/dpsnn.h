@@ -128,6 +128,8 @@ typedef struct dpsnn_stats {
                              index space of all networks (see below)      */
   int32_t n_nets;         /* networks in the handle                        */
   int32_t queue_cap;      /* entries per input queue in use (0 = none)   */
+  int32_t deliver_blocks; /* grid of the split schedule's delivery kernel  */
+  int32_t route_blocks;   /* inbox-routing blocks beside it               */
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */
@@ -190,9 +192,10 @@ int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
 int dpsnn_set_graph_steps(dpsnn_net* net, int64_t steps);
 
 /*
- * Time probe_steps real steps with each available schedule (they advance
- * the simulation; results do not depend on the schedule) and keep the
- * fastest; *chosen (may be NULL) receives it.  Synchronises.
+ * Time probe_steps real steps with each available schedule, and for the
+ * split schedule with several grid sizes of the delivery kernel (they
+ * advance the simulation; results do not depend on either) and keep the
+ * fastest; *chosen (may be NULL) receives the schedule.  Synchronises.
  */
 int dpsnn_autotune(dpsnn_net* net, int64_t probe_steps, int32_t* chosen);
 

@@ -286,7 +286,7 @@ int build_impl(dpsnn_net* n) {
   a.d_min = p0.d_min;
   a.M = (int32_t)M;
   a.n_tiles = (int32_t)n_tiles;
-  a.deliver_blocks = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(256, n_tiles));
+  a.deliver_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(256, n_tiles));
   a.rate_bin_steps = p0.rate_bin_steps;
   a.rate_bins_cap = (int32_t)p0.rate_bins_cap;
   a.inv2q = ldexpf(1.0f, -p0.q_frac_bits);
@@ -421,6 +421,7 @@ void drop_graph(dpsnn_net* n) {
 // counter update; replays then need no host work per step.
 int ensure_graph(dpsnn_net* n) {
   if (n->graph && n->graph_sched == n->sched && n->graph_stream == n->stream &&
+      n->graph_blocks == n->sa.deliver_blocks &&
       n->graph_K == n->graph_steps)
     return DPSNN_OK;
   drop_graph(n);
@@ -443,6 +444,7 @@ int ensure_graph(dpsnn_net* n) {
   n->graph = ge;
   n->graph_K = (int)n->graph_steps;
   n->graph_sched = n->sched;
+  n->graph_blocks = n->sa.deliver_blocks;
   n->graph_stream = n->stream;
   return DPSNN_OK;
 }
@@ -496,16 +498,31 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
 
 int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   if (!n || probe_steps < 1) return DPSNN_E_INVAL;
-  const int cands[2] = {DPSNN_SCHED_FUSED, DPSNN_SCHED_SPLIT};
+  // candidates: the fused schedule, and the split one with several grids of
+  // the delivery kernel
+  struct Cand {
+    int sched;
+    int32_t blocks;
+  };
+  std::vector<Cand> cands;
+  cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks});
+  if (n->split_ok) {
+    const int32_t tiles = n->sa.n_tiles;
+    for (int32_t b : {std::min<int32_t>(1024, std::max<int32_t>(256, tiles)), 512, 1024, 2048}) {
+      bool seen = false;
+      for (const Cand& c : cands) seen |= c.sched == DPSNN_SCHED_SPLIT && c.blocks == b;
+      if (!seen) cands.push_back({DPSNN_SCHED_SPLIT, b});
+    }
+  }
   float best_ms = -1.f;
-  int best = n->sched;
+  Cand best{n->sched, n->sa.deliver_blocks};
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   int rc = DPSNN_OK;
-  for (int c : cands) {
-    if (c == DPSNN_SCHED_SPLIT && !n->split_ok) continue;
-    n->sched = c;
+  for (const Cand& c : cands) {
+    n->sched = c.sched;
+    n->sa.deliver_blocks = c.blocks;
     // one untimed pass builds the graph and warms the caches
     if ((rc = dpsnn_step(n, probe_steps)) != DPSNN_OK) break;
     if (hipEventRecord(e0, n->stream) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
@@ -521,8 +538,9 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  n->sched = best;
-  if (chosen) *chosen = best;
+  n->sched = best.sched;
+  n->sa.deliver_blocks = best.blocks;
+  if (chosen) *chosen = best.sched;
   return rc;
 }
 
@@ -661,6 +679,8 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->n_index = n->N_index;
   out->n_nets = (int32_t)n->p.size();
   out->queue_cap = n->sa.q_cap;
+  out->deliver_blocks = n->sa.deliver_blocks;
+  out->route_blocks = n->sa.route_blocks;
   return DPSNN_OK;
 }
 

@@ -201,6 +201,7 @@ struct dpsnn_net {
   // captured steps: graph_K steps of the current schedule on `stream`
   hipGraphExec_t graph = nullptr;
   int graph_K = 0, graph_sched = -1;
+  int32_t graph_blocks = 0;     // delivery grid captured in the graph
   hipStream_t graph_stream = nullptr;
   int64_t graph_steps = 128;    // steps per captured graph (0 = no graphs)
 };

@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   // delivery blocks: inclusive prefix of the tile counts; routing blocks:
   // their RouteLds
   extern __shared__ __align__(16) int32_t s_pref[];
-  __shared__ int32_t s_part[256];
+  __shared__ int32_t s_part[8];
   __shared__ uint32_t s_b[4][256];
   const int tid = threadIdx.x;
   const int nb = a.n_tiles;
@@ -762,27 +762,33 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
       route_inbox<Acc>(a, tile, t, L);
     return;
   }
-  // block-wide scan: each thread sums a contiguous run of tile counts
+  // block-wide inclusive scan of the tile counts: a coalesced copy into
+  // LDS, each thread scans a contiguous run, wavefront shuffles and one
+  // exchange of the four wavefront totals
+  for (int b = tid; b < nb; b += 256) s_pref[b] = a.blk_cnt[b];
+  lds_barrier();
   const int per = (nb + 255) / 256;
   const int lo = tid * per;
   const int hi = lo + per < nb ? lo + per : nb;
   int run = 0;
-  for (int b = lo; b < hi; ++b) run += a.blk_cnt[b];
-  s_part[tid] = run;
-  lds_barrier();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int v = tid >= off ? s_part[tid - off] : 0;
-    lds_barrier();
-    s_part[tid] += v;
-    lds_barrier();
+  for (int b = lo; b < hi; ++b) run += s_pref[b];
+  int incl = run;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if ((tid & 63) >= off) incl += v;
   }
-  int acc = s_part[tid] - run;
+  if ((tid & 63) == 63) s_part[tid >> 6] = incl;
+  lds_barrier();
+  int acc = incl - run;
+  for (int w = 0; w < (tid >> 6); ++w) acc += s_part[w];
   for (int b = lo; b < hi; ++b) {
-    acc += a.blk_cnt[b];
+    acc += s_pref[b];
     s_pref[b] = acc;
   }
+  if (tid == 255) s_part[4] = acc;
   lds_barrier();
-  const int n_spk = s_part[255];
+  const int n_spk = s_part[4];
   const unsigned long long log0 = a.log_base[t & 1];
   if (blockIdx.x == 0 && tid == 0) {
     a.log_base[(t + 1) & 1] = log0 + (unsigned long long)n_spk;

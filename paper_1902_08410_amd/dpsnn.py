@@ -46,6 +46,7 @@ class DpsnnStats(C.Structure):
         ("build_ms", C.c_double), ("bytes_rows", C.c_int64), ("bytes_state", C.c_int64),
         ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("schedule", C.c_int32),
         ("n_index", C.c_int64), ("n_nets", C.c_int32), ("queue_cap", C.c_int32),
+        ("deliver_blocks", C.c_int32), ("route_blocks", C.c_int32),
     ]
 
 

@@ -283,10 +283,18 @@ def test_graph_replay_and_schedule_switching(L):
             orc.step(n)
             total += _compare_all(L, net, orc, ("chunk", k, sched))
         assert total > 200
+        t0 = net.stats()["t"]
         chosen = L.dpsnn_autotune(net, 200)
-        orc.step(800)
-        assert chosen in (0, 1)
+        st = net.stats()
+        assert chosen in (0, 1) and st["schedule"] == chosen
+        # two passes per candidate: the fused schedule and split delivery grids
+        assert (st["t"] - t0) % 400 == 0 and st["t"] - t0 >= 800
+        assert st["deliver_blocks"] in (256, 512, 1024, 2048)
+        orc.step(st["t"] - t0)
         _compare_all(L, net, orc, "after autotune")
+        L.dpsnn_step(net, 300)               # the tuned grid, replayed from graphs
+        orc.step(300)
+        _compare_all(L, net, orc, "tuned")
         net.close()
 
 
