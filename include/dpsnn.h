@@ -109,6 +109,28 @@ typedef struct dpsnn_params {
                                           (every event is an atomic add into
                                           its slot), else 1 .. 2^20.  Results
                                           do not depend on it.              */
+  /* Population model of Sec. 2.2 and Table S1 (n_pops = 2..4; 0 keeps the
+   * two-population model above).  Each module's K neurons are split into
+   * consecutive populations of pop_size[] neurons (sum K).  A neuron of
+   * population s projects n_syn[t][s] synapses into population t (every
+   * population's total must equal K_out): from an excitatory population
+   * (pop_exc = 1) to a module drawn with probability proportional to
+   * exp(-d / lambda) over all modules including its own (Eq. 1 from d = 0),
+   * from an inhibitory one to its own module; efficacy
+   * N(J_mean_ts[t][s], J_sd_ts[t][s]).  open_boundary = 1: the grid has
+   * edges, and each source draws among the modules that exist; 0: torus.
+   * The p_* arrays replace frac_exc, frac_local, J_*, nu_ext_hz, Jext_*,
+   * tau_m, E, V_th, V_r, tau_arp, alpha_c, tau_c, gc and I_const, and the
+   * rate bins count per population ([bins][modules][n_pops]). */
+  int32_t n_pops;
+  int32_t open_boundary;
+  int32_t pop_size[4];
+  int32_t pop_exc[4];
+  int32_t n_syn[4][4];
+  double J_mean_ts[4][4], J_sd_ts[4][4];
+  double p_nu_ext_hz[4], p_Jext_mean[4], p_Jext_sd[4];
+  double p_tau_m[4], p_E[4], p_V_th[4], p_V_r[4], p_tau_arp[4];
+  double p_alpha_c[4], p_tau_c[4], p_gc[4], p_I_const[4];
 } dpsnn_params;
 
 typedef struct dpsnn_stats {
@@ -130,6 +152,8 @@ typedef struct dpsnn_stats {
   int32_t queue_cap;      /* entries per input queue in use (0 = none)   */
   int32_t deliver_blocks; /* grid of the split schedule's delivery kernel  */
   int32_t route_blocks;   /* inbox-routing blocks beside it               */
+  int32_t n_pops;         /* populations per module (rate-bin stride)     */
+  int32_t reserved;
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */
@@ -225,8 +249,8 @@ int dpsnn_read_spikes(dpsnn_net* net, int32_t* host_step, int32_t* host_id,
 /*
  * Drain the completed population-count bins (Sec. 2.3: firing rates per
  * sub-population in bins of rate_bin_steps): host_counts is
- * [bins][modules][2] uint32 with capacity cap_bins bins; *n_bins = bins
- * available.  With cap_bins < *n_bins nothing is copied or drained.
+ * [bins][modules][n_pops] uint32 (n_pops = 2 for the two-population model)
+ * with capacity cap_bins bins; *n_bins = bins available.  With cap_bins < *n_bins nothing is copied or drained.
  * Synchronises.
  */
 int dpsnn_read_rates(dpsnn_net* net, uint32_t* host_counts, int64_t cap_bins,

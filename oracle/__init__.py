@@ -6,7 +6,8 @@ implementation (oracle/dpsnn_oracle.c) written from the paper and bound here
 with ctypes; it shares no code with the HIP library.
 
 Parameters are passed as a plain dict whose keys are the field names of
-``orc_params`` (pairs are ``[excitatory, inhibitory]``).
+``orc_params`` (pairs are ``[excitatory, inhibitory]``; the population-model
+fields default to the two-population model when absent).
 """
 import ctypes as C
 import os
@@ -23,6 +24,19 @@ EXACT64 = 1
 WEIGHT_DTYPES = {"f32": 0, "f16": 1, "i8": 2}
 
 _PAIR = C.c_double * 2
+_I4 = C.c_int32 * 4
+_D4 = C.c_double * 4
+_I44 = (C.c_int32 * 4) * 4
+_D44 = (C.c_double * 4) * 4
+# population-model fields and their defaults (two-population model)
+_POP_FIELDS = [
+    ("n_pops", C.c_int32), ("open_boundary", C.c_int32), ("pop_size", _I4),
+    ("pop_exc", _I4), ("n_syn", _I44), ("J_mean_ts", _D44), ("J_sd_ts", _D44),
+    ("p_nu_ext_hz", _D4), ("p_Jext_mean", _D4), ("p_Jext_sd", _D4),
+    ("p_tau_m", _D4), ("p_E", _D4), ("p_V_th", _D4), ("p_V_r", _D4),
+    ("p_tau_arp", _D4), ("p_alpha_c", _D4), ("p_tau_c", _D4), ("p_gc", _D4),
+    ("p_I_const", _D4),
+]
 
 
 class OrcParams(C.Structure):
@@ -37,18 +51,40 @@ class OrcParams(C.Structure):
         ("V_th", _PAIR), ("V_r", _PAIR), ("tau_arp", _PAIR), ("alpha_c", _PAIR),
         ("tau_c", _PAIR), ("gc", _PAIR), ("I_const", _PAIR),
         ("rate_bin_steps", C.c_int32),
-    ]
+    ] + _POP_FIELDS
+
+
+def _fill(ctype, v):
+    if ctype in (_I44, _D44):
+        out = ctype()
+        el = C.c_int32 if ctype is _I44 else C.c_double
+        for i in range(4):
+            for j in range(4):
+                x = v[i][j] if i < len(v) and j < len(v[i]) else 0
+                out[i][j] = el(int(x) if el is C.c_int32 else float(x)).value
+        return out
+    if ctype in (_I4, _D4):
+        vals = [v[i] if i < len(v) else 0 for i in range(4)]
+        return ctype(*[(int(x) if ctype is _I4 else float(x)) for x in vals])
+    return None
 
 
 def to_struct(params: dict) -> OrcParams:
     s = OrcParams()
+    pop_names = {n for n, _ in _POP_FIELDS}
     for name, ctype in OrcParams._fields_:
         key = "lambda" if name == "lambda_" else name
+        if key in pop_names and key not in params:
+            continue                      # zero: the two-population model
+        if params.get("n_pops", 0) and key not in params:
+            continue                      # two-population fields unused
         v = params[key]
         if key == "weight_dtype" and isinstance(v, str):
             v = WEIGHT_DTYPES[v]
         if ctype is _PAIR:
             setattr(s, name, _PAIR(float(v[0]), float(v[1])))
+        elif ctype in (_I4, _D4, _I44, _D44):
+            setattr(s, name, _fill(ctype, v))
         elif ctype is C.c_double:
             setattr(s, name, float(v))
         else:
@@ -89,6 +125,11 @@ def lib():
         L.orc_gen_row.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p]
         L.orc_gen_row.restype = C.c_int32
+        L.orc_gen_row_blocks.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_gen_row_blocks.restype = C.c_int32
+        L.orc_n_pops.argtypes = [C.c_void_p]
+        L.orc_n_pops.restype = C.c_int32
         L.orc_ext_input.argtypes = [C.c_void_p, C.c_int64, C.c_int64,
                                     P(C.c_int64), P(C.c_double)]
         L.orc_ext_input.restype = C.c_int32
@@ -155,6 +196,7 @@ class Oracle:
         self.D = int(lib().orc_n_slots(h))
         self.M = int(params["grid_w"]) * int(params["grid_h"])
         self.n_del = int(params["d_max"]) - int(params["d_min"]) + 1
+        self.P = int(lib().orc_n_pops(h))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -193,6 +235,20 @@ class Oracle:
         if rc != 0:
             raise ValueError(rc)
         return tgt, dl, wi, doff
+
+    def gen_row_blocks(self, s: int):
+        """(targets, delays, efficacy indices, delay offsets, blocks)."""
+        Ko = int(self.params["K_out"])
+        tgt = np.zeros(Ko, np.int32)
+        dl = np.zeros(Ko, np.uint8)
+        wi = np.zeros(Ko, np.uint16)
+        bk = np.zeros(Ko, np.uint8)
+        doff = np.zeros(self.n_del + 1, np.uint16)
+        rc = lib().orc_gen_row_blocks(self._h, int(s), _ptr(tgt), _ptr(dl), _ptr(wi),
+                                      _ptr(doff), _ptr(bk))
+        if rc != 0:
+            raise ValueError(rc)
+        return tgt, dl, wi, doff, bk
 
     def ext_input(self, i: int, t: int):
         fs = C.c_int64(0)
@@ -244,6 +300,6 @@ class Oracle:
 
     def rates(self) -> np.ndarray:
         nb = lib().orc_rates(self._h, None, 0)
-        out = np.zeros((nb, self.M, 2), np.uint32)
+        out = np.zeros((nb, self.M, self.P), np.uint32)
         lib().orc_rates(self._h, _ptr(out), nb)
         return out

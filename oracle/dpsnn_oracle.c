@@ -12,11 +12,16 @@
 #include "dpsnn_oracle.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ZN 65536              /* entries of every efficacy quantile table */
 #define MAX_POIS 16           /* Poisson count thresholds kept per pop    */
+#define MAXP 4                /* populations per module                   */
+#define MAX_ATTEMPTS 64       /* draws of a module inside open boundaries */
+
+enum { RULE_OWN = 0, RULE_OTHERS = 1, RULE_ALL = 2 };
 
 struct orc_net {
   orc_params p;
@@ -26,37 +31,52 @@ struct orc_net {
 
   int64_t N;                  /* neurons                                  */
   int32_t M;                  /* modules                                  */
-  int32_t K_exc;              /* excitatory neurons per module            */
-  int32_t n_local[2];         /* local synapses per source, by pop        */
+  int32_t P;                  /* populations per module                   */
+  int32_t pop_lo[MAXP], pop_hi[MAXP];  /* module-local index ranges       */
   int32_t D;                  /* ring slots = d_max + 1                   */
   int32_t n_del;              /* distinct delays = d_max - d_min + 1      */
-  int32_t n_arp[2];           /* refractory steps                         */
+  int32_t n_arp[MAXP];        /* refractory steps                         */
 
-  double Pm[2], Pc[2], PVc[2], Iterm[2];
-  float Pm32[2], Pc32[2], PVc32[2], Iterm32[2];
-  float E32[2], Vth32[2], Vr32[2], al32[2];
+  /* per-population neuron parameters (binary64 copies of the inputs) */
+  double tau_m[MAXP], E[MAXP], V_th[MAXP], V_r[MAXP], tau_arp[MAXP];
+  double alpha_c[MAXP], tau_c[MAXP], gc[MAXP], I_const[MAXP];
+  double nu_ext[MAXP], Jx_mean[MAXP], Jx_sd[MAXP];
 
-  int32_t n_off;              /* other modules reachable = M - 1          */
+  double Pm[MAXP], Pc[MAXP], PVc[MAXP], Iterm[MAXP];
+  float Pm32[MAXP], Pc32[MAXP], PVc32[MAXP], Iterm32[MAXP];
+  float E32[MAXP], Vth32[MAXP], Vr32[MAXP], al32[MAXP];
+
+  /* projections of a source population: blocks of synapses, in order */
+  int32_t n_blk[MAXP];
+  int32_t blk_n[MAXP][MAXP];  /* synapses                                 */
+  int32_t blk_lo[MAXP][MAXP], blk_hi[MAXP][MAXP];  /* target range        */
+  int32_t blk_rule[MAXP][MAXP];
+  double blk_J[MAXP][MAXP], blk_sd[MAXP][MAXP];
+
+  int32_t off_rule;           /* offsets of RULE_OTHERS or RULE_ALL        */
+  int32_t open;               /* open boundaries: draws outside rejected   */
+  int32_t n_off;              /* offsets in the table                      */
   int32_t* off_xy;            /* (ox, oy) per offset index                */
   uint32_t* off_thr;          /* n_off - 1 cumulative thresholds          */
 
-  int32_t n_pois[2];
-  uint32_t pois_thr[2][MAX_POIS];
+  int32_t n_pois[MAXP];
+  uint32_t pois_thr[MAXP][MAX_POIS];
 
-  double* wt64[2];
-  float* wt32[2];
-  uint16_t* wt16[2];
-  int8_t* wq8[2];
-  float s8[2];                /* int8 scale (binary32), by source pop     */
-  int64_t s8fix[2];           /* the scale in fixed point                 */
-  int64_t* wfix[2];           /* fixed-point efficacy for weight_dtype    */
-  double* jx64[2];
-  float* jx32[2];
-  int64_t* jxfix[2];
+  double* wt64[MAXP][MAXP];   /* efficacy tables by (source pop, block)    */
+  float* wt32[MAXP][MAXP];
+  uint16_t* wt16[MAXP][MAXP];
+  int8_t* wq8[MAXP][MAXP];
+  int64_t* wfix[MAXP][MAXP];  /* fixed-point efficacy for weight_dtype    */
+  float s8[MAXP];             /* int8 scale (binary32), by source pop     */
+  int64_t s8fix[MAXP];        /* the scale in fixed point                 */
+  double* jx64[MAXP];
+  float* jx32[MAXP];
+  int64_t* jxfix[MAXP];
 
   int32_t* r_tgt;             /* stored rows (store_rows = 1)             */
   uint8_t* r_del;
   uint16_t* r_widx;
+  uint8_t* r_blk;
   uint16_t* r_doff;
 
   int64_t t;
@@ -77,9 +97,11 @@ struct orc_net {
   int32_t* tmp_tgt;           /* unsorted draws inside orc_gen_row        */
   uint8_t* tmp_del;
   uint16_t* tmp_widx;
+  uint8_t* tmp_blk;
   int32_t* row_tgt;           /* a regenerated row (store_rows = 0)       */
   uint8_t* row_del;
   uint16_t* row_widx;
+  uint8_t* row_blk;
   uint16_t* row_doff;
   int64_t* spk_step;          /* ids that spiked in the current step      */
 };
@@ -112,6 +134,13 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
 static void draw(const orc_net* n, uint32_t w0, uint32_t w1, uint32_t w3,
                  uint32_t out[4]) {
   uint32_t ctr[4] = {w0, w1, 0u, w3};
+  orc_philox4x32_10(ctr, n->key, out);
+}
+
+/* The same with counter word 2 = w2 (repeated draws of one synapse). */
+static void draw2(const orc_net* n, uint32_t w0, uint32_t w1, uint32_t w2,
+                  uint32_t w3, uint32_t out[4]) {
+  uint32_t ctr[4] = {w0, w1, w2, w3};
   orc_philox4x32_10(ctr, n->key, out);
 }
 
@@ -191,22 +220,28 @@ double orc_f16_to_f64(uint16_t h) {
 
 /* ------------------------------------------------------------------------ */
 static int pop_of(const orc_net* n, int64_t i) {
-  return (int)(i % n->p.K) < n->K_exc ? 0 : 1;
+  int l = (int)(i % n->p.K), q = 0;
+  while (q + 1 < n->P && l >= n->pop_hi[q]) q++;
+  return q;
 }
 
 static void release(orc_net* n) {
   if (!n) return;
-  for (int q = 0; q < 2; q++) {
-    free(n->wt64[q]); free(n->wt32[q]); free(n->wt16[q]); free(n->wq8[q]);
-    free(n->wfix[q]); free(n->jx64[q]); free(n->jx32[q]); free(n->jxfix[q]);
+  for (int q = 0; q < MAXP; q++) {
+    for (int b = 0; b < MAXP; b++) {
+      free(n->wt64[q][b]); free(n->wt32[q][b]); free(n->wt16[q][b]);
+      free(n->wq8[q][b]); free(n->wfix[q][b]);
+    }
+    free(n->jx64[q]); free(n->jx32[q]); free(n->jxfix[q]);
   }
   free(n->off_xy); free(n->off_thr);
-  free(n->r_tgt); free(n->r_del); free(n->r_widx); free(n->r_doff);
+  free(n->r_tgt); free(n->r_del); free(n->r_widx); free(n->r_blk); free(n->r_doff);
   free(n->V32); free(n->c32); free(n->V64); free(n->c64); free(n->ref);
   free(n->ring_fix); free(n->ring64);
   free(n->sp_t); free(n->sp_id); free(n->rates);
-  free(n->tmp_tgt); free(n->tmp_del); free(n->tmp_widx);
-  free(n->row_tgt); free(n->row_del); free(n->row_widx); free(n->row_doff);
+  free(n->tmp_tgt); free(n->tmp_del); free(n->tmp_widx); free(n->tmp_blk);
+  free(n->row_tgt); free(n->row_del); free(n->row_widx); free(n->row_blk);
+  free(n->row_doff);
   free(n->spk_step);
   free(n);
 }
@@ -215,15 +250,7 @@ void orc_free(orc_net* n) { release(n); }
 
 static int valid(const orc_params* p) {
   if (p->grid_w < 1 || p->grid_h < 1 || p->K < 2 || p->K_out < 0) return 0;
-  if (!(p->frac_exc >= 0.0 && p->frac_exc <= 1.0)) return 0;
-  for (int q = 0; q < 2; q++) {
-    if (!(p->frac_local[q] >= 0.0 && p->frac_local[q] <= 1.0)) return 0;
-    if (!(p->tau_m[q] > 0.0) || !(p->tau_c[q] > 0.0)) return 0;
-    if (!(p->tau_arp[q] >= 0.0) || !(p->nu_ext_hz[q] >= 0.0)) return 0;
-    if (!(p->J_sd[q] >= 0.0) || !(p->Jext_sd[q] >= 0.0)) return 0;
-  }
   if (!(p->lambda > 0.0) || !(p->dt_ms > 0.0)) return 0;
-  if (p->torus != 1) return 0;      /* open boundaries: not built yet */
   if (p->d_min < 1 || p->d_max < p->d_min || p->d_max > 255) return 0;
   if (p->weight_dtype < ORC_WF32 || p->weight_dtype > ORC_WI8) return 0;
   if (p->acc_bits != 32 && p->acc_bits != 64) return 0;
@@ -232,16 +259,121 @@ static int valid(const orc_params* p) {
   if (p->rate_bin_steps < 1) return 0;
   if ((int64_t)p->grid_w * p->grid_h * p->K > 2147483647LL) return 0;
   if (p->K_out > 65535) return 0;
+  if (p->n_pops == 0) {
+    if (!(p->frac_exc >= 0.0 && p->frac_exc <= 1.0)) return 0;
+    for (int q = 0; q < 2; q++) {
+      if (!(p->frac_local[q] >= 0.0 && p->frac_local[q] <= 1.0)) return 0;
+      if (!(p->tau_m[q] > 0.0) || !(p->tau_c[q] > 0.0)) return 0;
+      if (!(p->tau_arp[q] >= 0.0) || !(p->nu_ext_hz[q] >= 0.0)) return 0;
+      if (!(p->J_sd[q] >= 0.0) || !(p->Jext_sd[q] >= 0.0)) return 0;
+    }
+    if (p->torus != 1) return 0;  /* open boundaries: population model */
+    return 1;
+  }
+  if (p->n_pops < 2 || p->n_pops > MAXP) return 0;
+  int64_t sum = 0;
+  for (int q = 0; q < p->n_pops; q++) {
+    if (p->pop_size[q] < 1) return 0;
+    sum += p->pop_size[q];
+    if (!(p->p_tau_m[q] > 0.0) || !(p->p_tau_c[q] > 0.0)) return 0;
+    if (!(p->p_tau_arp[q] >= 0.0) || !(p->p_nu_ext_hz[q] >= 0.0)) return 0;
+    if (!(p->p_Jext_sd[q] >= 0.0)) return 0;
+  }
+  if (sum != p->K) return 0;
+  for (int s = 0; s < p->n_pops; s++) {
+    int64_t deg = 0;
+    for (int t = 0; t < p->n_pops; t++) {
+      if (p->n_syn[t][s] < 0 || !(p->J_sd_ts[t][s] >= 0.0)) return 0;
+      deg += p->n_syn[t][s];
+      /* a block into the own population needs a second neuron */
+      if (t == s && p->n_syn[t][s] > 0 && p->pop_size[t] < 2) return 0;
+    }
+    if (deg != p->K_out) return 0;
+  }
   return 1;
+}
+
+/* Projection blocks of every source population, the neuron ranges of the
+ * populations and their parameters, from either parameter model. */
+static void set_model(orc_net* n) {
+  const orc_params* p = &n->p;
+  if (p->n_pops == 0) {
+    /* two populations; a source's first round(frac_local K_out) synapses
+     * stay in its module, the rest go to other modules (Eq. 1); targets are
+     * any neuron of the module */
+    const int K_exc = (int)llround(p->frac_exc * p->K);
+    n->P = 2;
+    n->pop_lo[0] = 0; n->pop_hi[0] = K_exc;
+    n->pop_lo[1] = K_exc; n->pop_hi[1] = p->K;
+    for (int q = 0; q < 2; q++) {
+      n->tau_m[q] = p->tau_m[q]; n->E[q] = p->E[q]; n->V_th[q] = p->V_th[q];
+      n->V_r[q] = p->V_r[q]; n->tau_arp[q] = p->tau_arp[q];
+      n->alpha_c[q] = p->alpha_c[q]; n->tau_c[q] = p->tau_c[q];
+      n->gc[q] = p->gc[q]; n->I_const[q] = p->I_const[q];
+      n->nu_ext[q] = p->nu_ext_hz[q]; n->Jx_mean[q] = p->Jext_mean[q];
+      n->Jx_sd[q] = p->Jext_sd[q];
+      const int nl = (int)llround(p->frac_local[q] * p->K_out);
+      n->n_blk[q] = 0;
+      int b = 0;
+      if (nl > 0) {
+        n->blk_n[q][b] = nl; n->blk_lo[q][b] = 0; n->blk_hi[q][b] = p->K;
+        n->blk_rule[q][b] = RULE_OWN; b++;
+      }
+      if (p->K_out - nl > 0) {
+        n->blk_n[q][b] = p->K_out - nl; n->blk_lo[q][b] = 0; n->blk_hi[q][b] = p->K;
+        n->blk_rule[q][b] = RULE_OTHERS; b++;
+      }
+      for (int k = 0; k < 2; k++) {  /* both blocks use the source's table */
+        n->blk_J[q][k] = p->J_mean[q];
+        n->blk_sd[q][k] = p->J_sd[q];
+      }
+      n->n_blk[q] = b;
+    }
+    n->off_rule = RULE_OTHERS;
+    n->open = 0;
+    return;
+  }
+  n->P = p->n_pops;
+  int lo = 0;
+  for (int q = 0; q < n->P; q++) {
+    n->pop_lo[q] = lo;
+    lo += p->pop_size[q];
+    n->pop_hi[q] = lo;
+    n->tau_m[q] = p->p_tau_m[q]; n->E[q] = p->p_E[q]; n->V_th[q] = p->p_V_th[q];
+    n->V_r[q] = p->p_V_r[q]; n->tau_arp[q] = p->p_tau_arp[q];
+    n->alpha_c[q] = p->p_alpha_c[q]; n->tau_c[q] = p->p_tau_c[q];
+    n->gc[q] = p->p_gc[q]; n->I_const[q] = p->p_I_const[q];
+    n->nu_ext[q] = p->p_nu_ext_hz[q]; n->Jx_mean[q] = p->p_Jext_mean[q];
+    n->Jx_sd[q] = p->p_Jext_sd[q];
+  }
+  for (int s = 0; s < n->P; s++) {
+    int b = 0;
+    for (int t = 0; t < n->P; t++) {
+      if (p->n_syn[t][s] == 0) continue;
+      n->blk_n[s][b] = p->n_syn[t][s];
+      n->blk_lo[s][b] = n->pop_lo[t];
+      n->blk_hi[s][b] = n->pop_hi[t];
+      n->blk_rule[s][b] = p->pop_exc[s] ? RULE_ALL : RULE_OWN;
+      n->blk_J[s][b] = p->J_mean_ts[t][s];
+      n->blk_sd[s][b] = p->J_sd_ts[t][s];
+      b++;
+    }
+    n->n_blk[s] = b;
+  }
+  n->off_rule = RULE_ALL;
+  n->open = p->open_boundary ? 1 : 0;
 }
 
 /* Host tables: propagators, Poisson thresholds, module-offset distribution,
  * efficacy quantile tables.  All computed in binary64, rounded once. */
+/* Efficacy tables of a source population: one per block, at least one. */
+static int n_tab(const orc_net* n, int q) { return n->n_blk[q] > 0 ? n->n_blk[q] : 1; }
+
 static int build_tables(orc_net* n) {
   const orc_params* p = &n->p;
   const double twoQ = ldexp(1.0, p->q_frac_bits);
 
-  for (int q = 0; q < 2; q++) {
+  for (int q = 0; q < n->P; q++) {
     /* Eq. 2 between inputs is linear: V relaxes to E with tau_m while the
      * fatigue c decays with tau_c and pulls V down at rate g_c c / C_m.
      * Over one step dt the exact solution is
@@ -249,28 +381,28 @@ static int build_tables(orc_net* n) {
      *   V' = E + (V - E) Pm - c (g_c/C_m) (Pc - Pm) / (1/tau_m - 1/tau_c)
      *        + I tau_m (1 - Pm)            (constant drive I, tests only).
      * Inhibitory neurons carry no c (Sec. 2.2): their gc is 0. */
-    double a = 1.0 / p->tau_m[q], b = 1.0 / p->tau_c[q];
-    n->Pm[q] = exp(-p->dt_ms / p->tau_m[q]);
-    n->Pc[q] = exp(-p->dt_ms / p->tau_c[q]);
+    double a = 1.0 / n->tau_m[q], b = 1.0 / n->tau_c[q];
+    n->Pm[q] = exp(-p->dt_ms / n->tau_m[q]);
+    n->Pc[q] = exp(-p->dt_ms / n->tau_c[q]);
     if (a != b)
-      n->PVc[q] = p->gc[q] * (n->Pc[q] - n->Pm[q]) / (a - b);
+      n->PVc[q] = n->gc[q] * (n->Pc[q] - n->Pm[q]) / (a - b);
     else
-      n->PVc[q] = p->gc[q] * p->dt_ms * n->Pm[q];
-    n->Iterm[q] = p->I_const[q] * p->tau_m[q] * (1.0 - n->Pm[q]);
+      n->PVc[q] = n->gc[q] * p->dt_ms * n->Pm[q];
+    n->Iterm[q] = n->I_const[q] * n->tau_m[q] * (1.0 - n->Pm[q]);
     n->Pm32[q] = (float)n->Pm[q];
     n->Pc32[q] = (float)n->Pc[q];
     n->PVc32[q] = (float)n->PVc[q];
     n->Iterm32[q] = (float)n->Iterm[q];
-    n->E32[q] = (float)p->E[q];
-    n->Vth32[q] = (float)p->V_th[q];
-    n->Vr32[q] = (float)p->V_r[q];
-    n->al32[q] = (float)p->alpha_c[q];
-    n->n_arp[q] = (int32_t)llround(p->tau_arp[q] / p->dt_ms);
+    n->E32[q] = (float)n->E[q];
+    n->Vth32[q] = (float)n->V_th[q];
+    n->Vr32[q] = (float)n->V_r[q];
+    n->al32[q] = (float)n->alpha_c[q];
+    n->n_arp[q] = (int32_t)llround(n->tau_arp[q] / p->dt_ms);
 
     /* External drive (Sec. 2.2 and Table S1): a Poisson process of total
      * rate nu_ext; per step the count k is Poisson with mean nu_ext dt.
      * k = number of thresholds floor(F(j) 2^32) not above the draw. */
-    double mean = p->nu_ext_hz[q] * p->dt_ms * 1e-3;
+    double mean = n->nu_ext[q] * p->dt_ms * 1e-3;
     n->n_pois[q] = 0;
     if (mean > 0.0) {
       double term = exp(-mean), F = term;
@@ -286,13 +418,25 @@ static int build_tables(orc_net* n) {
     }
   }
 
-  /* Eq. 1: a remote target module at distance d is chosen with probability
-   * proportional to exp(-d / lambda) among all other modules.  On the torus
-   * the distribution depends only on the offset, enumerated row-major over
-   * (ox, oy) in [0,W) x [0,H) without (0,0); d is the Euclidean length of
-   * the shortest periodic image of the offset. */
+  /* Eq. 1: a target module at distance d is chosen with probability
+   * proportional to exp(-d / lambda).
+   *  - RULE_OTHERS (two-population model, torus): among all other modules;
+   *    offsets (ox, oy) in [0,W) x [0,H) row-major without (0,0), d the
+   *    Euclidean length of the shortest periodic image.
+   *  - RULE_ALL on the torus: the same offsets with (0,0) (d = 0) first.
+   *  - RULE_ALL with open boundaries: plane offsets (dx, dy) in
+   *    [-(W-1), W-1] x [-(H-1), H-1] row-major, d = |(dx, dy)|; a draw that
+   *    leaves the grid is repeated, so that each source draws from exp(-d/l)
+   *    restricted to the modules that exist. */
   const int W = p->grid_w, H = p->grid_h;
-  n->n_off = n->M - 1;
+  int cnt_off;
+  if (n->off_rule == RULE_OTHERS)
+    cnt_off = n->M - 1;
+  else if (!n->open)
+    cnt_off = n->M;
+  else
+    cnt_off = (2 * W - 1) * (2 * H - 1);
+  n->n_off = cnt_off;
   if (n->n_off > 0) {
     double* wgt = (double*)malloc(sizeof(double) * n->n_off);
     n->off_xy = (int32_t*)malloc(sizeof(int32_t) * 2 * n->n_off);
@@ -300,18 +444,30 @@ static int build_tables(orc_net* n) {
     if (!wgt || !n->off_xy || !n->off_thr) { free(wgt); return ORC_E_NOMEM; }
     int k = 0;
     double Z = 0.0;
-    for (int oy = 0; oy < H; oy++)
-      for (int ox = 0; ox < W; ox++) {
-        if (ox == 0 && oy == 0) continue;
-        int dx = ox < W - ox ? ox : W - ox;
-        int dy = oy < H - oy ? oy : H - oy;
-        double d = sqrt((double)(dx * dx + dy * dy));
-        wgt[k] = exp(-d / p->lambda);
-        n->off_xy[2 * k] = ox;
-        n->off_xy[2 * k + 1] = oy;
-        Z += wgt[k];
-        k++;
-      }
+    if (!n->open) {
+      for (int oy = 0; oy < H; oy++)
+        for (int ox = 0; ox < W; ox++) {
+          if (ox == 0 && oy == 0 && n->off_rule == RULE_OTHERS) continue;
+          int dx = ox < W - ox ? ox : W - ox;
+          int dy = oy < H - oy ? oy : H - oy;
+          double d = sqrt((double)(dx * dx + dy * dy));
+          wgt[k] = exp(-d / p->lambda);
+          n->off_xy[2 * k] = ox;
+          n->off_xy[2 * k + 1] = oy;
+          Z += wgt[k];
+          k++;
+        }
+    } else {
+      for (int dy = -(H - 1); dy <= H - 1; dy++)
+        for (int dx = -(W - 1); dx <= W - 1; dx++) {
+          double d = sqrt((double)(dx * dx + dy * dy));
+          wgt[k] = exp(-d / p->lambda);
+          n->off_xy[2 * k] = dx;
+          n->off_xy[2 * k + 1] = dy;
+          Z += wgt[k];
+          k++;
+        }
+    }
     double cum = 0.0;
     for (k = 0; k + 1 < n->n_off; k++) {
       cum += wgt[k];
@@ -321,96 +477,147 @@ static int build_tables(orc_net* n) {
     free(wgt);
   }
 
-  /* Efficacy tables, recurrent (by source pop) and external (by target). */
+  /* Efficacy tables: recurrent by (source pop, block), external by target
+   * pop.  int8: symmetric codes q = rint(w / s) with one scale per source
+   * pop, s = (largest |w| of its tables) / 127 in binary32. */
   double* z = zgrid();
   if (!z) return ORC_E_NOMEM;
-  for (int q = 0; q < 2; q++) {
-    n->wt64[q] = (double*)malloc(sizeof(double) * ZN);
-    n->wt32[q] = (float*)malloc(sizeof(float) * ZN);
-    n->wt16[q] = (uint16_t*)malloc(sizeof(uint16_t) * ZN);
-    n->wq8[q] = (int8_t*)malloc(ZN);
-    n->wfix[q] = (int64_t*)malloc(sizeof(int64_t) * ZN);
+  for (int q = 0; q < n->P; q++) {
+    double amax = 0.0;
+    for (int b = 0; b < n_tab(n, q); b++) {
+      n->wt64[q][b] = (double*)malloc(sizeof(double) * ZN);
+      n->wt32[q][b] = (float*)malloc(sizeof(float) * ZN);
+      n->wt16[q][b] = (uint16_t*)malloc(sizeof(uint16_t) * ZN);
+      n->wq8[q][b] = (int8_t*)malloc(ZN);
+      n->wfix[q][b] = (int64_t*)malloc(sizeof(int64_t) * ZN);
+      if (!n->wt64[q][b] || !n->wt32[q][b] || !n->wt16[q][b] || !n->wq8[q][b] ||
+          !n->wfix[q][b])
+        return ORC_E_NOMEM;
+      for (int i = 0; i < ZN; i++) {
+        n->wt64[q][b][i] = n->blk_J[q][b] + n->blk_sd[q][b] * z[i];
+        n->wt32[q][b][i] = (float)n->wt64[q][b][i];
+        n->wt16[q][b][i] = orc_f64_to_f16(n->wt64[q][b][i]);
+        if (fabs(n->wt64[q][b][i]) > amax) amax = fabs(n->wt64[q][b][i]);
+      }
+    }
+    n->s8[q] = (float)(amax > 0.0 ? amax / 127.0 : 1.0);
+    n->s8fix[q] = (int64_t)rint((double)n->s8[q] * twoQ);
+    for (int b = 0; b < n_tab(n, q); b++)
+      for (int i = 0; i < ZN; i++) {
+        double c = rint(n->wt64[q][b][i] / (double)n->s8[q]);
+        if (c > 127.0) c = 127.0;
+        if (c < -127.0) c = -127.0;
+        n->wq8[q][b][i] = (int8_t)c;
+        if (p->weight_dtype == ORC_WF32)
+          n->wfix[q][b][i] = (int64_t)rint((double)n->wt32[q][b][i] * twoQ);
+        else if (p->weight_dtype == ORC_WF16)
+          n->wfix[q][b][i] = (int64_t)rint(orc_f16_to_f64(n->wt16[q][b][i]) * twoQ);
+        else
+          n->wfix[q][b][i] = (int64_t)n->wq8[q][b][i] * n->s8fix[q];
+      }
     n->jx64[q] = (double*)malloc(sizeof(double) * ZN);
     n->jx32[q] = (float*)malloc(sizeof(float) * ZN);
     n->jxfix[q] = (int64_t*)malloc(sizeof(int64_t) * ZN);
-    if (!n->wt64[q] || !n->wt32[q] || !n->wt16[q] || !n->wq8[q] ||
-        !n->wfix[q] || !n->jx64[q] || !n->jx32[q] || !n->jxfix[q])
-      return ORC_E_NOMEM;
-    double amax = 0.0;
+    if (!n->jx64[q] || !n->jx32[q] || !n->jxfix[q]) return ORC_E_NOMEM;
     for (int i = 0; i < ZN; i++) {
-      n->wt64[q][i] = p->J_mean[q] + p->J_sd[q] * z[i];
-      n->wt32[q][i] = (float)n->wt64[q][i];
-      n->wt16[q][i] = orc_f64_to_f16(n->wt64[q][i]);
-      if (fabs(n->wt64[q][i]) > amax) amax = fabs(n->wt64[q][i]);
-      n->jx64[q][i] = p->Jext_mean[q] + p->Jext_sd[q] * z[i];
+      n->jx64[q][i] = n->Jx_mean[q] + n->Jx_sd[q] * z[i];
       n->jx32[q][i] = (float)n->jx64[q][i];
       n->jxfix[q][i] = (int64_t)rint((double)n->jx32[q][i] * twoQ);
-    }
-    /* int8: symmetric codes q = rint(w / s), s = max|w| / 127 (binary32). */
-    n->s8[q] = (float)(amax > 0.0 ? amax / 127.0 : 1.0);
-    n->s8fix[q] = (int64_t)rint((double)n->s8[q] * twoQ);
-    for (int i = 0; i < ZN; i++) {
-      double c = rint(n->wt64[q][i] / (double)n->s8[q]);
-      if (c > 127.0) c = 127.0;
-      if (c < -127.0) c = -127.0;
-      n->wq8[q][i] = (int8_t)c;
-      if (p->weight_dtype == ORC_WF32)
-        n->wfix[q][i] = (int64_t)rint((double)n->wt32[q][i] * twoQ);
-      else if (p->weight_dtype == ORC_WF16)
-        n->wfix[q][i] = (int64_t)rint(orc_f16_to_f64(n->wt16[q][i]) * twoQ);
-      else
-        n->wfix[q][i] = (int64_t)n->wq8[q][i] * n->s8fix[q];
     }
   }
   return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
-/* One row of the connectivity of source s (Sec. 2.2, Eq. 1; BASELINE-style
- * fixed split): the first n_local draws target the source's own module
- * (uniform, no autapse), the rest target another module chosen by Eq. 1 and
- * a uniform neuron in it.  Delay uniform on [d_min, d_max]; efficacy index
- * uniform on the 16-bit quantile table.  Then a stable sort by delay. */
-int32_t orc_gen_row(const orc_net* n, int64_t s, int32_t* tgt, uint8_t* delay,
-                    uint16_t* widx, uint16_t* doff) {
+/* One row of the connectivity of source s (Sec. 2.2, Eq. 1).  Synapse j
+ * belongs to block b of the source's population (blocks in order, counts
+ * n_blk); it targets a uniform neuron of the block's target range in a
+ * module chosen by the block's rule:
+ *   RULE_OWN    the source's own module; neuron from word 0;
+ *   RULE_OTHERS another module by Eq. 1 (torus offsets without (0,0));
+ *   RULE_ALL    any module by Eq. 1 from d = 0; with open boundaries a draw
+ *               outside the grid is repeated with counter word 2 = attempt
+ *               (at most MAX_ATTEMPTS, then the own module);
+ * module from word 0 and neuron from word 1 of the draw (s, j, attempt,
+ * SYN).  In the own module the source itself is skipped (no autapse):
+ * r uniform on [0, size-1) and r + (r >= own offset).  Delay uniform on
+ * [d_min, d_max] from word 2; efficacy index = top 16 bits of word 3 of the
+ * accepted draw.  Then a stable sort by delay. */
+static void draw_synapse(const orc_net* n, int64_t s, int j, int32_t* target,
+                         uint8_t* dly, uint16_t* wi, uint8_t* bk) {
   const orc_params* p = &n->p;
-  if (s < 0 || s >= n->N) return ORC_E_INVAL;
   const int K = p->K, W = p->grid_w, H = p->grid_h;
   const int ps = pop_of(n, s);
   const int32_t ms = (int32_t)(s / K), ls = (int32_t)(s % K);
   const int xs = ms % W, ys = ms / W;
-  const int Ko = p->K_out;
+  int b = 0, first = 0;
+  while (b + 1 < n->n_blk[ps] && j >= first + n->blk_n[ps][b]) {
+    first += n->blk_n[ps][b];
+    b++;
+  }
+  const int lo = n->blk_lo[ps][b], size = n->blk_hi[ps][b] - lo;
+  const int rule = n->blk_rule[ps][b];
+  uint32_t u[4];
+  int32_t mt = ms;
+  uint32_t nu;                 /* the word that picks the neuron          */
+  if (rule == RULE_OWN) {
+    draw(n, (uint32_t)s, (uint32_t)j, ORC_TAG_SYN, u);
+    nu = u[0];
+  } else {
+    int att = 0;
+    for (;;) {
+      draw2(n, (uint32_t)s, (uint32_t)j, (uint32_t)att, ORC_TAG_SYN, u);
+      /* offset index = number of cumulative thresholds <= u[0] */
+      int a = 0, z = n->n_off - 1;
+      while (a < z) {
+        int mid = (a + z) / 2;
+        if (n->off_thr[mid] <= u[0])
+          a = mid + 1;
+        else
+          z = mid;
+      }
+      int xt, yt;
+      if (!n->open) {
+        xt = (xs + n->off_xy[2 * a]) % W;
+        yt = (ys + n->off_xy[2 * a + 1]) % H;
+      } else {
+        xt = xs + n->off_xy[2 * a];
+        yt = ys + n->off_xy[2 * a + 1];
+      }
+      if (xt >= 0 && xt < W && yt >= 0 && yt < H) {
+        mt = yt * W + xt;
+        break;
+      }
+      if (++att == MAX_ATTEMPTS) {
+        mt = ms;
+        break;
+      }
+    }
+    nu = u[1];
+  }
+  uint32_t r;
+  if (mt == ms && ls >= lo && ls < lo + size) {
+    r = scale_u32(nu, (uint32_t)(size - 1));
+    r += r >= (uint32_t)(ls - lo) ? 1u : 0u;
+  } else {
+    r = scale_u32(nu, (uint32_t)size);
+  }
+  *target = mt * K + lo + (int32_t)r;
+  *dly = (uint8_t)(p->d_min + (int)scale_u32(u[2], (uint32_t)n->n_del));
+  *wi = (uint16_t)(u[3] >> 16);
+  *bk = (uint8_t)b;
+}
 
+int32_t orc_gen_row_blocks(const orc_net* n, int64_t s, int32_t* tgt, uint8_t* delay,
+                           uint16_t* widx, uint16_t* doff, uint8_t* blk) {
+  const orc_params* p = &n->p;
+  if (s < 0 || s >= n->N) return ORC_E_INVAL;
+  const int Ko = p->K_out;
   int32_t* t0 = n->tmp_tgt;
   uint8_t* d0 = n->tmp_del;
   uint16_t* w0 = n->tmp_widx;
-  for (int j = 0; j < Ko; j++) {
-    uint32_t u[4];
-    draw(n, (uint32_t)s, (uint32_t)j, ORC_TAG_SYN, u);
-    int32_t target;
-    if (j < n->n_local[ps]) {
-      uint32_t r = scale_u32(u[0], (uint32_t)(K - 1));
-      uint32_t lt = r + (r >= (uint32_t)ls ? 1u : 0u);
-      target = ms * K + (int32_t)lt;
-    } else {
-      /* offset index = number of cumulative thresholds <= u[0] */
-      int lo = 0, hi = n->n_off - 1;
-      while (lo < hi) {
-        int mid = (lo + hi) / 2;
-        if (n->off_thr[mid] <= u[0])
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      int xt = (xs + n->off_xy[2 * lo]) % W;
-      int yt = (ys + n->off_xy[2 * lo + 1]) % H;
-      uint32_t lt = scale_u32(u[1], (uint32_t)K);
-      target = (yt * W + xt) * K + (int32_t)lt;
-    }
-    t0[j] = target;
-    d0[j] = (uint8_t)(p->d_min + (int)scale_u32(u[2], (uint32_t)n->n_del));
-    w0[j] = (uint16_t)(u[3] >> 16);
-  }
+  uint8_t* b0 = n->tmp_blk;
+  for (int j = 0; j < Ko; j++) draw_synapse(n, s, j, &t0[j], &d0[j], &w0[j], &b0[j]);
   /* stable counting sort by delay */
   int32_t cnt[256];
   memset(cnt, 0, sizeof(cnt));
@@ -425,9 +632,17 @@ int32_t orc_gen_row(const orc_net* n, int64_t s, int32_t* tgt, uint8_t* delay,
     tgt[at] = t0[j];
     delay[at] = d0[j];
     widx[at] = w0[j];
+    if (blk) blk[at] = b0[j];
   }
   return ORC_OK;
 }
+
+int32_t orc_gen_row(const orc_net* n, int64_t s, int32_t* tgt, uint8_t* delay,
+                    uint16_t* widx, uint16_t* doff) {
+  return orc_gen_row_blocks(n, s, tgt, delay, widx, doff, NULL);
+}
+
+int32_t orc_n_pops(const orc_net* n) { return n->P; }
 
 /* ------------------------------------------------------------------------ */
 /* External Poisson input (Sec. 2.1 "no memory structure associated with
@@ -481,16 +696,16 @@ orc_net* orc_create(const orc_params* p, uint64_t seed, int32_t mode,
   n->store_rows = store_rows;
   n->M = p->grid_w * p->grid_h;
   n->N = (int64_t)n->M * p->K;
-  n->K_exc = (int32_t)llround(p->frac_exc * p->K);
-  for (int q = 0; q < 2; q++)
-    n->n_local[q] = (int32_t)llround(p->frac_local[q] * p->K_out);
   n->D = p->d_max + 1;
   n->n_del = p->d_max - p->d_min + 1;
-  /* a single module has nowhere else to send remote synapses */
-  if (n->M == 1 && (n->n_local[0] < p->K_out || n->n_local[1] < p->K_out)) {
-    release(n);
-    return NULL;
-  }
+  set_model(n);
+  /* a single module has nowhere else to send synapses to other modules */
+  for (int q = 0; q < n->P; q++)
+    for (int b = 0; b < n->n_blk[q]; b++)
+      if (n->M == 1 && n->blk_rule[q][b] == RULE_OTHERS) {
+        release(n);
+        return NULL;
+      }
   int rc = build_tables(n);
   if (rc != ORC_OK) { *err = rc; release(n); return NULL; }
 
@@ -498,13 +713,15 @@ orc_net* orc_create(const orc_params* p, uint64_t seed, int32_t mode,
   n->tmp_tgt = (int32_t*)malloc(sizeof(int32_t) * (Ko ? Ko : 1));
   n->tmp_del = (uint8_t*)malloc(Ko ? Ko : 1);
   n->tmp_widx = (uint16_t*)malloc(sizeof(uint16_t) * (Ko ? Ko : 1));
+  n->tmp_blk = (uint8_t*)malloc(Ko ? Ko : 1);
+  n->row_blk = (uint8_t*)malloc(Ko ? Ko : 1);
   n->row_tgt = (int32_t*)malloc(sizeof(int32_t) * (Ko ? Ko : 1));
   n->row_del = (uint8_t*)malloc(Ko ? Ko : 1);
   n->row_widx = (uint16_t*)malloc(sizeof(uint16_t) * (Ko ? Ko : 1));
   n->row_doff = (uint16_t*)malloc(sizeof(uint16_t) * (n->n_del + 1));
   n->spk_step = (int64_t*)malloc(sizeof(int64_t) * N);
   n->ref = (int32_t*)calloc(N, sizeof(int32_t));
-  if (!n->tmp_tgt || !n->tmp_del || !n->tmp_widx || !n->row_tgt ||
+  if (!n->tmp_tgt || !n->tmp_del || !n->tmp_widx || !n->tmp_blk || !n->row_blk || !n->row_tgt ||
       !n->row_del || !n->row_widx || !n->row_doff || !n->spk_step || !n->ref) {
     *err = ORC_E_NOMEM; release(n); return NULL;
   }
@@ -541,13 +758,15 @@ orc_net* orc_create(const orc_params* p, uint64_t seed, int32_t mode,
     n->r_tgt = (int32_t*)malloc(sizeof(int32_t) * N * Ko);
     n->r_del = (uint8_t*)malloc((size_t)N * Ko);
     n->r_widx = (uint16_t*)malloc(sizeof(uint16_t) * N * Ko);
+    n->r_blk = (uint8_t*)malloc((size_t)N * Ko);
     n->r_doff = (uint16_t*)malloc(sizeof(uint16_t) * N * (n->n_del + 1));
-    if (!n->r_tgt || !n->r_del || !n->r_widx || !n->r_doff) {
+    if (!n->r_tgt || !n->r_del || !n->r_widx || !n->r_blk || !n->r_doff) {
       *err = ORC_E_NOMEM; release(n); return NULL;
     }
     for (int64_t s = 0; s < N; s++)
-      orc_gen_row(n, s, n->r_tgt + s * Ko, n->r_del + s * Ko,
-                  n->r_widx + s * Ko, n->r_doff + s * (n->n_del + 1));
+      orc_gen_row_blocks(n, s, n->r_tgt + s * Ko, n->r_del + s * Ko,
+                         n->r_widx + s * Ko, n->r_doff + s * (n->n_del + 1),
+                         n->r_blk + s * Ko);
   }
   *err = ORC_OK;
   return n;
@@ -577,15 +796,15 @@ static int record_spike(orc_net* n, int64_t t, int64_t i) {
   if (bin >= n->rate_bins_cap) {
     int64_t cap = n->rate_bins_cap ? n->rate_bins_cap : 64;
     while (cap <= bin) cap *= 2;
-    uint32_t* r = (uint32_t*)realloc(n->rates, sizeof(uint32_t) * cap * n->M * 2);
+    uint32_t* r = (uint32_t*)realloc(n->rates, sizeof(uint32_t) * cap * n->M * n->P);
     if (!r) return ORC_E_NOMEM;
-    memset(r + n->rate_bins_cap * n->M * 2, 0,
-           sizeof(uint32_t) * (cap - n->rate_bins_cap) * n->M * 2);
+    memset(r + n->rate_bins_cap * n->M * n->P, 0,
+           sizeof(uint32_t) * (cap - n->rate_bins_cap) * n->M * n->P);
     n->rates = r;
     n->rate_bins_cap = cap;
   }
   if (bin + 1 > n->rate_bins_used) n->rate_bins_used = bin + 1;
-  n->rates[(bin * n->M + i / n->p.K) * 2 + pop_of(n, i)] += 1;
+  n->rates[(bin * n->M + i / n->p.K) * n->P + pop_of(n, i)] += 1;
   return ORC_OK;
 }
 
@@ -624,25 +843,24 @@ static int update_neuron32(orc_net* n, int64_t i, float dv) {
 
 static int update_neuron64(orc_net* n, int64_t i, double dv) {
   const int q = pop_of(n, i);
-  const orc_params* p = &n->p;
   double V = n->V64[i], c = n->c64[i];
   int spiked = 0;
   if (n->ref[i] > 0) {
     n->ref[i] -= 1;
     c = c * n->Pc[q];
   } else {
-    double v = V - p->E[q];
+    double v = V - n->E[q];
     v = v * n->Pm[q];
-    v = p->E[q] + v;
+    v = n->E[q] + v;
     double cv = c * n->PVc[q];
     v = v - cv;
     v = v + n->Iterm[q];
     v = v + dv;
     c = c * n->Pc[q];
-    if (v > p->V_th[q]) {
+    if (v > n->V_th[q]) {
       spiked = 1;
-      v = p->V_r[q];
-      c = c + p->alpha_c[q];
+      v = n->V_r[q];
+      c = c + n->alpha_c[q];
       n->ref[i] = n->n_arp[q];
     }
     V = v;
@@ -662,24 +880,28 @@ static void deliver(orc_net* n, int64_t s, int64_t t) {
   const int32_t* tgt;
   const uint8_t* del;
   const uint16_t* widx;
+  const uint8_t* blk;
   if (n->store_rows) {
     tgt = n->r_tgt + s * Ko;
     del = n->r_del + s * Ko;
     widx = n->r_widx + s * Ko;
+    blk = n->r_blk + s * Ko;
   } else {
-    orc_gen_row(n, s, n->row_tgt, n->row_del, n->row_widx, n->row_doff);
+    orc_gen_row_blocks(n, s, n->row_tgt, n->row_del, n->row_widx, n->row_doff,
+                       n->row_blk);
     tgt = n->row_tgt;
     del = n->row_del;
     widx = n->row_widx;
+    blk = n->row_blk;
   }
   const int q = pop_of(n, s);
   for (int j = 0; j < Ko; j++) {
     int64_t slot = (t + del[j]) % n->D;
     size_t at = (size_t)slot * (size_t)n->N + (size_t)tgt[j];
     if (n->mode == ORC_MIRROR32)
-      n->ring_fix[at] += n->wfix[q][widx[j]];
+      n->ring_fix[at] += n->wfix[q][blk[j]][widx[j]];
     else
-      n->ring64[at] += n->wt64[q][widx[j]];
+      n->ring64[at] += n->wt64[q][blk[j]][widx[j]];
   }
 }
 
@@ -792,10 +1014,10 @@ int64_t orc_rates(const orc_net* n, uint32_t* counts, int64_t cap_bins) {
   int64_t bins = n->t / n->p.rate_bin_steps + (n->t % n->p.rate_bin_steps ? 1 : 0);
   int64_t m = bins < cap_bins ? bins : cap_bins;
   if (counts && m > 0) {
-    memset(counts, 0, sizeof(uint32_t) * (size_t)(m * n->M * 2));
+    memset(counts, 0, sizeof(uint32_t) * (size_t)(m * n->M * n->P));
     int64_t have = n->rate_bins_used < m ? n->rate_bins_used : m;
     if (have > 0)
-      memcpy(counts, n->rates, sizeof(uint32_t) * (size_t)(have * n->M * 2));
+      memcpy(counts, n->rates, sizeof(uint32_t) * (size_t)(have * n->M * n->P));
   }
   return bins;
 }
@@ -808,47 +1030,71 @@ static int64_t put(void* out, int64_t cap, const void* src, int64_t bytes) {
 
 int64_t orc_table(const orc_net* n, const char* name, void* out, int64_t cap) {
   if (!n || !name) return ORC_E_INVAL;
+  const int P = n->P;
   if (!strcmp(name, "prop_f64")) {     /* [pop][Pm, Pc, PVc, Iterm] */
-    double v[8];
-    for (int q = 0; q < 2; q++) {
+    double v[4 * MAXP];
+    for (int q = 0; q < P; q++) {
       v[4 * q] = n->Pm[q]; v[4 * q + 1] = n->Pc[q];
       v[4 * q + 2] = n->PVc[q]; v[4 * q + 3] = n->Iterm[q];
     }
-    return put(out, cap, v, sizeof(v));
+    return put(out, cap, v, 32 * (int64_t)P);
   }
   if (!strcmp(name, "prop_f32")) {
-    float v[8];
-    for (int q = 0; q < 2; q++) {
+    float v[4 * MAXP];
+    for (int q = 0; q < P; q++) {
       v[4 * q] = n->Pm32[q]; v[4 * q + 1] = n->Pc32[q];
       v[4 * q + 2] = n->PVc32[q]; v[4 * q + 3] = n->Iterm32[q];
     }
-    return put(out, cap, v, sizeof(v));
+    return put(out, cap, v, 16 * (int64_t)P);
   }
-  if (!strcmp(name, "n_arp")) return put(out, cap, n->n_arp, sizeof(n->n_arp));
-  if (!strcmp(name, "pois_thr_0"))
-    return put(out, cap, n->pois_thr[0], 4 * (int64_t)n->n_pois[0]);
-  if (!strcmp(name, "pois_thr_1"))
-    return put(out, cap, n->pois_thr[1], 4 * (int64_t)n->n_pois[1]);
+  if (!strcmp(name, "n_arp")) return put(out, cap, n->n_arp, 4 * (int64_t)P);
   if (!strcmp(name, "off_thr"))
     return put(out, cap, n->off_thr, 4 * (int64_t)(n->n_off > 1 ? n->n_off - 1 : 0));
   if (!strcmp(name, "off_xy"))
     return put(out, cap, n->off_xy, 8 * (int64_t)n->n_off);
-  if (!strcmp(name, "s8")) return put(out, cap, n->s8, sizeof(n->s8));
-  if (!strcmp(name, "s8fix")) return put(out, cap, n->s8fix, sizeof(n->s8fix));
-  for (int q = 0; q < 2; q++) {
-    char nm[32];
-#define TABLE(label, arr, bytes)                                   \
-    strcpy(nm, label); nm[strlen(nm) - 1] = (char)('0' + q);       \
-    if (!strcmp(name, nm)) return put(out, cap, arr[q], bytes);
-    TABLE("wt64_x", n->wt64, 8 * (int64_t)ZN)
-    TABLE("wt32_x", n->wt32, 4 * (int64_t)ZN)
-    TABLE("wt16_x", n->wt16, 2 * (int64_t)ZN)
-    TABLE("wq8_x", n->wq8, (int64_t)ZN)
-    TABLE("wfix_x", n->wfix, 8 * (int64_t)ZN)
-    TABLE("jx64_x", n->jx64, 8 * (int64_t)ZN)
-    TABLE("jx32_x", n->jx32, 4 * (int64_t)ZN)
-    TABLE("jxfix_x", n->jxfix, 8 * (int64_t)ZN)
-#undef TABLE
+  if (!strcmp(name, "s8")) return put(out, cap, n->s8, 4 * (int64_t)P);
+  if (!strcmp(name, "s8fix")) return put(out, cap, n->s8fix, 8 * (int64_t)P);
+  if (!strcmp(name, "blocks")) {     /* [pop][block][n, lo, hi, rule] */
+    int32_t v[MAXP * MAXP * 4];
+    memset(v, 0, sizeof(v));
+    for (int q = 0; q < P; q++)
+      for (int b = 0; b < n->n_blk[q]; b++) {
+        int32_t* e = v + (q * MAXP + b) * 4;
+        e[0] = n->blk_n[q][b]; e[1] = n->blk_lo[q][b];
+        e[2] = n->blk_hi[q][b]; e[3] = n->blk_rule[q][b];
+      }
+    return put(out, cap, v, 16 * (int64_t)P * MAXP);
+  }
+  /* per-population tables "<name>_<q>"; efficacy tables "<name>_<q>" (block
+   * 0) and "<name>_<q>_<b>" */
+  for (int q = 0; q < P; q++) {
+    char nm[40];
+    snprintf(nm, sizeof nm, "pois_thr_%d", q);
+    if (!strcmp(name, nm)) return put(out, cap, n->pois_thr[q], 4 * (int64_t)n->n_pois[q]);
+    snprintf(nm, sizeof nm, "jx64_%d", q);
+    if (!strcmp(name, nm)) return put(out, cap, n->jx64[q], 8 * (int64_t)ZN);
+    snprintf(nm, sizeof nm, "jx32_%d", q);
+    if (!strcmp(name, nm)) return put(out, cap, n->jx32[q], 4 * (int64_t)ZN);
+    snprintf(nm, sizeof nm, "jxfix_%d", q);
+    if (!strcmp(name, nm)) return put(out, cap, n->jxfix[q], 8 * (int64_t)ZN);
+    for (int b = -1; b < n_tab(n, q); b++) {
+      const int bb = b < 0 ? 0 : b;
+      char sfx[16];
+      if (b < 0)
+        snprintf(sfx, sizeof sfx, "_%d", q);
+      else
+        snprintf(sfx, sizeof sfx, "_%d_%d", q, b);
+      snprintf(nm, sizeof nm, "wt64%s", sfx);
+      if (!strcmp(name, nm)) return put(out, cap, n->wt64[q][bb], 8 * (int64_t)ZN);
+      snprintf(nm, sizeof nm, "wt32%s", sfx);
+      if (!strcmp(name, nm)) return put(out, cap, n->wt32[q][bb], 4 * (int64_t)ZN);
+      snprintf(nm, sizeof nm, "wt16%s", sfx);
+      if (!strcmp(name, nm)) return put(out, cap, n->wt16[q][bb], 2 * (int64_t)ZN);
+      snprintf(nm, sizeof nm, "wq8%s", sfx);
+      if (!strcmp(name, nm)) return put(out, cap, n->wq8[q][bb], (int64_t)ZN);
+      snprintf(nm, sizeof nm, "wfix%s", sfx);
+      if (!strcmp(name, nm)) return put(out, cap, n->wfix[q][bb], 8 * (int64_t)ZN);
+    }
   }
   return ORC_E_INVAL;
 }

@@ -11,8 +11,9 @@
  * model with long-range interconnections", Front. Syst. Neurosci. 2019).
  *
  * What it computes (paper references by section / equation / table):
- *   - the 2-D grid of modules of K point-like LIF neurons, 4:1 exc:inh
- *     (Sec. 2.2, "Model Architecture and Network States");
+ *   - the 2-D grid of modules of K point-like LIF neurons, 4:1 exc:inh, or
+ *     the foreground / background / inhibitory populations of Sec. 2.2
+ *     ("Model Architecture and Network States");
  *   - inter-module connectivity with probability decaying as exp(-d/lambda)
  *     (Eq. 1), Gaussian efficacies (Sec. 2.2), integer synaptic delays;
  *   - the LIF neuron with spike-frequency adaptation (Eq. 2, Table S1),
@@ -75,6 +76,26 @@ typedef struct orc_params {
   double  alpha_c[2], tau_c[2], gc[2]; /* gc = g_c / C_m in 1/ms           */
   double  I_const[2];         /* constant drive in mV/ms (tests only)        */
   int32_t rate_bin_steps;     /* steps per population-rate bin               */
+  /* Population model of Sec. 2.2 (n_pops = 2..4; 0 = the two-population
+   * model above).  Module neurons are split into consecutive populations of
+   * pop_size[] (sum K); a neuron of population s projects n_syn[t][s]
+   * synapses into population t: excitatory sources (pop_exc = 1) to a module
+   * drawn with probability proportional to exp(-d/lambda) over all modules
+   * including its own (Eq. 1 from d = 0), inhibitory sources to their own
+   * module.  Efficacy N(J_mean_ts[t][s], J_sd_ts[t][s]).  Boundaries open
+   * (open_boundary = 1) or periodic.  The per-population arrays replace
+   * frac_exc, frac_local, J_*, nu_ext_hz, Jext_*, tau_m, E, V_th, V_r,
+   * tau_arp, alpha_c, tau_c, gc and I_const; K_out must equal every
+   * population's total out-degree. */
+  int32_t n_pops;
+  int32_t open_boundary;
+  int32_t pop_size[4];
+  int32_t pop_exc[4];
+  int32_t n_syn[4][4];
+  double  J_mean_ts[4][4], J_sd_ts[4][4];
+  double  p_nu_ext_hz[4], p_Jext_mean[4], p_Jext_sd[4];
+  double  p_tau_m[4], p_E[4], p_V_th[4], p_V_r[4], p_tau_arp[4];
+  double  p_alpha_c[4], p_tau_c[4], p_gc[4], p_I_const[4];
 } orc_params;
 
 typedef struct orc_net orc_net;
@@ -109,9 +130,17 @@ int64_t  orc_table(const orc_net* n, const char* name, void* out, int64_t cap);
 
 /* One row of the connectivity, sorted stably by delay (draw order kept
  * within a delay).  Arrays hold K_out entries; doff holds d_max-d_min+2
- * offsets (doff[k] = first position with delay >= d_min + k). */
+ * offsets (doff[k] = first position with delay >= d_min + k); blk (may be
+ * NULL) receives each synapse's block: the index of its target population
+ * in the source population's projection list, which selects the efficacy
+ * table. */
 int32_t  orc_gen_row(const orc_net* n, int64_t s, int32_t* tgt,
                      uint8_t* delay, uint16_t* widx, uint16_t* doff);
+int32_t  orc_gen_row_blocks(const orc_net* n, int64_t s, int32_t* tgt,
+                            uint8_t* delay, uint16_t* widx, uint16_t* doff,
+                            uint8_t* blk);
+/* Populations per module (2 for the two-population model). */
+int32_t  orc_n_pops(const orc_net* n);
 
 /* External Poisson input of neuron i at step t: count and the fixed-point
  * (MIRROR32) / binary64 (EXACT64) sum of its efficacies. */
@@ -135,7 +164,8 @@ int32_t  orc_set_time(orc_net* n, int64_t t);
 /* Spikes since creation as (step, id) in the order they were emitted
  * (step-major, id ascending). Returns the count; copies min(count, cap). */
 int64_t  orc_spikes(const orc_net* n, int32_t* step, int32_t* id, int64_t cap);
-/* Population counts: [bins][modules][2]; returns number of bins touched. */
+/* Population counts: [bins][modules][n_pops]; returns number of bins
+ * touched. */
 int64_t  orc_rates(const orc_net* n, uint32_t* counts, int64_t cap_bins);
 
 #ifdef __cplusplus

@@ -11,7 +11,7 @@
 #include "dpsnn_internal.h"
 
 namespace dpsnn {
-std::vector<int64_t> fix_table(const dpsnn_params& p, const HostTables& T, int q);
+std::vector<int64_t> fix_table(const dpsnn_params& p, const HostTables& T, int q, int b);
 }
 
 using namespace dpsnn;
@@ -74,8 +74,9 @@ int build_impl(dpsnn_net* n) {
   for (int k = 0; k < nn; ++k) {
     const int rc = compute_tables(n->p[k], n->T[k]);
     if (rc != DPSNN_OK) return rc;
-    if (!same_structure(p0, n->p[k])) return DPSNN_E_INVAL;
+    if (!same_structure(p0, n->p[k]) || n->T[k].P != n->T[0].P) return DPSNN_E_INVAL;
   }
+  const int P = n->T[0].P;
   HIP_OK(hipGetDevice(&n->device));
   const hipStream_t st = n->stream;
   const HostTables& T0 = n->T[0];
@@ -114,15 +115,15 @@ int build_impl(dpsnn_net* n) {
   NetDev* nets = (NetDev*)dev_alloc(n, sizeof(NetDev) * nn);
   int2* log = (int2*)dev_alloc(n, (size_t)std::max<int64_t>(p0.spike_log_cap, 1) * 8);
   unsigned char* ctl = (unsigned char*)dev_alloc(n, 256);
-  unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p0.rate_bins_cap * M * 2 * 4);
-  int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * 2 * 8);
+  unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p0.rate_bins_cap * M * P * 4);
+  int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * P * 8);
   if (!tgt || !w || !V || !c || !ref || !slots || !spk || !blk_cnt || !tile_net ||
       !nets || !log || !ctl || !rates || !sfix)
     return DPSNN_E_NOMEM;
   HIP_OK(hipMemsetAsync(slots, 0, (size_t)T0.D * Np * ab, st));
   HIP_OK(hipMemsetAsync(ctl, 0, 256, st));
   HIP_OK(hipMemsetAsync(blk_cnt, 0, (size_t)n_tiles * 4, st));
-  HIP_OK(hipMemsetAsync(rates, 0, (size_t)p0.rate_bins_cap * M * 2 * 4, st));
+  HIP_OK(hipMemsetAsync(rates, 0, (size_t)p0.rate_bins_cap * M * P * 4, st));
 
   // int32 input slots: check at build that no step can leave the range.
   // The per-step sum at a neuron is bounded by the sum of |fixed-point
@@ -135,11 +136,11 @@ int build_impl(dpsnn_net* n) {
     HIP_OK(hipMemsetAsync(absum, 0, (size_t)Np * 8 + 256, st));
   }
 
-  void* jx_all = dev_alloc(n, (size_t)nn * 2 * kQuantN * ab);
+  void* jx_all = dev_alloc(n, (size_t)nn * kMaxPops * kQuantN * ab);
   if (!jx_all) return DPSNN_E_NOMEM;
   std::vector<NetDev> nd(nn);
   std::vector<int32_t> tn((size_t)n_tiles);
-  std::vector<int64_t> sf((size_t)M * 2);
+  std::vector<int64_t> sf((size_t)M * P);
   for (int k = 0; k < nn; ++k) {
     const dpsnn_params& p = n->p[k];
     const HostTables& T = n->T[k];
@@ -149,27 +150,38 @@ int build_impl(dpsnn_net* n) {
     // per-network tables
     uint32_t* off_thr = (uint32_t*)dev_alloc(n, std::max<size_t>(T.off_thr.size(), 1) * 4);
     int32_t* off_xy = (int32_t*)dev_alloc(n, std::max<size_t>(T.off_xy.size(), 2) * 4);
-    void* wtab[2];
-    for (int q = 0; q < 2; ++q) wtab[q] = dev_alloc(n, (size_t)kQuantN * wb);
-    void* jx = static_cast<unsigned char*>(jx_all) + (size_t)k * 2 * kQuantN * ab;
-    int64_t* wfix_dev = absum ? (int64_t*)dev_alloc(n, (size_t)2 * kQuantN * 8) : nullptr;
-    if (!off_thr || !off_xy || !wtab[0] || !wtab[1] || (absum && !wfix_dev))
-      return DPSNN_E_NOMEM;
+    if (!off_thr || !off_xy) return DPSNN_E_NOMEM;
     if (!T.off_thr.empty())
       HIP_OK(hipMemcpyAsync(off_thr, T.off_thr.data(), T.off_thr.size() * 4,
                             hipMemcpyHostToDevice, st));
     if (!T.off_xy.empty())
       HIP_OK(hipMemcpyAsync(off_xy, T.off_xy.data(), T.off_xy.size() * 4,
                             hipMemcpyHostToDevice, st));
-    for (int q = 0; q < 2; ++q) {
-      const void* src = p.weight_dtype == DPSNN_W_F32 ? (const void*)T.wt32[q].data()
-                        : p.weight_dtype == DPSNN_W_F16 ? (const void*)T.wt16[q].data()
-                                                        : (const void*)T.wq8[q].data();
-      HIP_OK(hipMemcpyAsync(wtab[q], src, (size_t)kQuantN * wb, hipMemcpyHostToDevice, st));
-    }
-    // host staging buffers must outlive the asynchronous copies: sync below
-    std::vector<unsigned char> jxh((size_t)2 * kQuantN * ab);
-    for (int q = 0; q < 2; ++q)
+    // efficacy tables by (source pop, block), in the stored format; their
+    // fixed-point values for the range check
+    void* wtab[kMaxPops][kMaxPops] = {};
+    int64_t* wfix_dev[kMaxPops][kMaxPops] = {};
+    std::vector<std::vector<int64_t>> wf;  // staging: kept until the sync below
+    for (int q = 0; q < T.P; ++q)
+      for (int bb = 0; bb < T.tables(q); ++bb) {
+        wtab[q][bb] = dev_alloc(n, (size_t)kQuantN * wb);
+        if (!wtab[q][bb]) return DPSNN_E_NOMEM;
+        const void* src = p.weight_dtype == DPSNN_W_F32 ? (const void*)T.wt32[q][bb].data()
+                          : p.weight_dtype == DPSNN_W_F16 ? (const void*)T.wt16[q][bb].data()
+                                                          : (const void*)T.wq8[q][bb].data();
+        HIP_OK(hipMemcpyAsync(wtab[q][bb], src, (size_t)kQuantN * wb, hipMemcpyHostToDevice, st));
+        if (absum) {
+          wfix_dev[q][bb] = (int64_t*)dev_alloc(n, (size_t)kQuantN * 8);
+          if (!wfix_dev[q][bb]) return DPSNN_E_NOMEM;
+          wf.push_back(fix_table(p, T, q, bb));
+          HIP_OK(hipMemcpyAsync(wfix_dev[q][bb], wf.back().data(), (size_t)kQuantN * 8,
+                                hipMemcpyHostToDevice, st));
+        }
+      }
+    // external fixed-point efficacies by target pop
+    void* jx = static_cast<unsigned char*>(jx_all) + (size_t)k * kMaxPops * kQuantN * ab;
+    std::vector<unsigned char> jxh((size_t)kMaxPops * kQuantN * ab, 0);
+    for (int q = 0; q < T.P; ++q)
       for (int i = 0; i < kQuantN; ++i) {
         const int64_t v = T.jxfix[q][i];
         if (ab == 4) {
@@ -180,33 +192,23 @@ int build_impl(dpsnn_net* n) {
         }
       }
     HIP_OK(hipMemcpyAsync(jx, jxh.data(), jxh.size(), hipMemcpyHostToDevice, st));
-    std::vector<int64_t> wf;
-    if (absum) {
-      wf.resize((size_t)2 * kQuantN);
-      for (int q = 0; q < 2; ++q) {
-        std::vector<int64_t> t = fix_table(p, T, q);
-        std::copy(t.begin(), t.end(), wf.begin() + (size_t)q * kQuantN);
-      }
-      HIP_OK(hipMemcpyAsync(wfix_dev, wf.data(), wf.size() * 8, hipMemcpyHostToDevice, st));
-    }
     // int8 scale per (module, source pop); modules of one network share the
-    // parameters, hence the scale of their population table
-    for (int64_t m = 0; m < T.M; ++m) {
-      sf[2 * (n->mbase[k] + m)] = T.s8fix[0];
-      sf[2 * (n->mbase[k] + m) + 1] = T.s8fix[1];
-    }
+    // parameters, hence the scale of their population
+    for (int64_t m = 0; m < T.M; ++m)
+      for (int q = 0; q < P; ++q) sf[(size_t)P * (n->mbase[k] + m) + q] = T.s8fix[q];
     for (int64_t tl = b / 1024; tl < (b + T.N_pad) / 1024; ++tl) tn[(size_t)tl] = k;
 
     InitArgs ia{};
     ia.N = T.N;
     ia.N_pad = T.N_pad;
     ia.K = p.K;
-    ia.K_exc = T.K_exc;
+    ia.P = T.P;
     ia.key0 = key0;
     ia.key1 = key1;
-    for (int q = 0; q < 2; ++q) {
-      ia.E[q] = (float)p.E[q];
-      ia.Vth[q] = (float)p.V_th[q];
+    for (int q = 0; q < kMaxPops; ++q) {
+      ia.pop_hi[q] = q < T.P - 1 ? T.pop_hi[q] : p.K;
+      ia.E[q] = q < T.P ? (float)T.E[q] : 0.f;
+      ia.Vth[q] = q < T.P ? (float)T.Vth[q] : 0.f;
     }
     ia.V = V + b;
     ia.c = c + b;
@@ -217,7 +219,6 @@ int build_impl(dpsnn_net* n) {
     ga.N = T.N;
     ga.tgt_base = b;
     ga.K = p.K;
-    ga.K_exc = T.K_exc;
     ga.K_out = p.K_out;
     ga.row_stride = rs;
     ga.n_del = T.n_del;
@@ -225,39 +226,52 @@ int build_impl(dpsnn_net* n) {
     ga.W = p.grid_w;
     ga.H = p.grid_h;
     ga.n_off = (int32_t)(T.off_xy.size() / 2);
-    ga.n_local[0] = T.n_local[0];
-    ga.n_local[1] = T.n_local[1];
+    ga.open = T.open;
+    ga.P = T.P;
+    for (int q = 0; q < kMaxPops; ++q) {
+      ga.pop_hi[q] = q < T.P - 1 ? T.pop_hi[q] : p.K;
+      ga.n_blk[q] = q < T.P ? T.n_blk[q] : 0;
+      int end = 0;
+      for (int bb = 0; bb < kMaxPops; ++bb) {
+        const bool on = q < T.P && bb < T.n_blk[q];
+        end += on ? T.blk_n[q][bb] : 0;
+        ga.blk_end[q][bb] = end;
+        ga.blk_lo[q][bb] = on ? T.blk_lo[q][bb] : 0;
+        ga.blk_hi[q][bb] = on ? T.blk_hi[q][bb] : 1;
+        ga.blk_rule[q][bb] = on ? T.blk_rule[q][bb] : kRuleOwn;
+        ga.wtab[q][bb] = wtab[q][bb];
+        ga.wfix_tab[q][bb] = wfix_dev[q][bb];
+      }
+    }
     ga.key0 = key0;
     ga.key1 = key1;
     ga.off_thr = off_thr;
     ga.off_xy = off_xy;
-    ga.wtab[0] = wtab[0];
-    ga.wtab[1] = wtab[1];
     ga.tgt = tgt + b * rs;
     ga.w = static_cast<unsigned char*>(w) + (size_t)b * rs * wb;
     ga.absum = absum;
-    ga.wfix_tab[0] = wfix_dev;
-    ga.wfix_tab[1] = wfix_dev ? wfix_dev + kQuantN : nullptr;
     if (p.K_out > 0) HIP_OK(launch_gen(ga, p.weight_dtype, st));
     HIP_OK(hipStreamSynchronize(st));
 
     NetDev& d = nd[k];
+    memset(&d, 0, sizeof(d));
     d.base = b;
     d.N = T.N;
     d.mbase = (int32_t)n->mbase[k];
     d.K = p.K;
-    d.K_exc = T.K_exc;
+    d.P = T.P;
     d.key0 = key0;
     d.key1 = key1;
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < kMaxPops; ++q) d.pop_hi[q] = q < T.P - 1 ? T.pop_hi[q] : p.K;
+    for (int q = 0; q < T.P; ++q) {
       d.Pm[q] = T.prop32[q][0];
       d.Pc[q] = T.prop32[q][1];
       d.PVc[q] = T.prop32[q][2];
       d.Iterm[q] = T.prop32[q][3];
-      d.E[q] = (float)p.E[q];
-      d.Vth[q] = (float)p.V_th[q];
-      d.Vr[q] = (float)p.V_r[q];
-      d.alpha[q] = (float)p.alpha_c[q];
+      d.E[q] = (float)T.E[q];
+      d.Vth[q] = (float)T.Vth[q];
+      d.Vr[q] = (float)T.Vr[q];
+      d.alpha[q] = (float)T.alpha[q];
       d.n_arp[q] = T.n_arp[q];
       d.n_pois[q] = T.n_pois[q];
       for (int x = 0; x < kMaxPois; ++x) d.pois[q][x] = T.pois[q][x];
@@ -285,6 +299,7 @@ int build_impl(dpsnn_net* n) {
   a.n_del = T0.n_del;
   a.d_min = p0.d_min;
   a.M = (int32_t)M;
+  a.P = P;
   a.n_tiles = (int32_t)n_tiles;
   a.deliver_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(256, n_tiles));
   a.rate_bin_steps = p0.rate_bin_steps;
@@ -640,7 +655,7 @@ int dpsnn_read_rates(dpsnn_net* n, uint32_t* host_counts, int64_t cap_bins, int6
   const int64_t nb = done - n->rate_first;
   *n_bins = nb;
   if (nb <= 0 || cap_bins < nb || !host_counts) return DPSNN_OK;
-  const int64_t per = (int64_t)n->M_total * 2;
+  const int64_t per = (int64_t)n->M_total * n->sa.P;
   const int64_t cap = n->p[0].rate_bins_cap;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t src = (n->rate_first + b) % cap;
@@ -681,6 +696,7 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->queue_cap = n->sa.q_cap;
   out->deliver_blocks = n->sa.deliver_blocks;
   out->route_blocks = n->sa.route_blocks;
+  out->n_pops = n->sa.P;
   return DPSNN_OK;
 }
 
@@ -777,8 +793,18 @@ int64_t dpsnn_host_table(const dpsnn_params* p, const char* name, void* out, int
   HostTables T;
   const int rc = compute_tables(*p, T);
   if (rc != DPSNN_OK) return rc;
-  if (!strcmp(name, "wfix_0") || !strcmp(name, "wfix_1")) {
-    std::vector<int64_t> v = fix_table(*p, T, name[5] - '0');
+  if (!strncmp(name, "wfix_", 5)) {  // wfix_<q> (block 0) or wfix_<q>_<b>
+    const char* d = name + 5;
+    int q = -1, b = 0;
+    if (strlen(d) == 1 && d[0] >= '0' && d[0] <= '3') {
+      q = d[0] - '0';
+    } else if (strlen(d) == 3 && d[0] >= '0' && d[0] <= '3' && d[1] == '_' && d[2] >= '0' &&
+               d[2] <= '3') {
+      q = d[0] - '0';
+      b = d[2] - '0';
+    }
+    if (q < 0 || q >= T.P || b >= T.tables(q)) return DPSNN_E_INVAL;
+    std::vector<int64_t> v = fix_table(*p, T, q, b);
     const int64_t bytes = (int64_t)v.size() * 8;
     if (out && cap >= bytes) memcpy(out, v.data(), (size_t)bytes);
     return bytes;

@@ -37,38 +37,58 @@ struct __attribute__((aligned(16))) QEntry<int64_t> {
   int64_t w;
 };
 
+constexpr int kMaxPops = 4;     // populations per module
+constexpr int kMaxAttempts = 64; // draws of a module inside open boundaries
+// how a block of a source's synapses picks the target module
+constexpr int kRuleOwn = 0;      // the source's module
+constexpr int kRuleOthers = 1;   // another module by Eq. 1 (torus)
+constexpr int kRuleAll = 2;      // any module by Eq. 1 from d = 0
+
 // Everything dpsnn_build derives from the parameters on the host, in
-// binary64 first and rounded once to the width the device uses.
+// binary64 first and rounded once to the width the device uses.  The
+// two-population parameters are expressed in the same terms as the
+// population model: populations with module-local index ranges, and per
+// source population an ordered list of synapse blocks.
 struct HostTables {
   int64_t N = 0;          // neurons
   int64_t N_pad = 0;      // neurons rounded up to the step kernel's tile
   int32_t M = 0;          // modules
-  int32_t K_exc = 0;      // excitatory neurons per module
-  int32_t n_local[2] = {0, 0};
+  int32_t P = 2;          // populations per module
+  int32_t pop_lo[kMaxPops] = {0, 0, 0, 0}, pop_hi[kMaxPops] = {0, 0, 0, 0};
   int32_t D = 0;          // input slots = d_max + 1
   int32_t n_del = 0;      // distinct delays
   int32_t row_stride = 0; // K_out rounded up to a multiple of 4
-  int32_t n_arp[2] = {0, 0};
+  int32_t n_arp[kMaxPops] = {0, 0, 0, 0};
 
-  double prop64[2][4];    // Pm, Pc, PVc, Iterm
-  float prop32[2][4];
+  double prop64[kMaxPops][4];    // Pm, Pc, PVc, Iterm
+  float prop32[kMaxPops][4];
+  double E[kMaxPops], Vth[kMaxPops], Vr[kMaxPops], alpha[kMaxPops];
 
-  int32_t n_pois[2] = {0, 0};
-  uint32_t pois[2][kMaxPois];
+  int32_t n_pois[kMaxPops] = {0, 0, 0, 0};
+  uint32_t pois[kMaxPops][kMaxPois];
 
-  std::vector<uint32_t> off_thr;  // M - 2 cumulative thresholds
-  std::vector<int32_t> off_xy;    // (ox, oy) per offset, M - 1 offsets
+  int32_t n_blk[kMaxPops] = {0, 0, 0, 0};
+  int32_t blk_n[kMaxPops][kMaxPops], blk_lo[kMaxPops][kMaxPops];
+  int32_t blk_hi[kMaxPops][kMaxPops], blk_rule[kMaxPops][kMaxPops];
+  double blk_J[kMaxPops][kMaxPops], blk_sd[kMaxPops][kMaxPops];
 
-  std::vector<double> wt64[2];    // recurrent efficacy by source pop
-  std::vector<float> wt32[2];
-  std::vector<uint16_t> wt16[2];
-  std::vector<int8_t> wq8[2];
-  float s8[2] = {1.f, 1.f};
-  int64_t s8fix[2] = {0, 0};
-  std::vector<double> jx64[2];    // external efficacy by target pop
-  std::vector<float> jx32[2];
-  std::vector<int64_t> jxfix[2];
+  int32_t open = 0;               // open boundaries (draws outside repeated)
+  std::vector<uint32_t> off_thr;  // cumulative thresholds of the offsets
+  std::vector<int32_t> off_xy;    // (ox, oy) per offset
+
+  // efficacy tables by (source pop, block); a pop with no block has one
+  std::vector<double> wt64[kMaxPops][kMaxPops];
+  std::vector<float> wt32[kMaxPops][kMaxPops];
+  std::vector<uint16_t> wt16[kMaxPops][kMaxPops];
+  std::vector<int8_t> wq8[kMaxPops][kMaxPops];
+  float s8[kMaxPops] = {1.f, 1.f, 1.f, 1.f};
+  int64_t s8fix[kMaxPops] = {0, 0, 0, 0};
+  std::vector<double> jx64[kMaxPops];    // external efficacy by target pop
+  std::vector<float> jx32[kMaxPops];
+  std::vector<int64_t> jxfix[kMaxPops];
   int64_t ext_bound = 0;          // largest |external sum| of one step
+
+  int tables(int q) const { return n_blk[q] > 0 ? n_blk[q] : 1; }
 };
 
 int validate(const dpsnn_params& p);
@@ -83,18 +103,21 @@ struct NetDev {
   int64_t base;             // global index of the network's neuron 0
   int64_t N;                // neurons of the network
   int32_t mbase;            // global index of the network's module 0
-  int32_t K, K_exc;         // neurons and excitatory neurons per module
+  int32_t K, P;             // neurons and populations per module
+  int32_t pop_hi[kMaxPops]; // module-local end of each population (K past P)
   uint32_t key0, key1;      // Philox key (the network's seed)
-  float Pm[2], Pc[2], PVc[2], Iterm[2], E[2], Vth[2], Vr[2], alpha[2];
-  int32_t n_arp[2];
-  int32_t n_pois[2];
-  uint32_t pois[2][kMaxPois];
+  float Pm[kMaxPops], Pc[kMaxPops], PVc[kMaxPops], Iterm[kMaxPops];
+  float E[kMaxPops], Vth[kMaxPops], Vr[kMaxPops], alpha[kMaxPops];
+  int32_t n_arp[kMaxPops];
+  int32_t n_pois[kMaxPops];
+  uint32_t pois[kMaxPops][kMaxPois];
 };
 
 // Arguments of the step kernels (passed by value).
 struct StepArgs {
   int64_t N_pad;           // size of the global index space
   int32_t K_out, row_stride, D, n_del, d_min, M;  // M: modules of all networks
+  int32_t P;               // populations per module (rate-bin and scale stride)
   int32_t n_tiles;         // neuron tiles of 1024 = N_pad / 1024
   int32_t deliver_blocks;  // delivery blocks of the delivery kernel
   int32_t route_blocks;    // inbox-routing blocks that follow them
@@ -103,7 +126,7 @@ struct StepArgs {
   int64_t spike_log_cap;
   const NetDev* nets;
   const int32_t* tile_net;  // [n_tiles] network of each tile
-  const void* jx;          // [networks][2][65536] external fixed-point
+  const void* jx;          // [networks][kMaxPops][65536] external fixed-point
                            // efficacies of the slot width
   float* V;
   float* c;
@@ -111,7 +134,7 @@ struct StepArgs {
   void* slots;
   const int32_t* tgt;      // global target | delay index << 26
   const void* w;
-  const int64_t* sfix;     // [M][2] int8 scale in fixed point (int8 format)
+  const int64_t* sfix;     // [M][P] int8 scale in fixed point (int8 format)
   int32_t* spk;            // [n_tiles][1024] spike ids of the step, per tile
   int32_t* blk_cnt;        // [n_tiles] spikes per tile
   int2* log;
@@ -136,25 +159,30 @@ struct StepArgs {
 struct GenArgs {
   int64_t N;
   int64_t tgt_base;        // global index of the network's neuron 0
-  int32_t K, K_exc, K_out, row_stride, n_del, d_min;
-  int32_t W, H, n_off;
-  int32_t n_local[2];
+  int32_t K, K_out, row_stride, n_del, d_min;
+  int32_t W, H, n_off, open;
+  int32_t P, pop_hi[kMaxPops];
+  // synapse blocks of each source pop: end (cumulative count), target range,
+  // module rule
+  int32_t n_blk[kMaxPops];
+  int32_t blk_end[kMaxPops][kMaxPops], blk_lo[kMaxPops][kMaxPops];
+  int32_t blk_hi[kMaxPops][kMaxPops], blk_rule[kMaxPops][kMaxPops];
   uint32_t key0, key1;
   const uint32_t* off_thr;
   const int32_t* off_xy;
-  const void* wtab[2];     // stored-format table by source pop
+  const void* wtab[kMaxPops][kMaxPops];  // stored-format table by (pop, block)
   int32_t* tgt;
   void* w;
   // fixed-point in-weight sums for the int32 range check (may be null)
   unsigned long long* absum;
-  const int64_t* wfix_tab[2];
+  const int64_t* wfix_tab[kMaxPops][kMaxPops];
 };
 
 struct InitArgs {
   int64_t N, N_pad;
-  int32_t K, K_exc;
+  int32_t K, P, pop_hi[kMaxPops];
   uint32_t key0, key1;
-  float E[2], Vth[2];
+  float E[kMaxPops], Vth[kMaxPops];
   float* V;
   float* c;
   uint8_t* ref;

@@ -1,11 +1,11 @@
 // HIP kernels of libdpsnn for gfx950 (64-lane wavefronts).
 //
 //  k_gen      one wavefront per source row: draws the K_out synapses of the
-//             source from Philox (Eq. 1 targets, uniform delay, quantile-table
-//             efficacy), ranks them stably by delay with wavefront ballots and
-//             writes the delay-sorted row plus its delay offsets.  The delay
-//             index also rides in the top 6 bits of each target word, so that
-//             delivery needs no lookup.
+//             source from Philox (blocks of synapses per target population,
+//             Eq. 1 targets, uniform delay, quantile-table efficacy), sorts
+//             them by (target, delay, draw index) in LDS and writes the row.
+//             The delay index rides in the top 6 bits of each target word,
+//             so that delivery needs no lookup.
 //  k_init     initial membrane potentials, fatigue and refractory counters.
 //  k_neuron   one step of dt for a tile of 1024 neurons (4 per thread):
 //             input slot read-and-clear, external Poisson drive, Eq. 2 update,
@@ -71,8 +71,9 @@ __host__ __device__ inline int gen_pow2(int Ko) {
   return P;
 }
 __host__ __device__ inline int gen_stage_bytes(int Ko) {
-  // sort keys (8 per slot of the power-of-two sort) + efficacy index (2)
-  return gen_pow2(Ko) * 8 + ((2 * Ko + 15) / 16) * 16;
+  // sort keys (8 per slot of the power-of-two sort) + efficacy index (2) +
+  // block (1)
+  return gen_pow2(Ko) * 8 + ((3 * Ko + 15) / 16) * 16;
 }
 
 template <int WDT>
@@ -89,39 +90,65 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
   unsigned char* base = smem + (size_t)wave * gen_stage_bytes(Ko);
   uint64_t* st_key = reinterpret_cast<uint64_t*>(base);
   uint16_t* st_w = reinterpret_cast<uint16_t*>(base + (size_t)P * 8);
+  uint8_t* st_b = reinterpret_cast<uint8_t*>(st_w + Ko);
 
   const int32_t ls = (int32_t)(s % a.K);
   const int32_t ms = (int32_t)(s / a.K);
-  const int pop = ls < a.K_exc ? 0 : 1;
+  const int pop = (ls >= a.pop_hi[0]) + (ls >= a.pop_hi[1]) + (ls >= a.pop_hi[2]);
   const int xs = ms % a.W, ys = ms / a.W;
 
-  // draw synapse j: sort key = target << 18 | delay index << 12 | j
+  // draw synapse j of block b: sort key = target << 18 | delay index << 12 | j
   for (int j = lane; j < P; j += 64) {
     uint64_t key = ~0ull;
     if (j < Ko) {
-      const uint4 u = philox10(make_uint4((uint32_t)s, (uint32_t)j, 0u, kTagSyn),
-                               a.key0, a.key1);
-      int32_t tg;
-      if (j < a.n_local[pop]) {
-        const uint32_t r = scale32(u.x, (uint32_t)(a.K - 1));
-        tg = ms * a.K + (int32_t)(r + (r >= (uint32_t)ls ? 1u : 0u));
+      int b = 0;
+      while (b + 1 < a.n_blk[pop] && j >= a.blk_end[pop][b]) ++b;
+      const int lo = a.blk_lo[pop][b], size = a.blk_hi[pop][b] - lo;
+      const int rule = a.blk_rule[pop][b];
+      uint4 u;
+      int32_t mt = ms;
+      uint32_t nu;  // the word that picks the neuron
+      if (rule == kRuleOwn) {
+        u = philox10(make_uint4((uint32_t)s, (uint32_t)j, 0u, kTagSyn), a.key0, a.key1);
+        nu = u.x;
       } else {
-        int lo = 0, hi = a.n_off - 1;  // first threshold above u.x
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (a.off_thr[mid] <= u.x)
-            lo = mid + 1;
-          else
-            hi = mid;
+        // Eq. 1: module offset from word 0; with open edges a draw that
+        // leaves the grid is repeated with counter word 2 = attempt
+        for (uint32_t att = 0;; ++att) {
+          u = philox10(make_uint4((uint32_t)s, (uint32_t)j, att, kTagSyn), a.key0, a.key1);
+          int lo2 = 0, hi2 = a.n_off - 1;  // first threshold above u.x
+          while (lo2 < hi2) {
+            const int mid = (lo2 + hi2) >> 1;
+            if (a.off_thr[mid] <= u.x)
+              lo2 = mid + 1;
+            else
+              hi2 = mid;
+          }
+          int xt = xs + a.off_xy[2 * lo2];
+          int yt = ys + a.off_xy[2 * lo2 + 1];
+          if (!a.open) {
+            if (xt >= a.W) xt -= a.W;
+            if (yt >= a.H) yt -= a.H;
+          }
+          if (xt >= 0 && xt < a.W && yt >= 0 && yt < a.H) {
+            mt = yt * a.W + xt;
+            break;
+          }
+          if (att + 1 == (uint32_t)kMaxAttempts) break;  // own module
         }
-        int xt = xs + a.off_xy[2 * lo];
-        int yt = ys + a.off_xy[2 * lo + 1];
-        if (xt >= a.W) xt -= a.W;
-        if (yt >= a.H) yt -= a.H;
-        tg = (yt * a.W + xt) * a.K + (int32_t)scale32(u.y, (uint32_t)a.K);
+        nu = u.y;
       }
+      uint32_t r;
+      if (mt == ms && ls >= lo && ls < lo + size) {  // no autapse
+        r = scale32(nu, (uint32_t)(size - 1));
+        r += r >= (uint32_t)(ls - lo) ? 1u : 0u;
+      } else {
+        r = scale32(nu, (uint32_t)size);
+      }
+      const int32_t tg = mt * a.K + lo + (int32_t)r;
       const uint32_t k = scale32(u.z, (uint32_t)a.n_del);
       st_w[j] = (uint16_t)(u.w >> 16);
+      st_b[j] = (uint8_t)b;
       key = ((uint64_t)(uint32_t)tg << 18) | ((uint64_t)k << 12) | (uint64_t)j;
     }
     st_key[j] = key;
@@ -149,17 +176,18 @@ __global__ void __launch_bounds__(256) k_gen(GenArgs a) {
     const int32_t tg = (int32_t)(key >> 18);
     const int k = (int)((key >> 12) & 63u);
     const uint16_t wi = st_w[key & 4095u];
+    const int b = st_b[key & 4095u];
     const int64_t o = rb + pos;
     const int32_t gt = tg + (int32_t)a.tgt_base;  // global target index
     a.tgt[o] = gt | (k << kDelayShift);
     if (WDT == DPSNN_W_F32)
-      static_cast<float*>(a.w)[o] = static_cast<const float*>(a.wtab[pop])[wi];
+      static_cast<float*>(a.w)[o] = static_cast<const float*>(a.wtab[pop][b])[wi];
     else if (WDT == DPSNN_W_F16)
-      static_cast<uint16_t*>(a.w)[o] = static_cast<const uint16_t*>(a.wtab[pop])[wi];
+      static_cast<uint16_t*>(a.w)[o] = static_cast<const uint16_t*>(a.wtab[pop][b])[wi];
     else
-      static_cast<int8_t*>(a.w)[o] = static_cast<const int8_t*>(a.wtab[pop])[wi];
+      static_cast<int8_t*>(a.w)[o] = static_cast<const int8_t*>(a.wtab[pop][b])[wi];
     if (a.absum) {
-      const int64_t f = a.wfix_tab[pop][wi];
+      const int64_t f = a.wfix_tab[pop][b][wi];
       atomicAdd(&a.absum[gt], (unsigned long long)(f < 0 ? -f : f));
     }
   }
@@ -190,7 +218,8 @@ __global__ void k_init(InitArgs a) {
   if (i >= a.N_pad) return;
   float V = 0.f;
   if (i < a.N) {
-    const int q = (int)(i % a.K) < a.K_exc ? 0 : 1;
+    const int l = (int)(i % a.K);
+    const int q = (l >= a.pop_hi[0]) + (l >= a.pop_hi[1]) + (l >= a.pop_hi[2]);
     const uint4 u = philox10(make_uint4((uint32_t)i, 0u, 0u, kTagInit), a.key0, a.key1);
     const float f = (float)(u.x >> 8) * 0x1p-24f;
     V = a.E[q] + (a.Vth[q] - a.E[q]) * f;
@@ -417,6 +446,12 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
     if (k != cur) a.q_cnt[(int64_t)tile * D + k] = L.qc[k];
 }
 
+// Entry q (0..3) of a four-entry array of uniform values, without indexing.
+template <typename T>
+__device__ __forceinline__ T sel4(const T (&v)[kMaxPops], int q) {
+  return q == 0 ? v[0] : q == 1 ? v[1] : q == 2 ? v[2] : v[3];
+}
+
 // ------------------------------------------------------------------------
 // Neuron update of the 4 neurons i0..i0+3 (global indices) of one thread at
 // step t; nd is the tile's network.  neuron_load reads and clears the input
@@ -464,29 +499,31 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
   const int64_t m0 = il0 / nd.K;
   const int l0 = (int)(il0 - m0 * nd.K);
   int q[4], k[4];
+  const int h0 = nd.pop_hi[0], h1 = nd.pop_hi[1], h2 = nd.pop_hi[2];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
-    q[j] = lj < nd.K_exc ? 0 : 1;
+    q[j] = (lj >= h0) + (lj >= h1) + (lj >= h2);
     k[j] = 0;
   }
   // Poisson counts: thresholds are uniform over the block (scalar loads),
   // each lane picks its population's
-  const int np0 = nd.n_pois[0], np1 = nd.n_pois[1];
+  const int np[kMaxPops] = {nd.n_pois[0], nd.n_pois[1], nd.n_pois[2], nd.n_pois[3]};
+  int npj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) npj[j] = sel4(np, q[j]);
 #pragma unroll
   for (int x = 0; x < kMaxPois; ++x) {
-    const uint32_t t0 = nd.pois[0][x], t1 = nd.pois[1][x];
+    const uint32_t th[kMaxPops] = {nd.pois[0][x], nd.pois[1][x], nd.pois[2][x], nd.pois[3][x]};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bool in_range = x < (q[j] ? np1 : np0);
-      if (in_range && uu[j] >= (q[j] ? t1 : t0)) k[j] += 1;
-    }
+    for (int j = 0; j < 4; ++j)
+      if (x < npj[j] && uu[j] >= sel4(th, q[j])) k[j] += 1;
   }
   int kmax = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) kmax = k[j] > kmax ? k[j] : kmax;
-  const Acc* jx = static_cast<const Acc*>(a.jx) + (int64_t)net * 2 * kQuantN;
+  const Acc* jx = static_cast<const Acc*>(a.jx) + (int64_t)net * kMaxPops * kQuantN;
   for (int b = 0; 2 * b < kmax; ++b) {
     const uint4 v = philox10(make_uint4(g, t, 0u, kTagExtJ | ((uint32_t)b << 8)), nd.key0, nd.key1);
     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
@@ -513,40 +550,45 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
   const int64_t m0 = il0 / nd.K;
   const int l0 = (int)(il0 - m0 * nd.K);
   // per-population constants: uniform loads, selected per lane
-  const float Pm0 = nd.Pm[0], Pm1 = nd.Pm[1], Pc0 = nd.Pc[0], Pc1 = nd.Pc[1];
-  const float PVc0 = nd.PVc[0], PVc1 = nd.PVc[1], It0 = nd.Iterm[0], It1 = nd.Iterm[1];
-  const float E0 = nd.E[0], E1 = nd.E[1], Vth0 = nd.Vth[0], Vth1 = nd.Vth[1];
-  const float Vr0 = nd.Vr[0], Vr1 = nd.Vr[1], al0 = nd.alpha[0], al1 = nd.alpha[1];
-  const int na0 = nd.n_arp[0], na1 = nd.n_arp[1];
+  const float Pm[kMaxPops] = {nd.Pm[0], nd.Pm[1], nd.Pm[2], nd.Pm[3]};
+  const float Pc[kMaxPops] = {nd.Pc[0], nd.Pc[1], nd.Pc[2], nd.Pc[3]};
+  const float PVc[kMaxPops] = {nd.PVc[0], nd.PVc[1], nd.PVc[2], nd.PVc[3]};
+  const float It[kMaxPops] = {nd.Iterm[0], nd.Iterm[1], nd.Iterm[2], nd.Iterm[3]};
+  const float E[kMaxPops] = {nd.E[0], nd.E[1], nd.E[2], nd.E[3]};
+  const float Vth[kMaxPops] = {nd.Vth[0], nd.Vth[1], nd.Vth[2], nd.Vth[3]};
+  const float Vr[kMaxPops] = {nd.Vr[0], nd.Vr[1], nd.Vr[2], nd.Vr[3]};
+  const float al[kMaxPops] = {nd.alpha[0], nd.alpha[1], nd.alpha[2], nd.alpha[3]};
+  const int na[kMaxPops] = {nd.n_arp[0], nd.n_arp[1], nd.n_arp[2], nd.n_arp[3]};
+  const int h0 = nd.pop_hi[0], h1 = nd.pop_hi[1], h2 = nd.pop_hi[2];
   uint32_t r_out = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
-    const bool inh = lj >= nd.K_exc;
+    const int qq = (lj >= h0) + (lj >= h1) + (lj >= h2);
     uint32_t rj = (R.r4 >> (8 * j)) & 0xFFu;
     if (il0 + j < nd.N) {
       const float dv = fix_to_f32(R.I[j]) * a.inv2q;
       float Vj = R.V[j], cj = R.c[j];
-      const float Pc = inh ? Pc1 : Pc0, E = inh ? E1 : E0;
+      const float Pcq = sel4(Pc, qq), Eq = sel4(E, qq);
       bool spk = false;
       if (rj > 0) {
         rj -= 1;
-        cj = cj * Pc;
+        cj = cj * Pcq;
       } else {
-        float vv = Vj - E;
-        vv = vv * (inh ? Pm1 : Pm0);
-        vv = E + vv;
-        const float cc = cj * (inh ? PVc1 : PVc0);
+        float vv = Vj - Eq;
+        vv = vv * sel4(Pm, qq);
+        vv = Eq + vv;
+        const float cc = cj * sel4(PVc, qq);
         vv = vv - cc;
-        vv = vv + (inh ? It1 : It0);
+        vv = vv + sel4(It, qq);
         vv = vv + dv;
-        cj = cj * Pc;
-        if (vv > (inh ? Vth1 : Vth0)) {
+        cj = cj * Pcq;
+        if (vv > sel4(Vth, qq)) {
           spk = true;
-          vv = inh ? Vr1 : Vr0;
-          cj = cj + (inh ? al1 : al0);
-          rj = (uint32_t)(inh ? na1 : na0);
+          vv = sel4(Vr, qq);
+          cj = cj + sel4(al, qq);
+          rj = (uint32_t)sel4(na, qq);
         }
         Vj = vv;
       }
@@ -571,7 +613,8 @@ __device__ __forceinline__ void module_pop(const StepArgs& a, int32_t id, int32_
   const int32_t local = id - (int32_t)nd.base;
   const int32_t m = local / nd.K;
   *mod = nd.mbase + m;
-  *pop = (local - m * nd.K) < nd.K_exc ? 0 : 1;
+  const int32_t l = local - m * nd.K;
+  *pop = (l >= nd.pop_hi[0]) + (l >= nd.pop_hi[1]) + (l >= nd.pop_hi[2]);
 }
 
 // 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.  s_b is
@@ -586,7 +629,7 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
     int32_t ms;
     int q;
     module_pop(a, s, &ms, &q);
-    scale = a.sfix[2 * ms + q];
+    scale = a.sfix[(int64_t)a.P * ms + q];
   }
   const int p = p0 + lane * 4;
   int tv[4] = {0, 0, 0, 0};
@@ -714,7 +757,7 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
   int32_t mod;
   int q;
   module_pop(a, id, &mod, &q);
-  atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * 2 + q], 1u);
+  atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * a.P + q], 1u);
 }
 
 // ------------------------------------------------------------------------

@@ -21,6 +21,19 @@ ERRORS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "RANGE",
           -5: "SPIKELOG_FULL", -6: "STATE", -7: "RATES_FULL"}
 
 _PAIR = C.c_double * 2
+_I4 = C.c_int32 * 4
+_D4 = C.c_double * 4
+_I44 = (C.c_int32 * 4) * 4
+_D44 = (C.c_double * 4) * 4
+# population-model fields (zero = the two-population model)
+_POP_FIELDS = [
+    ("n_pops", C.c_int32), ("open_boundary", C.c_int32), ("pop_size", _I4),
+    ("pop_exc", _I4), ("n_syn", _I44), ("J_mean_ts", _D44), ("J_sd_ts", _D44),
+    ("p_nu_ext_hz", _D4), ("p_Jext_mean", _D4), ("p_Jext_sd", _D4),
+    ("p_tau_m", _D4), ("p_E", _D4), ("p_V_th", _D4), ("p_V_r", _D4),
+    ("p_tau_arp", _D4), ("p_alpha_c", _D4), ("p_tau_c", _D4), ("p_gc", _D4),
+    ("p_I_const", _D4),
+]
 
 
 class DpsnnParams(C.Structure):
@@ -36,7 +49,7 @@ class DpsnnParams(C.Structure):
         ("gc", _PAIR), ("I_const", _PAIR), ("rate_bin_steps", C.c_int32),
         ("spike_log_cap", C.c_int64), ("rate_bins_cap", C.c_int64),
         ("queue_cap", C.c_int32),
-    ]
+    ] + _POP_FIELDS
 
 
 class DpsnnStats(C.Structure):
@@ -47,6 +60,7 @@ class DpsnnStats(C.Structure):
         ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("schedule", C.c_int32),
         ("n_index", C.c_int64), ("n_nets", C.c_int32), ("queue_cap", C.c_int32),
         ("deliver_blocks", C.c_int32), ("route_blocks", C.c_int32),
+        ("n_pops", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -54,13 +68,31 @@ DEFAULT_SPIKE_LOG_CAP = 1 << 24
 DEFAULT_RATE_BINS_CAP = 4096
 
 
+def _fill(ctype, v):
+    if ctype in (_I44, _D44):
+        out = ctype()
+        for i in range(4):
+            for j in range(4):
+                x = v[i][j] if i < len(v) and j < len(v[i]) else 0
+                out[i][j] = int(x) if ctype is _I44 else float(x)
+        return out
+    vals = [v[i] if i < len(v) else 0 for i in range(4)]
+    return ctype(*[(int(x) if ctype is _I4 else float(x)) for x in vals])
+
+
 def to_struct(params: dict) -> DpsnnParams:
     s = DpsnnParams()
     s.abi_version = ABI_VERSION
+    pop_names = {n for n, _ in _POP_FIELDS}
     for name, ctype in DpsnnParams._fields_:
         if name == "abi_version":
             continue
         key = "lambda" if name == "lambda_" else name
+        if key in pop_names and key not in params:
+            continue                      # zero: the two-population model
+        if params.get("n_pops", 0) and key not in params and key not in (
+                "spike_log_cap", "rate_bins_cap", "queue_cap"):
+            continue                      # two-population fields unused
         if key == "spike_log_cap":
             v = params.get(key, DEFAULT_SPIKE_LOG_CAP)
         elif key == "rate_bins_cap":
@@ -73,6 +105,8 @@ def to_struct(params: dict) -> DpsnnParams:
             v = WEIGHT_DTYPES[v]
         if ctype is _PAIR:
             setattr(s, name, _PAIR(float(v[0]), float(v[1])))
+        elif ctype in (_I4, _D4, _I44, _D44):
+            setattr(s, name, _fill(ctype, v))
         elif ctype is C.c_double:
             setattr(s, name, float(v))
         else:
@@ -208,6 +242,7 @@ class Net:
         self.N = int(st["n_index"])          # entries of the inspection arrays
         self.M = int(st["n_modules"])
         self.n_nets = int(st["n_nets"])
+        self.n_pops = int(st["n_pops"])
         self.D = int(self.params["d_max"]) + 1
         self.n_del = int(self.params["d_max"]) - int(self.params["d_min"]) + 1
 
@@ -305,7 +340,7 @@ def dpsnn_read_spikes(net: Net):
 def dpsnn_read_rates(net: Net) -> np.ndarray:
     nb = C.c_int64(0)
     _check("dpsnn_read_rates", lib().dpsnn_read_rates(net.h, None, 0, C.byref(nb)))
-    out = np.zeros((max(nb.value, 0), net.M, 2), np.uint32)
+    out = np.zeros((max(nb.value, 0), net.M, net.n_pops), np.uint32)
     if nb.value > 0:
         _check("dpsnn_read_rates",
                lib().dpsnn_read_rates(net.h, _ptr(out), nb.value, C.byref(nb)))

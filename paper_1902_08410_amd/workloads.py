@@ -91,3 +91,47 @@ def c5(regime: str) -> dict:
     """96x96 grid (11.52M neurons), lambda = 2, int8 efficacies, int64 slots."""
     return grid(96, 96, regime, **{"lambda": 2.0, "weight_dtype": "i8",
                                    "acc_bits": 64, "q_frac_bits": 32})
+
+
+# ---------------------------------------------------------------------------
+# Population model of Sec. 2.2 and Table S1: per module 250 foreground (F),
+# 750 background (B) excitatory and 250 inhibitory (I) neurons; every neuron
+# projects 0.9 K_t synapses into each population t (1125 in all);
+# excitatory projections reach any module with probability proportional to
+# exp(-d / lambda) (Eq. 1 from d = 0), inhibitory ones stay in the module;
+# open boundaries.  Efficacies J_{t,s} of Table S1 with SD 0.25 |J|; the SW
+# row's inhibitory entries repeat the external-rate row (garbled) and are
+# read as the AW rows' -1.5 mV.  External drive: 400 Poisson trains of
+# 3.17 / 3.17 / 3.0 Hz with the J_{t,ext} of the state.
+_FBI_J = {
+    #        F<-F   B<-F   I<-F   F<-B   B<-B   I<-B   F<-I  B<-I  I<-I
+    "sw": [0.600, 0.382, 0.560, 0.382, 0.429, 0.560, -1.5, -1.5, -1.5],
+    "aw28": [0.515, 0.412, 0.560, 0.412, 0.429, 0.560, -1.5, -1.5, -1.5],
+    "aw88": [0.515, 0.412, 0.560, 0.412, 0.429, 0.560, -1.5, -1.5, -1.5],
+}
+_FBI_JEXT = {"sw": [0.832, 0.858, 1.120], "aw28": [0.858, 0.858, 1.120],
+             "aw88": [1.416, 1.416, 1.120]}
+
+
+def fbi(w: int, h: int, state: str = "sw", lam: float = 0.5, scale: float = 1.0,
+        **over) -> dict:
+    """The F/B/I network of w x h modules in state "sw", "aw28" or "aw88";
+    scale < 1 shrinks the populations (and out-degrees) for quick tests."""
+    j = _FBI_J[state]
+    # J_mean_ts[t][s]: target t, source s (order F, B, I)
+    jts = [[j[0], j[3], j[6]], [j[1], j[4], j[7]], [j[2], j[5], j[8]]]
+    sizes = [round(250 * scale), round(750 * scale), round(250 * scale)]
+    nsyn = [[round(0.9 * sizes[t])] * 3 for t in range(3)]
+    p = swa(grid_w=w, grid_h=h, K=sum(sizes), K_out=sum(r[0] for r in nsyn),
+            n_pops=3, open_boundary=1, pop_size=sizes, pop_exc=[1, 1, 0],
+            n_syn=nsyn, J_mean_ts=jts,
+            J_sd_ts=[[0.25 * abs(x) for x in row] for row in jts],
+            p_nu_ext_hz=[400 * 3.17, 400 * 3.17, 400 * 3.0],
+            p_Jext_mean=_FBI_JEXT[state],
+            p_Jext_sd=[0.25 * x for x in _FBI_JEXT[state]],
+            p_tau_m=[20.0, 20.0, 10.0], p_E=[0.0, 0.0, 0.0], p_V_th=[20.0] * 3,
+            p_V_r=[15.0] * 3, p_tau_arp=[2.0, 2.0, 1.0], p_alpha_c=[1.0, 1.0, 0.0],
+            p_tau_c=[1000.0] * 3, p_gc=[0.02, 0.02, 0.0], p_I_const=[0.0] * 3)
+    p["lambda"] = lam
+    p.update(over)
+    return p

@@ -148,3 +148,54 @@ def test_queue_cap_validated():
         assert e.value.code == -1
     for cap in (-1, 0, 1, 1 << 20):
         assert len(L.dpsnn_host_table(W.swa(queue_cap=cap), "prop_f64", np.float64)) == 8
+
+
+# population model (Sec. 2.2, Table S1): F/B/I populations, per-pair
+# efficacies, Eq. 1 from d = 0, open or periodic boundaries
+POP_SETS = {
+    "fbi_sw_open_6x5": W.fbi(6, 5, "sw", scale=0.05),
+    "fbi_aw88_torus_4x4_f16": W.fbi(4, 4, "aw88", scale=0.05, open_boundary=0,
+                                   weight_dtype="f16", lam=0.7),
+    "fbi_aw28_open_i8_q32": W.fbi(5, 3, "aw28", scale=0.05, weight_dtype="i8",
+                                 acc_bits=64, q_frac_bits=32, lam=0.4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(POP_SETS))
+def test_population_model_tables_bitwise_equal_to_oracle(name):
+    p = POP_SETS[name]
+    o = O.Oracle(p, 1, store_rows=False)
+    names = [("prop_f64", np.float64), ("prop_f32", np.float32), ("n_arp", np.int32),
+             ("off_thr", np.uint32), ("off_xy", np.int32), ("s8", np.float32),
+             ("s8fix", np.int64), ("blocks", np.int32)]
+    for q in range(3):
+        names += [(f"pois_thr_{q}", np.uint32), (f"jx64_{q}", np.float64),
+                  (f"jx32_{q}", np.float32), (f"jxfix_{q}", np.int64)]
+        for b in range(3):
+            names += [(f"wt64_{q}_{b}", np.float64), (f"wt32_{q}_{b}", np.float32),
+                      (f"wt16_{q}_{b}", np.uint16), (f"wq8_{q}_{b}", np.int8),
+                      (f"wfix_{q}_{b}", np.int64)]
+    for tname, dt in names:
+        a = L.dpsnn_host_table(p, tname, dt)
+        b = o.table(tname, dt)
+        assert a.dtype == b.dtype and a.shape == b.shape, (name, tname)
+        assert a.tobytes() == b.tobytes(), (name, tname)
+    blocks = L.dpsnn_host_table(p, "blocks", np.int32).reshape(3, 4, 4)
+    # blocks of source s: (0.9 K_t synapses, population t's range, rule)
+    lo = np.cumsum([0] + p["pop_size"][:2])
+    for s in range(3):
+        for t in range(3):
+            n, a, b, rule = blocks[s, t]
+            assert n == p["n_syn"][t][s] and a == lo[t] and b == lo[t] + p["pop_size"][t]
+            assert rule == (2 if p["pop_exc"][s] else 0)
+
+
+def test_population_model_invalid_parameters_rejected():
+    base = W.fbi(3, 3, "sw", scale=0.05)
+    bad = [dict(pop_size=[5, 38, 13]),                       # does not sum to K
+           dict(n_syn=[[11, 11, 11], [34, 34, 34], [11, 11, 12]]),  # unequal rows
+           dict(n_pops=5), dict(open_boundary=2)]
+    for over in bad:
+        with pytest.raises(L.DpsnnError) as e:
+            L.dpsnn_host_table(dict(base, **over), "prop_f64", np.float64)
+        assert e.value.code == -1, over

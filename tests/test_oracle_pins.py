@@ -509,3 +509,87 @@ def test_rates_are_binned_spike_counts():
         ref[t // 7, i // 20, 0 if (i % 20) < 16 else 1] += 1
     assert r.shape[0] == (300 + 6) // 7
     assert np.array_equal(r, ref) and len(st) > 0
+
+
+# ---------------------------------------------------------------------------
+# Population model (Sec. 2.2, Eq. 1 from d = 0, Table S1)
+
+def _pop_of(p, local):
+    edges = np.cumsum(p["pop_size"])
+    return int(np.searchsorted(edges, local, side="right"))
+
+
+def test_population_rows_counts_locality_no_autapse():
+    """Every source projects exactly n_syn[t][s] synapses into population t;
+    inhibitory sources stay in their module; no autapse; rows stay sorted by
+    delay; blocks name the target population."""
+    p = W.fbi(4, 3, "sw", scale=0.1)
+    o = O.Oracle(p, 5, store_rows=False)
+    K = p["K"]
+    rng = np.random.default_rng(1)
+    for s in rng.choice(o.N, 60, replace=False):
+        s = int(s)
+        tgt, dl, wi, doff, bk = o.gen_row_blocks(s)
+        ps = _pop_of(p, s % K)
+        pops = np.array([_pop_of(p, t % K) for t in tgt])
+        for t in range(3):
+            assert (pops == t).sum() == p["n_syn"][t][ps]
+        assert np.array_equal(bk, pops)          # block b targets population b here
+        assert not np.any(tgt == s)
+        if not p["pop_exc"][ps]:
+            assert np.all(tgt // K == s // K)
+        assert np.all(np.diff(dl.astype(int)) >= 0)
+
+
+def _module_law(w, h, src, lam, torus):
+    """Exact Eq. 1 law of the target module of one excitatory synapse: weight
+    exp(-d/lambda) over the modules that exist (open) or all periodic images
+    (torus, shortest image), from d = 0."""
+    xs, ys = src % w, src // w
+    wts = np.zeros(w * h)
+    for m in range(w * h):
+        dx, dy = abs(m % w - xs), abs(m // w - ys)
+        if torus:
+            dx, dy = min(dx, w - dx), min(dy, h - dy)
+        wts[m] = np.exp(-np.hypot(dx, dy) / lam)
+    return wts / wts.sum()
+
+
+@pytest.mark.parametrize("torus", [False, True])
+def test_eq1_target_modules_from_distance_zero(torus):
+    """Target modules of excitatory synapses follow exp(-d/lambda) restricted
+    to the grid (open edges: corner and edge sources draw among the modules
+    that exist) — chi-square against the law computed directly."""
+    from scipy import stats
+    w, h, lam = 5, 4, 0.7
+    p = W.fbi(w, h, "sw", scale=0.08, lam=lam, open_boundary=0 if torus else 1)
+    o = O.Oracle(p, 3, store_rows=False)
+    K = p["K"]
+    n_exc = p["pop_size"][0] + p["pop_size"][1]
+    for src in (0, 7, 19):                       # corner, interior, corner
+        counts = np.zeros(w * h)
+        for l in range(n_exc):
+            tgt = o.gen_row(src * K + l)[0]
+            counts += np.bincount(tgt // K, minlength=w * h)
+        exp = _module_law(w, h, src, lam, torus) * counts.sum()
+        keep = exp >= 5
+        obs = np.append(counts[keep], counts[~keep].sum())
+        ex = np.append(exp[keep], exp[~keep].sum())
+        if ex[-1] == 0:
+            obs, ex = obs[:-1], ex[:-1]
+        chi2 = ((obs - ex) ** 2 / ex).sum()
+        assert stats.chi2.sf(chi2, len(ex) - 1) > 1e-4, (src, chi2)
+
+
+def test_table_s1_states_give_the_paper_rates():
+    """Table S1 labels its states by mean rate: SW 3.1 Hz, AW 2.8 Hz and AW
+    8.8 Hz.  A 4x4 grid of full-size modules (open edges, lambda 0.5) run for
+    1 s reproduces them within 25 % (module average over F, B, I after 0.1 s)."""
+    want = {"sw": 3.1, "aw28": 2.8, "aw88": 8.8}
+    for state, hz in want.items():
+        p = W.fbi(4, 4, state)
+        o = O.Oracle(p, 1, store_rows=False)
+        o.step(10000)
+        st, _ = o.spikes()
+        rate = (st >= 1000).sum() / o.N / 0.9
+        assert abs(rate - hz) <= 0.25 * hz, (state, rate)
