@@ -12,7 +12,9 @@ region.
 
 Other workloads: --workload c4 (64 networks of 4x4 to 16x16 modules in one
 batched handle, FP16 efficacies), --workload c5 (96x96 modules, 11.52M
-neurons, int8 efficacies, int64 slots).
+neurons, int8 efficacies, int64 slots), --workload fbi (24x24 modules of
+the foreground / background / inhibitory populations of Sec. 2.2 with the
+Table S1 states, open boundaries).
 
 Prints one JSON line.
 """
@@ -29,7 +31,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-K_OUT = 1000
 
 
 def bytes_per_neuron_step(p) -> float:
@@ -38,7 +39,12 @@ def bytes_per_neuron_step(p) -> float:
     acc = 4 if p["acc_bits"] == 32 else 8
     exc = 4 + 4 + 4 + 4 + 1 + 1 + 2 * acc
     inh = 4 + 4 + 1 + 1 + 2 * acc
-    return p["frac_exc"] * exc + (1 - p["frac_exc"]) * inh
+    if p.get("n_pops", 0):
+        n = p["n_pops"]
+        f = sum(p["pop_size"][q] for q in range(n) if p["pop_exc"][q]) / p["K"]
+    else:
+        f = p["frac_exc"]
+    return f * exc + (1 - f) * inh
 
 
 def bytes_per_event(p) -> float:
@@ -128,7 +134,7 @@ def cpu_baseline(params, gpu_net, dpsnn, steps: int, budget_s: float):
         done += 1
     el = time.perf_counter() - t0
     n_sp = len(orc.spikes()[0])
-    return {"value": n_sp * K_OUT / el, "unit": "synaptic events/s", "cores": 1,
+    return {"value": n_sp * params["K_out"] / el, "unit": "synaptic events/s", "cores": 1,
             "kind": "oracle",
             "sample": (f"{done} steps ({done * 0.1:.1f} ms biological) of the 24x24 SWA "
                        f"network from the GPU state at step {t}; {n_sp} spikes, "
@@ -144,6 +150,8 @@ def build_workload(name, dpsnn, workloads, total_bins):
     """Handles of the workload: {label: (handle, params of its first net)}."""
     if name == "c2":
         regs = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
+    elif name == "fbi":
+        regs = {"sw": workloads.fbi(24, 24, "sw"), "aw88": workloads.fbi(24, 24, "aw88")}
     elif name == "c5":
         regs = {"swa": workloads.c5("swa"), "aw": workloads.c5("aw")}
     else:
@@ -172,16 +180,19 @@ DESCRIPTIONS = {
     "c5": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
            "SWA + AW networks, int8 efficacies with per-module scale, int64 fixed-point "
            "slots (Q = 32)"),
+    "fbi": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
+            "synapses, 1125 per neuron), Table S1 SW and AW 8.8 Hz states, Eq. 1 from "
+            "d = 0 with lambda 0.5, open boundaries, FP32 efficacies, int32 slots"),
 }
-DTYPES = {"c2": "f32", "c4": "f16", "c5": "i8"}
+DTYPES = {"c2": "f32", "c4": "f16", "c5": "i8", "fbi": "f32"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "fbi"], default="c2")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 10 for c2, 2 for c4/c5)")
+                    help="timed steps (default 10 for c2 and fbi, 2 for c4/c5)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dt-steps", type=int, default=None,
                     help="dt steps per bench step (default 10000 = 1 s; 2000 for c4/c5)")
@@ -202,13 +213,14 @@ def main():
         summarize_rocprof(*args.summarize_rocprof)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py runs on one GPU only (there is no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
-    steps = args.steps if args.steps is not None else (10 if wl == "c2" else 2)
-    S = args.dt_steps if args.dt_steps is not None else (10000 if wl == "c2" else 2000)
-    if wl != "c2":
+    small = wl in ("c2", "fbi")
+    steps = args.steps if args.steps is not None else (10 if small else 2)
+    S = args.dt_steps if args.dt_steps is not None else (10000 if small else 2000)
+    if not small:
         args.profile_steps = min(args.profile_steps, 200)
 
     import torch
@@ -232,6 +244,7 @@ def main():
     variants = {}
     with torch.cuda.stream(stream):
         nets = build_workload(wl, dpsnn, workloads, total_bins)
+        K_OUT = next(iter(nets.values()))[1]["K_out"]  # same for every handle
         for _ in range(args.warmup):
             for h, _ in nets.values():
                 dpsnn.dpsnn_step(h, S)

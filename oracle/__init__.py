@@ -198,6 +198,15 @@ class Oracle:
         self.n_del = int(params["d_max"]) - int(params["d_min"]) + 1
         self.P = int(lib().orc_n_pops(h))
 
+    def pop_of(self, i: int) -> int:
+        """Population of neuron i (module-local index against the ranges)."""
+        K = int(self.params["K"])
+        if self.params.get("n_pops", 0):
+            edges = np.cumsum(self.params["pop_size"][: self.P])
+        else:
+            edges = [round(self.params["frac_exc"] * K), K]
+        return int(np.searchsorted(edges, int(i) % K, side="right"))
+
     def close(self):
         if getattr(self, "_h", None):
             lib().orc_free(self._h)

@@ -45,14 +45,13 @@ def _compare_rows(L, net, orc, rows, wd):
     """Rows on the device are sorted by (target, delay, draw index); the
     oracle's are sorted by delay in draw order.  The same order is taken from
     the oracle's row by a stable sort, then targets, delays and stored
-    efficacies must agree bit for bit."""
+    efficacies (from the table of the synapse's source population and
+    block) must agree bit for bit."""
     tgt, w, dk = L.dpsnn_read_rows(net, rows[0], len(rows)) if len(rows) and \
         rows == list(range(rows[0], rows[0] + len(rows))) else (None, None, None)
-    tabs = {"f32": [orc.table(f"wt32_{q}", np.float32) for q in (0, 1)],
-            "f16": [orc.table(f"wt16_{q}", np.uint16) for q in (0, 1)],
-            "i8": [orc.table(f"wq8_{q}", np.int8) for q in (0, 1)]}[wd]
-    K = int(orc.params["K"])
-    Kexc = round(orc.params["frac_exc"] * K)
+    stem = {"f32": ("wt32", np.float32), "f16": ("wt16", np.uint16), "i8": ("wq8", np.int8)}[wd]
+    P = orc.P
+    tabs = {}
     d_min = int(orc.params["d_min"])
     for k, s in enumerate(rows):
         if tgt is None:
@@ -60,13 +59,20 @@ def _compare_rows(L, net, orc, rows, wd):
             t1, w1, d1 = t1[0], w1[0], d1[0]
         else:
             t1, w1, d1 = tgt[k], w[k], dk[k]
-        ot, od, ow, oo = orc.gen_row(s)
+        ot, od, ow, oo, ob = orc.gen_row_blocks(s)
         order = np.lexsort((np.arange(len(ot)), od, ot))
-        q = 0 if (s % K) < Kexc else 1
+        q = orc.pop_of(s)
         assert np.array_equal(t1, ot[order]), s
         assert np.array_equal(d1.astype(np.int64), od[order].astype(np.int64) - d_min), s
-        assert w1.tobytes() == tabs[q][ow[order]].tobytes(), s
+        want = np.empty(len(ot), stem[1])
+        for b in np.unique(ob):
+            if (q, b) not in tabs:
+                tabs[(q, b)] = orc.table(f"{stem[0]}_{q}_{b}", stem[1])
+            sel = ob == b
+            want[sel] = tabs[(q, b)][ow[sel]]
+        assert w1.tobytes() == want[order].tobytes(), s
         assert np.all(np.diff(t1.astype(np.int64)) >= 0), s
+        assert P in (2, 3, 4)
 
 
 @pytest.mark.parametrize("case", ["c1_f32", "tiny_f16", "tiny_i8", "ragged_3x3",
@@ -447,4 +453,97 @@ def test_more_work_items_than_delivery_wavefronts(L, sched):
         orc.step(100)
         n += _compare_all(L, net, orc, ("many items", sched, j))
     assert n > 50000
+    net.close()
+
+
+# ---------------------------------------------------------------------------
+# Population model (Sec. 2.2, Table S1): F/B/I populations, per-pair
+# efficacies, Eq. 1 from d = 0, open or periodic boundaries
+
+POP_CASES = {
+    "fbi_sw_open_f32": W.fbi(4, 3, "sw", scale=0.1),
+    "fbi_aw88_torus_f32": W.fbi(3, 3, "aw88", scale=0.1, open_boundary=0, lam=0.7),
+    "fbi_aw28_open_f16": W.fbi(3, 4, "aw28", scale=0.1, weight_dtype="f16", lam=0.4),
+    "fbi_aw88_open_i8_q32": W.fbi(4, 2, "aw88", scale=0.1, weight_dtype="i8",
+                                  acc_bits=64, q_frac_bits=32),
+}
+
+
+@pytest.mark.parametrize("case", sorted(POP_CASES))
+def test_population_rows_bitwise_equal(L, case):
+    p = POP_CASES[case]
+    _say("population rows", case)
+    net, orc = _pair(p, 7)
+    _compare_rows(L, net, orc, list(range(net.N)), p["weight_dtype"])
+    net.close()
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+@pytest.mark.parametrize("case", sorted(POP_CASES))
+def test_population_raster_bit_exact(L, case, sched):
+    p = POP_CASES[case]
+    _say("population raster", case, "schedule", sched)
+    net, orc = _pair(p, 11)
+    L.dpsnn_set_schedule(net, sched)
+    n = 0
+    for k in range(3):
+        L.dpsnn_step(net, 1000)
+        orc.step(1000)
+        n += _compare_all(L, net, orc, (case, sched, k))
+    assert n > 200
+    r = L.dpsnn_read_rates(net)
+    assert r.shape[2] == 3
+    assert np.array_equal(r, orc.rates()[: 3000 // p["rate_bin_steps"]])
+    net.close()
+
+
+def test_population_full_size_start_and_teacher_forced_step(L):
+    """F/B/I SW network of 24x24 full-size modules (720k neurons, 0.81G
+    synapses, open edges): sampled rows, the first 30 steps bit-exact, then
+    after 1000 more steps one step re-run by the oracle from the GPU's state,
+    slots and time."""
+    p = W.fbi(24, 24, "sw")
+    _say("F/B/I 24x24 build")
+    net, orc = _pair(p, 1, store_rows=False)
+    rng = np.random.default_rng(0)
+    rows = sorted(rng.choice(net.N, 200, replace=False).tolist())
+    _compare_rows(L, net, orc, rows, "f32")
+    L.dpsnn_step(net, 30)
+    orc.step(30)
+    _compare_all(L, net, orc, "fbi start")
+    L.dpsnn_step(net, 1000)
+    L.dpsnn_read_spikes(net)
+    V, c, r = L.dpsnn_read_state(net)
+    slots = L.dpsnn_read_slots(net)
+    orc2 = O.Oracle(p, 1, store_rows=False)
+    orc2.set_state(V.astype(np.float64), c.astype(np.float64), r.astype(np.int32))
+    orc2.set_ring(slots)
+    orc2.set_time(1030)
+    L.dpsnn_step(net, 1)
+    orc2.step(1)
+    st, ids = L.dpsnn_read_spikes(net)
+    ost, oids = _new_oracle_spikes(orc2)
+    assert np.array_equal(st, ost) and np.array_equal(ids, oids)
+    assert len(st) > 0
+    _compare_state(L, net, orc2, "fbi teacher forced")
+    assert np.array_equal(L.dpsnn_read_slots(net), orc2.ring())
+    net.close()
+
+
+def test_population_batch_matches_solo_runs(L):
+    plist = [W.fbi(3, 3, "sw", scale=0.1), W.fbi(2, 4, "aw88", scale=0.1, lam=0.7),
+             W.fbi(4, 4, "aw28", scale=0.1, open_boundary=0)]
+    seeds = [3, 4, 5]
+    _say("population batch vs solo")
+    net = L.dpsnn_build_batch(plist, seeds)
+    L.dpsnn_step(net, 2000)
+    st, ids = L.dpsnn_read_spikes(net)
+    parts = _split_spikes(L, net, st, ids)
+    for (s_k, i_k, info), p, sd in zip(parts, plist, seeds):
+        solo = L.dpsnn_build(p, sd)
+        L.dpsnn_step(solo, 2000)
+        ss, si = L.dpsnn_read_spikes(solo)
+        assert np.array_equal(s_k, ss) and np.array_equal(i_k, si)
+        assert len(ss) > 500
+        solo.close()
     net.close()
