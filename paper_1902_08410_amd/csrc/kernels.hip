@@ -446,10 +446,20 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
     if (k != cur) a.q_cnt[(int64_t)tile * D + k] = L.qc[k];
 }
 
-// Entry q (0..3) of a four-entry array of uniform values, without indexing.
-template <typename T>
-__device__ __forceinline__ T sel4(const T (&v)[kMaxPops], int q) {
+// Entry q of a four-entry array of uniform values, without indexing; the
+// update is compiled for NP = 2 populations (q in 0..1) or up to 4.
+template <int NP, typename T>
+__device__ __forceinline__ T sel(const T (&v)[kMaxPops], int q) {
+  if (NP == 2) return q ? v[1] : v[0];
   return q == 0 ? v[0] : q == 1 ? v[1] : q == 2 ? v[2] : v[3];
+}
+
+// Population of module-local index l from the ends h[0..2] of the first
+// three populations.
+template <int NP>
+__device__ __forceinline__ int pop_index(int l, int h0, int h1, int h2) {
+  if (NP == 2) return l >= h0 ? 1 : 0;
+  return (l >= h0) + (l >= h1) + (l >= h2);
 }
 
 // ------------------------------------------------------------------------
@@ -467,7 +477,7 @@ struct NeuronRegs {
   uint32_t r4;
 };
 
-template <typename Acc>
+template <typename Acc, int NP>
 __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd, int net,
                                             int64_t i0, uint32_t t, NeuronRegs<Acc>& R) {
   const int slot = (int)(t % (uint32_t)a.D);
@@ -504,21 +514,23 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
-    q[j] = (lj >= h0) + (lj >= h1) + (lj >= h2);
+    q[j] = pop_index<NP>(lj, h0, h1, h2);
     k[j] = 0;
   }
   // Poisson counts: thresholds are uniform over the block (scalar loads),
   // each lane picks its population's
-  const int np[kMaxPops] = {nd.n_pois[0], nd.n_pois[1], nd.n_pois[2], nd.n_pois[3]};
+  const int np[kMaxPops] = {nd.n_pois[0], nd.n_pois[1], NP > 2 ? nd.n_pois[2] : 0,
+                            NP > 2 ? nd.n_pois[3] : 0};
   int npj[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) npj[j] = sel4(np, q[j]);
+  for (int j = 0; j < 4; ++j) npj[j] = sel<NP>(np, q[j]);
 #pragma unroll
   for (int x = 0; x < kMaxPois; ++x) {
-    const uint32_t th[kMaxPops] = {nd.pois[0][x], nd.pois[1][x], nd.pois[2][x], nd.pois[3][x]};
+    const uint32_t th[kMaxPops] = {nd.pois[0][x], nd.pois[1][x],
+                                   NP > 2 ? nd.pois[2][x] : 0u, NP > 2 ? nd.pois[3][x] : 0u};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (x < npj[j] && uu[j] >= sel4(th, q[j])) k[j] += 1;
+      if (x < npj[j] && uu[j] >= sel<NP>(th, q[j])) k[j] += 1;
   }
   int kmax = 0;
 #pragma unroll
@@ -538,7 +550,7 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
   }
 }
 
-template <typename Acc>
+template <typename Acc, int NP>
 __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& nd, int64_t i0,
                                               NeuronRegs<Acc>& R, const Acc* s_in,
                                               int32_t* s_spk, int* s_n) {
@@ -565,30 +577,30 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
-    const int qq = (lj >= h0) + (lj >= h1) + (lj >= h2);
+    const int qq = pop_index<NP>(lj, h0, h1, h2);
     uint32_t rj = (R.r4 >> (8 * j)) & 0xFFu;
     if (il0 + j < nd.N) {
       const float dv = fix_to_f32(R.I[j]) * a.inv2q;
       float Vj = R.V[j], cj = R.c[j];
-      const float Pcq = sel4(Pc, qq), Eq = sel4(E, qq);
+      const float Pcq = sel<NP>(Pc, qq), Eq = sel<NP>(E, qq);
       bool spk = false;
       if (rj > 0) {
         rj -= 1;
         cj = cj * Pcq;
       } else {
         float vv = Vj - Eq;
-        vv = vv * sel4(Pm, qq);
+        vv = vv * sel<NP>(Pm, qq);
         vv = Eq + vv;
-        const float cc = cj * sel4(PVc, qq);
+        const float cc = cj * sel<NP>(PVc, qq);
         vv = vv - cc;
-        vv = vv + sel4(It, qq);
+        vv = vv + sel<NP>(It, qq);
         vv = vv + dv;
         cj = cj * Pcq;
-        if (vv > sel4(Vth, qq)) {
+        if (vv > sel<NP>(Vth, qq)) {
           spk = true;
-          vv = sel4(Vr, qq);
-          cj = cj + sel4(al, qq);
-          rj = (uint32_t)sel4(na, qq);
+          vv = sel<NP>(Vr, qq);
+          cj = cj + sel<NP>(al, qq);
+          rj = (uint32_t)sel<NP>(na, qq);
         }
         Vj = vv;
       }
@@ -762,7 +774,7 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 
 // ------------------------------------------------------------------------
 // Split schedule: neuron kernel, then the delivery kernel.
-template <typename Acc>
+template <typename Acc, int NP>
 __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
   __shared__ Acc s_in[1024];
@@ -774,12 +786,12 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
   const NetDev& nd = a.nets[net];
   NeuronRegs<Acc> R;
-  neuron_load<Acc>(a, nd, net, i0, t, R);
+  neuron_load<Acc, NP>(a, nd, net, i0, t, R);
   if (a.q_cap)
     gather_now<Acc>(a, blockIdx.x, t, s_in);
   else
     lds_barrier();
-  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  neuron_finish<Acc, NP>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
   lds_barrier();
   const int n = s_n;
   int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
@@ -863,7 +875,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
 
 // Fused schedule (small networks): the tile's own spikes are delivered by
 // its four wavefronts right after the update.
-template <typename Acc, int WDT>
+template <typename Acc, int WDT, int NP>
 __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
   __shared__ Acc s_in[1024];
@@ -878,12 +890,12 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
   const NetDev& nd = a.nets[net];
   NeuronRegs<Acc> R;
-  neuron_load<Acc>(a, nd, net, i0, t, R);
+  neuron_load<Acc, NP>(a, nd, net, i0, t, R);
   if (a.q_cap)
     gather_now<Acc>(a, blockIdx.x, t, s_in);
   else
     lds_barrier();
-  neuron_finish<Acc>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  neuron_finish<Acc, NP>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
   if (a.q_cap) route_inbox<Acc>(a, blockIdx.x, t, s_route);  // has barriers
   lds_barrier();
   const int n = s_n;
@@ -994,9 +1006,18 @@ static size_t deliver_lds(const StepArgs& a) {
 }
 
 template <typename Acc>
-static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
+static void launch_neuron(const StepArgs& a, uint32_t t_off, hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
-  hipLaunchKernelGGL(k_neuron<Acc>, tiles, block, 0, st, a, t_off);
+  if (a.P <= 2)
+    hipLaunchKernelGGL((k_neuron<Acc, 2>), tiles, block, 0, st, a, t_off);
+  else
+    hipLaunchKernelGGL((k_neuron<Acc, 4>), tiles, block, 0, st, a, t_off);
+}
+
+template <typename Acc>
+static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
+  const dim3 block(256);
+  launch_neuron<Acc>(a, t_off, st);
   const size_t lds = deliver_lds<Acc>(a);
   const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
   if (wdt == DPSNN_W_F32)
@@ -1007,15 +1028,23 @@ static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t
     hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
 }
 
-template <typename Acc>
-static void launch_fused(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
+template <typename Acc, int NP>
+static void launch_fused_np(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
   if (wdt == DPSNN_W_F32)
-    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F32>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F32, NP>), tiles, block, 0, st, a, t_off);
   else if (wdt == DPSNN_W_F16)
-    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F16>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F16, NP>), tiles, block, 0, st, a, t_off);
   else
-    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_I8>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_I8, NP>), tiles, block, 0, st, a, t_off);
+}
+
+template <typename Acc>
+static void launch_fused(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
+  if (a.P <= 2)
+    launch_fused_np<Acc, 2>(a, wdt, t_off, st);
+  else
+    launch_fused_np<Acc, 4>(a, wdt, t_off, st);
 }
 
 hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint32_t t_off,
@@ -1042,9 +1071,9 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
   const size_t lds = acc_bits == 32 ? deliver_lds<int32_t>(a) : deliver_lds<int64_t>(a);
   if (phase == 0) {
     if (acc_bits == 32)
-      hipLaunchKernelGGL(k_neuron<int32_t>, tiles, block, 0, st, a, t_off);
+      launch_neuron<int32_t>(a, t_off, st);
     else
-      hipLaunchKernelGGL(k_neuron<int64_t>, tiles, block, 0, st, a, t_off);
+      launch_neuron<int64_t>(a, t_off, st);
   } else if (acc_bits == 32) {
     if (wdt == DPSNN_W_F32)
       hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
