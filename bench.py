@@ -10,9 +10,9 @@ steps of dt) of both networks.  Inputs are synthetic and seeded; the
 networks are built (connectivity generated on the device) before the timed
 region.
 
-Other workloads: --workload c4 (64 networks of 4x4 to 16x16 modules in one
-batched handle, FP16 efficacies), --workload c5 (96x96 modules, 11.52M
-neurons, int8 efficacies, int64 slots), --workload fbi (24x24 modules of
+Other workloads: --workload sweep64 (64 networks of 4x4 to 16x16 modules in one
+batched handle, FP16 efficacies), --workload grid96 (96x96 modules, 11.52M
+neurons, int8 efficacies, int64 slots), --workload fbi24 (24x24 modules of
 the foreground / background / inhibitory populations of Sec. 2.2 with the
 Table S1 states, open boundaries).
 
@@ -56,7 +56,7 @@ def bytes_per_event(p) -> float:
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_08410_amd", "csrc", "kernels.hip")
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "c2_24x24_traffic.json")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_deliver_k_neuron_grid24_traffic.json")
 
 
 def kernels_sha256() -> str:
@@ -148,12 +148,12 @@ def progress(msg: str) -> None:
 
 def build_workload(name, dpsnn, workloads, total_bins):
     """Handles of the workload: {label: (handle, params of its first net)}."""
-    if name == "c2":
+    if name == "grid24":
         regs = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
-    elif name == "fbi":
+    elif name == "fbi24":
         regs = {"sw": workloads.fbi(24, 24, "sw"), "aw88": workloads.fbi(24, 24, "aw88")}
-    elif name == "c5":
-        regs = {"swa": workloads.c5("swa"), "aw": workloads.c5("aw")}
+    elif name == "grid96":
+        regs = {"swa": workloads.grid96("swa"), "aw": workloads.grid96("aw")}
     else:
         regs = None
     nets = {}
@@ -163,7 +163,7 @@ def build_workload(name, dpsnn, workloads, total_bins):
             nets[label] = (dpsnn.dpsnn_build(p, 1), p)
             progress(f"built {label}: {nets[label][0].stats()['build_ms']:.0f} ms")
     else:
-        plist, seeds = workloads.sweep_c4()
+        plist, seeds = workloads.sweep()
         for p in plist:
             p.update(spike_log_cap=0, rate_bins_cap=total_bins)
         nets["sweep"] = (dpsnn.dpsnn_build_batch(plist, seeds), plist[0])
@@ -172,30 +172,30 @@ def build_workload(name, dpsnn, workloads, total_bins):
 
 
 DESCRIPTIONS = {
-    "c2": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
+    "grid24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
            "SWA + AW networks, FP32 efficacies, int32 fixed-point slots"),
-    "c4": ("batched sweep: 64 networks of 4x4..16x16 modules (9.5M neurons, 9.5G synapses), "
+    "sweep64": ("batched sweep: 64 networks of 4x4..16x16 modules (9.5M neurons, 9.5G synapses), "
            "g_c log-uniform 0.002-0.02, lambda 1 or 2, FP16 efficacies, int32 slots, "
            "one handle"),
-    "c5": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
+    "grid96": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
            "SWA + AW networks, int8 efficacies with per-module scale, int64 fixed-point "
            "slots (Q = 32)"),
-    "fbi": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
+    "fbi24": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
             "synapses, 1125 per neuron), Table S1 SW and AW 8.8 Hz states, Eq. 1 from "
             "d = 0 with lambda 0.5, open boundaries, FP32 efficacies, int32 slots"),
 }
-DTYPES = {"c2": "f32", "c4": "f16", "c5": "i8", "fbi": "f32"}
+DTYPES = {"grid24": "f32", "sweep64": "f16", "grid96": "i8", "fbi24": "f32"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "fbi"], default="c2")
+    ap.add_argument("--workload", choices=["grid24", "sweep64", "grid96", "fbi24"], default="grid24")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 10 for c2 and fbi, 2 for c4/c5)")
+                    help="timed steps (default 10 for grid24 and fbi24, 2 for sweep64 and grid96)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dt-steps", type=int, default=None,
-                    help="dt steps per bench step (default 10000 = 1 s; 2000 for c4/c5)")
+                    help="dt steps per bench step (default 10000 = 1 s; 2000 for sweep64 and grid96)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--autotune", type=int, default=1)
@@ -207,7 +207,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps timed per kernel with events for the roofline")
     ap.add_argument("--variants", type=int, default=1,
-                    help="c2: also time FP16 and int8 efficacies")
+                    help="grid24: also time FP16 and int8 efficacies")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof)
@@ -217,7 +217,7 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
-    small = wl in ("c2", "fbi")
+    small = wl in ("grid24", "fbi24")
     steps = args.steps if args.steps is not None else (10 if small else 2)
     S = args.dt_steps if args.dt_steps is not None else (10000 if small else 2000)
     if not small:
@@ -279,7 +279,7 @@ def main():
             upd_ms, del_ms = dpsnn.dpsnn_profile_steps(h, args.profile_steps)
             prof[name] = (upd_ms, del_ms, (h.stats()["n_spikes"] - s_a) * K_OUT)
         progress("kernel timing done")
-        if wl == "c2" and args.variants:
+        if wl == "grid24" and args.variants:
             for wd in ("f16", "i8"):
                 for reg in ("swa", "aw"):
                     q = dict(nets[reg][1], weight_dtype=wd)
@@ -317,11 +317,11 @@ def main():
     achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
     n_mean = sum(neurons.values()) / len(neurons)
     traffic = None
-    rec = recorded_traffic() if wl == "c2" else None
+    rec = recorded_traffic() if wl == "grid24" else None
     if rec and "k_deliver" in rec["kernels"]:
         traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"]
     cpu = None
-    if wl == "c2" and not args.no_cpu_baseline:
+    if wl == "grid24" and not args.no_cpu_baseline:
         cpu = cpu_baseline(nets["swa"][1], nets["swa"][0], dpsnn, 400, args.cpu_budget)
 
     out = {

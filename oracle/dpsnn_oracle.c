@@ -645,8 +645,8 @@ int32_t orc_gen_row(const orc_net* n, int64_t s, int32_t* tgt, uint8_t* delay,
 int32_t orc_n_pops(const orc_net* n) { return n->P; }
 
 /* ------------------------------------------------------------------------ */
-/* External Poisson input (Sec. 2.1 "no memory structure associated with
- * external synapses": counts and efficacies generated on the fly).  The
+/* External Poisson input (Sec. 2.1: external synapses are not stored;
+ * counts and efficacies are generated on the fly).  The
  * count of neuron i at step t comes from word (i mod 4) of the draw
  * (i / 4, t, EXT).  Efficacy e of the neuron uses 16 bits of the draw
  * (i / 4, t, EXTJ | (e / 2) << 8): word (i mod 4), high half for even e,

@@ -12,8 +12,7 @@
  *
  * What it computes (paper references by section / equation / table):
  *   - the 2-D grid of modules of K point-like LIF neurons, 4:1 exc:inh, or
- *     the foreground / background / inhibitory populations of Sec. 2.2
- *     ("Model Architecture and Network States");
+ *     the foreground / background / inhibitory populations (Sec. 2.2);
  *   - inter-module connectivity with probability decaying as exp(-d/lambda)
  *     (Eq. 1), Gaussian efficacies (Sec. 2.2), integer synaptic delays;
  *   - the LIF neuron with spike-frequency adaptation (Eq. 2, Table S1),

@@ -53,27 +53,7 @@ def tiny(w: int = 2, h: int = 2, K: int = 16, K_out: int = 8, **over) -> dict:
     return p
 
 
-# Named configurations: (params, seeds, steps)
-CONFIGS = {
-    # 2x2 grid, 5000 neurons, FP32 weights, SWA, 2 s
-    "c1": dict(params=[swa()], seeds=[1, 2, 3, 4, 5], steps=20000),
-    # 24x24 grid, 720k neurons, FP32 weights, SWA and AW, 10 s
-    "c2": dict(params=[grid(24, 24, "swa"), grid(24, 24, "aw")], seeds=[1, 2, 3],
-               steps=100000),
-    # 48x48 grid, 2.88M neurons, lambda sweep, FP32/FP16/int8
-    "c3": dict(params=[grid(48, 48, r, **{"lambda": lam, "weight_dtype": wd})
-                       for r in ("swa", "aw") for lam in (0.5, 1.0, 2.0, 4.0)
-                       for wd in ("f32", "f16", "i8")],
-               seeds=[1, 2, 3, 4, 5], steps=50000),
-    # 96x96 grid, 11.52M neurons, int8 weights, int64 ring with Q = 32
-    "c5": dict(params=[grid(96, 96, r, **{"lambda": 2.0, "weight_dtype": "i8",
-                                          "acc_bits": 64, "q_frac_bits": 32})
-                       for r in ("swa", "aw")],
-               seeds=[1], steps=20000),
-}
-
-
-def sweep_c4(n: int = 64, seed: int = 1):
+def sweep(n: int = 64, seed: int = 1):
     """Batched sweep: n networks, grids uniform in {4x4, 8x8, 12x12, 16x16}
     modules, adaptation g_c/C_m log-uniform on [0.002, 0.02] 1/ms (AW to
     SWA), lambda in {1, 2}, binary16 efficacies.  Returns (params, seeds)."""
@@ -87,7 +67,7 @@ def sweep_c4(n: int = 64, seed: int = 1):
     return params, list(range(1, n + 1))
 
 
-def c5(regime: str) -> dict:
+def grid96(regime: str) -> dict:
     """96x96 grid (11.52M neurons), lambda = 2, int8 efficacies, int64 slots."""
     return grid(96, 96, regime, **{"lambda": 2.0, "weight_dtype": "i8",
                                    "acc_bits": 64, "q_frac_bits": 32})

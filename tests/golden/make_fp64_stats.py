@@ -1,5 +1,5 @@
-"""Write fp64_stats_c1.json: statistics of the binary64 oracle (EXACT64
-mode) on config 1 (2x2 grid of 1250-neuron modules), SWA and AW, seeds
+"""Write fp64_stats_2x2.json: statistics of the binary64 oracle (EXACT64
+mode) on the 2x2 grid of 1250-neuron modules, SWA and AW, seeds
 1-5, 2 s of biological time each: mean rates after a 0.5 s transient,
 up-state and burst frequencies and per-neuron spike-count histograms.
 
@@ -36,11 +36,11 @@ def main():
     jobs = [(r, s) for r in ("swa", "aw") for s in SEEDS]
     with mp.Pool(min(8, len(jobs))) as pool:
         res = pool.map(one, jobs)
-    out = {"steps": STEPS, "seeds": SEEDS, "config": "c1: 2x2 grid, K=1250, K_out=1000",
+    out = {"steps": STEPS, "seeds": SEEDS, "config": "2x2 grid, K=1250, K_out=1000",
            "mode": "EXACT64", "runs": {}}
     for regime, seed, s in res:
         out["runs"].setdefault(regime, {})[str(seed)] = s
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fp64_stats_c1.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fp64_stats_2x2.json")
     json.dump(out, open(path, "w"))
     for regime in ("swa", "aw"):
         for seed in SEEDS:

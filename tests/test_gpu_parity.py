@@ -75,10 +75,10 @@ def _compare_rows(L, net, orc, rows, wd):
         assert P in (2, 3, 4)
 
 
-@pytest.mark.parametrize("case", ["c1_f32", "tiny_f16", "tiny_i8", "ragged_3x3",
+@pytest.mark.parametrize("case", ["2x2_f32", "tiny_f16", "tiny_i8", "ragged_3x3",
                                   "odd_7x5", "delays64", "single_delay"])
 def test_rows_bitwise_equal(L, case):
-    p = {"c1_f32": W.swa(),
+    p = {"2x2_f32": W.swa(),
          "tiny_f16": W.tiny(w=3, h=2, K=40, K_out=30, weight_dtype="f16"),
          "tiny_i8": W.tiny(w=2, h=3, K=40, K_out=30, weight_dtype="i8"),
          "ragged_3x3": W.tiny(w=3, h=3, K=47, K_out=37, d_max=11),
@@ -94,7 +94,7 @@ def test_rows_bitwise_equal(L, case):
 
 
 def test_initial_state_equal(L):
-    _say("initial state c1")
+    _say("initial state 2x2")
     net, orc = _pair(W.swa(), 3, store_rows=False)
     V, c, r = L.dpsnn_read_state(net)
     oV, oc, orr = orc.state()
@@ -184,9 +184,10 @@ def test_raster_bit_exact(L, case, sched):
     net.close()
 
 
-def test_raster_bit_exact_c1_two_seconds(L):
-    """Config 1: 2x2 grid, 5000 neurons, FP32 weights, SWA, 2 s = 20000 steps."""
-    _say("c1 2 s")
+def test_raster_bit_exact_2x2_two_seconds(L):
+    """2x2 grid of 1250-neuron modules (5000 neurons), FP32 weights, SWA, 2 s =
+    20000 steps."""
+    _say("2x2 2 s")
     net, orc = _pair(W.swa(), 1)
     total = 0
     for k in range(4):
@@ -199,22 +200,22 @@ def test_raster_bit_exact_c1_two_seconds(L):
     net.close()
 
 
-def test_c2_full_size_start_and_teacher_forced_step(L):
-    """Config 2 at full size (24x24, 720k neurons, 0.72G synapses) in the
+def test_24x24_full_size_start_and_teacher_forced_step(L):
+    """24x24 grid at full size (720k neurons, 0.72G synapses) in the
     benchmark's launch configuration: sampled rows, the first 30 steps
     bit-exact, then after 2000 more steps one step re-run by the oracle from
     the GPU's state, slots and time."""
     p = W.grid(24, 24, "swa")
-    _say("c2 build")
+    _say("24x24 build")
     net, orc = _pair(p, 1, store_rows=False)
     rng = np.random.default_rng(0)
     rows = sorted(rng.choice(net.N, 300, replace=False).tolist())
     _compare_rows(L, net, orc, rows, "f32")
-    _say("c2 first 30 steps")
+    _say("24x24 first 30 steps")
     L.dpsnn_step(net, 30)
     orc.step(30)
-    _compare_all(L, net, orc, "c2 start")
-    _say("c2 2000 steps + teacher forced step")
+    _compare_all(L, net, orc, "24x24 start")
+    _say("24x24 2000 steps + teacher forced step")
     L.dpsnn_step(net, 2000)
     L.dpsnn_read_spikes(net)
     V, c, r = L.dpsnn_read_state(net)
@@ -304,10 +305,11 @@ def test_graph_replay_and_schedule_switching(L):
         net.close()
 
 
-def test_c1_graph_stream_two_seconds(L):
-    """Config 1 for 2 s on a non-default stream with graph replay."""
+def test_2x2_graph_stream_two_seconds(L):
+    """2x2 grid of 1250-neuron modules for 2 s on a non-default stream with
+    graph replay."""
     import torch
-    _say("c1 graphs")
+    _say("2x2 graphs")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         net, orc = _pair(W.swa(), 2)

@@ -1,9 +1,9 @@
 """Error of the binary32 / binary16 / int8 efficacy paths against the binary64
 oracle (EXACT64 mode: unrounded efficacies, binary64 sums and state).
 
-Long runs: config 1 (2x2 grid of 1250-neuron modules), SWA and AW, seeds
+Long runs: 2x2 grid of 1250-neuron modules, SWA and AW, seeds
 1-5, 2 s each; statistics after a 0.5 s transient are compared with the
-oracle's, stored in tests/golden/fp64_stats_c1.json (written by
+oracle's, stored in tests/golden/fp64_stats_2x2.json (written by
 tests/golden/make_fp64_stats.py from the oracle only):
   - mean excitatory and inhibitory rates within max(5 %, 2 sigma_seed),
   - burst (population up-state) frequency within max(10 %, 2 sigma_seed),
@@ -24,7 +24,7 @@ from paper_1902_08410_amd import analysis
 from paper_1902_08410_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp64_stats_c1.json")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp64_stats_2x2.json")
 
 
 def _say(*a):
@@ -95,7 +95,7 @@ def test_long_run_statistics_vs_fp64(L, wd):
 @pytest.mark.parametrize("wd", ["f32", "f16", "i8"])
 def test_short_horizon_membrane_error_vs_fp64(L, wd):
     """Max and RMS |V - V_fp64| over all neurons at each step until the first
-    spike raster difference (config 1, SWA, seed 1)."""
+    spike raster difference (2x2 grid of 1250-neuron modules, SWA, seed 1)."""
     p = dict(W.swa(), weight_dtype=wd, spike_log_cap=1 << 20, rate_bins_cap=64)
     _say("short horizon", wd)
     net = L.dpsnn_build(p, 1)

@@ -46,11 +46,11 @@ for _q in (0, 1):
                (f"jxfix_{_q}", np.int64)]
 
 PARAM_SETS = {
-    "c1_swa": W.swa(),
-    "c2_aw": W.grid(24, 24, "aw"),
-    "c3_f16_l05": W.grid(48, 48, "swa", **{"lambda": 0.5, "weight_dtype": "f16"}),
-    "c3_i8_l4": W.grid(48, 48, "aw", **{"lambda": 4.0, "weight_dtype": "i8"}),
-    "c5_i8_q32": W.grid(96, 96, "swa", **{"lambda": 2.0, "weight_dtype": "i8",
+    "2x2_swa": W.swa(),
+    "24x24_aw": W.grid(24, 24, "aw"),
+    "48x48_f16_l05": W.grid(48, 48, "swa", **{"lambda": 0.5, "weight_dtype": "f16"}),
+    "48x48_i8_l4": W.grid(48, 48, "aw", **{"lambda": 4.0, "weight_dtype": "i8"}),
+    "96x96_i8_q32": W.grid(96, 96, "swa", **{"lambda": 2.0, "weight_dtype": "i8",
                                           "acc_bits": 64, "q_frac_bits": 32}),
     "tiny_3x2": W.tiny(w=3, h=2, K=16, K_out=8, tau_c=[300.0, 300.0], I_const=[0.5, 0.2]),
     "odd_7x5": W.grid(7, 5, "swa", **{"lambda": 1.7, "J_sd": [0.3, 0.9]}),
