@@ -349,12 +349,14 @@ int build_impl(dpsnn_net* n) {
     a.in_q = dev_alloc(n, n_in * eb);
     a.q_cnt = (uint32_t*)dev_alloc(n, (size_t)n_tiles * T0.D * 4);
     a.q_q = dev_alloc(n, n_q * eb);
-    if (!a.in_cnt || !a.in_q || !a.q_cnt || !a.q_q) return DPSNN_E_NOMEM;
+    a.s_dirty = (uint32_t*)dev_alloc(n, (size_t)n_tiles * T0.D * 4);
+    if (!a.in_cnt || !a.in_q || !a.q_cnt || !a.q_q || !a.s_dirty) return DPSNN_E_NOMEM;
     HIP_OK(hipMemsetAsync(a.in_cnt, 0, (size_t)2 * n_tiles * kInboxStride * 4, st));
     HIP_OK(hipMemsetAsync(a.q_cnt, 0, (size_t)n_tiles * T0.D * 4, st));
+    HIP_OK(hipMemsetAsync(a.s_dirty, 0, (size_t)n_tiles * T0.D * 4, st));
     HIP_OK(hipStreamSynchronize(st));
     n->bytes_state += (int64_t)((n_in + n_q) * eb) +
-                      (2 * n_tiles * kInboxStride + n_tiles * T0.D) * 4;
+                      (2 * n_tiles * kInboxStride + 2 * n_tiles * T0.D) * 4;
   }
   n->split_ok = n_tiles <= kMaxSplitTiles;
   n->sched = (n->split_ok && n->N_total >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;

@@ -148,12 +148,14 @@ struct StepArgs {
   // into its own per-slot queues and sums the queue of the current slot.
   // An entry (QEntry) holds in-tile index | delay index << 10 and the
   // fixed-point efficacy.  Events that find a queue full are added into the
-  // slot.
+  // slot, and the slot is marked in s_dirty: the update reads and clears
+  // the slots marked only (with queues every other slot holds zeros).
   int32_t q_cap, in_cap;
   uint32_t* in_cnt;        // [2][n_tiles * kInboxStride] (may exceed in_cap)
   void* in_q;              // [2][n_tiles][in_cap] entries
   uint32_t* q_cnt;         // [n_tiles][D], written by the owning tile only
   void* q_q;               // [n_tiles][D][q_cap] entries
+  uint32_t* s_dirty;       // [n_tiles][D]: slot holds added input
 };
 
 struct GenArgs {

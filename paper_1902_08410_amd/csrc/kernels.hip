@@ -319,8 +319,12 @@ __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t
     }
   }
   lds_barrier();
-  // every thread has used the count: the current queue is empty now
-  if (tid == 0) a.q_cnt[(int64_t)tile * D + cur] = 0;
+  // every thread has used the count and the slot mark: the current queue
+  // is empty and the slot cleared now
+  if (tid == 0) {
+    a.q_cnt[(int64_t)tile * D + cur] = 0;
+    a.s_dirty[(int64_t)tile * D + cur] = 0u;
+  }
 }
 
 // LDS of route_inbox.
@@ -410,6 +414,7 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
       } else {
         atomic_add_fix<Acc>(slots + (int64_t)sl[u] * a.N_pad + (int64_t)tile * 1024 + idx,
                             ie[u].w);
+        a.s_dirty[(int64_t)tile * D + sl[u]] = 1u;
       }
     }
     lds_barrier();
@@ -427,6 +432,7 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
       } else {
         atomic_add_fix<Acc>(slots + (int64_t)s2 * a.N_pad + (int64_t)tile * 1024 + L.sx[e],
                             L.sw[e]);
+        a.s_dirty[(int64_t)tile * D + s2] = 1u;
       }
     }
     lds_barrier();
@@ -482,7 +488,13 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
                                             int64_t i0, uint32_t t, NeuronRegs<Acc>& R) {
   const int slot = (int)(t % (uint32_t)a.D);
   Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
-  if (sizeof(Acc) == 4) {
+  // with queues the slot holds input only where an event found its queue
+  // full (marked per tile and slot); gather_now clears the mark
+  const bool marked = a.q_cap == 0 || a.s_dirty[(i0 >> 10) * a.D + slot] != 0u;
+  if (!marked) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) R.I[j] = 0;
+  } else if (sizeof(Acc) == 4) {
     const int4 v = *reinterpret_cast<const int4*>(sl);
     R.I[0] = v.x; R.I[1] = v.y; R.I[2] = v.z; R.I[3] = v.w;
     *reinterpret_cast<int4*>(sl) = make_int4(0, 0, 0, 0);
@@ -552,7 +564,7 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
 
 template <typename Acc, int NP>
 __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& nd, int64_t i0,
-                                              NeuronRegs<Acc>& R, const Acc* s_in,
+                                              uint32_t t, NeuronRegs<Acc>& R, const Acc* s_in,
                                               int32_t* s_spk, int* s_n) {
   if (s_in) {  // this thread's four entries of the tile's queue sums
 #pragma unroll
@@ -609,6 +621,10 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
       if (spk) {
         const int pos = atomicAdd(s_n, 1);
         s_spk[pos] = (int32_t)(i0 + j);
+        // population count of the rate bin (Sec. 2.3)
+        const int64_t mod = nd.mbase + m0 + (l0 + j >= nd.K ? 1 : 0);
+        const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
+        atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * a.P + qq], 1u);
       }
     }
     r_out |= rj << (8 * j);
@@ -756,6 +772,7 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
         int sl = slot0 + (int)dk;
         if (sl >= a.D) sl -= a.D;
         atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+        a.s_dirty[(int64_t)tl[j] * a.D + sl] = 1u;
       }
     }
   }
@@ -765,11 +782,6 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
 __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint32_t t,
                                              unsigned long long pos) {
   if (pos < (unsigned long long)a.spike_log_cap) a.log[pos] = make_int2((int)t, id);
-  const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
-  int32_t mod;
-  int q;
-  module_pop(a, id, &mod, &q);
-  atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * a.P + q], 1u);
 }
 
 // ------------------------------------------------------------------------
@@ -791,7 +803,7 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
     gather_now<Acc>(a, blockIdx.x, t, s_in);
   else
     lds_barrier();
-  neuron_finish<Acc, NP>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  neuron_finish<Acc, NP>(a, nd, i0, t, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
   lds_barrier();
   const int n = s_n;
   int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
@@ -895,7 +907,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
     gather_now<Acc>(a, blockIdx.x, t, s_in);
   else
     lds_barrier();
-  neuron_finish<Acc, NP>(a, nd, i0, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  neuron_finish<Acc, NP>(a, nd, i0, t, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
   if (a.q_cap) route_inbox<Acc>(a, blockIdx.x, t, s_route);  // has barriers
   lds_barrier();
   const int n = s_n;
@@ -964,7 +976,10 @@ __global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
   }
   __syncthreads();
   if (threadIdx.x == 0) a.in_cnt[ic] = 0;
-  for (int k = threadIdx.x; k < D; k += blockDim.x) a.q_cnt[(int64_t)tile * D + k] = 0;
+  for (int k = threadIdx.x; k < D; k += blockDim.x) {
+    a.q_cnt[(int64_t)tile * D + k] = 0;
+    a.s_dirty[(int64_t)tile * D + k] = 1u;
+  }
 }
 
 // ------------------------------------------------------------------------
