@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package.  It is a plain, slow C
-implementation (oracle/dpsnn_oracle.c) written from the paper and bound here
-with ctypes; it shares no code with the HIP library.
+implementation (oracle/dpsnn_oracle.c, and oracle/dpsnn_waves.c for the
+slow-wave analysis of Sec. 2.3) written from the paper and bound here with
+ctypes; it shares no code with the HIP library.
 
 Parameters are passed as a plain dict whose keys are the field names of
 ``orc_params`` (pairs are ``[excitatory, inhibitory]``; the population-model
@@ -92,6 +93,13 @@ def to_struct(params: dict) -> OrcParams:
     return s
 
 
+class OrcWaveParams(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("n_pops", C.c_int32),
+                ("bin_steps", C.c_int32), ("dt_ms", C.c_double), ("bin0", C.c_int64),
+                ("noise_var", C.c_double), ("seed", C.c_uint64), ("min_down", C.c_int32),
+                ("min_up", C.c_int32), ("min_modules", C.c_int32), ("reserved", C.c_int32)]
+
+
 _lib = None
 
 
@@ -149,6 +157,12 @@ def lib():
         L.orc_spikes.restype = C.c_int64
         L.orc_rates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.orc_rates.restype = C.c_int64
+        L.orc_waves.argtypes = [P(OrcWaveParams), C.c_void_p, C.c_int64, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.orc_waves.restype = C.c_int64
+        L.orc_wave_transitions_max.argtypes = [C.c_int64, C.c_int32, C.c_int32]
+        L.orc_wave_transitions_max.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -175,6 +189,35 @@ def f16_bits_to_f64(h: int) -> float:
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def waves(counts, W: int, H: int, bin_steps: int, dt_ms: float, bin0: int = 0,
+          noise_var: float = 0.5, seed: int = 1, min_down: int = 2, min_up: int = 2,
+          min_modules: int = 1) -> dict:
+    """Slow-wave analysis (Sec. 2.3, Eq. 4) of counts [bins][W*H][pops]:
+    transitions in the order (bin, fraction, module) with module, time (ms)
+    and wave; per wave the speed (inter-module distances per second, NaN
+    where not measured), first transition time and module count."""
+    c = np.ascontiguousarray(counts, dtype=np.uint32)
+    nb, M, P = c.shape
+    assert M == W * H
+    wp = OrcWaveParams(W, H, P, bin_steps, dt_ms, bin0, noise_var, seed, min_down, min_up,
+                       min_modules, 0)
+    cap = M * lib().orc_wave_transitions_max(nb, min_down, min_up)
+    tm = np.zeros(cap, np.int32)
+    tT = np.zeros(cap, np.float64)
+    tw = np.zeros(cap, np.int32)
+    ws = np.zeros(cap, np.float64)
+    wt = np.zeros(cap, np.float64)
+    wn = np.zeros(cap, np.int32)
+    nw = C.c_int64(0)
+    n = lib().orc_waves(C.byref(wp), _ptr(c), nb, _ptr(tm), _ptr(tT), _ptr(tw), cap,
+                        _ptr(ws), _ptr(wt), _ptr(wn), cap, C.byref(nw))
+    if n < 0:
+        raise ValueError(f"orc_waves failed ({n})")
+    k = nw.value
+    return {"module": tm[:n], "T": tT[:n], "wave": tw[:n], "speed": ws[:k], "t0": wt[:k],
+            "n": wn[:k]}
 
 
 class Oracle:

@@ -9,13 +9,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "dpsnn_oracle.c")
+SRCS = [os.path.join(HERE, "dpsnn_oracle.c"), os.path.join(HERE, "dpsnn_waves.c")]
 LIB = os.path.join(HERE, "liborc.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fno-fast-math", "-Wall", "-Wextra", "-o", LIB + ".tmp"] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
