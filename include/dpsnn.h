@@ -285,6 +285,74 @@ int dpsnn_read_slots(dpsnn_net* net, int64_t* host_slots);
 int dpsnn_read_rows(dpsnn_net* net, int64_t first, int64_t count,
                     int32_t* host_tgt, void* host_w, uint8_t* host_dk);
 
+/* ---- Slow-wave analysis (Sec. 2.3 and Eq. 4) ----
+ *
+ * The multi-unit activity of a module is its spike count per rate bin (all
+ * populations); the analysed signal is log(MUA / MUA_down) plus zero-mean
+ * white noise, a threshold gives the Down-to-Up transition time T(x, y) of
+ * every module, and Eq. 4 the wavefront speed 1 / |grad T| averaged over
+ * the modules of a wave.  The paper leaves the Down-state level, the
+ * threshold and the grouping into waves open; the library takes: Down bins
+ * = bins at or below the lower median count of the window, MUA_down and
+ * MUA_up = rounded mean counts of the Down and Up bins, one spike added to
+ * every count, threshold halfway between the two levels in log units, a
+ * transition needs min_down bins at or below and min_up bins above the
+ * threshold, its time interpolates the signal linearly between bin centres;
+ * transitions of all modules in the order (bin, interpolation fraction in
+ * 2^-32 units, module) are grouped greedily (a module entering the current
+ * wave again starts the next one); grad T by central differences over the
+ * wave's modules, one-sided at its edge, no wrap-around.  The noise of
+ * module m in absolute bin b is sqrt(noise_var) * Phi^-1((i + 1/2) / 65536),
+ * i = top 16 bits of word 0 of Philox4x32-10((m, b, b >> 32, 5), seed).
+ * Limits: at most 4096 bins and 8192 modules.  Speeds are in inter-module
+ * distances per second, times in ms. */
+typedef struct dpsnn_wave_params {
+  uint32_t abi_version;  /* must be DPSNN_ABI_VERSION                        */
+  int32_t net;           /* network of a batch handle (dpsnn_waves)          */
+  int64_t n_bins;        /* analyse the last n_bins bins not yet drained by
+                            dpsnn_read_rates; 0 = all of them (dpsnn_waves)  */
+  double noise_var;      /* variance of the added noise (the paper: 0.5)    */
+  uint64_t seed;         /* key of the noise draws                           */
+  int32_t min_down;      /* >= 1 */
+  int32_t min_up;        /* >= 1 */
+  int32_t min_modules;   /* smallest wave whose speed is measured            */
+  int32_t reserved;
+} dpsnn_wave_params;
+
+typedef struct dpsnn_wave_result {
+  int64_t bin0;          /* absolute index of the first analysed bin         */
+  int64_t n_bins;
+  int64_t n_transitions;
+  int64_t n_waves;
+  double mean_speed;     /* mean of the measured wave speeds; NaN if none    */
+  double reserved[3];
+} dpsnn_wave_result;
+
+/* Analyse the rate bins a handle holds (not drained; they stay).  Host
+ * outputs (each may be NULL; up to its capacity): transitions in order
+ * with module (network-local), time and wave; per wave its speed (NaN where
+ * not measured: fewer than min_modules modules, or no module with both
+ * gradients defined), first transition time and number of modules.
+ * Synchronises; allocates its scratch with the handle's allocator and
+ * frees it before returning. */
+int dpsnn_waves(dpsnn_net* net, const dpsnn_wave_params* wp, dpsnn_wave_result* out,
+                int32_t* host_tr_module, double* host_tr_T, int32_t* host_tr_wave,
+                int64_t cap_tr, double* host_wave_speed, double* host_wave_t0,
+                int32_t* host_wave_n, int64_t cap_waves);
+
+/* The same analysis of counts held in device memory: dev_counts is
+ * [n_bins][grid_w * grid_h][n_pops] uint32 (module m at x = m % grid_w,
+ * y = m / grid_w), bin b of it is absolute bin bin0 + b of width bin_steps
+ * steps of dt_ms.  stream: a hipStream_t, or NULL for the default stream;
+ * wp->net and wp->n_bins are ignored.  Scratch from hipMalloc, freed before
+ * returning. */
+int dpsnn_waves_counts(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_w,
+                       int32_t grid_h, int32_t n_pops, int32_t bin_steps, double dt_ms,
+                       int64_t bin0, const dpsnn_wave_params* wp, void* stream,
+                       dpsnn_wave_result* out, int32_t* host_tr_module, double* host_tr_T,
+                       int32_t* host_tr_wave, int64_t cap_tr, double* host_wave_speed,
+                       double* host_wave_t0, int32_t* host_wave_n, int64_t cap_waves);
+
 /* Host table computed from p without any device (named arrays, see the
  * library source); returns the size in bytes, or a negative code. */
 int64_t dpsnn_host_table(const dpsnn_params* p, const char* name, void* out,

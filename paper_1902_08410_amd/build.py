@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpsnn.so")
-SOURCES = ["api.hip", "kernels.hip", "tables.cpp"]
+SOURCES = ["api.hip", "kernels.hip", "waves.hip", "tables.cpp"]
 ARCH = os.environ.get("DPSNN_OFFLOAD_ARCH", "gfx950")
 
 

@@ -387,6 +387,140 @@ int build_common(const dpsnn_params* p, const uint64_t* seeds, int32_t n_nets,
 
 }  // namespace
 
+namespace {
+
+// Device scratch of one analysis call: from the handle's allocator when it
+// has one, else hipMalloc; freed when the call returns.
+struct Scratch {
+  dpsnn_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+  std::vector<void*> ptrs;
+  void* get(size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (free_fn) {
+      p = g_alloc ? g_alloc(bytes, ctx) : nullptr;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) ptrs.push_back(p);
+    return p;
+  }
+  ~Scratch() {
+    for (void* p : ptrs) {
+      if (free_fn)
+        free_fn(p, ctx);
+      else
+        (void)hipFree(p);
+    }
+  }
+};
+
+// The slow-wave analysis over a window of count bins (see dpsnn.h).
+int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
+               const dpsnn_wave_params* wp, hipStream_t st, Scratch& S,
+               dpsnn_wave_result* out, int32_t* h_mod, double* h_T, int32_t* h_wave,
+               int64_t cap_tr, double* h_speed, double* h_t0, int32_t* h_n, int64_t cap_w) {
+  if (!wp || !out || wp->abi_version != DPSNN_ABI_VERSION || cap_tr < 0 || cap_w < 0)
+    return DPSNN_E_INVAL;
+  if (src.nb < 1 || src.nb > kWaveMaxBins || src.M < 1 || src.M > kWaveMaxModules ||
+      src.P < 1 || wp->min_down < 1 || wp->min_up < 1 || wp->min_modules < 0 ||
+      !(wp->noise_var >= 0.0) || !std::isfinite(wp->noise_var) || bin_steps < 1 ||
+      !(dt_ms > 0.0))
+    return DPSNN_E_INVAL;
+  WaveArgs a = src;
+  a.min_down = wp->min_down;
+  a.min_up = wp->min_up;
+  a.min_modules = wp->min_modules;
+  a.cap_pm = a.nb / (a.min_down + a.min_up) + 1;
+  a.dbin = (double)bin_steps * dt_ms;
+  a.sd = sqrt(wp->noise_var);
+  a.key0 = (uint32_t)wp->seed;
+  a.key1 = (uint32_t)(wp->seed >> 32);
+  const int64_t nt = (int64_t)a.M * a.cap_pm;
+  uint32_t* maxc = (uint32_t*)S.get(4);
+  a.cnt = (uint32_t*)S.get((size_t)a.M * 4);
+  a.tr_k = (uint32_t*)S.get((size_t)nt * 4);
+  a.tr_q = (uint32_t*)S.get((size_t)nt * 4);
+  a.tr_T = (double*)S.get((size_t)nt * 8);
+  a.hist = (uint32_t*)S.get((size_t)a.nb * 4);
+  a.fill = (uint32_t*)S.get((size_t)a.nb * 4);
+  a.off = (uint32_t*)S.get((size_t)(a.nb + 1) * 4);
+  a.keys = (unsigned long long*)S.get((size_t)nt * 8);
+  a.out_module = (int32_t*)S.get((size_t)nt * 4);
+  a.out_T = (double*)S.get((size_t)nt * 8);
+  a.out_wave = (int32_t*)S.get((size_t)nt * 4);
+  a.wave_first = (int32_t*)S.get((size_t)(nt + 1) * 4);
+  a.n_waves = (int32_t*)S.get(4);
+  a.wave_speed = (double*)S.get((size_t)nt * 8);
+  a.wave_t0 = (double*)S.get((size_t)nt * 8);
+  a.wave_n = (int32_t*)S.get((size_t)nt * 4);
+  a.grid = (double*)S.get((size_t)kWaveBatch * a.M * 8);
+  double* d_mean = (double*)S.get(8);
+  double* d_z = (double*)S.get((size_t)kQuantN * 8);
+  for (const void* q : {(const void*)maxc, (const void*)a.cnt, (const void*)a.tr_k,
+                        (const void*)a.tr_q, (const void*)a.tr_T, (const void*)a.hist,
+                        (const void*)a.fill, (const void*)a.off, (const void*)a.keys,
+                        (const void*)a.out_module, (const void*)a.out_T,
+                        (const void*)a.out_wave, (const void*)a.wave_first,
+                        (const void*)a.n_waves, (const void*)a.wave_speed,
+                        (const void*)a.wave_t0, (const void*)a.wave_n, (const void*)a.grid,
+                        (const void*)d_mean, (const void*)d_z})
+    if (!q) return DPSNN_E_NOMEM;
+  a.z = d_z;
+  const std::vector<double>& z = standard_normal_grid();
+  HIP_OK(hipMemcpyAsync(d_z, z.data(), (size_t)kQuantN * 8, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemsetAsync(maxc, 0, 4, st));
+  HIP_OK(hipMemsetAsync(a.hist, 0, (size_t)a.nb * 4, st));
+  HIP_OK(hipMemsetAsync(a.fill, 0, (size_t)a.nb * 4, st));
+  HIP_OK(hipMemsetAsync(a.n_waves, 0, 4, st));
+  HIP_OK(launch_wave_max(a, maxc, st));
+  uint32_t mx = 0;
+  HIP_OK(hipMemcpyAsync(&mx, maxc, 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  // log(i) for every count + 1 that can occur (host binary64 log)
+  std::vector<double> lnt((size_t)mx + 2);
+  lnt[0] = -INFINITY;
+  for (size_t i = 1; i < lnt.size(); ++i) lnt[i] = log((double)i);
+  double* d_lnt = (double*)S.get(lnt.size() * 8);
+  if (!d_lnt) return DPSNN_E_NOMEM;
+  a.lnt = d_lnt;
+  HIP_OK(hipMemcpyAsync(d_lnt, lnt.data(), lnt.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_OK(launch_wave_transitions(a, st));
+  int32_t nw = 0;
+  uint32_t total = 0;
+  HIP_OK(hipMemcpyAsync(&nw, a.n_waves, 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(&total, a.off + a.nb, 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int32_t w0 = 0; w0 < nw; w0 += kWaveBatch)
+    HIP_OK(launch_wave_speed(a, w0, std::min<int32_t>(kWaveBatch, nw - w0), st));
+  HIP_OK(launch_wave_mean(a, d_mean, st));
+  double mean = 0.0;
+  HIP_OK(hipMemcpyAsync(&mean, d_mean, 8, hipMemcpyDeviceToHost, st));
+  const int64_t ntr = std::min<int64_t>(total, cap_tr);
+  const int64_t nwc = std::min<int64_t>(nw, cap_w);
+  if (ntr > 0) {
+    if (h_mod) HIP_OK(hipMemcpyAsync(h_mod, a.out_module, ntr * 4, hipMemcpyDeviceToHost, st));
+    if (h_T) HIP_OK(hipMemcpyAsync(h_T, a.out_T, ntr * 8, hipMemcpyDeviceToHost, st));
+    if (h_wave) HIP_OK(hipMemcpyAsync(h_wave, a.out_wave, ntr * 4, hipMemcpyDeviceToHost, st));
+  }
+  if (nwc > 0) {
+    if (h_speed) HIP_OK(hipMemcpyAsync(h_speed, a.wave_speed, nwc * 8, hipMemcpyDeviceToHost, st));
+    if (h_t0) HIP_OK(hipMemcpyAsync(h_t0, a.wave_t0, nwc * 8, hipMemcpyDeviceToHost, st));
+    if (h_n) HIP_OK(hipMemcpyAsync(h_n, a.wave_n, nwc * 4, hipMemcpyDeviceToHost, st));
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  out->bin0 = a.bin0;
+  out->n_bins = a.nb;
+  out->n_transitions = total;
+  out->n_waves = nw;
+  out->mean_speed = mean;
+  return DPSNN_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int dpsnn_set_allocator(dpsnn_alloc_fn alloc, dpsnn_free_fn release, void* ctx) {
@@ -812,6 +946,65 @@ int64_t dpsnn_host_table(const dpsnn_params* p, const char* name, void* out, int
     return bytes;
   }
   return host_table(T, name, out, cap);
+}
+
+int dpsnn_waves(dpsnn_net* n, const dpsnn_wave_params* wp, dpsnn_wave_result* out,
+                int32_t* host_tr_module, double* host_tr_T, int32_t* host_tr_wave,
+                int64_t cap_tr, double* host_wave_speed, double* host_wave_t0,
+                int32_t* host_wave_n, int64_t cap_waves) {
+  if (!n || !wp || !out || wp->net < 0 || wp->net >= (int32_t)n->p.size() || wp->n_bins < 0)
+    return DPSNN_E_INVAL;
+  const int64_t done = n->t / n->p[0].rate_bin_steps;
+  const int64_t avail = done - n->rate_first;
+  if (avail < 1) return DPSNN_E_STATE;
+  const int64_t nb = wp->n_bins > 0 ? std::min<int64_t>(wp->n_bins, avail) : avail;
+  if (nb > kWaveMaxBins) return DPSNN_E_INVAL;
+  const dpsnn_params& q = n->p[wp->net];
+  WaveArgs a{};
+  a.counts = n->sa.rates;
+  a.ring = n->p[0].rate_bins_cap;
+  a.M_stride = n->M_total;
+  a.mbase = n->mbase[wp->net];
+  a.bin0 = done - nb;
+  a.slot0 = a.bin0 % a.ring;
+  a.nb = (int32_t)nb;
+  a.W = q.grid_w;
+  a.H = q.grid_h;
+  a.M = q.grid_w * q.grid_h;
+  a.P = n->sa.P;
+  Scratch S;
+  S.free_fn = n->free_fn;
+  S.ctx = n->alloc_ctx;
+  return waves_impl(a, n->p[0].rate_bin_steps, n->p[0].dt_ms, wp, n->stream, S, out,
+                    host_tr_module, host_tr_T, host_tr_wave, cap_tr, host_wave_speed,
+                    host_wave_t0, host_wave_n, cap_waves);
+}
+
+int dpsnn_waves_counts(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_w,
+                       int32_t grid_h, int32_t n_pops, int32_t bin_steps, double dt_ms,
+                       int64_t bin0, const dpsnn_wave_params* wp, void* stream,
+                       dpsnn_wave_result* out, int32_t* host_tr_module, double* host_tr_T,
+                       int32_t* host_tr_wave, int64_t cap_tr, double* host_wave_speed,
+                       double* host_wave_t0, int32_t* host_wave_n, int64_t cap_waves) {
+  if (!dev_counts || n_bins < 1 || n_bins > kWaveMaxBins || grid_w < 1 || grid_h < 1 ||
+      bin0 < 0 || (int64_t)grid_w * grid_h > kWaveMaxModules)
+    return DPSNN_E_INVAL;
+  WaveArgs a{};
+  a.counts = dev_counts;
+  a.ring = n_bins;
+  a.M_stride = (int64_t)grid_w * grid_h;
+  a.mbase = 0;
+  a.slot0 = 0;  // the window is the whole buffer
+  a.bin0 = bin0;
+  a.nb = (int32_t)n_bins;
+  a.W = grid_w;
+  a.H = grid_h;
+  a.M = grid_w * grid_h;
+  a.P = n_pops;
+  Scratch S;
+  return waves_impl(a, bin_steps, dt_ms, wp, static_cast<hipStream_t>(stream), S, out,
+                    host_tr_module, host_tr_T, host_tr_wave, cap_tr, host_wave_speed,
+                    host_wave_t0, host_wave_n, cap_waves);
 }
 
 }  // extern "C"

@@ -203,6 +203,49 @@ hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t
 hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
                             unsigned long long* out, hipStream_t s);
 
+// Slow-wave analysis (waves.hip).  Counts of window bin k, module m,
+// population q at counts[(((slot0 + k) % ring) * M_stride + mbase + m) * P + q];
+// bin0 = absolute index of window bin 0 (noise draws and times).
+struct WaveArgs {
+  const uint32_t* counts;
+  int64_t ring, slot0, M_stride, mbase, bin0;
+  int32_t nb, M, W, H, P;
+  int32_t min_down, min_up, min_modules, cap_pm;
+  double dbin, sd;
+  uint32_t key0, key1;
+  const double* lnt;        // lnt[i] = log(i)
+  const double* z;          // 65536 standard normal quantiles
+  // per module: transitions in bin order
+  uint32_t* cnt;            // [M]
+  uint32_t* tr_k;           // [M][cap_pm] window bin
+  uint32_t* tr_q;           // [M][cap_pm] interpolation fraction, 2^-32 units
+  double* tr_T;             // [M][cap_pm] time, ms
+  // ordering
+  uint32_t* hist;           // [nb]
+  uint32_t* fill;           // [nb]
+  uint32_t* off;            // [nb + 1]
+  unsigned long long* keys; // [M * cap_pm] fraction << 32 | module << 12 | index
+  // ordered transitions and waves
+  int32_t* out_module;
+  double* out_T;
+  int32_t* out_wave;
+  int32_t* wave_first;      // [M * cap_pm + 1]
+  int32_t* n_waves;         // [1]
+  double* wave_speed;
+  double* wave_t0;
+  int32_t* wave_n;
+  double* grid;             // [batch][M] transition times of a wave batch
+};
+constexpr int kWaveMaxBins = 4096;
+constexpr int kWaveMaxModules = 8192;
+constexpr int kWaveBatch = 256;  // waves per launch of the speed kernel
+hipError_t launch_wave_max(const WaveArgs& a, uint32_t* out, hipStream_t s);
+hipError_t launch_wave_transitions(const WaveArgs& a, hipStream_t s);
+hipError_t launch_wave_speed(const WaveArgs& a, int32_t w0, int32_t n, hipStream_t s);
+hipError_t launch_wave_mean(const WaveArgs& a, double* out, hipStream_t s);
+// The 65536 standard normal quantiles of the efficacy tables.
+const std::vector<double>& standard_normal_grid();
+
 }  // namespace dpsnn
 
 // The opaque handle of the C-ABI.

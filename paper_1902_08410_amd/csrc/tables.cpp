@@ -429,4 +429,6 @@ std::vector<int64_t> fix_table(const dpsnn_params& p, const HostTables& T, int q
   return v;
 }
 
+const std::vector<double>& standard_normal_grid() { return normal_grid(); }
+
 }  // namespace dpsnn

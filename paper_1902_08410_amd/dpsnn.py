@@ -64,6 +64,21 @@ class DpsnnStats(C.Structure):
     ]
 
 
+class DpsnnWaveParams(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("net", C.c_int32), ("n_bins", C.c_int64),
+        ("noise_var", C.c_double), ("seed", C.c_uint64), ("min_down", C.c_int32),
+        ("min_up", C.c_int32), ("min_modules", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class DpsnnWaveResult(C.Structure):
+    _fields_ = [
+        ("bin0", C.c_int64), ("n_bins", C.c_int64), ("n_transitions", C.c_int64),
+        ("n_waves", C.c_int64), ("mean_speed", C.c_double), ("reserved", C.c_double * 3),
+    ]
+
+
 DEFAULT_SPIKE_LOG_CAP = 1 << 24
 DEFAULT_RATE_BINS_CAP = 4096
 
@@ -157,6 +172,12 @@ def lib():
             "dpsnn_build_batch": ([P(DpsnnParams), P(C.c_uint64), C.c_int32, P(V)], C.c_int),
             "dpsnn_net_info": ([V, C.c_int32, P(C.c_int64), P(C.c_int64), P(C.c_int64),
                                 P(C.c_int64)], C.c_int),
+            "dpsnn_waves": ([V, P(DpsnnWaveParams), P(DpsnnWaveResult), V, V, V, C.c_int64,
+                             V, V, V, C.c_int64], C.c_int),
+            "dpsnn_waves_counts": ([V, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_double, C.c_int64, P(DpsnnWaveParams), V,
+                                    P(DpsnnWaveResult), V, V, V, C.c_int64, V, V, V,
+                                    C.c_int64], C.c_int),
         }
         for fn, (args, res) in sig.items():
             f = getattr(L, fn)
@@ -171,7 +192,7 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_free", "dpsnn_strerror", "dpsnn_read_state", "dpsnn_write_state",
            "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
            "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps",
-           "dpsnn_build_batch", "dpsnn_net_info"]
+           "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -407,3 +428,61 @@ def dpsnn_host_table(params: dict, name: str, dtype) -> np.ndarray:
     out = np.zeros(nb // np.dtype(dtype).itemsize, dtype)
     lib().dpsnn_host_table(C.byref(s), name.encode(), _ptr(out), nb)
     return out
+
+
+# ---- slow-wave analysis (Sec. 2.3, Eq. 4) ---------------------------------
+def _wave_params(net_index, n_bins, noise_var, seed, min_down, min_up, min_modules):
+    return DpsnnWaveParams(ABI_VERSION, net_index, n_bins, noise_var, seed, min_down, min_up,
+                           min_modules, 0)
+
+
+def _wave_outputs(cap_tr, cap_w):
+    return (np.zeros(cap_tr, np.int32), np.zeros(cap_tr, np.float64),
+            np.zeros(cap_tr, np.int32), np.zeros(cap_w, np.float64),
+            np.zeros(cap_w, np.float64), np.zeros(cap_w, np.int32))
+
+
+def _wave_dict(res, o):
+    nt, nw = int(res.n_transitions), int(res.n_waves)
+    return {"bin0": int(res.bin0), "n_bins": int(res.n_bins), "n_transitions": nt,
+            "n_waves": nw, "mean_speed": float(res.mean_speed), "module": o[0][:nt],
+            "T": o[1][:nt], "wave": o[2][:nt], "speed": o[3][:nw], "t0": o[4][:nw],
+            "n": o[5][:nw]}
+
+
+def dpsnn_waves(net: Net, net_index: int = 0, n_bins: int = 0, noise_var: float = 0.5,
+                seed: int = 1, min_down: int = 2, min_up: int = 2,
+                min_modules: int = 1) -> dict:
+    """Slow-wave analysis of the rate bins the handle holds (not drained)."""
+    wp = _wave_params(net_index, n_bins, noise_var, seed, min_down, min_up, min_modules)
+    res = DpsnnWaveResult()
+    _check("dpsnn_waves", lib().dpsnn_waves(net.h, C.byref(wp), C.byref(res), None, None,
+                                            None, 0, None, None, None, 0))
+    o = _wave_outputs(int(res.n_transitions), int(res.n_waves))
+    _check("dpsnn_waves", lib().dpsnn_waves(net.h, C.byref(wp), C.byref(res), _ptr(o[0]),
+                                            _ptr(o[1]), _ptr(o[2]), len(o[0]), _ptr(o[3]),
+                                            _ptr(o[4]), _ptr(o[5]), len(o[3])))
+    return _wave_dict(res, o)
+
+
+def dpsnn_waves_counts(counts, grid_w: int, grid_h: int, bin_steps: int, dt_ms: float,
+                       bin0: int = 0, noise_var: float = 0.5, seed: int = 1,
+                       min_down: int = 2, min_up: int = 2, min_modules: int = 1) -> dict:
+    """Slow-wave analysis of a device tensor of counts [bins][modules][pops]
+    (uint32 data, e.g. a torch.int32 CUDA tensor)."""
+    import torch
+    assert counts.is_cuda and counts.is_contiguous() and counts.dim() == 3
+    assert counts.dtype in (torch.int32, torch.uint32)
+    nb, M, P = counts.shape
+    wp = _wave_params(0, 0, noise_var, seed, min_down, min_up, min_modules)
+    st = torch.cuda.current_stream().cuda_stream
+    args = (C.c_void_p(counts.data_ptr()), nb, grid_w, grid_h, P, bin_steps, dt_ms, bin0,
+            C.byref(wp), C.c_void_p(st))
+    res = DpsnnWaveResult()
+    _check("dpsnn_waves_counts", lib().dpsnn_waves_counts(*args, C.byref(res), None, None,
+                                                          None, 0, None, None, None, 0))
+    o = _wave_outputs(int(res.n_transitions), int(res.n_waves))
+    _check("dpsnn_waves_counts", lib().dpsnn_waves_counts(
+        *args, C.byref(res), _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), len(o[0]), _ptr(o[3]),
+        _ptr(o[4]), _ptr(o[5]), len(o[3])))
+    return _wave_dict(res, o)

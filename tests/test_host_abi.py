@@ -199,3 +199,40 @@ def test_population_model_invalid_parameters_rejected():
         with pytest.raises(L.DpsnnError) as e:
             L.dpsnn_host_table(dict(base, **over), "prop_f64", np.float64)
         assert e.value.code == -1, over
+
+
+def test_wave_analysis_rejects_invalid_requests_before_any_device_call():
+    """Argument checks of dpsnn_waves_counts / dpsnn_waves come first: none of
+    these calls touches the device (the count pointer is never read)."""
+    import ctypes as C
+    lib = L.lib()
+    fake = C.c_void_p(0x1000)
+    res = L.DpsnnWaveResult()
+
+    def call(nb=10, w=4, h=4, pops=2, bin_steps=50, dt=0.1, bin0=0, **kw):
+        f = dict(abi_version=L.ABI_VERSION, net=0, n_bins=0, noise_var=0.5, seed=1,
+                 min_down=2, min_up=2, min_modules=1, reserved=0)
+        f.update(kw)
+        wp = L.DpsnnWaveParams(**f)
+        return lib.dpsnn_waves_counts(fake, nb, w, h, pops, bin_steps, dt, bin0, C.byref(wp),
+                                      None, C.byref(res), None, None, None, 0, None, None,
+                                      None, 0)
+
+    E = -1  # DPSNN_E_INVAL
+    assert call(nb=4097) == E            # more than 4096 bins
+    assert call(nb=0) == E
+    assert call(w=128, h=65) == E        # more than 8192 modules
+    assert call(w=0) == E
+    assert call(pops=0) == E
+    assert call(bin_steps=0) == E
+    assert call(dt=0.0) == E
+    assert call(bin0=-1) == E
+    assert call(min_down=0) == E
+    assert call(min_up=0) == E
+    assert call(min_modules=-1) == E
+    assert call(noise_var=-0.5) == E
+    assert call(noise_var=float("inf")) == E
+    assert call(abi_version=1) == E
+    wp = L.DpsnnWaveParams(L.ABI_VERSION, 0, 0, 0.5, 1, 2, 2, 1, 0)
+    assert lib.dpsnn_waves(None, C.byref(wp), C.byref(res), None, None, None, 0, None, None,
+                           None, 0) == E
