@@ -187,6 +187,51 @@ DESCRIPTIONS = {
 DTYPES = {"grid24": "f32", "sweep64": "f16", "grid96": "i8", "fbi24": "f32"}
 
 
+def wave_bench(dpsnn, workloads, torch):
+    """Slow-wave analysis of the 24x24 F/B/I network in the SW state
+    (lambda = 0.5): 1 s of transient drained, then 3 s (600 bins of 5 ms)
+    analysed in place; one JSON line with the best of five timed calls."""
+    import ctypes as C
+    import numpy as np
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = dict(workloads.fbi(24, 24, "sw", lam=0.5), rate_bins_cap=4096)
+        net = dpsnn.dpsnn_build(p, 1)
+        dpsnn.dpsnn_step(net, 10000)
+        dpsnn.dpsnn_read_rates(net)
+        dpsnn.dpsnn_step(net, 30000)
+        r = dpsnn.dpsnn_waves(net, noise_var=0.5, seed=1, min_modules=50)
+        progress("analysis warm")
+        wp = dpsnn.DpsnnWaveParams(dpsnn.ABI_VERSION, 0, 0, 0.5, 1, 2, 2, 50, 0)
+        res = dpsnn.DpsnnWaveResult()
+        nt, nw = max(1, r["n_transitions"]), max(1, r["n_waves"])
+        bufs = [np.zeros(nt, np.int32), np.zeros(nt), np.zeros(nt, np.int32),
+                np.zeros(nw), np.zeros(nw), np.zeros(nw, np.int32)]
+        ptr = [b.ctypes.data_as(C.c_void_p) for b in bufs]
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc = dpsnn.lib().dpsnn_waves(net.h, C.byref(wp), C.byref(res), ptr[0], ptr[1],
+                                         ptr[2], nt, ptr[3], ptr[4], ptr[5], nw)
+            times.append(time.perf_counter() - t0)
+            if rc != 0:
+                raise dpsnn.DpsnnError("dpsnn_waves", rc)
+        net.close()
+    M, P = 576, 3
+    print(json.dumps({
+        "metric": "slow-wave analysis time (Sec. 2.3, Eq. 4), one call",
+        "value": min(times) * 1e3, "unit": "ms", "higher_is_better": False,
+        "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": "24x24 F/B/I network, SW state, lambda 0.5; 600 bins of 5 ms "
+                               "(3 s after 1 s of transient), noise variance 0.5, "
+                               "min_down = min_up = 2, min_modules = 50",
+                   "count_bytes": int(r["n_bins"]) * M * P * 4},
+        "transitions": int(res.n_transitions), "waves": int(res.n_waves),
+        "mean_speed_imd_per_s": float(res.mean_speed),
+        "all_calls_ms": [t * 1e3 for t in times]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +253,9 @@ def main():
                     help="steps timed per kernel with events for the roofline")
     ap.add_argument("--variants", type=int, default=1,
                     help="grid24: also time FP16 and int8 efficacies")
+    ap.add_argument("--waves", action="store_true",
+                    help="time the slow-wave analysis (Sec. 2.3, Eq. 4) of 3 s of the 24x24 "
+                         "F/B/I SW network instead of the step")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof)
@@ -237,6 +285,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
+    if args.waves:
+        wave_bench(dpsnn, workloads, torch)
         return
     stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
     total_bins = (args.warmup + steps) * S // 50 + 400   # + autotune/profile steps

@@ -448,6 +448,8 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
   a.fill = (uint32_t*)S.get((size_t)a.nb * 4);
   a.off = (uint32_t*)S.get((size_t)(a.nb + 1) * 4);
   a.keys = (unsigned long long*)S.get((size_t)nt * 8);
+  a.pos = (uint32_t*)S.get((size_t)nt * 4);
+  a.nxt = (uint32_t*)S.get((size_t)nt * 4);
   a.out_module = (int32_t*)S.get((size_t)nt * 4);
   a.out_T = (double*)S.get((size_t)nt * 8);
   a.out_wave = (int32_t*)S.get((size_t)nt * 4);
@@ -462,6 +464,7 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
   for (const void* q : {(const void*)maxc, (const void*)a.cnt, (const void*)a.tr_k,
                         (const void*)a.tr_q, (const void*)a.tr_T, (const void*)a.hist,
                         (const void*)a.fill, (const void*)a.off, (const void*)a.keys,
+                        (const void*)a.pos, (const void*)a.nxt,
                         (const void*)a.out_module, (const void*)a.out_T,
                         (const void*)a.out_wave, (const void*)a.wave_first,
                         (const void*)a.n_waves, (const void*)a.wave_speed,

@@ -225,6 +225,9 @@ struct WaveArgs {
   uint32_t* fill;           // [nb]
   uint32_t* off;            // [nb + 1]
   unsigned long long* keys; // [M * cap_pm] fraction << 32 | module << 12 | index
+  uint32_t* pos;            // [M][cap_pm] position of each transition in the order
+  uint32_t* nxt;            // [M * cap_pm] next position of the module, then its
+                            // suffix minimum (end of the wave starting there)
   // ordered transitions and waves
   int32_t* out_module;
   double* out_T;

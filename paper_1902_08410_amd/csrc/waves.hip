@@ -18,6 +18,8 @@
 // the mean V.  Logarithms of integers come from a table built on the host,
 // so that every threshold decision is the same binary64 comparison on any
 // machine.
+#include <algorithm>
+
 #include "dpsnn_internal.h"
 #include "philox.h"
 
@@ -216,53 +218,98 @@ __global__ void __launch_bounds__(256) k_wave_bsort(WaveArgs a) {
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) a.keys[o0 + i] = sk[i];
 }
 
-// Greedy grouping over the ordered transitions (one wavefront; lane 0 walks
-// 64 staged keys at a time).  Writes module, time and wave of every
-// transition in order, the first position of every wave and their number.
-__global__ void __launch_bounds__(64) k_wave_group(WaveArgs a) {
-  extern __shared__ __align__(16) int32_t s_last[];  // [modules]
-  __shared__ unsigned long long s_key[64];
-  __shared__ int32_t s_w[64];
-  __shared__ int32_t s_cur;
-  const int lane = threadIdx.x;
-  for (int m = lane; m < a.M; m += 64) s_last[m] = -1;
-  if (lane == 0) s_cur = 0;
-  __syncthreads();
+// Greedy grouping over the ordered transitions.  A wave that starts at
+// position s ends just before the first position whose module already
+// occurred at or after s: nxt(s) = min over s' >= s of next(s'), next(s')
+// being the following position of the module at s'.  So the wave starts
+// are the chain 0, nxt(0), nxt(nxt(0)), ...: the next positions and their
+// suffix minimum are computed in parallel, the chain is walked once per
+// wave, and every position then finds its wave by bisection.
+
+// Position of every transition in the order: pos[m][j] = i.
+__global__ void __launch_bounds__(256) k_wave_inv(WaveArgs a) {
   const uint32_t total = a.off[a.nb];
-  for (uint32_t i0 = 0; i0 < total; i0 += 64) {
-    const uint32_t i = i0 + lane;
-    if (i < total) s_key[lane] = a.keys[i];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += gridDim.x * blockDim.x) {
+    const unsigned long long key = a.keys[i];
+    const int m = (int)((key >> 12) & 0xFFFFFu);
+    const uint32_t j = (uint32_t)(key & 0xFFFu);
+    a.pos[(int64_t)m * a.cap_pm + j] = i;
+  }
+}
+
+// next(i): the position of the same module's following transition, or
+// total.
+__global__ void __launch_bounds__(256) k_wave_next(WaveArgs a) {
+  const uint32_t total = a.off[a.nb];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += gridDim.x * blockDim.x) {
+    const unsigned long long key = a.keys[i];
+    const int m = (int)((key >> 12) & 0xFFFFFu);
+    const uint32_t j = (uint32_t)(key & 0xFFFu);
+    a.nxt[i] = j + 1 < a.cnt[m] ? a.pos[(int64_t)m * a.cap_pm + j + 1] : total;
+  }
+}
+
+// Suffix minimum of next() in place (one block): nxt(s).
+__global__ void __launch_bounds__(1024) k_wave_sufmin(WaveArgs a) {
+  __shared__ uint32_t s[1024];
+  const int tid = threadIdx.x;
+  const uint32_t total = a.off[a.nb];
+  const uint32_t per = (total + 1023) / 1024;
+  const uint32_t lo = tid * per < total ? tid * per : total;
+  const uint32_t hi = lo + per < total ? lo + per : total;
+  uint32_t run = total;
+  for (uint32_t i = hi; i > lo; --i) {
+    const uint32_t v = a.nxt[i - 1];
+    run = v < run ? v : run;
+    a.nxt[i - 1] = run;
+  }
+  s[tid] = run;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // suffix minimum of the chunk minima
+    const uint32_t v = tid + o < 1024 ? s[tid + o] : total;
     __syncthreads();
-    if (lane == 0) {
-      int32_t w = s_cur;
-      const uint32_t n = total - i0 < 64 ? total - i0 : 64;
-      for (uint32_t r = 0; r < n; ++r) {
-        const int m = (int)((s_key[r] >> 12) & 0xFFFFFu);
-        if (s_last[m] == w) {
-          w += 1;
-          a.wave_first[w] = (int32_t)(i0 + r);
-        }
-        s_last[m] = w;
-        s_w[r] = w;
-      }
-      s_cur = w;
-    }
-    __syncthreads();
-    if (i < total) {
-      const unsigned long long key = s_key[lane];
-      const int m = (int)((key >> 12) & 0xFFFFFu);
-      const uint32_t j = (uint32_t)(key & 0xFFFu);
-      a.out_module[i] = m;
-      a.out_T[i] = a.tr_T[(int64_t)m * a.cap_pm + j];
-      a.out_wave[i] = s_w[lane];
-    }
+    s[tid] = v < s[tid] ? v : s[tid];
     __syncthreads();
   }
-  if (lane == 0) {
-    a.wave_first[0] = 0;
-    const int32_t nw = total > 0 ? s_cur + 1 : 0;
-    a.n_waves[0] = nw;
-    a.wave_first[nw] = (int32_t)total;
+  const uint32_t later = tid + 1 < 1024 ? s[tid + 1] : total;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t v = a.nxt[i];
+    a.nxt[i] = later < v ? later : v;
+  }
+}
+
+// The chain of wave starts (one thread).
+__global__ void k_wave_chain(WaveArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t total = a.off[a.nb];
+  int32_t w = 0;
+  for (uint32_t st = 0; st < total; st = a.nxt[st]) a.wave_first[w++] = (int32_t)st;
+  a.wave_first[w] = (int32_t)total;
+  a.n_waves[0] = w;
+}
+
+// Module, time and wave of every position.
+__global__ void __launch_bounds__(256) k_wave_assign(WaveArgs a) {
+  const uint32_t total = a.off[a.nb];
+  const int32_t nw = a.n_waves[0];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += gridDim.x * blockDim.x) {
+    const unsigned long long key = a.keys[i];
+    const int m = (int)((key >> 12) & 0xFFFFFu);
+    const uint32_t j = (uint32_t)(key & 0xFFFu);
+    int32_t l = 0, h = nw - 1;  // last wave whose first position is <= i
+    while (l < h) {
+      const int32_t mid = (l + h + 1) >> 1;
+      if ((uint32_t)a.wave_first[mid] <= i)
+        l = mid;
+      else
+        h = mid - 1;
+    }
+    a.out_module[i] = m;
+    a.out_T[i] = a.tr_T[(int64_t)m * a.cap_pm + j];
+    a.out_wave[i] = l;
   }
 }
 
@@ -370,7 +417,12 @@ hipError_t launch_wave_transitions(const WaveArgs& a, hipStream_t st) {
   int mp2 = 1;
   while (mp2 < a.M) mp2 <<= 1;
   hipLaunchKernelGGL(k_wave_bsort, dim3((unsigned)a.nb), dim3(256), (size_t)mp2 * 8, st, a);
-  hipLaunchKernelGGL(k_wave_group, dim3(1), dim3(64), (size_t)a.M * 4, st, a);
+  const unsigned gb = (unsigned)std::min<int64_t>(4096, ((int64_t)a.M * a.cap_pm + 255) / 256);
+  hipLaunchKernelGGL(k_wave_inv, dim3(gb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_wave_next, dim3(gb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_wave_sufmin, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(k_wave_chain, dim3(1), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(k_wave_assign, dim3(gb), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
