@@ -154,3 +154,36 @@ def test_noise_variance_from_crossing_rate():
     # the standard deviation taken for the variance would be far off
     p_bad = 0.5 * math.erfc(theta / v / math.sqrt(2.0))
     assert abs(n - pairs * p_bad * (1 - p_bad)) > 0.2 * exp
+
+
+def test_threshold_is_strict():
+    # Down bins 0 (c_down = 0); Up bins {2, 9 x6}: mean 56 / 7 = 8, so
+    # theta = log(9) / 2, which equals log(3) in binary64: the bin of count
+    # 2 sits exactly at the threshold and is not Up.  Only the rise into the
+    # 9s is a transition (min_down = min_up = 1).
+    assert math.log(3.0) == 0.5 * math.log(9.0)
+    c = np.zeros((28, 1, 1), np.uint32)
+    c[10, 0, 0] = 2
+    c[12:18, 0, 0] = 9
+    r = O.waves(c, 1, 1, BIN_STEPS, DT, noise_var=0.0, min_down=1, min_up=1)
+    assert len(r["T"]) == 1
+    frac = math.log(3.0) / math.log(10.0)
+    assert r["T"][0] == pytest.approx((12 - 0.5 + frac) * DBIN, rel=1e-15)
+
+
+def test_down_bins_are_at_or_below_the_lower_median():
+    # an even window, half the bins Up: the lower median is the Down level
+    # (the upper median would leave no Up bins at all)
+    c = np.zeros((20, 1, 1), np.uint32)
+    c[10:20, 0, 0] = 50
+    assert len(O.waves(c, 1, 1, BIN_STEPS, DT, noise_var=0.0)["T"]) == 1
+
+
+def test_down_level_is_the_rounded_mean():
+    # Down bins alternate 2 and 3 (mean 2.5, rounded half up to 3), Up bins
+    # 99: theta = (log(100) - log(4)) / 2 and the bin before the rise has
+    # count 3, i.e. L = 0, so the crossing is halfway: T is the bin edge.
+    # (With the mean floored to 2 the crossing would move by 0.04 bin.)
+    c = np.array([2, 3] * 5 + [99] * 8, np.uint32).reshape(18, 1, 1)
+    r = O.waves(c, 1, 1, BIN_STEPS, DT, noise_var=0.0)
+    assert len(r["T"]) == 1 and r["T"][0] == 10 * DBIN
