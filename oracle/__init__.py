@@ -38,6 +38,13 @@ _POP_FIELDS = [
     ("p_tau_arp", _D4), ("p_alpha_c", _D4), ("p_tau_c", _D4), ("p_gc", _D4),
     ("p_I_const", _D4),
 ]
+# plasticity fields (default: off)
+_STDP_FIELDS = [
+    ("plastic", C.c_int32), ("stdp_update_steps", C.c_int32), ("stdp_A_plus", C.c_double),
+    ("stdp_A_minus", C.c_double), ("stdp_tau_plus", C.c_double),
+    ("stdp_tau_minus", C.c_double), ("stdp_tau_y", C.c_double), ("stdp_eta", C.c_double),
+    ("stdp_w_max", C.c_double),
+]
 
 
 class OrcParams(C.Structure):
@@ -52,7 +59,7 @@ class OrcParams(C.Structure):
         ("V_th", _PAIR), ("V_r", _PAIR), ("tau_arp", _PAIR), ("alpha_c", _PAIR),
         ("tau_c", _PAIR), ("gc", _PAIR), ("I_const", _PAIR),
         ("rate_bin_steps", C.c_int32),
-    ] + _POP_FIELDS
+    ] + _POP_FIELDS + _STDP_FIELDS
 
 
 def _fill(ctype, v):
@@ -73,10 +80,13 @@ def _fill(ctype, v):
 def to_struct(params: dict) -> OrcParams:
     s = OrcParams()
     pop_names = {n for n, _ in _POP_FIELDS}
+    stdp_names = {n for n, _ in _STDP_FIELDS}
     for name, ctype in OrcParams._fields_:
         key = "lambda" if name == "lambda_" else name
         if key in pop_names and key not in params:
             continue                      # zero: the two-population model
+        if key in stdp_names and key not in params:
+            continue                      # zero: no plasticity
         if params.get("n_pops", 0) and key not in params:
             continue                      # two-population fields unused
         v = params[key]
@@ -157,6 +167,9 @@ def lib():
         L.orc_spikes.restype = C.c_int64
         L.orc_rates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.orc_rates.restype = C.c_int64
+        L.orc_plasticity.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+        L.orc_plasticity.restype = C.c_int32
         L.orc_waves.argtypes = [P(OrcWaveParams), C.c_void_p, C.c_int64, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_int64, P(C.c_int64)]
@@ -355,3 +368,15 @@ class Oracle:
         out = np.zeros((nb, self.M, self.P), np.uint32)
         lib().orc_rates(self._h, _ptr(out), nb)
         return out
+
+    def plasticity(self, s: int):
+        """Row s's last activation steps, signals and efficacies, in the
+        order of gen_row_blocks."""
+        Ko = int(self.params["K_out"])
+        ta = np.zeros(Ko, np.int32)
+        y = np.zeros(Ko, np.float64)
+        w = np.zeros(Ko, np.float64)
+        rc = lib().orc_plasticity(self._h, s, _ptr(ta), _ptr(y), _ptr(w))
+        if rc != 0:
+            raise ValueError("no plasticity state")
+        return ta, y, w

@@ -104,6 +104,22 @@ struct orc_net {
   uint8_t* row_blk;
   uint16_t* row_doff;
   int64_t* spk_step;          /* ids that spiked in the current step      */
+
+  /* plasticity (p.plastic): per synapse [s * K_out + j], oracle row order */
+  int32_t L;                  /* table length = stdp_update_steps          */
+  int32_t* syn_t;             /* last activation step, -1 = never          */
+  float* syn_y32;
+  float* syn_w32;
+  double* syn_y64;
+  double* syn_w64;
+  int32_t* t_post;            /* last spike step of each neuron, -1 = none */
+  float* Ep32;                /* A+ e^(-k dt / tau+), A- e^(-k dt / tau-),  */
+  float* Em32;                /* e^(-k dt / tau_y), k < L                   */
+  float* Dy32;
+  double* Ep64;
+  double* Em64;
+  double* Dy64;
+  float eta32, wmax32;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -243,6 +259,9 @@ static void release(orc_net* n) {
   free(n->row_tgt); free(n->row_del); free(n->row_widx); free(n->row_blk);
   free(n->row_doff);
   free(n->spk_step);
+  free(n->syn_t); free(n->syn_y32); free(n->syn_w32); free(n->syn_y64); free(n->syn_w64);
+  free(n->t_post);
+  free(n->Ep32); free(n->Em32); free(n->Dy32); free(n->Ep64); free(n->Em64); free(n->Dy64);
   free(n);
 }
 
@@ -259,6 +278,14 @@ static int valid(const orc_params* p) {
   if (p->rate_bin_steps < 1) return 0;
   if ((int64_t)p->grid_w * p->grid_h * p->K > 2147483647LL) return 0;
   if (p->K_out > 65535) return 0;
+  if (p->plastic != 0 && p->plastic != 1) return 0;
+  if (p->plastic) {
+    if (p->weight_dtype != ORC_WF32 || p->stdp_update_steps < 1) return 0;
+    if (!(p->stdp_A_plus >= 0.0) || !(p->stdp_A_minus >= 0.0)) return 0;
+    if (!(p->stdp_tau_plus > 0.0) || !(p->stdp_tau_minus > 0.0) || !(p->stdp_tau_y > 0.0))
+      return 0;
+    if (!isfinite(p->stdp_eta) || !(p->stdp_w_max > 0.0) || !isfinite(p->stdp_w_max)) return 0;
+  }
   if (p->n_pops == 0) {
     if (!(p->frac_exc >= 0.0 && p->frac_exc <= 1.0)) return 0;
     for (int q = 0; q < 2; q++) {
@@ -768,6 +795,66 @@ orc_net* orc_create(const orc_params* p, uint64_t seed, int32_t mode,
                          n->r_widx + s * Ko, n->r_doff + s * (n->n_del + 1),
                          n->r_blk + s * Ko);
   }
+  if (p->plastic) {
+    const int32_t L = p->stdp_update_steps;
+    const size_t ns = (size_t)N * (size_t)(Ko ? Ko : 1);
+    n->L = L;
+    n->syn_t = (int32_t*)malloc(sizeof(int32_t) * ns);
+    n->t_post = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+    n->Ep32 = (float*)malloc(sizeof(float) * L);
+    n->Em32 = (float*)malloc(sizeof(float) * L);
+    n->Dy32 = (float*)malloc(sizeof(float) * L);
+    n->Ep64 = (double*)malloc(sizeof(double) * L);
+    n->Em64 = (double*)malloc(sizeof(double) * L);
+    n->Dy64 = (double*)malloc(sizeof(double) * L);
+    if (mode == ORC_MIRROR32) {
+      n->syn_y32 = (float*)calloc(ns, sizeof(float));
+      n->syn_w32 = (float*)malloc(sizeof(float) * ns);
+    } else {
+      n->syn_y64 = (double*)calloc(ns, sizeof(double));
+      n->syn_w64 = (double*)malloc(sizeof(double) * ns);
+    }
+    if (!n->syn_t || !n->t_post || !n->Ep32 || !n->Em32 || !n->Dy32 || !n->Ep64 ||
+        !n->Em64 || !n->Dy64 || (mode == ORC_MIRROR32 ? (!n->syn_y32 || !n->syn_w32)
+                                                     : (!n->syn_y64 || !n->syn_w64))) {
+      *err = ORC_E_NOMEM; release(n); return NULL;
+    }
+    for (int32_t k = 0; k < L; k++) {
+      const double x = (double)k * p->dt_ms;
+      n->Ep64[k] = p->stdp_A_plus * exp(-x / p->stdp_tau_plus);
+      n->Em64[k] = p->stdp_A_minus * exp(-x / p->stdp_tau_minus);
+      n->Dy64[k] = exp(-x / p->stdp_tau_y);
+      n->Ep32[k] = (float)n->Ep64[k];
+      n->Em32[k] = (float)n->Em64[k];
+      n->Dy32[k] = (float)n->Dy64[k];
+    }
+    n->eta32 = (float)p->stdp_eta;
+    n->wmax32 = (float)p->stdp_w_max;
+    for (int64_t i = 0; i < N; i++) n->t_post[i] = -1;
+    /* initial efficacies: the table values of the stored format */
+    for (int64_t s0 = 0; s0 < N; s0++) {
+      const uint16_t* wi;
+      const uint8_t* bk;
+      if (store_rows) {
+        wi = n->r_widx + s0 * Ko;
+        bk = n->r_blk + s0 * Ko;
+      } else {
+        orc_gen_row_blocks(n, s0, n->row_tgt, n->row_del, n->row_widx, n->row_doff,
+                           n->row_blk);
+        wi = n->row_widx;
+        bk = n->row_blk;
+      }
+      const int q = pop_of(n, s0);
+      for (int64_t j = 0; j < Ko; j++) {
+        const size_t at = (size_t)s0 * (size_t)Ko + (size_t)j;
+        n->syn_t[at] = -1;
+        if (mode == ORC_MIRROR32)
+          n->syn_w32[at] = n->wt32[q][bk[j]][wi[j]];
+        else
+          n->syn_w64[at] = n->wt64[q][bk[j]][wi[j]];
+      }
+    }
+  }
   *err = ORC_OK;
   return n;
 }
@@ -870,6 +957,96 @@ static int update_neuron64(orc_net* n, int64_t i, double dv) {
   return spiked;
 }
 
+/* Is population q excitatory (its synapses are the plastic ones)? */
+static int pop_is_exc(const orc_net* n, int q) {
+  return n->p.n_pops == 0 ? q == 0 : n->p.pop_exc[q] != 0;
+}
+
+/* Plasticity event of synapse `at` activated at step ta (Sec. 2.1: the
+ * synapse notes its previous activation; contributions through a low-pass
+ * filter), target's last spike tp; the reading is in the header. */
+static void stdp_event(orc_net* n, size_t at, int64_t ta, int64_t tp) {
+  const int64_t L = n->L;
+  const int64_t tl = n->syn_t[at];
+  if (n->mode == ORC_MIRROR32) {
+    float y = n->syn_y32[at];
+    y = (tl >= 0 && ta - tl < L) ? y * n->Dy32[ta - tl] : 0.0f;
+    if (tl >= 0 && tp > tl && tp - tl < L && ta - tp < L)
+      y = y + n->Ep32[tp - tl] * n->Dy32[ta - tp];
+    if (tp >= 0 && ta - tp < L) y = y - n->Em32[ta - tp];
+    n->syn_y32[at] = y;
+  } else {
+    double y = n->syn_y64[at];
+    y = (tl >= 0 && ta - tl < L) ? y * n->Dy64[ta - tl] : 0.0;
+    if (tl >= 0 && tp > tl && tp - tl < L && ta - tp < L)
+      y = y + n->Ep64[tp - tl] * n->Dy64[ta - tp];
+    if (tp >= 0 && ta - tp < L) y = y - n->Em64[ta - tp];
+    n->syn_y64[at] = y;
+  }
+  n->syn_t[at] = (int32_t)ta;
+}
+
+/* Delivery with plastic efficacies: each synapse's own efficacy (in fixed
+ * point rint(w 2^Q) in MIRROR32 mode); the synapses of excitatory sources
+ * register the activation first. */
+static void deliver_plastic(orc_net* n, int64_t s, int64_t t, int q, const int32_t* tgt,
+                            const uint8_t* del) {
+  const int Ko = n->p.K_out;
+  const double twoQ = ldexp(1.0, n->p.q_frac_bits);
+  const int plastic = pop_is_exc(n, q);
+  for (int j = 0; j < Ko; j++) {
+    const size_t si = (size_t)s * (size_t)Ko + (size_t)j;
+    if (plastic) stdp_event(n, si, t, n->t_post[tgt[j]]);
+    int64_t slot = (t + del[j]) % n->D;
+    size_t at = (size_t)slot * (size_t)n->N + (size_t)tgt[j];
+    if (n->mode == ORC_MIRROR32)
+      n->ring_fix[at] += (int64_t)rint((double)n->syn_w32[si] * twoQ);
+    else
+      n->ring64[at] += n->syn_w64[si];
+  }
+}
+
+/* Periodic efficacy update at step T (Sec. 2.1: every plastic synapse
+ * applies its integrated signal): w <- clip(w + eta y(T), 0, w_max), y <- 0. */
+static void stdp_update(orc_net* n, int64_t T) {
+  const int64_t Ko = n->p.K_out, L = n->L;
+  for (int64_t s = 0; s < n->N; s++) {
+    if (!pop_is_exc(n, pop_of(n, s))) continue;
+    for (int64_t j = 0; j < Ko; j++) {
+      const size_t at = (size_t)s * (size_t)Ko + (size_t)j;
+      const int64_t tl = n->syn_t[at];
+      const int live = tl >= 0 && T - tl < L;
+      if (n->mode == ORC_MIRROR32) {
+        if (live) {
+          float w = n->syn_w32[at] + n->eta32 * (n->syn_y32[at] * n->Dy32[T - tl]);
+          w = w < 0.0f ? 0.0f : (w > n->wmax32 ? n->wmax32 : w);
+          n->syn_w32[at] = w;
+        }
+        n->syn_y32[at] = 0.0f;
+      } else {
+        if (live) {
+          double w = n->syn_w64[at] + n->p.stdp_eta * (n->syn_y64[at] * n->Dy64[T - tl]);
+          w = w < 0.0 ? 0.0 : (w > n->p.stdp_w_max ? n->p.stdp_w_max : w);
+          n->syn_w64[at] = w;
+        }
+        n->syn_y64[at] = 0.0;
+      }
+    }
+  }
+}
+
+int32_t orc_plasticity(const orc_net* n, int64_t s, int32_t* t_act, double* y, double* w) {
+  if (!n->p.plastic || s < 0 || s >= n->N) return ORC_E_INVAL;
+  const int64_t Ko = n->p.K_out;
+  for (int64_t j = 0; j < Ko; j++) {
+    const size_t at = (size_t)s * (size_t)Ko + (size_t)j;
+    if (t_act) t_act[j] = n->syn_t[at];
+    if (y) y[j] = n->mode == ORC_MIRROR32 ? (double)n->syn_y32[at] : n->syn_y64[at];
+    if (w) w[j] = n->mode == ORC_MIRROR32 ? (double)n->syn_w32[at] : n->syn_w64[at];
+  }
+  return ORC_OK;
+}
+
 /* Delivery of one spike (Sec. 2.1.1, steps 3-4): every synapse of the
  * source adds its efficacy to the input queue of its target, in the slot of
  * the step at which the delay expires. */
@@ -895,6 +1072,10 @@ static void deliver(orc_net* n, int64_t s, int64_t t) {
     blk = n->row_blk;
   }
   const int q = pop_of(n, s);
+  if (n->p.plastic) {
+    deliver_plastic(n, s, t, q, tgt, del);
+    return;
+  }
   for (int j = 0; j < Ko; j++) {
     int64_t slot = (t + del[j]) % n->D;
     size_t at = (size_t)slot * (size_t)n->N + (size_t)tgt[j];
@@ -929,7 +1110,10 @@ static int step_once(orc_net* n) {
       n->ring64[at] = 0.0;
       spiked = update_neuron64(n, i, I);
     }
-    if (spiked) n->spk_step[n_spk++] = i;
+    if (spiked) {
+      n->spk_step[n_spk++] = i;
+      if (n->p.plastic) n->t_post[i] = (int32_t)t;
+    }
   }
   for (int64_t k = 0; k < n_spk; k++) {
     int rc = record_spike(n, t, n->spk_step[k]);
@@ -945,6 +1129,7 @@ int32_t orc_step(orc_net* n, int64_t n_steps) {
   for (int64_t k = 0; k < n_steps; k++) {
     int rc = step_once(n);
     if (rc != ORC_OK) return rc;
+    if (n->p.plastic && n->t % n->p.stdp_update_steps == 0) stdp_update(n, n->t);
   }
   return n->status;
 }

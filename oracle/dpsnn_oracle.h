@@ -95,6 +95,21 @@ typedef struct orc_params {
   double  p_nu_ext_hz[4], p_Jext_mean[4], p_Jext_sd[4];
   double  p_tau_m[4], p_E[4], p_V_th[4], p_V_r[4], p_tau_arp[4];
   double  p_alpha_c[4], p_tau_c[4], p_gc[4], p_I_const[4];
+  /* Spike-timing-dependent plasticity (Sec. 2.1; off in the paper's
+   * experiments).  plastic = 1 makes every synapse of an excitatory source
+   * plastic (binary32 efficacies only).  A synapse keeps the step of its
+   * last activation and a low-pass filtered plasticity signal y; at each
+   * activation (a spike of its source, at the emission step ta) y decays by
+   * exp(-lag / tau_y), gains A_plus exp(-(tp - t_act) / tau_plus) decayed
+   * from tp to ta when the target's last spike tp came after the previous
+   * activation t_act (LTP), and loses A_minus exp(-(ta - tp) / tau_minus)
+   * for the target's last spike tp <= ta (LTD).  Every stdp_update_steps
+   * steps each plastic efficacy becomes clip(w + eta y(T), 0, w_max) and y
+   * is reset.  Lags of stdp_update_steps steps or more contribute 0. */
+  int32_t plastic, stdp_update_steps;
+  double  stdp_A_plus, stdp_A_minus;     /* mV of plasticity signal        */
+  double  stdp_tau_plus, stdp_tau_minus, stdp_tau_y;  /* ms                */
+  double  stdp_eta, stdp_w_max;          /* gain; largest efficacy (mV)    */
 } orc_params;
 
 typedef struct orc_net orc_net;
@@ -166,6 +181,12 @@ int64_t  orc_spikes(const orc_net* n, int32_t* step, int32_t* id, int64_t cap);
 /* Population counts: [bins][modules][n_pops]; returns number of bins
  * touched. */
 int64_t  orc_rates(const orc_net* n, uint32_t* counts, int64_t cap_bins);
+
+/* Plasticity state of row s, in the oracle's row order (that of
+ * orc_gen_row_blocks): last activation step (-1: never), signal y and
+ * efficacy w of each synapse (binary32 values widened in MIRROR32 mode).
+ * ORC_E_INVAL without plasticity. */
+int32_t  orc_plasticity(const orc_net* n, int64_t s, int32_t* t_act, double* y, double* w);
 
 #ifdef __cplusplus
 }
