@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define DPSNN_ABI_VERSION 2u
+#define DPSNN_ABI_VERSION 3u
 
 /* Error codes. */
 #define DPSNN_OK 0
@@ -131,6 +131,29 @@ typedef struct dpsnn_params {
   double p_nu_ext_hz[4], p_Jext_mean[4], p_Jext_sd[4];
   double p_tau_m[4], p_E[4], p_V_th[4], p_V_r[4], p_tau_arp[4];
   double p_alpha_c[4], p_tau_c[4], p_gc[4], p_I_const[4];
+  /* Spike-timing-dependent plasticity (Sec. 2.1: each synapse notes its
+   * previous activation time; every synaptic event and postsynaptic spike
+   * contributes to LTP / LTD through a slow first-order low-pass filter
+   * whose state lives in the synapse; efficacies change every second).
+   * The paper gives no constants (plasticity is off in its experiments); the
+   * rule taken: plastic = 1 makes the synapses of excitatory sources
+   * plastic (binary32 efficacies only, split schedule only).  A synapse
+   * keeps its last activation step t_act and a binary32 signal y.  When its
+   * source spikes at step ta (activation), with tp the target's last spike
+   * step (-1: none): y decays by Dy(ta - t_act); if tp > t_act (a spike of
+   * the target since the previous activation), y += Ep(tp - t_act) *
+   * Dy(ta - tp) (LTP); if tp >= 0, y -= Em(ta - tp) (LTD); t_act = ta.
+   * After every stdp_update_steps steps (T = steps done): w = clip(w + eta *
+   * (y * Dy(T - t_act)), 0, w_max), y = 0.  Ep(k) = A_plus exp(-k dt /
+   * tau_plus), Em(k) = A_minus exp(-k dt / tau_minus), Dy(k) =
+   * exp(-k dt / tau_y), each rounded to binary32, and 0 for k >=
+   * stdp_update_steps.  Adds 8 bytes per synapse (t_act, y). */
+  int32_t plastic;
+  int32_t stdp_update_steps;
+  double stdp_A_plus, stdp_A_minus;      /* mV of signal per spike pair   */
+  double stdp_tau_plus, stdp_tau_minus, stdp_tau_y;  /* ms                 */
+  double stdp_eta;                       /* efficacy change per unit of y */
+  double stdp_w_max;                     /* largest plastic efficacy, mV  */
 } dpsnn_params;
 
 typedef struct dpsnn_stats {
@@ -352,6 +375,13 @@ int dpsnn_waves_counts(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_
                        dpsnn_wave_result* out, int32_t* host_tr_module, double* host_tr_T,
                        int32_t* host_tr_wave, int64_t cap_tr, double* host_wave_speed,
                        double* host_wave_t0, int32_t* host_wave_n, int64_t cap_waves);
+
+/* Plasticity state of rows first..first+count-1, in the order of
+ * dpsnn_read_rows: host_t_act int32 [count][K_out] (last activation step,
+ * -1: never), host_y float [count][K_out]; efficacies via dpsnn_read_rows.
+ * DPSNN_E_STATE without plasticity.  Either pointer may be NULL. */
+int dpsnn_read_plasticity(dpsnn_net* net, int64_t first, int64_t count,
+                          int32_t* host_t_act, float* host_y);
 
 /* Host table computed from p without any device (named arrays, see the
  * library source); returns the size in bytes, or a negative code. */

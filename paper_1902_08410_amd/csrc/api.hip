@@ -64,7 +64,13 @@ bool same_structure(const dpsnn_params& a, const dpsnn_params& b) {
   return a.K_out == b.K_out && a.d_min == b.d_min && a.d_max == b.d_max &&
          a.weight_dtype == b.weight_dtype && a.acc_bits == b.acc_bits &&
          a.q_frac_bits == b.q_frac_bits && a.rate_bin_steps == b.rate_bin_steps &&
-         a.dt_ms == b.dt_ms;
+         a.dt_ms == b.dt_ms && a.plastic == b.plastic &&
+         (!a.plastic || (a.stdp_update_steps == b.stdp_update_steps &&
+                         a.stdp_A_plus == b.stdp_A_plus && a.stdp_A_minus == b.stdp_A_minus &&
+                         a.stdp_tau_plus == b.stdp_tau_plus &&
+                         a.stdp_tau_minus == b.stdp_tau_minus &&
+                         a.stdp_tau_y == b.stdp_tau_y && a.stdp_eta == b.stdp_eta &&
+                         a.stdp_w_max == b.stdp_w_max));
 }
 
 int build_impl(dpsnn_net* n) {
@@ -275,6 +281,7 @@ int build_impl(dpsnn_net* n) {
       d.n_arp[q] = T.n_arp[q];
       d.n_pois[q] = T.n_pois[q];
       for (int x = 0; x < kMaxPois; ++x) d.pois[q][x] = T.pois[q][x];
+      d.exc[q] = p.n_pops == 0 ? (q == 0) : (p.pop_exc[q] != 0);
     }
   }
   HIP_OK(hipMemcpyAsync(nets, nd.data(), sizeof(NetDev) * nn, hipMemcpyHostToDevice, st));
@@ -360,6 +367,38 @@ int build_impl(dpsnn_net* n) {
   }
   n->split_ok = n_tiles <= kMaxSplitTiles;
   n->sched = (n->split_ok && n->N_total >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
+
+  // plasticity: per-synapse activation step and signal, per-neuron last
+  // spike, the three binary32 tables; the split schedule only (a delivery
+  // reads the targets' spike steps of the same step)
+  if (p0.plastic) {
+    if (!n->split_ok) return DPSNN_E_INVAL;
+    n->sched = DPSNN_SCHED_SPLIT;
+    const int32_t L = p0.stdp_update_steps;
+    a.plastic = 1;
+    a.stdp_L = L;
+    a.stdp_eta = (float)p0.stdp_eta;
+    a.stdp_wmax = (float)p0.stdp_w_max;
+    a.syn_t = (int32_t*)dev_alloc(n, (size_t)Np * rs * 4);
+    a.syn_y = (float*)dev_alloc(n, (size_t)Np * rs * 4);
+    a.t_post = (int32_t*)dev_alloc(n, (size_t)Np * 4);
+    float* tab = (float*)dev_alloc(n, (size_t)3 * L * 4);
+    if (!a.syn_t || !a.syn_y || !a.t_post || !tab) return DPSNN_E_NOMEM;
+    std::vector<float> h((size_t)3 * L);
+    for (int32_t k = 0; k < L; ++k) {
+      const double x = (double)k * p0.dt_ms;
+      h[k] = (float)(p0.stdp_A_plus * exp(-x / p0.stdp_tau_plus));
+      h[(size_t)L + k] = (float)(p0.stdp_A_minus * exp(-x / p0.stdp_tau_minus));
+      h[(size_t)2 * L + k] = (float)exp(-x / p0.stdp_tau_y);
+    }
+    HIP_OK(hipMemcpyAsync(tab, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
+    a.stdp_tab = tab;
+    HIP_OK(hipMemsetAsync(a.syn_t, 0xFF, (size_t)Np * rs * 4, st));  // -1: never
+    HIP_OK(hipMemsetAsync(a.syn_y, 0, (size_t)Np * rs * 4, st));
+    HIP_OK(hipMemsetAsync(a.t_post, 0xFF, (size_t)Np * 4, st));
+    HIP_OK(hipStreamSynchronize(st));
+    n->bytes_state += (int64_t)Np * rs * 8 + Np * 4;
+  }
   return DPSNN_OK;
 }
 
@@ -610,6 +649,7 @@ extern "C" {
 int dpsnn_set_schedule(dpsnn_net* n, int32_t sched) {
   if (!n || (sched != DPSNN_SCHED_FUSED && sched != DPSNN_SCHED_SPLIT)) return DPSNN_E_INVAL;
   if (sched == DPSNN_SCHED_SPLIT && !n->split_ok) return DPSNN_E_INVAL;
+  if (sched == DPSNN_SCHED_FUSED && n->sa.plastic) return DPSNN_E_INVAL;
   n->sched = sched;
   return DPSNN_OK;
 }
@@ -620,16 +660,8 @@ int dpsnn_set_graph_steps(dpsnn_net* n, int64_t steps) {
   return DPSNN_OK;
 }
 
-int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
-  if (!n || n_steps < 0) return DPSNN_E_INVAL;
-  if (n_steps == 0) return DPSNN_OK;
-  if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
-  const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
-  if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
-  // the fused schedule advances both spike-log bases: align them after split
-  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
-    HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
-  n->last_sched = n->sched;
+// n_steps steps: captured graphs for the bulk, the rest launched directly.
+static int run_steps(dpsnn_net* n, int64_t n_steps) {
   int64_t done = 0;
   if (n->stream && n->graph_steps > 0 && n_steps >= n->graph_steps) {
     const int rc = ensure_graph(n);
@@ -650,6 +682,29 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
   return DPSNN_OK;
 }
 
+int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
+  if (!n || n_steps < 0) return DPSNN_E_INVAL;
+  if (n_steps == 0) return DPSNN_OK;
+  if (n->t + n_steps > (n->sa.plastic ? 0x7FFFFFFFll : 0xFFFFFFFFll)) return DPSNN_E_INVAL;
+  const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
+  if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
+  // the fused schedule advances both spike-log bases: align them after split
+  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
+    HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
+  n->last_sched = n->sched;
+  if (!n->sa.plastic) return run_steps(n, n_steps);
+  // plastic: steps up to each update time, then the efficacy update
+  const int64_t U = n->sa.stdp_L;
+  for (int64_t left = n_steps; left > 0;) {
+    const int64_t k = std::min<int64_t>(left, U - n->t % U);
+    const int rc = run_steps(n, k);
+    if (rc != DPSNN_OK) return rc;
+    left -= k;
+    if (n->t % U == 0) HIP_OK(launch_stdp_update(n->sa, (int32_t)n->t, n->stream));
+  }
+  return DPSNN_OK;
+}
+
 int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   if (!n || probe_steps < 1) return DPSNN_E_INVAL;
   // candidates: the fused schedule, and the split one with several grids of
@@ -659,7 +714,7 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
     int32_t blocks;
   };
   std::vector<Cand> cands;
-  cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks});
+  if (!n->sa.plastic) cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks});
   if (n->split_ok) {
     const int32_t tiles = n->sa.n_tiles;
     for (int32_t b : {std::min<int32_t>(1024, std::max<int32_t>(256, tiles)), 512, 1024, 2048}) {
@@ -700,7 +755,7 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
 
 int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
   if (!n || n_steps < 1 || !host_ms) return DPSNN_E_INVAL;
-  if (n->t + n_steps > 0xFFFFFFFFll) return DPSNN_E_INVAL;
+  if (n->t + n_steps > (n->sa.plastic ? 0x7FFFFFFFll : 0xFFFFFFFFll)) return DPSNN_E_INVAL;
   const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
   if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
   if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
@@ -726,6 +781,10 @@ int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
         rc = DPSNN_E_DEVICE;
     }
     if (hipEventRecord(e[2], n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
+    const int64_t T = n->t + k + 1;  // plastic: the update after step T - 1
+    if (n->sa.plastic && T % n->sa.stdp_L == 0 &&
+        launch_stdp_update(n->sa, (int32_t)T, n->stream) != hipSuccess)
+      rc = DPSNN_E_DEVICE;
   }
   if (rc == DPSNN_OK && launch_tick(n->sa, (uint32_t)n_steps, 0, n->stream) != hipSuccess)
     rc = DPSNN_E_DEVICE;
@@ -924,6 +983,22 @@ int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tg
     HIP_OK(hipMemcpy2D(host_w, (size_t)Ko * wb,
                        static_cast<const unsigned char*>(n->sa.w) + (size_t)first * rs * wb,
                        (size_t)rs * wb, (size_t)Ko * wb, (size_t)count, hipMemcpyDeviceToHost));
+  return DPSNN_OK;
+}
+
+int dpsnn_read_plasticity(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_t_act,
+                          float* host_y) {
+  if (!n || first < 0 || count < 0 || first + count > n->N_index) return DPSNN_E_INVAL;
+  if (!n->sa.plastic) return DPSNN_E_STATE;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const int Ko = n->p[0].K_out, rs = n->T[0].row_stride;
+  if (Ko == 0 || count == 0) return DPSNN_OK;
+  if (host_t_act)
+    HIP_OK(hipMemcpy2D(host_t_act, (size_t)Ko * 4, n->sa.syn_t + first * rs, (size_t)rs * 4,
+                       (size_t)Ko * 4, (size_t)count, hipMemcpyDeviceToHost));
+  if (host_y)
+    HIP_OK(hipMemcpy2D(host_y, (size_t)Ko * 4, n->sa.syn_y + first * rs, (size_t)rs * 4,
+                       (size_t)Ko * 4, (size_t)count, hipMemcpyDeviceToHost));
   return DPSNN_OK;
 }
 

@@ -111,6 +111,7 @@ struct NetDev {
   int32_t n_arp[kMaxPops];
   int32_t n_pois[kMaxPops];
   uint32_t pois[kMaxPops][kMaxPois];
+  int32_t exc[kMaxPops];    // 1: excitatory population (its synapses are plastic)
 };
 
 // Arguments of the step kernels (passed by value).
@@ -156,6 +157,13 @@ struct StepArgs {
   uint32_t* q_cnt;         // [n_tiles][D], written by the owning tile only
   void* q_q;               // [n_tiles][D][q_cap] entries
   uint32_t* s_dirty;       // [n_tiles][D]: slot holds added input
+  // Plasticity (plastic networks; the rule is documented with dpsnn_params).
+  int32_t plastic, stdp_L;   // stdp_L = update period = table length
+  float stdp_eta, stdp_wmax;
+  int32_t* syn_t;          // [N_pad][row_stride] last activation step, -1 never
+  float* syn_y;            // [N_pad][row_stride] plasticity signal
+  int32_t* t_post;         // [N_pad] last spike step, -1 none
+  const float* stdp_tab;   // [3][stdp_L]: Ep, Em, Dy
 };
 
 struct GenArgs {
@@ -200,6 +208,8 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
 // Fold every pending queue entry into its slot and empty the queues; t is
 // the number of steps taken.
 hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t s);
+// Periodic efficacy update of the plastic synapses after T steps.
+hipError_t launch_stdp_update(const StepArgs& a, int32_t T, hipStream_t s);
 hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,
                             unsigned long long* out, hipStream_t s);
 

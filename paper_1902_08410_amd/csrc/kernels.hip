@@ -39,6 +39,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dpsnn_internal.h"
 #include "philox.h"
 
@@ -621,6 +623,7 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
       if (spk) {
         const int pos = atomicAdd(s_n, 1);
         s_spk[pos] = (int32_t)(i0 + j);
+        if (a.t_post) a.t_post[i0 + j] = (int32_t)t;  // plastic networks
         // population count of the rate bin (Sec. 2.3)
         const int64_t mod = nd.mbase + m0 + (l0 + j >= nd.K ? 1 : 0);
         const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
@@ -645,10 +648,27 @@ __device__ __forceinline__ void module_pop(const StepArgs& a, int32_t id, int32_
   *pop = (l >= nd.pop_hi[0]) + (l >= nd.pop_hi[1]) + (l >= nd.pop_hi[2]);
 }
 
+// Plasticity event of one synapse (Sec. 2.1): source spike at step ta,
+// target's last spike tp; t_act and y are the synapse's state (the rule is
+// documented with dpsnn_params; binary32, no contraction).
+__device__ __forceinline__ void stdp_event(const StepArgs& a, int32_t ta, int32_t tp,
+                                           int32_t& t_act, float& y) {
+  const int32_t L = a.stdp_L;
+  const float* Ep = a.stdp_tab;
+  const float* Em = Ep + L;
+  const float* Dy = Em + L;
+  const int32_t tl = t_act;
+  y = (tl >= 0 && ta - tl < L) ? y * Dy[ta - tl] : 0.0f;
+  if (tl >= 0 && tp > tl && tp - tl < L && ta - tp < L) y = y + Ep[tp - tl] * Dy[ta - tp];
+  if (tp >= 0 && ta - tp < L) y = y - Em[ta - tp];
+  t_act = ta;
+}
+
 // 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.  s_b is
 // the wavefront's 256-entry LDS scratch.  Every lane of the wavefront takes
-// part, also past the end of the row.
-template <typename Acc, int WDT>
+// part, also past the end of the row.  PLAST: the row's synapses register
+// the activation first when the source is excitatory.
+template <typename Acc, int WDT, bool PLAST = false>
 __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int p0,
                                               uint32_t t, int lane, uint32_t* s_b) {
   const int64_t rb = (int64_t)s * a.row_stride;
@@ -676,6 +696,22 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
+    }
+  }
+  if (PLAST) {
+    int32_t ms;
+    int q;
+    module_pop(a, s, &ms, &q);
+    if (a.nets[a.tile_net[s >> 10]].exc[q] && p < a.K_out) {
+      int4 ta4 = *reinterpret_cast<const int4*>(a.syn_t + rb + p);
+      float4 y4 = *reinterpret_cast<const float4*>(a.syn_y + rb + p);
+      int32_t tav[4] = {ta4.x, ta4.y, ta4.z, ta4.w};
+      float yv[4] = {y4.x, y4.y, y4.z, y4.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (p + j < a.K_out) stdp_event(a, (int32_t)t, a.t_post[tv[j] & kTargetMask], tav[j], yv[j]);
+      *reinterpret_cast<int4*>(a.syn_t + rb + p) = make_int4(tav[0], tav[1], tav[2], tav[3]);
+      *reinterpret_cast<float4*>(a.syn_y + rb + p) = make_float4(yv[0], yv[1], yv[2], yv[3]);
     }
   }
   const int slot0 = (int)((t + (uint32_t)a.d_min) % (uint32_t)a.D);
@@ -811,7 +847,7 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   if (tid == 0) a.blk_cnt[blockIdx.x] = n;
 }
 
-template <typename Acc, int WDT>
+template <typename Acc, int WDT, bool PLAST = false>
 __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   // delivery blocks: inclusive prefix of the tile counts; routing blocks:
   // their RouteLds
@@ -881,7 +917,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
     const int first = l ? s_pref[l - 1] : 0;
     const int32_t s = __builtin_amdgcn_readfirstlane(a.spk[(int64_t)l * 1024 + (sidx - first)]);
     if (chunk == 0 && lane == 0) record_spike(a, s, t, log0 + (unsigned long long)sidx);
-    deliver_chunk<Acc, WDT>(a, s, chunk * 256, t, lane, s_b[tid >> 6]);
+    deliver_chunk<Acc, WDT, PLAST>(a, s, chunk * 256, t, lane, s_b[tid >> 6]);
   }
 }
 
@@ -1035,7 +1071,9 @@ static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t
   launch_neuron<Acc>(a, t_off, st);
   const size_t lds = deliver_lds<Acc>(a);
   const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
-  if (wdt == DPSNN_W_F32)
+  if (a.plastic)
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32, true>), grid, block, lds, st, a, t_off);
+  else if (wdt == DPSNN_W_F32)
     hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
   else if (wdt == DPSNN_W_F16)
     hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
@@ -1089,6 +1127,11 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
       launch_neuron<int32_t>(a, t_off, st);
     else
       launch_neuron<int64_t>(a, t_off, st);
+  } else if (a.plastic) {
+    if (acc_bits == 32)
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32, true>), grid, block, lds, st, a, t_off);
+    else
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32, true>), grid, block, lds, st, a, t_off);
   } else if (acc_bits == 32) {
     if (wdt == DPSNN_W_F32)
       hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
@@ -1114,6 +1157,42 @@ hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t
     hipLaunchKernelGGL(k_drain<int32_t>, grid, dim3(256), 0, st, a, t);
   else
     hipLaunchKernelGGL(k_drain<int64_t>, grid, dim3(256), 0, st, a, t);
+  return hipGetLastError();
+}
+
+// Periodic efficacy update of every plastic synapse after T steps (Sec. 2.1:
+// the synapses apply their integrated plasticity signal once per period):
+// w = clip(w + eta (y Dy(T - t_act)), 0, w_max), y = 0.
+__global__ void __launch_bounds__(256) k_stdp_update(StepArgs a, int32_t T) {
+  const int64_t total = a.N_pad * a.row_stride;
+  const int32_t L = a.stdp_L;
+  const float* Dy = a.stdp_tab + 2 * L;
+  float* w = static_cast<float*>(const_cast<void*>(a.w));  // plastic efficacies
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = x / a.row_stride;
+    const int j = (int)(x - s * a.row_stride);
+    if (j >= a.K_out) continue;
+    const NetDev& nd = a.nets[a.tile_net[s >> 10]];
+    const int64_t il = s - nd.base;
+    if (il >= nd.N) continue;  // padding
+    const int l = (int)(il % nd.K);
+    const int q = (l >= nd.pop_hi[0]) + (l >= nd.pop_hi[1]) + (l >= nd.pop_hi[2]);
+    if (!nd.exc[q]) continue;
+    const int32_t tl = a.syn_t[x];
+    if (tl >= 0 && T - tl < L) {
+      float v = w[x] + a.stdp_eta * (a.syn_y[x] * Dy[T - tl]);
+      v = v < 0.0f ? 0.0f : (v > a.stdp_wmax ? a.stdp_wmax : v);
+      w[x] = v;
+    }
+    a.syn_y[x] = 0.0f;
+  }
+}
+
+hipError_t launch_stdp_update(const StepArgs& a, int32_t T, hipStream_t st) {
+  const int64_t total = a.N_pad * a.row_stride;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_stdp_update, dim3((unsigned)blocks), dim3(256), 0, st, a, T);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // Host-side tables of libdpsnn, computed once per build in binary64 and
 // rounded once to the width the device uses.
 #include <math.h>
+
+#include <cmath>
 #include <string.h>
 
 #include <algorithm>
@@ -83,6 +85,16 @@ int validate(const dpsnn_params& p) {
     return DPSNN_E_INVAL;
   if (p.weight_dtype < DPSNN_W_F32 || p.weight_dtype > DPSNN_W_I8) return DPSNN_E_INVAL;
   if (p.acc_bits != 32 && p.acc_bits != 64) return DPSNN_E_INVAL;
+  if (p.plastic != 0 && p.plastic != 1) return DPSNN_E_INVAL;
+  if (p.plastic) {
+    if (p.weight_dtype != DPSNN_W_F32 || p.stdp_update_steps < 1 ||
+        p.stdp_update_steps > (1 << 24))
+      return DPSNN_E_INVAL;
+    if (!(p.stdp_A_plus >= 0) || !(p.stdp_A_minus >= 0) || !(p.stdp_tau_plus > 0) ||
+        !(p.stdp_tau_minus > 0) || !(p.stdp_tau_y > 0) || !std::isfinite(p.stdp_eta) ||
+        !(p.stdp_w_max > 0) || !std::isfinite(p.stdp_w_max))
+      return DPSNN_E_INVAL;
+  }
   if (p.q_frac_bits < 0 || p.q_frac_bits > (p.acc_bits == 32 ? 30 : 40))
     return DPSNN_E_INVAL;
   if (p.rate_bin_steps < 1 || p.rate_bins_cap < 1 || p.spike_log_cap < 0)

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libdpsnn.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 W_F32, W_F16, W_I8 = 0, 1, 2
 WEIGHT_DTYPES = {"f32": W_F32, "f16": W_F16, "i8": W_I8}
 ERRORS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "RANGE",
@@ -36,6 +36,15 @@ _POP_FIELDS = [
 ]
 
 
+# plasticity fields (default: off)
+_STDP_FIELDS = [
+    ("plastic", C.c_int32), ("stdp_update_steps", C.c_int32), ("stdp_A_plus", C.c_double),
+    ("stdp_A_minus", C.c_double), ("stdp_tau_plus", C.c_double),
+    ("stdp_tau_minus", C.c_double), ("stdp_tau_y", C.c_double), ("stdp_eta", C.c_double),
+    ("stdp_w_max", C.c_double),
+]
+
+
 class DpsnnParams(C.Structure):
     _fields_ = [
         ("abi_version", C.c_uint32), ("grid_w", C.c_int32), ("grid_h", C.c_int32),
@@ -49,7 +58,7 @@ class DpsnnParams(C.Structure):
         ("gc", _PAIR), ("I_const", _PAIR), ("rate_bin_steps", C.c_int32),
         ("spike_log_cap", C.c_int64), ("rate_bins_cap", C.c_int64),
         ("queue_cap", C.c_int32),
-    ] + _POP_FIELDS
+    ] + _POP_FIELDS + _STDP_FIELDS
 
 
 class DpsnnStats(C.Structure):
@@ -99,12 +108,15 @@ def to_struct(params: dict) -> DpsnnParams:
     s = DpsnnParams()
     s.abi_version = ABI_VERSION
     pop_names = {n for n, _ in _POP_FIELDS}
+    stdp_names = {n for n, _ in _STDP_FIELDS}
     for name, ctype in DpsnnParams._fields_:
         if name == "abi_version":
             continue
         key = "lambda" if name == "lambda_" else name
         if key in pop_names and key not in params:
             continue                      # zero: the two-population model
+        if key in stdp_names and key not in params:
+            continue                      # zero: no plasticity
         if params.get("n_pops", 0) and key not in params and key not in (
                 "spike_log_cap", "rate_bins_cap", "queue_cap"):
             continue                      # two-population fields unused
@@ -172,6 +184,7 @@ def lib():
             "dpsnn_build_batch": ([P(DpsnnParams), P(C.c_uint64), C.c_int32, P(V)], C.c_int),
             "dpsnn_net_info": ([V, C.c_int32, P(C.c_int64), P(C.c_int64), P(C.c_int64),
                                 P(C.c_int64)], C.c_int),
+            "dpsnn_read_plasticity": ([V, C.c_int64, C.c_int64, V, V], C.c_int),
             "dpsnn_waves": ([V, P(DpsnnWaveParams), P(DpsnnWaveResult), V, V, V, C.c_int64,
                              V, V, V, C.c_int64], C.c_int),
             "dpsnn_waves_counts": ([V, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -192,7 +205,8 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_free", "dpsnn_strerror", "dpsnn_read_state", "dpsnn_write_state",
            "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
            "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps",
-           "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts"]
+           "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts",
+           "dpsnn_read_plasticity"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -418,6 +432,17 @@ def dpsnn_read_rows(net: Net, first: int, count: int):
     _check("dpsnn_read_rows",
            lib().dpsnn_read_rows(net.h, int(first), int(count), _ptr(tgt), _ptr(w), _ptr(dk)))
     return tgt, w, dk
+
+
+def dpsnn_read_plasticity(net: Net, first: int, count: int):
+    """(last activation step, plasticity signal) of the synapses of rows
+    first..first+count-1, in the order of dpsnn_read_rows."""
+    Ko = int(net.params["K_out"])
+    ta = np.zeros((count, Ko), np.int32)
+    y = np.zeros((count, Ko), np.float32)
+    _check("dpsnn_read_plasticity",
+           lib().dpsnn_read_plasticity(net.h, int(first), int(count), _ptr(ta), _ptr(y)))
+    return ta, y
 
 
 def dpsnn_host_table(params: dict, name: str, dtype) -> np.ndarray:

@@ -90,6 +90,18 @@ def test_f16_table_matches_numpy_rounding():
     dict(dt_ms=0.0), dict(tau_m=[0.0, 10.0]), dict(frac_exc=1.5),
     dict(frac_local=[1.2, 0.5]), dict(tau_arp=[30.0, 1.0]),
     dict(grid_w=64, grid_h=64, K=20000, K_out=10),   # more than 2^26 neurons
+    # plasticity: binary32 efficacies only, positive constants
+    dict(plastic=2),
+    dict(plastic=1, weight_dtype="f16", stdp_update_steps=100, stdp_tau_plus=2.0,
+         stdp_tau_minus=2.0, stdp_tau_y=5.0, stdp_w_max=1.0),
+    dict(plastic=1, stdp_update_steps=0, stdp_tau_plus=2.0, stdp_tau_minus=2.0,
+         stdp_tau_y=5.0, stdp_w_max=1.0),
+    dict(plastic=1, stdp_update_steps=100, stdp_tau_plus=0.0, stdp_tau_minus=2.0,
+         stdp_tau_y=5.0, stdp_w_max=1.0),
+    dict(plastic=1, stdp_update_steps=100, stdp_tau_plus=2.0, stdp_tau_minus=2.0,
+         stdp_tau_y=5.0, stdp_w_max=0.0),
+    dict(plastic=1, stdp_update_steps=100, stdp_A_minus=-1.0, stdp_tau_plus=2.0,
+         stdp_tau_minus=2.0, stdp_tau_y=5.0, stdp_w_max=1.0),
 ])
 def test_invalid_parameters_rejected(bad):
     p = W.swa(rate_bins_cap=16, spike_log_cap=16)
