@@ -49,10 +49,15 @@ def bytes_per_neuron_step(p) -> float:
 
 def bytes_per_event(p) -> float:
     """Algorithmic bytes of one synaptic event: target index, stored
-    efficacy, read-modify-write of the target's input slot."""
+    efficacy, read-modify-write of the target's input slot; with plasticity
+    the events of excitatory sources also read and write the synapse's
+    activation step and signal and read the target's last spike step."""
     acc = 4 if p["acc_bits"] == 32 else 8
     wb = {"f32": 4, "f16": 2, "i8": 1}[p["weight_dtype"]]
-    return 4 + wb + 2 * acc
+    b = 4 + wb + 2 * acc
+    if p.get("plastic", 0):
+        b += p["frac_exc"] * (4 + 4 + 4 + 4 + 4)
+    return b
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_08410_amd", "csrc", "kernels.hip")
@@ -154,6 +159,9 @@ def build_workload(name, dpsnn, workloads, total_bins):
         regs = {"sw": workloads.fbi(24, 24, "sw"), "aw88": workloads.fbi(24, 24, "aw88")}
     elif name == "grid96":
         regs = {"swa": workloads.grid96("swa"), "aw": workloads.grid96("aw")}
+    elif name == "stdp24":
+        regs = {"swa": workloads.grid(24, 24, "swa", **workloads.stdp()),
+                "aw": workloads.grid(24, 24, "aw", **workloads.stdp())}
     else:
         regs = None
     nets = {}
@@ -180,11 +188,14 @@ DESCRIPTIONS = {
     "grid96": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
            "SWA + AW networks, int8 efficacies with per-module scale, int64 fixed-point "
            "slots (Q = 32)"),
+    "stdp24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
+               "SWA + AW networks, FP32 efficacies, int32 slots, STDP on the synapses of "
+               "excitatory sources (20 ms windows, 1 s filter and update period)"),
     "fbi24": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
             "synapses, 1125 per neuron), Table S1 SW and AW 8.8 Hz states, Eq. 1 from "
             "d = 0 with lambda 0.5, open boundaries, FP32 efficacies, int32 slots"),
 }
-DTYPES = {"grid24": "f32", "sweep64": "f16", "grid96": "i8", "fbi24": "f32"}
+DTYPES = {"grid24": "f32", "sweep64": "f16", "grid96": "i8", "fbi24": "f32", "stdp24": "f32"}
 
 
 def wave_bench(dpsnn, workloads, torch):
@@ -235,9 +246,10 @@ def wave_bench(dpsnn, workloads, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["grid24", "sweep64", "grid96", "fbi24"], default="grid24")
+    ap.add_argument("--workload", choices=["grid24", "sweep64", "grid96", "fbi24", "stdp24"],
+                    default="grid24")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 10 for grid24 and fbi24, 2 for sweep64 and grid96)")
+                    help="timed steps (default 10 for grid24, fbi24 and stdp24, 2 for sweep64 and grid96)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dt-steps", type=int, default=None,
                     help="dt steps per bench step (default 10000 = 1 s; 2000 for sweep64 and grid96)")
@@ -265,7 +277,7 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
-    small = wl in ("grid24", "fbi24")
+    small = wl in ("grid24", "fbi24", "stdp24")
     steps = args.steps if args.steps is not None else (10 if small else 2)
     S = args.dt_steps if args.dt_steps is not None else (10000 if small else 2000)
     if not small:

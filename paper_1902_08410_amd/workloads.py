@@ -53,6 +53,17 @@ def tiny(w: int = 2, h: int = 2, K: int = 16, K_out: int = 8, **over) -> dict:
     return p
 
 
+def stdp(**over) -> dict:
+    """Plasticity fields (Sec. 2.1; the paper gives no constants): pair
+    windows of 20 ms with slightly stronger depression, a 1 s low-pass filter
+    and a 1 s update period, efficacies kept in [0, 1] mV."""
+    p = dict(plastic=1, stdp_update_steps=10000, stdp_A_plus=0.01, stdp_A_minus=0.0105,
+             stdp_tau_plus=20.0, stdp_tau_minus=20.0, stdp_tau_y=1000.0, stdp_eta=1.0,
+             stdp_w_max=1.0)
+    p.update(over)
+    return p
+
+
 def sweep(n: int = 64, seed: int = 1):
     """Batched sweep: n networks, grids uniform in {4x4, 8x8, 12x12, 16x16}
     modules, adaptation g_c/C_m log-uniform on [0.002, 0.02] 1/ms (AW to
