@@ -176,7 +176,8 @@ typedef struct dpsnn_stats {
   int32_t deliver_blocks; /* grid of the split schedule's delivery kernel  */
   int32_t route_blocks;   /* inbox-routing blocks beside it               */
   int32_t n_pops;         /* populations per module (rate-bin stride)     */
-  int32_t reserved;
+  int32_t queue_entry_bytes; /* bytes per per-slot queue entry: 4 (packed:
+                             every efficacy fits 21 bits), 8, 16, 0 = none */
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */

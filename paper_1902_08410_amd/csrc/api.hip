@@ -136,6 +136,7 @@ int build_impl(dpsnn_net* n) {
   // efficacy| over its incoming synapses plus the largest external sum.
   unsigned long long* absum = nullptr;
   int64_t ext_bound = 0;
+  int64_t max_fix = 0;  // largest |fixed-point efficacy| of every table
   if (p0.acc_bits == 32 && p0.K_out > 0) {
     absum = (unsigned long long*)dev_alloc(n, (size_t)Np * 8 + 256);
     if (!absum) return DPSNN_E_NOMEM;
@@ -180,6 +181,7 @@ int build_impl(dpsnn_net* n) {
           wfix_dev[q][bb] = (int64_t*)dev_alloc(n, (size_t)kQuantN * 8);
           if (!wfix_dev[q][bb]) return DPSNN_E_NOMEM;
           wf.push_back(fix_table(p, T, q, bb));
+          for (int64_t v : wf.back()) max_fix = std::max<int64_t>(max_fix, v < 0 ? -v : v);
           HIP_OK(hipMemcpyAsync(wfix_dev[q][bb], wf.back().data(), (size_t)kQuantN * 8,
                                 hipMemcpyHostToDevice, st));
         }
@@ -362,6 +364,11 @@ int build_impl(dpsnn_net* n) {
     HIP_OK(hipMemsetAsync(a.q_cnt, 0, (size_t)n_tiles * T0.D * 4, st));
     HIP_OK(hipMemsetAsync(a.s_dirty, 0, (size_t)n_tiles * T0.D * 4, st));
     HIP_OK(hipStreamSynchronize(st));
+    // 4-byte queue entries when every efficacy (and a plastic one's
+    // largest value) fits 21 bits
+    const int64_t wmax_fix =
+        p0.plastic ? (int64_t)llrint(ldexp(p0.stdp_w_max, p0.q_frac_bits)) : 0;
+    a.q_packed = ab == 4 && absum && max_fix < (1 << 21) && wmax_fix < (1 << 21);
     n->bytes_state += (int64_t)((n_in + n_q) * eb) +
                       (2 * n_tiles * kInboxStride + 2 * n_tiles * T0.D) * 4;
   }
@@ -895,6 +902,10 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->deliver_blocks = n->sa.deliver_blocks;
   out->route_blocks = n->sa.route_blocks;
   out->n_pops = n->sa.P;
+  out->queue_entry_bytes = n->sa.q_cap == 0 ? 0
+                           : n->sa.q_packed ? 4
+                           : (acc_bytes(n->p[0]) == 4 ? (int32_t)sizeof(QEntry<int32_t>)
+                                                      : (int32_t)sizeof(QEntry<int64_t>));
   return DPSNN_OK;
 }
 

@@ -152,6 +152,8 @@ struct StepArgs {
   // slot, and the slot is marked in s_dirty: the update reads and clears
   // the slots marked only (with queues every other slot holds zeros).
   int32_t q_cap, in_cap;
+  int32_t q_packed;        // queue entries packed in 4 bytes (int32 inputs
+                           // whose efficacies all fit 21 bits: w << 10 | idx)
   uint32_t* in_cnt;        // [2][n_tiles * kInboxStride] (may exceed in_cap)
   void* in_q;              // [2][n_tiles][in_cap] entries
   uint32_t* q_cnt;         // [n_tiles][D], written by the owning tile only

@@ -283,6 +283,49 @@ __device__ __forceinline__ void lds_add<int64_t>(int64_t* p, int64_t v) {
 // that their memory latency is paid once per batch.
 constexpr int kQBatch = 8;
 
+// Packed queue entry (int32 inputs whose efficacies all fit 21 bits):
+// fixed-point efficacy << 10 | in-tile index.
+__device__ __forceinline__ uint32_t pack_entry(int32_t w, uint32_t idx) {
+  return ((uint32_t)w << 10) | idx;
+}
+__device__ __forceinline__ int32_t packed_w(uint32_t v) { return (int32_t)v >> 10; }
+
+// The batches of gather_now: the current queue (packed or not) and the
+// inbox of step t-1, kQBatch entries per thread at a time.
+template <typename Acc, bool PK>
+__device__ __forceinline__ void gather_batches(const void* qbase, const QEntry<Acc>* iq,
+                                               uint32_t n_cur, uint32_t n_in, Acc* s_in) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const uint32_t n_max = n_cur > n_in ? n_cur : n_in;
+  for (uint32_t r0 = 0; r0 < n_max; r0 += (uint32_t)nth * kQBatch) {
+    QEntry<Acc> ce[kQBatch], ie[kQBatch];
+    uint32_t cp[kQBatch];
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      const uint32_t e = r0 + (uint32_t)(u * nth + tid);
+      ce[u].x = 0xFFFFFFFFu;
+      ie[u].x = 0xFFFFFFFFu;
+      if (PK) {
+        if (e < n_cur) cp[u] = static_cast<const uint32_t*>(qbase)[e];
+      } else if (e < n_cur) {
+        ce[u] = static_cast<const QEntry<Acc>*>(qbase)[e];
+      }
+      if (e < n_in) ie[u] = iq[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kQBatch; ++u) {
+      const uint32_t e = r0 + (uint32_t)(u * nth + tid);
+      if (PK) {
+        if (e < n_cur) lds_add<Acc>(&s_in[cp[u] & 1023u], (Acc)packed_w(cp[u]));
+      } else if (ce[u].x != 0xFFFFFFFFu) {
+        lds_add<Acc>(&s_in[ce[u].x & 1023u], ce[u].w);
+      }
+      if (ie[u].x != 0xFFFFFFFFu && (ie[u].x >> 10) == 0u)  // delay d_min = 1
+        lds_add<Acc>(&s_in[ie[u].x & 1023u], ie[u].w);
+    }
+  }
+}
+
 template <typename Acc>
 __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t t, Acc* s_in) {
   const int D = a.D;
@@ -298,28 +341,14 @@ __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t
   }
   for (int k = tid; k < 1024; k += nth) s_in[k] = 0;
   lds_barrier();
-  const QEntry<Acc>* qq =
-      static_cast<const QEntry<Acc>*>(a.q_q) + ((int64_t)tile * D + cur) * a.q_cap;
+  const int64_t qo = ((int64_t)tile * D + cur) * a.q_cap;
   const QEntry<Acc>* iq =
       static_cast<const QEntry<Acc>*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
-  const uint32_t n_max = n_cur > n_in ? n_cur : n_in;
-  for (uint32_t r0 = 0; r0 < n_max; r0 += (uint32_t)nth * kQBatch) {
-    QEntry<Acc> ce[kQBatch], ie[kQBatch];
-#pragma unroll
-    for (int u = 0; u < kQBatch; ++u) {
-      const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      ce[u].x = 0xFFFFFFFFu;
-      ie[u].x = 0xFFFFFFFFu;
-      if (e < n_cur) ce[u] = qq[e];
-      if (e < n_in) ie[u] = iq[e];
-    }
-#pragma unroll
-    for (int u = 0; u < kQBatch; ++u) {
-      if (ce[u].x != 0xFFFFFFFFu) lds_add<Acc>(&s_in[ce[u].x & 1023u], ce[u].w);
-      if (ie[u].x != 0xFFFFFFFFu && (ie[u].x >> 10) == 0u)  // delay d_min = 1
-        lds_add<Acc>(&s_in[ie[u].x & 1023u], ie[u].w);
-    }
-  }
+  if (sizeof(Acc) == 4 && a.q_packed)
+    gather_batches<Acc, true>(static_cast<const uint32_t*>(a.q_q) + qo, iq, n_cur, n_in, s_in);
+  else
+    gather_batches<Acc, false>(static_cast<const QEntry<Acc>*>(a.q_q) + qo, iq, n_cur, n_in,
+                               s_in);
   lds_barrier();
   // every thread has used the count and the slot mark: the current queue
   // is empty and the slot cleared now
@@ -426,11 +455,16 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
       const int s2 = L.ss[e];
       const uint32_t gpos = L.qc[s2] + (e - L.off[s2]);
       if (gpos < (uint32_t)a.q_cap) {
-        QEntry<Acc> q;
-        q.x = L.sx[e];
-        q.w = L.sw[e];
-        if (sizeof(QEntry<Acc>) == 16) reinterpret_cast<uint32_t*>(&q)[1] = 0u;
-        qw[qb + (int64_t)s2 * a.q_cap + gpos] = q;
+        if (sizeof(Acc) == 4 && a.q_packed) {
+          static_cast<uint32_t*>(a.q_q)[qb + (int64_t)s2 * a.q_cap + gpos] =
+              pack_entry((int32_t)L.sw[e], L.sx[e]);
+        } else {
+          QEntry<Acc> q;
+          q.x = L.sx[e];
+          q.w = L.sw[e];
+          if (sizeof(QEntry<Acc>) == 16) reinterpret_cast<uint32_t*>(&q)[1] = 0u;
+          qw[qb + (int64_t)s2 * a.q_cap + gpos] = q;
+        }
       } else {
         atomic_add_fix<Acc>(slots + (int64_t)s2 * a.N_pad + (int64_t)tile * 1024 + L.sx[e],
                             L.sw[e]);
@@ -1005,9 +1039,18 @@ __global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
     const uint32_t n = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
     const int64_t qc = qb + (int64_t)k * a.q_cap;
     for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
-      const QEntry<Acc> q = qq[qc + e];
-      atomic_add_fix<Acc>(slots + (int64_t)k * a.N_pad + (int64_t)tile * 1024 + (q.x & 1023u),
-                          q.w);
+      uint32_t x;
+      Acc w;
+      if (sizeof(Acc) == 4 && a.q_packed) {
+        const uint32_t v = static_cast<const uint32_t*>(a.q_q)[qc + e];
+        x = v;
+        w = (Acc)packed_w(v);
+      } else {
+        const QEntry<Acc> q = qq[qc + e];
+        x = q.x;
+        w = q.w;
+      }
+      atomic_add_fix<Acc>(slots + (int64_t)k * a.N_pad + (int64_t)tile * 1024 + (x & 1023u), w);
     }
   }
   __syncthreads();

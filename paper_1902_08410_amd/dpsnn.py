@@ -69,7 +69,7 @@ class DpsnnStats(C.Structure):
         ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("schedule", C.c_int32),
         ("n_index", C.c_int64), ("n_nets", C.c_int32), ("queue_cap", C.c_int32),
         ("deliver_blocks", C.c_int32), ("route_blocks", C.c_int32),
-        ("n_pops", C.c_int32), ("reserved", C.c_int32),
+        ("n_pops", C.c_int32), ("queue_entry_bytes", C.c_int32),
     ]
 
 
