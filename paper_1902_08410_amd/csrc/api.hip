@@ -177,11 +177,11 @@ int build_impl(dpsnn_net* n) {
                           : p.weight_dtype == DPSNN_W_F16 ? (const void*)T.wt16[q][bb].data()
                                                           : (const void*)T.wq8[q][bb].data();
         HIP_OK(hipMemcpyAsync(wtab[q][bb], src, (size_t)kQuantN * wb, hipMemcpyHostToDevice, st));
+        for (int64_t v : fix_table(p, T, q, bb)) max_fix = std::max<int64_t>(max_fix, v < 0 ? -v : v);
         if (absum) {
           wfix_dev[q][bb] = (int64_t*)dev_alloc(n, (size_t)kQuantN * 8);
           if (!wfix_dev[q][bb]) return DPSNN_E_NOMEM;
           wf.push_back(fix_table(p, T, q, bb));
-          for (int64_t v : wf.back()) max_fix = std::max<int64_t>(max_fix, v < 0 ? -v : v);
           HIP_OK(hipMemcpyAsync(wfix_dev[q][bb], wf.back().data(), (size_t)kQuantN * 8,
                                 hipMemcpyHostToDevice, st));
         }
@@ -341,7 +341,12 @@ int build_impl(dpsnn_net* n) {
   int64_t qcap = p0.queue_cap == 0 ? kQueueDefaultCap
                  : p0.queue_cap < 0 ? 0 : p0.queue_cap;
   if (p0.K_out == 0 || T0.D > kQueueMaxSlots) qcap = 0;
-  const int64_t per_cap = (int64_t)n_tiles * (T0.D + 4) * (ab == 4 ? 8 : 16);  // bytes per unit of cap
+  const int64_t per_cap = (int64_t)n_tiles * (T0.D + 4) * 8;  // bytes per unit of cap
+  // int64 entries hold efficacies below 2^46 in fixed point (a plastic
+  // efficacy up to w_max); past that, no queues
+  const int64_t wmax_fix =
+      p0.plastic ? (int64_t)llrint(ldexp(p0.stdp_w_max, p0.q_frac_bits)) : 0;
+  if (ab == 8 && (max_fix >= kQEntry64Max || wmax_fix >= kQEntry64Max)) qcap = 0;
   if (p0.queue_cap == 0 && qcap > 0) {
     const int64_t budget = (int64_t)16 << 30;
     qcap = std::min(qcap, budget / std::max<int64_t>(per_cap, 1));
@@ -366,9 +371,7 @@ int build_impl(dpsnn_net* n) {
     HIP_OK(hipStreamSynchronize(st));
     // 4-byte queue entries when every efficacy (and a plastic one's
     // largest value) fits 21 bits
-    const int64_t wmax_fix =
-        p0.plastic ? (int64_t)llrint(ldexp(p0.stdp_w_max, p0.q_frac_bits)) : 0;
-    a.q_packed = ab == 4 && absum && max_fix < (1 << 21) && wmax_fix < (1 << 21);
+    a.q_packed = ab == 4 && max_fix < (1 << 21) && wmax_fix < (1 << 21);
     n->bytes_state += (int64_t)((n_in + n_q) * eb) +
                       (2 * n_tiles * kInboxStride + 2 * n_tiles * T0.D) * 4;
   }

@@ -22,20 +22,37 @@ constexpr int kQueueDefaultCap = 4096; // entries per (tile, slot) queue
 constexpr int kInboxStride = 16;       // inbox counters 64 bytes apart
 constexpr int kStage = 2048;           // LDS staging of a tile's routed events
 
-// Queue entry: one 8-byte (int32 slots) or 16-byte (int64) word.
+// Queue entry, 8 bytes: x = in-tile index | delay index << 10 (17 bits at
+// most) and the fixed-point efficacy w.  int32 inputs: two words; int64
+// inputs: one word w << 17 | x (efficacies below 2^46 in fixed point; the
+// build checks, and uses no queues otherwise).
 template <typename Acc>
 struct QEntry;
 template <>
 struct __attribute__((aligned(8))) QEntry<int32_t> {
-  uint32_t x;
-  int32_t w;
+  uint32_t xv;
+  int32_t wv;
+  __host__ __device__ uint32_t x() const { return xv; }
+  __host__ __device__ int32_t w() const { return wv; }
+  __host__ __device__ static QEntry make(uint32_t x, int32_t w) {
+    QEntry q;
+    q.xv = x;
+    q.wv = w;
+    return q;
+  }
 };
 template <>
-struct __attribute__((aligned(16))) QEntry<int64_t> {
-  uint32_t x;
-  uint32_t pad;
-  int64_t w;
+struct __attribute__((aligned(8))) QEntry<int64_t> {
+  uint64_t v;
+  __host__ __device__ uint32_t x() const { return (uint32_t)(v & 0x1FFFFu); }
+  __host__ __device__ int64_t w() const { return (int64_t)v >> 17; }
+  __host__ __device__ static QEntry make(uint32_t x, int64_t w) {
+    QEntry q;
+    q.v = ((uint64_t)w << 17) | x;
+    return q;
+  }
 };
+constexpr int64_t kQEntry64Max = (int64_t)1 << 46;  // |w| bound of the int64 entry
 
 constexpr int kMaxPops = 4;     // populations per module
 constexpr int kMaxAttempts = 64; // draws of a module inside open boundaries

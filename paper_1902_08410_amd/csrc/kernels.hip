@@ -303,8 +303,6 @@ __device__ __forceinline__ void gather_batches(const void* qbase, const QEntry<A
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      ce[u].x = 0xFFFFFFFFu;
-      ie[u].x = 0xFFFFFFFFu;
       if (PK) {
         if (e < n_cur) cp[u] = static_cast<const uint32_t*>(qbase)[e];
       } else if (e < n_cur) {
@@ -315,13 +313,14 @@ __device__ __forceinline__ void gather_batches(const void* qbase, const QEntry<A
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      if (PK) {
-        if (e < n_cur) lds_add<Acc>(&s_in[cp[u] & 1023u], (Acc)packed_w(cp[u]));
-      } else if (ce[u].x != 0xFFFFFFFFu) {
-        lds_add<Acc>(&s_in[ce[u].x & 1023u], ce[u].w);
+      if (e < n_cur) {
+        if (PK)
+          lds_add<Acc>(&s_in[cp[u] & 1023u], (Acc)packed_w(cp[u]));
+        else
+          lds_add<Acc>(&s_in[ce[u].x() & 1023u], ce[u].w());
       }
-      if (ie[u].x != 0xFFFFFFFFu && (ie[u].x >> 10) == 0u)  // delay d_min = 1
-        lds_add<Acc>(&s_in[ie[u].x & 1023u], ie[u].w);
+      if (e < n_in && (ie[u].x() >> 10) == 0u)  // delay d_min = 1
+        lds_add<Acc>(&s_in[ie[u].x() & 1023u], ie[u].w());
     }
   }
 }
@@ -400,14 +399,13 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      ie[u].x = 0xFFFFFFFFu;
       if (e < n_in) ie[u] = iq[e];
     }
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       sl[u] = -1;
-      if (ie[u].x != 0xFFFFFFFFu) {
-        const uint32_t x = ie[u].x;
+      if (r0 + (uint32_t)(u * nth + tid) < n_in) {
+        const uint32_t x = ie[u].x();
         const int dk = (int)(x >> 10) < a.n_del ? (int)(x >> 10) : a.n_del - 1;
         const int off = a.d_min + dk - 1;  // arrival in off steps: 0 .. D - 2
         if (off > 0) {
@@ -437,14 +435,14 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
     for (int u = 0; u < kQBatch; ++u) {
       if (sl[u] < 0) continue;
       const uint32_t sp = L.off[sl[u]] + rk[u];
-      const uint32_t idx = ie[u].x & 1023u;
+      const uint32_t idx = ie[u].x() & 1023u;
       if (sp < (uint32_t)kStage) {
         L.sx[sp] = (uint16_t)idx;
         L.ss[sp] = (uint8_t)sl[u];
-        L.sw[sp] = ie[u].w;
+        L.sw[sp] = ie[u].w();
       } else {
         atomic_add_fix<Acc>(slots + (int64_t)sl[u] * a.N_pad + (int64_t)tile * 1024 + idx,
-                            ie[u].w);
+                            ie[u].w());
         a.s_dirty[(int64_t)tile * D + sl[u]] = 1u;
       }
     }
@@ -459,11 +457,7 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
           static_cast<uint32_t*>(a.q_q)[qb + (int64_t)s2 * a.q_cap + gpos] =
               pack_entry((int32_t)L.sw[e], L.sx[e]);
         } else {
-          QEntry<Acc> q;
-          q.x = L.sx[e];
-          q.w = L.sw[e];
-          if (sizeof(QEntry<Acc>) == 16) reinterpret_cast<uint32_t*>(&q)[1] = 0u;
-          qw[qb + (int64_t)s2 * a.q_cap + gpos] = q;
+          qw[qb + (int64_t)s2 * a.q_cap + gpos] = QEntry<Acc>::make(L.sx[e], L.sw[e]);
         }
       } else {
         atomic_add_fix<Acc>(slots + (int64_t)s2 * a.N_pad + (int64_t)tile * 1024 + L.sx[e],
@@ -833,11 +827,8 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
       const int32_t target = tv[j] & kTargetMask;
       const uint32_t dk = (uint32_t)tv[j] >> kDelayShift;
       if (pos < (uint32_t)a.in_cap) {
-        QEntry<Acc> q;
-        q.x = (uint32_t)(target & 1023) | (dk << 10);
-        q.w = wv[j];
-        if (sizeof(QEntry<Acc>) == 16) reinterpret_cast<uint32_t*>(&q)[1] = 0u;
-        iq[((int64_t)par * a.n_tiles + tl[j]) * a.in_cap + pos] = q;
+        iq[((int64_t)par * a.n_tiles + tl[j]) * a.in_cap + pos] =
+            QEntry<Acc>::make((uint32_t)(target & 1023) | (dk << 10), wv[j]);
       } else {
         int sl = slot0 + (int)dk;
         if (sl >= a.D) sl -= a.D;
@@ -1026,11 +1017,11 @@ __global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
   const QEntry<Acc>* iq = static_cast<const QEntry<Acc>*>(a.in_q);
   for (uint32_t e = threadIdx.x; e < n_in; e += blockDim.x) {
     const QEntry<Acc> q = iq[ib + e];
-    const int dk = (int)(q.x >> 10) < a.n_del ? (int)(q.x >> 10) : a.n_del - 1;
+    const int dk = (int)(q.x() >> 10) < a.n_del ? (int)(q.x() >> 10) : a.n_del - 1;
     // emitted at t - 1, arrives at t - 1 + d_min + dk
     const int sl = (int)(((uint64_t)t + (uint64_t)(a.d_min + dk) - 1u) % (uint64_t)D);
-    atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + (int64_t)tile * 1024 + (q.x & 1023u),
-                        q.w);
+    atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + (int64_t)tile * 1024 + (q.x() & 1023u),
+                        q.w());
   }
   const int64_t qb = (int64_t)tile * D * a.q_cap;
   const QEntry<Acc>* qq = static_cast<const QEntry<Acc>*>(a.q_q);
@@ -1047,8 +1038,8 @@ __global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
         w = (Acc)packed_w(v);
       } else {
         const QEntry<Acc> q = qq[qc + e];
-        x = q.x;
-        w = q.w;
+        x = q.x();
+        w = q.w();
       }
       atomic_add_fix<Acc>(slots + (int64_t)k * a.N_pad + (int64_t)tile * 1024 + (x & 1023u), w);
     }

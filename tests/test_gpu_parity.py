@@ -553,15 +553,16 @@ def test_population_batch_matches_solo_runs(L):
 
 def test_queue_entry_formats(L):
     """4-byte queue entries when every fixed-point efficacy fits 21 bits
-    (the benchmark's networks), 8 bytes otherwise (int32), 16 with int64
-    inputs; the 8-byte form stays bit-exact (efficacies of up to 40 mV)."""
+    (the benchmark's networks), 8 bytes otherwise: two words with int32
+    inputs (bit-exact with efficacies of up to 40 mV), one packed word with
+    int64 inputs."""
     _say("queue entry formats")
     p = W.tiny(2, 2, K=64, K_out=32)
     net = L.dpsnn_build(dict(p, spike_log_cap=1 << 20), 1)
     assert net.stats()["queue_entry_bytes"] == 4
     net.close()
     net = L.dpsnn_build(dict(p, acc_bits=64, q_frac_bits=32, spike_log_cap=1 << 20), 1)
-    assert net.stats()["queue_entry_bytes"] == 16
+    assert net.stats()["queue_entry_bytes"] == 8
     net.close()
     big = dict(p, J_mean=[35.0, -40.0], J_sd=[5.0, 5.0])
     net, orc = _pair(big, 4)
