@@ -727,7 +727,8 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   if (!n->sa.plastic) cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks});
   if (n->split_ok) {
     const int32_t tiles = n->sa.n_tiles;
-    for (int32_t b : {std::min<int32_t>(1024, std::max<int32_t>(256, tiles)), 512, 1024, 2048}) {
+    for (int32_t b : {std::min<int32_t>(1024, std::max<int32_t>(256, tiles)), 256, 512, 1024,
+                      2048}) {
       bool seen = false;
       for (const Cand& c : cands) seen |= c.sched == DPSNN_SCHED_SPLIT && c.blocks == b;
       if (!seen) cands.push_back({DPSNN_SCHED_SPLIT, b});
