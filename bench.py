@@ -379,6 +379,11 @@ def main():
     alg_del = ev_per_launch * Be
     achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
     n_mean = sum(neurons.values()) / len(neurons)
+    # whole-step bound: every neuron-step and every event of the timed window
+    # at its algorithmic bytes, over the wall time of the window
+    step_bytes = sum(neurons[k] * steps * S * bytes_per_neuron_step(nets[k][1])
+                     + spikes[k] * K_OUT * bytes_per_event(nets[k][1]) for k in nets)
+    step_gbs = step_bytes / wall / 1e9
     traffic = None
     rec = recorded_traffic() if wl == "grid24" else None
     if rec and "k_deliver" in rec["kernels"]:
@@ -427,6 +432,10 @@ def main():
                               if upd_us else None,
                               "bytes_per_neuron_step": Bn},
             "step_us": gpu_ms * 1e3 / (n_steps_all / max(1, len(nets))) / max(1, len(nets)),
+            "whole_step": {"algorithmic_bytes": step_bytes,
+                           "achieved_GB_s": step_gbs,
+                           "frac": step_gbs / HBM_PEAK_GBS,
+                           "bound_events_per_s": value / (step_gbs / HBM_PEAK_GBS)},
         },
         "cpu_baseline": cpu,
         "per_handle": {k: {"spikes": spikes[k], "rate_hz": rates[k],
