@@ -176,8 +176,10 @@ typedef struct dpsnn_stats {
   int32_t deliver_blocks; /* grid of the split schedule's delivery kernel  */
   int32_t route_blocks;   /* inbox-routing blocks beside it               */
   int32_t n_pops;         /* populations per module (rate-bin stride)     */
-  int32_t queue_entry_bytes; /* bytes per per-slot queue entry: 4 (packed:
-                             every efficacy fits 21 bits), 8, 16, 0 = none */
+  int32_t queue_entry_bytes; /* bytes per per-slot queue entry: 4 (binary16
+                             or int8 efficacy codes; binary32 efficacies
+                             that all fit 21 bits in fixed point), else 8;
+                             0 = no queues                                */
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */

@@ -341,12 +341,20 @@ int build_impl(dpsnn_net* n) {
   int64_t qcap = p0.queue_cap == 0 ? kQueueDefaultCap
                  : p0.queue_cap < 0 ? 0 : p0.queue_cap;
   if (p0.K_out == 0 || T0.D > kQueueMaxSlots) qcap = 0;
-  const int64_t per_cap = (int64_t)n_tiles * (T0.D + 4) * 8;  // bytes per unit of cap
+  // binary16 and int8 efficacies travel as their stored codes (4-byte code
+  // entries, whatever the slot width); binary32 ones in fixed point
+  const int q_code = p0.weight_dtype == DPSNN_W_F16 ? kCodeF16
+                     : p0.weight_dtype == DPSNN_W_I8 ? kCodeI8
+                                                     : 0;
+  const size_t eb = q_code      ? 4
+                    : ab == 4   ? sizeof(QEntry<int32_t>)
+                                : sizeof(QEntry<int64_t>);
+  const int64_t per_cap = (int64_t)n_tiles * (T0.D + 4) * (int64_t)eb;  // bytes per unit of cap
   // int64 entries hold efficacies below 2^46 in fixed point (a plastic
   // efficacy up to w_max); past that, no queues
   const int64_t wmax_fix =
       p0.plastic ? (int64_t)llrint(ldexp(p0.stdp_w_max, p0.q_frac_bits)) : 0;
-  if (ab == 8 && (max_fix >= kQEntry64Max || wmax_fix >= kQEntry64Max)) qcap = 0;
+  if (!q_code && ab == 8 && (max_fix >= kQEntry64Max || wmax_fix >= kQEntry64Max)) qcap = 0;
   if (p0.queue_cap == 0 && qcap > 0) {
     const int64_t budget = (int64_t)16 << 30;
     qcap = std::min(qcap, budget / std::max<int64_t>(per_cap, 1));
@@ -356,7 +364,6 @@ int build_impl(dpsnn_net* n) {
     a.q_cap = (int32_t)qcap;
     a.in_cap = (int32_t)(2 * qcap);
     a.route_blocks = (int32_t)std::min<int64_t>(n_tiles, 4096);
-    const size_t eb = ab == 4 ? sizeof(QEntry<int32_t>) : sizeof(QEntry<int64_t>);
     const size_t n_in = (size_t)2 * n_tiles * a.in_cap;
     const size_t n_q = (size_t)n_tiles * T0.D * qcap;
     a.in_cnt = (uint32_t*)dev_alloc(n, (size_t)2 * n_tiles * kInboxStride * 4);
@@ -372,6 +379,7 @@ int build_impl(dpsnn_net* n) {
     // 4-byte queue entries when every efficacy (and a plastic one's
     // largest value) fits 21 bits
     a.q_packed = ab == 4 && max_fix < (1 << 21) && wmax_fix < (1 << 21);
+    a.q_code = q_code;
     n->bytes_state += (int64_t)((n_in + n_q) * eb) +
                       (2 * n_tiles * kInboxStride + 2 * n_tiles * T0.D) * 4;
   }
@@ -907,7 +915,7 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->route_blocks = n->sa.route_blocks;
   out->n_pops = n->sa.P;
   out->queue_entry_bytes = n->sa.q_cap == 0 ? 0
-                           : n->sa.q_packed ? 4
+                           : n->sa.q_code || n->sa.q_packed ? 4
                            : (acc_bytes(n->p[0]) == 4 ? (int32_t)sizeof(QEntry<int32_t>)
                                                       : (int32_t)sizeof(QEntry<int64_t>));
   return DPSNN_OK;

@@ -54,6 +54,19 @@ struct __attribute__((aligned(8))) QEntry<int64_t> {
 };
 constexpr int64_t kQEntry64Max = (int64_t)1 << 46;  // |w| bound of the int64 entry
 
+// Code entry, 4 bytes, for binary16 and int8 efficacies: the stored
+// efficacy code << 16 | delay index << 10 | in-tile index, the code being
+// the binary16 bits, or the int8 code | source population << 8.  The
+// consumer converts the code to fixed point exactly as delivery does (the
+// int8 scale of a source population is the same in every module of a
+// network), so the sums do not change.
+constexpr int kCodeShift = 16;
+constexpr int kCodeF16 = 1;     // StepArgs::q_code
+constexpr int kCodeI8 = 2;
+__host__ __device__ inline uint32_t code_entry(uint32_t code, uint32_t x) {
+  return (code << kCodeShift) | x;
+}
+
 constexpr int kMaxPops = 4;     // populations per module
 constexpr int kMaxAttempts = 64; // draws of a module inside open boundaries
 // how a block of a source's synapses picks the target module
@@ -171,6 +184,8 @@ struct StepArgs {
   int32_t q_cap, in_cap;
   int32_t q_packed;        // queue entries packed in 4 bytes (int32 inputs
                            // whose efficacies all fit 21 bits: w << 10 | idx)
+  int32_t q_code;          // 0, or kCodeF16 / kCodeI8: inbox and queue entries
+                           // are code entries (takes precedence over q_packed)
   uint32_t* in_cnt;        // [2][n_tiles * kInboxStride] (may exceed in_cap)
   void* in_q;              // [2][n_tiles][in_cap] entries
   uint32_t* q_cnt;         // [n_tiles][D], written by the owning tile only

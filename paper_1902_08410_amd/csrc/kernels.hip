@@ -40,6 +40,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dpsnn_internal.h"
 #include "philox.h"
@@ -274,6 +275,70 @@ __device__ __forceinline__ void lds_add<int64_t>(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 
+// Fixed-point efficacy of a code entry, computed as delivery computes it
+// from the stored code (same conversions, same int8 scale).
+template <typename Acc>
+struct CodeDec {
+  float two_q;
+  int f16;
+  Acc sc[kMaxPops];  // int8 scale of each source population of the network
+  __device__ __forceinline__ Acc operator()(uint32_t e) const {
+    const uint32_t code = e >> kCodeShift;
+    if (f16) {
+      __half_raw r;
+      r.x = (unsigned short)code;
+      return (Acc)__builtin_rintf(__half2float(__half(r)) * two_q);
+    }
+    const Acc q = (Acc)(int8_t)(uint8_t)(code & 0xFFu);
+    const uint32_t pop = (code >> 8) & 3u;
+    const Acc s = pop == 0u ? sc[0] : pop == 1u ? sc[1] : pop == 2u ? sc[2] : sc[3];
+    return q * s;
+  }
+};
+
+// Decoder for the entries of tile `tile` (uniform loads).
+template <typename Acc>
+__device__ __forceinline__ CodeDec<Acc> code_dec(const StepArgs& a, int tile) {
+  CodeDec<Acc> d;
+  d.two_q = a.two_q;
+  d.f16 = a.q_code == kCodeF16;
+#pragma unroll
+  for (int q = 0; q < kMaxPops; ++q) d.sc[q] = 0;
+  if (a.q_code == kCodeI8) {
+    const int64_t b = (int64_t)a.P * a.nets[a.tile_net[tile]].mbase;
+#pragma unroll
+    for (int q = 0; q < kMaxPops; ++q)
+      if (q < a.P) d.sc[q] = (Acc)a.sfix[b + q];
+  }
+  return d;
+}
+
+// Entry views: the in-tile index | delay index << 10 (x) and the
+// fixed-point efficacy (w) of each format.  Packed queue entries carry no
+// delay index.
+struct PackedEntry {
+  uint32_t v;
+};
+struct CodeEntry {
+  uint32_t v;
+};
+template <typename Acc>
+__device__ __forceinline__ uint32_t ent_x(const QEntry<Acc>& e) { return e.x(); }
+__device__ __forceinline__ uint32_t ent_x(PackedEntry e) { return e.v & 1023u; }
+__device__ __forceinline__ uint32_t ent_x(CodeEntry e) { return e.v & 0xFFFFu; }
+template <typename Acc>
+__device__ __forceinline__ Acc ent_w(const QEntry<Acc>& e, const CodeDec<Acc>&) {
+  return e.w();
+}
+template <typename Acc>
+__device__ __forceinline__ Acc ent_w(PackedEntry e, const CodeDec<Acc>&) {
+  return (Acc)((int32_t)e.v >> 10);
+}
+template <typename Acc>
+__device__ __forceinline__ Acc ent_w(CodeEntry e, const CodeDec<Acc>& d) {
+  return d(e.v);
+}
+
 // Event queues of one tile.  At step t the tile sums the queue of slot
 // t mod D and the events of its inbox of step t-1 that arrive now
 // (gather_now, before the neuron update); the other events of that inbox are
@@ -288,39 +353,30 @@ constexpr int kQBatch = 8;
 __device__ __forceinline__ uint32_t pack_entry(int32_t w, uint32_t idx) {
   return ((uint32_t)w << 10) | idx;
 }
-__device__ __forceinline__ int32_t packed_w(uint32_t v) { return (int32_t)v >> 10; }
 
-// The batches of gather_now: the current queue (packed or not) and the
-// inbox of step t-1, kQBatch entries per thread at a time.
-template <typename Acc, bool PK>
-__device__ __forceinline__ void gather_batches(const void* qbase, const QEntry<Acc>* iq,
-                                               uint32_t n_cur, uint32_t n_in, Acc* s_in) {
+// The batches of gather_now: the current queue (entries CE) and the inbox
+// of step t-1 (entries IE), kQBatch entries per thread at a time.
+template <typename Acc, typename CE, typename IE>
+__device__ __forceinline__ void gather_batches(const CE* cq, const IE* iq, uint32_t n_cur,
+                                               uint32_t n_in, Acc* s_in,
+                                               const CodeDec<Acc>& dec) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const uint32_t n_max = n_cur > n_in ? n_cur : n_in;
   for (uint32_t r0 = 0; r0 < n_max; r0 += (uint32_t)nth * kQBatch) {
-    QEntry<Acc> ce[kQBatch], ie[kQBatch];
-    uint32_t cp[kQBatch];
+    CE ce[kQBatch];
+    IE ie[kQBatch];
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      if (PK) {
-        if (e < n_cur) cp[u] = static_cast<const uint32_t*>(qbase)[e];
-      } else if (e < n_cur) {
-        ce[u] = static_cast<const QEntry<Acc>*>(qbase)[e];
-      }
+      if (e < n_cur) ce[u] = cq[e];
       if (e < n_in) ie[u] = iq[e];
     }
 #pragma unroll
     for (int u = 0; u < kQBatch; ++u) {
       const uint32_t e = r0 + (uint32_t)(u * nth + tid);
-      if (e < n_cur) {
-        if (PK)
-          lds_add<Acc>(&s_in[cp[u] & 1023u], (Acc)packed_w(cp[u]));
-        else
-          lds_add<Acc>(&s_in[ce[u].x() & 1023u], ce[u].w());
-      }
-      if (e < n_in && (ie[u].x() >> 10) == 0u)  // delay d_min = 1
-        lds_add<Acc>(&s_in[ie[u].x() & 1023u], ie[u].w());
+      if (e < n_cur) lds_add<Acc>(&s_in[ent_x(ce[u]) & 1023u], ent_w<Acc>(ce[u], dec));
+      if (e < n_in && (ent_x(ie[u]) >> 10) == 0u)  // delay d_min = 1
+        lds_add<Acc>(&s_in[ent_x(ie[u]) & 1023u], ent_w<Acc>(ie[u], dec));
     }
   }
 }
@@ -341,13 +397,17 @@ __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t
   for (int k = tid; k < 1024; k += nth) s_in[k] = 0;
   lds_barrier();
   const int64_t qo = ((int64_t)tile * D + cur) * a.q_cap;
-  const QEntry<Acc>* iq =
-      static_cast<const QEntry<Acc>*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
-  if (sizeof(Acc) == 4 && a.q_packed)
-    gather_batches<Acc, true>(static_cast<const uint32_t*>(a.q_q) + qo, iq, n_cur, n_in, s_in);
+  const int64_t io = ((int64_t)par * a.n_tiles + tile) * a.in_cap;
+  const CodeDec<Acc> dec = code_dec<Acc>(a, tile);
+  if (a.q_code)
+    gather_batches<Acc>(static_cast<const CodeEntry*>(a.q_q) + qo,
+                        static_cast<const CodeEntry*>(a.in_q) + io, n_cur, n_in, s_in, dec);
+  else if (sizeof(Acc) == 4 && a.q_packed)
+    gather_batches<Acc>(static_cast<const PackedEntry*>(a.q_q) + qo,
+                        static_cast<const QEntry<Acc>*>(a.in_q) + io, n_cur, n_in, s_in, dec);
   else
-    gather_batches<Acc, false>(static_cast<const QEntry<Acc>*>(a.q_q) + qo, iq, n_cur, n_in,
-                               s_in);
+    gather_batches<Acc>(static_cast<const QEntry<Acc>*>(a.q_q) + qo,
+                        static_cast<const QEntry<Acc>*>(a.in_q) + io, n_cur, n_in, s_in, dec);
   lds_barrier();
   // every thread has used the count and the slot mark: the current queue
   // is empty and the slot cleared now
@@ -372,9 +432,10 @@ struct RouteLds {
 // tile's per-slot queues, one contiguous run per slot (past the staging
 // space or a full queue they are added into the slot), and empties the
 // inbox.  The queue of slot t mod D is neither read nor written.
-template <typename Acc>
-__device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_t t,
-                                            RouteLds<Acc>& L) {
+template <typename Acc, typename IE>
+__device__ __forceinline__ void route_entries(const StepArgs& a, int tile, uint32_t t,
+                                              RouteLds<Acc>& L) {
+  constexpr bool CODE = std::is_same<IE, CodeEntry>::value;
   const int D = a.D;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int cur = (int)(t % (uint32_t)D);
@@ -388,12 +449,12 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
   }
   lds_barrier();
   Acc* slots = static_cast<Acc*>(a.slots);
-  const QEntry<Acc>* iq =
-      static_cast<const QEntry<Acc>*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
+  const IE* iq = static_cast<const IE*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
   QEntry<Acc>* qw = static_cast<QEntry<Acc>*>(a.q_q);
   const int64_t qb = (int64_t)tile * D * a.q_cap;
+  const CodeDec<Acc> dec = code_dec<Acc>(a, tile);
   for (uint32_t r0 = 0; r0 < n_in; r0 += (uint32_t)nth * kQBatch) {
-    QEntry<Acc> ie[kQBatch];
+    IE ie[kQBatch];
     int sl[kQBatch];
     uint32_t rk[kQBatch];
 #pragma unroll
@@ -405,7 +466,7 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
     for (int u = 0; u < kQBatch; ++u) {
       sl[u] = -1;
       if (r0 + (uint32_t)(u * nth + tid) < n_in) {
-        const uint32_t x = ie[u].x();
+        const uint32_t x = ent_x(ie[u]);
         const int dk = (int)(x >> 10) < a.n_del ? (int)(x >> 10) : a.n_del - 1;
         const int off = a.d_min + dk - 1;  // arrival in off steps: 0 .. D - 2
         if (off > 0) {
@@ -435,14 +496,17 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
     for (int u = 0; u < kQBatch; ++u) {
       if (sl[u] < 0) continue;
       const uint32_t sp = L.off[sl[u]] + rk[u];
-      const uint32_t idx = ie[u].x() & 1023u;
+      const uint32_t idx = ent_x(ie[u]) & 1023u;
       if (sp < (uint32_t)kStage) {
         L.sx[sp] = (uint16_t)idx;
         L.ss[sp] = (uint8_t)sl[u];
-        L.sw[sp] = ie[u].w();
+        if constexpr (CODE)
+          L.sw[sp] = (Acc)ie[u].v;  // the entry itself, moved unchanged
+        else
+          L.sw[sp] = ie[u].w();
       } else {
         atomic_add_fix<Acc>(slots + (int64_t)sl[u] * a.N_pad + (int64_t)tile * 1024 + idx,
-                            ie[u].w());
+                            ent_w<Acc>(ie[u], dec));
         a.s_dirty[(int64_t)tile * D + sl[u]] = 1u;
       }
     }
@@ -453,15 +517,17 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
       const int s2 = L.ss[e];
       const uint32_t gpos = L.qc[s2] + (e - L.off[s2]);
       if (gpos < (uint32_t)a.q_cap) {
-        if (sizeof(Acc) == 4 && a.q_packed) {
+        if (CODE) {
+          static_cast<uint32_t*>(a.q_q)[qb + (int64_t)s2 * a.q_cap + gpos] = (uint32_t)L.sw[e];
+        } else if (sizeof(Acc) == 4 && a.q_packed) {
           static_cast<uint32_t*>(a.q_q)[qb + (int64_t)s2 * a.q_cap + gpos] =
               pack_entry((int32_t)L.sw[e], L.sx[e]);
         } else {
           qw[qb + (int64_t)s2 * a.q_cap + gpos] = QEntry<Acc>::make(L.sx[e], L.sw[e]);
         }
       } else {
-        atomic_add_fix<Acc>(slots + (int64_t)s2 * a.N_pad + (int64_t)tile * 1024 + L.sx[e],
-                            L.sw[e]);
+        const Acc w = CODE ? dec((uint32_t)L.sw[e]) : L.sw[e];
+        atomic_add_fix<Acc>(slots + (int64_t)s2 * a.N_pad + (int64_t)tile * 1024 + L.sx[e], w);
         a.s_dirty[(int64_t)tile * D + s2] = 1u;
       }
     }
@@ -480,6 +546,15 @@ __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_
   if (tid == 0) a.in_cnt[ic] = 0;
   for (int k = tid; k < D; k += nth)
     if (k != cur) a.q_cnt[(int64_t)tile * D + k] = L.qc[k];
+}
+
+template <typename Acc>
+__device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_t t,
+                                            RouteLds<Acc>& L) {
+  if (a.q_code)
+    route_entries<Acc, CodeEntry>(a, tile, t, L);
+  else
+    route_entries<Acc, QEntry<Acc>>(a, tile, t, L);
 }
 
 // Entry q of a four-entry array of uniform values, without indexing; the
@@ -701,15 +776,16 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
                                               uint32_t t, int lane, uint32_t* s_b) {
   const int64_t rb = (int64_t)s * a.row_stride;
   int64_t scale = 0;
+  int q_src = 0;  // source population (int8 codes)
   if (WDT == DPSNN_W_I8) {
     int32_t ms;
-    int q;
-    module_pop(a, s, &ms, &q);
-    scale = a.sfix[(int64_t)a.P * ms + q];
+    module_pop(a, s, &ms, &q_src);
+    scale = a.sfix[(int64_t)a.P * ms + q_src];
   }
   const int p = p0 + lane * 4;
   int tv[4] = {0, 0, 0, 0};
   Acc wv[4] = {0, 0, 0, 0};
+  uint32_t cv[4] = {0, 0, 0, 0};  // efficacy codes of code entries
   if (p < a.K_out) {  // rows are padded to a multiple of 4 words
     const int4 tg = *reinterpret_cast<const int4*>(a.tgt + rb + p);
     tv[0] = tg.x; tv[1] = tg.y; tv[2] = tg.z; tv[3] = tg.w;
@@ -722,8 +798,14 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
       wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
         wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
+        if (WDT == DPSNN_W_F16)
+          cv[j] = static_cast<const uint16_t*>(a.w)[rb + p + j];
+        else
+          cv[j] = (uint32_t)(uint8_t)static_cast<const int8_t*>(a.w)[rb + p + j] |
+                  (uint32_t)q_src << 8;
+      }
     }
   }
   if (PLAST) {
@@ -826,9 +908,13 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
       const uint32_t pos = s_b[rs[j] - p0] + (uint32_t)(p + j - rs[j]);
       const int32_t target = tv[j] & kTargetMask;
       const uint32_t dk = (uint32_t)tv[j] >> kDelayShift;
+      const uint32_t x = (uint32_t)(target & 1023) | (dk << 10);
       if (pos < (uint32_t)a.in_cap) {
-        iq[((int64_t)par * a.n_tiles + tl[j]) * a.in_cap + pos] =
-            QEntry<Acc>::make((uint32_t)(target & 1023) | (dk << 10), wv[j]);
+        const int64_t o = ((int64_t)par * a.n_tiles + tl[j]) * a.in_cap + pos;
+        if (WDT != DPSNN_W_F32 && a.q_code)
+          static_cast<uint32_t*>(a.in_q)[o] = code_entry(cv[j], x);
+        else
+          iq[o] = QEntry<Acc>::make(x, wv[j]);
       } else {
         int sl = slot0 + (int)dk;
         if (sl >= a.D) sl -= a.D;
@@ -1002,46 +1088,33 @@ __global__ void k_tick(uint32_t* t_base, uint32_t n, unsigned long long* log_bas
   }
 }
 
-// Pending queue entries of tile blockIdx.x after t steps added into the
-// slots: the inbox of step t-1 and every per-slot queue; all left empty.
-template <typename Acc>
-__global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
-  const int tile = blockIdx.x;
+// k_drain for one entry format (IE: inbox entries, CE: queue entries).
+template <typename Acc, typename IE, typename CE>
+__device__ __forceinline__ void drain_tile(const StepArgs& a, int tile, uint32_t t,
+                                           const CodeDec<Acc>& dec) {
   const int D = a.D;
   Acc* slots = static_cast<Acc*>(a.slots);
   const uint32_t par = (t - 1u) & 1u;
   const int64_t ic = ((int64_t)par * a.n_tiles + tile) * kInboxStride;
   const uint32_t got = a.in_cnt[ic];
   const uint32_t n_in = got < (uint32_t)a.in_cap ? got : (uint32_t)a.in_cap;
-  const int64_t ib = ((int64_t)par * a.n_tiles + tile) * a.in_cap;
-  const QEntry<Acc>* iq = static_cast<const QEntry<Acc>*>(a.in_q);
+  const IE* iq = static_cast<const IE*>(a.in_q) + ((int64_t)par * a.n_tiles + tile) * a.in_cap;
   for (uint32_t e = threadIdx.x; e < n_in; e += blockDim.x) {
-    const QEntry<Acc> q = iq[ib + e];
-    const int dk = (int)(q.x() >> 10) < a.n_del ? (int)(q.x() >> 10) : a.n_del - 1;
+    const uint32_t x = ent_x(iq[e]);
+    const int dk = (int)(x >> 10) < a.n_del ? (int)(x >> 10) : a.n_del - 1;
     // emitted at t - 1, arrives at t - 1 + d_min + dk
     const int sl = (int)(((uint64_t)t + (uint64_t)(a.d_min + dk) - 1u) % (uint64_t)D);
-    atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + (int64_t)tile * 1024 + (q.x() & 1023u),
-                        q.w());
+    atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + (int64_t)tile * 1024 + (x & 1023u),
+                        ent_w<Acc>(iq[e], dec));
   }
-  const int64_t qb = (int64_t)tile * D * a.q_cap;
-  const QEntry<Acc>* qq = static_cast<const QEntry<Acc>*>(a.q_q);
+  const CE* qq = static_cast<const CE*>(a.q_q) + (int64_t)tile * D * a.q_cap;
   for (int k = 0; k < D; ++k) {
     const uint32_t qn = a.q_cnt[(int64_t)tile * D + k];
     const uint32_t n = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
-    const int64_t qc = qb + (int64_t)k * a.q_cap;
     for (uint32_t e = threadIdx.x; e < n; e += blockDim.x) {
-      uint32_t x;
-      Acc w;
-      if (sizeof(Acc) == 4 && a.q_packed) {
-        const uint32_t v = static_cast<const uint32_t*>(a.q_q)[qc + e];
-        x = v;
-        w = (Acc)packed_w(v);
-      } else {
-        const QEntry<Acc> q = qq[qc + e];
-        x = q.x();
-        w = q.w();
-      }
-      atomic_add_fix<Acc>(slots + (int64_t)k * a.N_pad + (int64_t)tile * 1024 + (x & 1023u), w);
+      const CE q = qq[(int64_t)k * a.q_cap + e];
+      atomic_add_fix<Acc>(slots + (int64_t)k * a.N_pad + (int64_t)tile * 1024 + (ent_x(q) & 1023u),
+                          ent_w<Acc>(q, dec));
     }
   }
   __syncthreads();
@@ -1050,6 +1123,20 @@ __global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
     a.q_cnt[(int64_t)tile * D + k] = 0;
     a.s_dirty[(int64_t)tile * D + k] = 1u;
   }
+}
+
+// Pending queue entries of tile blockIdx.x after t steps added into the
+// slots: the inbox of step t-1 and every per-slot queue; all left empty.
+template <typename Acc>
+__global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
+  const int tile = blockIdx.x;
+  const CodeDec<Acc> dec = code_dec<Acc>(a, tile);
+  if (a.q_code)
+    drain_tile<Acc, CodeEntry, CodeEntry>(a, tile, t, dec);
+  else if (sizeof(Acc) == 4 && a.q_packed)
+    drain_tile<Acc, QEntry<Acc>, PackedEntry>(a, tile, t, dec);
+  else
+    drain_tile<Acc, QEntry<Acc>, QEntry<Acc>>(a, tile, t, dec);
 }
 
 // ------------------------------------------------------------------------

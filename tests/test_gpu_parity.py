@@ -552,10 +552,12 @@ def test_population_batch_matches_solo_runs(L):
 
 
 def test_queue_entry_formats(L):
-    """4-byte queue entries when every fixed-point efficacy fits 21 bits
-    (the benchmark's networks), 8 bytes otherwise: two words with int32
-    inputs (bit-exact with efficacies of up to 40 mV), one packed word with
-    int64 inputs."""
+    """Binary32 efficacies: 4-byte queue entries when every fixed-point
+    efficacy fits 21 bits (the benchmark's networks), 8 bytes otherwise: two
+    words with int32 inputs (bit-exact with efficacies of up to 40 mV), one
+    packed word with int64 inputs.  Binary16 and int8 efficacies: 4-byte
+    code entries with either slot width (bit-exact, both schedules, also
+    with efficacies of up to 40 mV)."""
     _say("queue entry formats")
     p = W.tiny(2, 2, K=64, K_out=32)
     net = L.dpsnn_build(dict(p, spike_log_cap=1 << 20), 1)
@@ -573,3 +575,16 @@ def test_queue_entry_formats(L):
         orc.step(150)
         assert _compare_all(L, net, orc, f"8-byte entries {sched}") > 0
     net.close()
+    for wd in ("f16", "i8"):
+        for acc in (32, 64):
+            q = dict(big, weight_dtype=wd)
+            if acc == 64:
+                q.update(acc_bits=64, q_frac_bits=32)
+            net, orc = _pair(q, 6)
+            assert net.stats()["queue_entry_bytes"] == 4, (wd, acc)
+            for sched in (L.SCHED_SPLIT, L.SCHED_FUSED, L.SCHED_SPLIT):
+                L.dpsnn_set_schedule(net, sched)
+                L.dpsnn_step(net, 100)
+                orc.step(100)
+                assert _compare_all(L, net, orc, f"code entries {wd} {acc} {sched}") > 0
+            net.close()
