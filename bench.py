@@ -302,7 +302,10 @@ def main():
         wave_bench(dpsnn, workloads, torch)
         return
     stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
-    total_bins = (args.warmup + steps) * S // 50 + 400   # + autotune/profile steps
+    # rate bins: warm-up and timed steps, the autotuner's two passes over
+    # at most 11 candidates, the per-kernel timing steps
+    tune_steps = 22 * min(1000, S // 2) if args.autotune else 0
+    total_bins = ((args.warmup + steps) * S + tune_steps + args.profile_steps) // 50 + 100
     sched = {}
     variants = {}
     with torch.cuda.stream(stream):
@@ -442,7 +445,9 @@ def main():
                            "events_per_s": spikes[k] * K_OUT / wall,
                            "build_ms": nets[k][0].stats()["build_ms"],
                            "schedule": "split" if sched[k] == 1 else "fused",
-                           "deliver_blocks": nets[k][0].stats()["deliver_blocks"]}
+                           "deliver_blocks": nets[k][0].stats()["deliver_blocks"],
+                           "spike_lists": "appended" if nets[k][0].stats()["spike_lists"]
+                           else "per tile"}
                        for k in nets},
         "gpu_ms_timed": gpu_ms,
         "weight_variants": variants,

@@ -180,6 +180,8 @@ typedef struct dpsnn_stats {
                              or int8 efficacy codes; binary32 efficacies
                              that all fit 21 bits in fixed point), else 8;
                              0 = no queues                                */
+  int32_t spike_lists;    /* spike lists of the split schedule (see
+                             dpsnn_set_delivery)                          */
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */
@@ -233,19 +235,31 @@ int dpsnn_set_stream(dpsnn_net* net, void* hip_stream);
  */
 int dpsnn_step(dpsnn_net* net, int64_t n_steps);
 
-/* Choose the step schedule (DPSNN_SCHED_*).  SPLIT needs at most 16000
- * tiles of 1024 neurons (else INVAL). */
+/* Choose the step schedule (DPSNN_SCHED_*).  INVAL: an unknown schedule,
+ * or FUSED for a plastic network. */
 int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
+
+/* The split schedule's delivery: grid of the delivery kernel (blocks > 0;
+ * 0 keeps the current one) and the spike lists it reads (0: one list per
+ * tile of 1024 neurons, whose counts every delivery block scans, for at most
+ * 16000 tiles; 1: lists appended by the tiles through 64 counters; -1 keeps
+ * the current kind).  Results do not depend on either.  The default: 1024
+ * blocks at most, per-tile lists up to 2048 tiles.  INVAL otherwise. */
+int dpsnn_set_delivery(dpsnn_net* net, int32_t deliver_blocks, int32_t spike_lists);
 
 /* Steps captured per HIP graph replay (0 disables graphs; graphs are only
  * used on a non-default stream).  Default 128. */
 int dpsnn_set_graph_steps(dpsnn_net* net, int64_t steps);
 
 /*
- * Time probe_steps real steps with each available schedule, and for the
- * split schedule with several grid sizes of the delivery kernel (they
- * advance the simulation; results do not depend on either) and keep the
- * fastest; *chosen (may be NULL) receives the schedule.  Synchronises.
+ * Time real steps with each available schedule, and for the split schedule
+ * with several grid sizes of the delivery kernel and both spike-list kinds
+ * (they advance the simulation; results do not depend on any of them), and
+ * keep the fastest.  Steps run in runs of K (the graph length when graphs
+ * are in use, else min(probe_steps, 128)): one untimed run per candidate,
+ * then max(1, probe_steps / K) rounds of one timed run per candidate, so
+ * that every candidate sees the same mix of activity.  *chosen (may be
+ * NULL) receives the schedule.  Synchronises.
  */
 int dpsnn_autotune(dpsnn_net* net, int64_t probe_steps, int32_t* chosen);
 

@@ -115,19 +115,20 @@ int build_impl(dpsnn_net* n) {
   void* slots = dev_alloc(n, (size_t)T0.D * Np * ab);
   n->bytes_state = Np * 9 + (int64_t)T0.D * Np * ab;
   const int64_t n_tiles = Np / 1024;
-  int32_t* spk = (int32_t*)dev_alloc(n, (size_t)Np * 4);
+  const int64_t spk_cap = (n_tiles + kSpkLists - 1) / kSpkLists * 1024;
+  int32_t* spk = (int32_t*)dev_alloc(n, (size_t)(kSpkLists * spk_cap) * 4);
   int32_t* blk_cnt = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
   int32_t* tile_net = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
   NetDev* nets = (NetDev*)dev_alloc(n, sizeof(NetDev) * nn);
   int2* log = (int2*)dev_alloc(n, (size_t)std::max<int64_t>(p0.spike_log_cap, 1) * 8);
-  unsigned char* ctl = (unsigned char*)dev_alloc(n, 256);
+  unsigned char* ctl = (unsigned char*)dev_alloc(n, 256 + 2 * kSpkLists * kSpkStride * 4);
   unsigned int* rates = (unsigned int*)dev_alloc(n, (size_t)p0.rate_bins_cap * M * P * 4);
   int64_t* sfix = (int64_t*)dev_alloc(n, (size_t)M * P * 8);
   if (!tgt || !w || !V || !c || !ref || !slots || !spk || !blk_cnt || !tile_net ||
       !nets || !log || !ctl || !rates || !sfix)
     return DPSNN_E_NOMEM;
   HIP_OK(hipMemsetAsync(slots, 0, (size_t)T0.D * Np * ab, st));
-  HIP_OK(hipMemsetAsync(ctl, 0, 256, st));
+  HIP_OK(hipMemsetAsync(ctl, 0, 256 + 2 * kSpkLists * kSpkStride * 4, st));
   HIP_OK(hipMemsetAsync(blk_cnt, 0, (size_t)n_tiles * 4, st));
   HIP_OK(hipMemsetAsync(rates, 0, (size_t)p0.rate_bins_cap * M * P * 4, st));
 
@@ -327,11 +328,14 @@ int build_impl(dpsnn_net* n) {
   a.w = w;
   a.sfix = sfix;
   a.spk = spk;
+  a.spk_cap = spk_cap;
   a.blk_cnt = blk_cnt;
+  a.spk_lists = n_tiles > kScanTilesDefault ? 1 : 0;
   a.log = log;
   a.log_base = reinterpret_cast<unsigned long long*>(ctl);
   a.n_spikes = reinterpret_cast<unsigned long long*>(ctl + 16);
   a.t_base = reinterpret_cast<uint32_t*>(ctl + 32);
+  a.spk_n = reinterpret_cast<uint32_t*>(ctl + 256);  // spike-list counters
   a.rates = rates;
   n->ctl = ctl;
 
@@ -383,14 +387,12 @@ int build_impl(dpsnn_net* n) {
     n->bytes_state += (int64_t)((n_in + n_q) * eb) +
                       (2 * n_tiles * kInboxStride + 2 * n_tiles * T0.D) * 4;
   }
-  n->split_ok = n_tiles <= kMaxSplitTiles;
-  n->sched = (n->split_ok && n->N_total >= 65536) ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
+  n->sched = n->N_total >= 65536 ? DPSNN_SCHED_SPLIT : DPSNN_SCHED_FUSED;
 
   // plasticity: per-synapse activation step and signal, per-neuron last
   // spike, the three binary32 tables; the split schedule only (a delivery
   // reads the targets' spike steps of the same step)
   if (p0.plastic) {
-    if (!n->split_ok) return DPSNN_E_INVAL;
     n->sched = DPSNN_SCHED_SPLIT;
     const int32_t L = p0.stdp_update_steps;
     a.plastic = 1;
@@ -632,7 +634,7 @@ void drop_graph(dpsnn_net* n) {
 // counter update; replays then need no host work per step.
 int ensure_graph(dpsnn_net* n) {
   if (n->graph && n->graph_sched == n->sched && n->graph_stream == n->stream &&
-      n->graph_blocks == n->sa.deliver_blocks &&
+      n->graph_blocks == n->sa.deliver_blocks && n->graph_lists == n->sa.spk_lists &&
       n->graph_K == n->graph_steps)
     return DPSNN_OK;
   drop_graph(n);
@@ -656,6 +658,7 @@ int ensure_graph(dpsnn_net* n) {
   n->graph_K = (int)n->graph_steps;
   n->graph_sched = n->sched;
   n->graph_blocks = n->sa.deliver_blocks;
+  n->graph_lists = n->sa.spk_lists;
   n->graph_stream = n->stream;
   return DPSNN_OK;
 }
@@ -666,9 +669,17 @@ extern "C" {
 
 int dpsnn_set_schedule(dpsnn_net* n, int32_t sched) {
   if (!n || (sched != DPSNN_SCHED_FUSED && sched != DPSNN_SCHED_SPLIT)) return DPSNN_E_INVAL;
-  if (sched == DPSNN_SCHED_SPLIT && !n->split_ok) return DPSNN_E_INVAL;
   if (sched == DPSNN_SCHED_FUSED && n->sa.plastic) return DPSNN_E_INVAL;
   n->sched = sched;
+  return DPSNN_OK;
+}
+
+int dpsnn_set_delivery(dpsnn_net* n, int32_t deliver_blocks, int32_t spike_lists) {
+  if (!n || deliver_blocks < 0 || deliver_blocks > (1 << 20) || spike_lists < -1 ||
+      spike_lists > 1 || (spike_lists == 0 && n->sa.n_tiles > kMaxScanTiles))
+    return DPSNN_E_INVAL;
+  if (deliver_blocks > 0) n->sa.deliver_blocks = deliver_blocks;
+  if (spike_lists >= 0) n->sa.spk_lists = spike_lists;
   return DPSNN_OK;
 }
 
@@ -726,48 +737,77 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
 int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   if (!n || probe_steps < 1) return DPSNN_E_INVAL;
   // candidates: the fused schedule, and the split one with several grids of
-  // the delivery kernel
+  // the delivery kernel, each with per-tile and with appended spike lists
   struct Cand {
     int sched;
     int32_t blocks;
+    int32_t lists;
   };
   std::vector<Cand> cands;
-  if (!n->sa.plastic) cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks});
-  if (n->split_ok) {
-    const int32_t tiles = n->sa.n_tiles;
+  if (!n->sa.plastic) cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks, n->sa.spk_lists});
+  const int32_t tiles = n->sa.n_tiles;
+  for (int32_t lists : {0, 1}) {
+    if (!lists && tiles > kMaxScanTiles) continue;
     for (int32_t b : {std::min<int32_t>(1024, std::max<int32_t>(256, tiles)), 256, 512, 1024,
                       2048}) {
       bool seen = false;
-      for (const Cand& c : cands) seen |= c.sched == DPSNN_SCHED_SPLIT && c.blocks == b;
-      if (!seen) cands.push_back({DPSNN_SCHED_SPLIT, b});
+      for (const Cand& c : cands)
+        seen |= c.sched == DPSNN_SCHED_SPLIT && c.blocks == b && c.lists == lists;
+      if (!seen) cands.push_back({DPSNN_SCHED_SPLIT, b, lists});
     }
   }
-  float best_ms = -1.f;
-  Cand best{n->sched, n->sa.deliver_blocks};
-  hipEvent_t e0, e1;
-  HIP_OK(hipEventCreate(&e0));
-  HIP_OK(hipEventCreate(&e1));
-  int rc = DPSNN_OK;
-  for (const Cand& c : cands) {
+  // runs of K steps (whole graph replays when graphs are in use): one
+  // untimed run per candidate, then `rounds` timed runs of every candidate
+  // in turn, so that all of them see the same mix of activity
+  const bool graphs = n->stream && n->graph_steps > 0;
+  const int64_t K = graphs ? n->graph_steps : std::min<int64_t>(probe_steps, 128);
+  const int64_t rounds = std::max<int64_t>(1, probe_steps / K);
+  const size_t nc = cands.size();
+  auto use = [&](const Cand& c) {
     n->sched = c.sched;
     n->sa.deliver_blocks = c.blocks;
-    // one untimed pass builds the graph and warms the caches
-    if ((rc = dpsnn_step(n, probe_steps)) != DPSNN_OK) break;
-    if (hipEventRecord(e0, n->stream) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
-    if ((rc = dpsnn_step(n, probe_steps)) != DPSNN_OK) break;
-    if (hipEventRecord(e1, n->stream) != hipSuccess ||
-        hipEventSynchronize(e1) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (best_ms < 0.f || ms < best_ms) {
-      best_ms = ms;
-      best = c;
+    n->sa.spk_lists = c.lists;
+  };
+  Cand best{n->sched, n->sa.deliver_blocks, n->sa.spk_lists};
+  std::vector<hipEvent_t> ev((size_t)2 * nc * rounds, nullptr);
+  int rc = DPSNN_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) rc = DPSNN_E_DEVICE;
+  for (size_t i = 0; i < nc && rc == DPSNN_OK; ++i) {
+    use(cands[i]);
+    rc = dpsnn_step(n, K);
+  }
+  for (int64_t r = 0; r < rounds && rc == DPSNN_OK; ++r) {
+    for (size_t i = 0; i < nc && rc == DPSNN_OK; ++i) {
+      use(cands[i]);
+      // the graph is captured before the timed run
+      if (graphs && (rc = ensure_graph(n)) != DPSNN_OK) break;
+      hipEvent_t* e = &ev[(size_t)2 * (r * nc + i)];
+      if (hipEventRecord(e[0], n->stream) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
+      if ((rc = dpsnn_step(n, K)) != DPSNN_OK) break;
+      if (hipEventRecord(e[1], n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  n->sched = best.sched;
-  n->sa.deliver_blocks = best.blocks;
+  if (rc == DPSNN_OK && hipStreamSynchronize(n->stream) != hipSuccess) rc = DPSNN_E_DEVICE;
+  if (rc == DPSNN_OK) {
+    double best_ms = -1.0;
+    for (size_t i = 0; i < nc; ++i) {
+      double sum = 0.0;
+      for (int64_t r = 0; r < rounds; ++r) {
+        const size_t k = (size_t)2 * (r * nc + i);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        sum += ms;
+      }
+      if (best_ms < 0.0 || sum < best_ms) {
+        best_ms = sum;
+        best = cands[i];
+      }
+    }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  use(best);
   if (chosen) *chosen = best.sched;
   return rc;
 }
@@ -913,6 +953,7 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
   out->queue_cap = n->sa.q_cap;
   out->deliver_blocks = n->sa.deliver_blocks;
   out->route_blocks = n->sa.route_blocks;
+  out->spike_lists = n->sa.spk_lists;
   out->n_pops = n->sa.P;
   out->queue_entry_bytes = n->sa.q_cap == 0 ? 0
                            : n->sa.q_code || n->sa.q_packed ? 4

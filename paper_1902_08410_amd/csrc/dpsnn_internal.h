@@ -16,7 +16,10 @@ constexpr int kMaxDelays = 64;  // distinct delays handled by one wavefront
 constexpr int kMaxKout = 4096;
 constexpr int kDelayShift = 26;  // target word = target | delay index << 26
 constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
-constexpr int kMaxSplitTiles = 16000;  // LDS prefix of the delivery kernel
+constexpr int kSpkLists = 64;          // appended spike lists per step
+constexpr int kMaxScanTiles = 16000;   // per-tile lists: LDS prefix of the tile counts
+constexpr int kScanTilesDefault = 2048; // per-tile lists by default up to this size
+constexpr int kSpkStride = 16;         // their counters 64 bytes apart
 constexpr int kQueueMaxSlots = 128;   // input queues need D <= 128 slots
 constexpr int kQueueDefaultCap = 4096; // entries per (tile, slot) queue
 constexpr int kInboxStride = 16;       // inbox counters 64 bytes apart
@@ -166,8 +169,18 @@ struct StepArgs {
   const int32_t* tgt;      // global target | delay index << 26
   const void* w;
   const int64_t* sfix;     // [M][P] int8 scale in fixed point (int8 format)
-  int32_t* spk;            // [n_tiles][1024] spike ids of the step, per tile
-  int32_t* blk_cnt;        // [n_tiles] spikes per tile
+  // Spikes of the step (split schedule).  Per-tile lists (spk_lists = 0):
+  // tile b writes its spike ids to spk[b * 1024 ...] and their count to
+  // blk_cnt[b]; each delivery block scans the counts.  Appended lists
+  // (spk_lists = 1, large networks): tile b appends its ids to list
+  // g = b mod kSpkLists, spk[g * spk_cap ...], counted in
+  // spk_n[((t & 1) * kSpkLists + g) * kSpkStride]; the delivery of step t
+  // zeroes the counters of step t + 1, and so does the step-counter kernel.
+  int32_t spk_lists;
+  int32_t* spk;            // [kSpkLists][spk_cap] (>= n_tiles * 1024)
+  int64_t spk_cap;         // ceil(n_tiles / kSpkLists) * 1024
+  int32_t* blk_cnt;        // [n_tiles]
+  uint32_t* spk_n;         // [2][kSpkLists][kSpkStride]
   int2* log;
   unsigned long long* log_base;  // [2]: log entries before step t at [t & 1]
   unsigned int* rates;
@@ -314,14 +327,14 @@ struct dpsnn_net {
   int64_t t = 0;
   int64_t rate_first = 0;      // first rate bin not yet drained
   dpsnn::StepArgs sa;
-  unsigned char* ctl = nullptr;  // log bases, spike total, step counter
+  unsigned char* ctl = nullptr;  // log bases, spike total, step counter, spike-list counts
   int sched = DPSNN_SCHED_SPLIT;
   int last_sched = -1;
-  bool split_ok = true;
   // captured steps: graph_K steps of the current schedule on `stream`
   hipGraphExec_t graph = nullptr;
   int graph_K = 0, graph_sched = -1;
   int32_t graph_blocks = 0;     // delivery grid captured in the graph
+  int32_t graph_lists = 0;      // spike-list kind captured in the graph
   hipStream_t graph_stream = nullptr;
   int64_t graph_steps = 128;    // steps per captured graph (0 = no graphs)
 };

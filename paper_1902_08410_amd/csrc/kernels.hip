@@ -381,7 +381,13 @@ __device__ __forceinline__ void gather_batches(const CE* cq, const IE* iq, uint3
   }
 }
 
-template <typename Acc>
+// Entry formats of queues and inboxes, fixed per kernel instance: QEntry in
+// both; packed queue entries with QEntry inboxes; code entries in both.
+constexpr int kFmtWide = 0;
+constexpr int kFmtPacked = 1;
+constexpr int kFmtCode = 2;
+
+template <typename Acc, int FMT>
 __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t t, Acc* s_in) {
   const int D = a.D;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -398,16 +404,19 @@ __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t
   lds_barrier();
   const int64_t qo = ((int64_t)tile * D + cur) * a.q_cap;
   const int64_t io = ((int64_t)par * a.n_tiles + tile) * a.in_cap;
-  const CodeDec<Acc> dec = code_dec<Acc>(a, tile);
-  if (a.q_code)
+  if constexpr (FMT == kFmtCode) {
+    const CodeDec<Acc> dec = code_dec<Acc>(a, tile);
     gather_batches<Acc>(static_cast<const CodeEntry*>(a.q_q) + qo,
                         static_cast<const CodeEntry*>(a.in_q) + io, n_cur, n_in, s_in, dec);
-  else if (sizeof(Acc) == 4 && a.q_packed)
-    gather_batches<Acc>(static_cast<const PackedEntry*>(a.q_q) + qo,
-                        static_cast<const QEntry<Acc>*>(a.in_q) + io, n_cur, n_in, s_in, dec);
-  else
-    gather_batches<Acc>(static_cast<const QEntry<Acc>*>(a.q_q) + qo,
-                        static_cast<const QEntry<Acc>*>(a.in_q) + io, n_cur, n_in, s_in, dec);
+  } else {
+    const CodeDec<Acc> none{};
+    if constexpr (FMT == kFmtPacked)
+      gather_batches<Acc>(static_cast<const PackedEntry*>(a.q_q) + qo,
+                          static_cast<const QEntry<Acc>*>(a.in_q) + io, n_cur, n_in, s_in, none);
+    else
+      gather_batches<Acc>(static_cast<const QEntry<Acc>*>(a.q_q) + qo,
+                          static_cast<const QEntry<Acc>*>(a.in_q) + io, n_cur, n_in, s_in, none);
+  }
   lds_barrier();
   // every thread has used the count and the slot mark: the current queue
   // is empty and the slot cleared now
@@ -548,10 +557,11 @@ __device__ __forceinline__ void route_entries(const StepArgs& a, int tile, uint3
     if (k != cur) a.q_cnt[(int64_t)tile * D + k] = L.qc[k];
 }
 
-template <typename Acc>
+// CODE: code entries (binary16 and int8 efficacies), else QEntry inboxes.
+template <typename Acc, bool CODE>
 __device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_t t,
                                             RouteLds<Acc>& L) {
-  if (a.q_code)
+  if constexpr (CODE)
     route_entries<Acc, CodeEntry>(a, tile, t, L);
   else
     route_entries<Acc, QEntry<Acc>>(a, tile, t, L);
@@ -933,7 +943,7 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 
 // ------------------------------------------------------------------------
 // Split schedule: neuron kernel, then the delivery kernel.
-template <typename Acc, int NP>
+template <typename Acc, int NP, int FMT>
 __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   __shared__ int32_t s_spk[1024];
   __shared__ Acc s_in[1024];
@@ -947,77 +957,40 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
   NeuronRegs<Acc> R;
   neuron_load<Acc, NP>(a, nd, net, i0, t, R);
   if (a.q_cap)
-    gather_now<Acc>(a, blockIdx.x, t, s_in);
+    gather_now<Acc, FMT>(a, blockIdx.x, t, s_in);
   else
     lds_barrier();
   neuron_finish<Acc, NP>(a, nd, i0, t, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
   lds_barrier();
   const int n = s_n;
-  int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
-  for (int k = tid; k < n; k += 256) out[k] = s_spk[k];
-  if (tid == 0) a.blk_cnt[blockIdx.x] = n;
-}
-
-template <typename Acc, int WDT, bool PLAST = false>
-__global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
-  // delivery blocks: inclusive prefix of the tile counts; routing blocks:
-  // their RouteLds
-  extern __shared__ __align__(16) int32_t s_pref[];
-  __shared__ int32_t s_part[8];
-  __shared__ uint32_t s_b[4][256];
-  const int tid = threadIdx.x;
-  const int nb = a.n_tiles;
-  const uint32_t t = a.t_base[0] + t_off;
-  if ((int)blockIdx.x >= a.deliver_blocks) {
-    // routing of the inboxes of step t-1, one tile at a time
-    RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_pref);
-    const int nr = (int)gridDim.x - a.deliver_blocks;
-    for (int tile = (int)blockIdx.x - a.deliver_blocks; tile < nb; tile += nr)
-      route_inbox<Acc>(a, tile, t, L);
+  if (!a.spk_lists) {  // the tile's own list and count
+    int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
+    for (int k = tid; k < n; k += 256) out[k] = s_spk[k];
+    if (tid == 0) a.blk_cnt[blockIdx.x] = n;
     return;
   }
-  // block-wide inclusive scan of the tile counts: a coalesced copy into
-  // LDS, each thread scans a contiguous run, wavefront shuffles and one
-  // exchange of the four wavefront totals
-  for (int b = tid; b < nb; b += 256) s_pref[b] = a.blk_cnt[b];
+  if (n == 0) return;
+  // append the tile's spikes to spike list g = tile mod kSpkLists of the
+  // step (the counters share the appends)
+  __shared__ uint32_t s_base;
+  const int g = (int)(blockIdx.x % kSpkLists);
+  if (tid == 0)
+    s_base = atomicAdd(&a.spk_n[((t & 1u) * kSpkLists + g) * kSpkStride], (uint32_t)n);
   lds_barrier();
-  const int per = (nb + 255) / 256;
-  const int lo = tid * per;
-  const int hi = lo + per < nb ? lo + per : nb;
-  int run = 0;
-  for (int b = lo; b < hi; ++b) run += s_pref[b];
-  int incl = run;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off);
-    if ((tid & 63) >= off) incl += v;
-  }
-  if ((tid & 63) == 63) s_part[tid >> 6] = incl;
-  lds_barrier();
-  int acc = incl - run;
-  for (int w = 0; w < (tid >> 6); ++w) acc += s_part[w];
-  for (int b = lo; b < hi; ++b) {
-    acc += s_pref[b];
-    s_pref[b] = acc;
-  }
-  if (tid == 255) s_part[4] = acc;
-  lds_barrier();
-  const int n_spk = s_part[4];
-  const unsigned long long log0 = a.log_base[t & 1];
-  if (blockIdx.x == 0 && tid == 0) {
-    a.log_base[(t + 1) & 1] = log0 + (unsigned long long)n_spk;
-    a.n_spikes[0] += (unsigned long long)n_spk;
-  }
-  const int cpr = (a.K_out + 255) / 256;  // chunks per row
-  const int64_t items = (int64_t)n_spk * cpr;
-  const int lane = tid & 63;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + (tid >> 6);
-  const int64_t nw = (int64_t)a.deliver_blocks * 4;  // delivery wavefronts
-  for (int64_t it = wid; it < items; it += nw) {
-    const int sidx = (int)(it / cpr);
-    const int chunk = (int)(it - (int64_t)sidx * cpr);
-    // tile holding spike number sidx: first b with s_pref[b] > sidx
-    int l = 0, h = nb - 1;
+  // (a list holds every neuron of its tiles: the bound only guards)
+  const int64_t room = a.spk_cap - (int64_t)s_base;
+  const int n_w = (int64_t)n < room ? n : (room > 0 ? (int)room : 0);
+  int32_t* out = a.spk + (int64_t)g * a.spk_cap + s_base;
+  for (int k = tid; k < n_w; k += 256) out[k] = s_spk[k];
+}
+
+// Spike number sidx of the step: per-tile lists, the tile found by binary
+// search in the LDS prefix of the tile counts; or appended lists, found by
+// the wavefront's prefix of the list counts (lane g: list g).
+__device__ __forceinline__ int32_t spike_at(const StepArgs& a, int sidx, const int32_t* s_pref,
+                                            uint32_t incl, uint32_t excl) {
+  if (!a.spk_lists) {
+    int l = 0, h = a.n_tiles - 1;  // first tile with s_pref[tile] > sidx
     while (l < h) {
       const int mid = (l + h) >> 1;
       if (s_pref[mid] > sidx)
@@ -1026,7 +999,96 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
         l = mid + 1;
     }
     const int first = l ? s_pref[l - 1] : 0;
-    const int32_t s = __builtin_amdgcn_readfirstlane(a.spk[(int64_t)l * 1024 + (sidx - first)]);
+    return __builtin_amdgcn_readfirstlane(a.spk[(int64_t)l * 1024 + (sidx - first)]);
+  }
+  // the first list whose inclusive prefix exceeds sidx
+  const int g = (int)__popcll(__ballot(incl <= (uint32_t)sidx));
+  const uint32_t first = __shfl(excl, g);
+  return __builtin_amdgcn_readfirstlane(
+      a.spk[(int64_t)g * a.spk_cap + ((uint32_t)sidx - first)]);
+}
+
+template <typename Acc, int WDT, bool PLAST = false>
+__global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
+  // delivery blocks: inclusive prefix of the tile counts (per-tile lists);
+  // routing blocks: their RouteLds
+  extern __shared__ __align__(16) int32_t s_dyn[];
+  __shared__ int32_t s_part[8];
+  __shared__ uint32_t s_b[4][256];
+  const int tid = threadIdx.x;
+  const int nb = a.n_tiles;
+  const uint32_t t = a.t_base[0] + t_off;
+  if ((int)blockIdx.x >= a.deliver_blocks) {
+    // routing of the inboxes of step t-1, one tile at a time
+    RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_dyn);
+    const int nr = (int)gridDim.x - a.deliver_blocks;
+    for (int tile = (int)blockIdx.x - a.deliver_blocks; tile < nb; tile += nr)
+      route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, t, L);
+    return;
+  }
+  const int lane = tid & 63;
+  int32_t* s_pref = s_dyn;
+  uint32_t incl = 0, excl = 0;
+  int n_spk;
+  if (!a.spk_lists) {
+    // block-wide inclusive scan of the tile counts: a coalesced copy into
+    // LDS, each thread scans a contiguous run, wavefront shuffles and one
+    // exchange of the four wavefront totals
+    for (int b = tid; b < nb; b += 256) s_pref[b] = a.blk_cnt[b];
+    lds_barrier();
+    const int per = (nb + 255) / 256;
+    const int lo = tid * per;
+    const int hi = lo + per < nb ? lo + per : nb;
+    int run = 0;
+    for (int b = lo; b < hi; ++b) run += s_pref[b];
+    int inc = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(inc, off);
+      if (lane >= off) inc += v;
+    }
+    if (lane == 63) s_part[tid >> 6] = inc;
+    lds_barrier();
+    int acc = inc - run;
+    for (int w = 0; w < (tid >> 6); ++w) acc += s_part[w];
+    for (int b = lo; b < hi; ++b) {
+      acc += s_pref[b];
+      s_pref[b] = acc;
+    }
+    if (tid == 255) s_part[4] = acc;
+    lds_barrier();
+    n_spk = s_part[4];
+  } else {
+    // the appended lists, one per lane: inclusive and exclusive prefix of
+    // their counts
+    uint32_t cnt = a.spk_n[((t & 1u) * kSpkLists + lane) * kSpkStride];
+    if (cnt > (uint64_t)a.spk_cap) cnt = (uint32_t)a.spk_cap;
+    incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    excl = incl - cnt;
+    n_spk = (int)__shfl(incl, 63);
+  }
+  const unsigned long long log0 = a.log_base[t & 1];
+  if (blockIdx.x == 0 && tid == 0) {
+    a.log_base[(t + 1) & 1] = log0 + (unsigned long long)n_spk;
+    a.n_spikes[0] += (unsigned long long)n_spk;
+  }
+  // the list counters of the next step start from zero (nothing else reads
+  // them in this step)
+  if (a.spk_lists && blockIdx.x == 0 && tid < kSpkLists)
+    a.spk_n[(((t + 1u) & 1u) * kSpkLists + tid) * kSpkStride] = 0u;
+  const int cpr = (a.K_out + 255) / 256;  // chunks per row
+  const int64_t items = (int64_t)n_spk * cpr;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (tid >> 6);
+  const int64_t nw = (int64_t)a.deliver_blocks * 4;  // delivery wavefronts
+  for (int64_t it = wid; it < items; it += nw) {
+    const int sidx = (int)(it / cpr);
+    const int chunk = (int)(it - (int64_t)sidx * cpr);
+    const int32_t s = spike_at(a, sidx, s_pref, incl, excl);
     if (chunk == 0 && lane == 0) record_spike(a, s, t, log0 + (unsigned long long)sidx);
     deliver_chunk<Acc, WDT, PLAST>(a, s, chunk * 256, t, lane, s_b[tid >> 6]);
   }
@@ -1050,12 +1112,16 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   const NetDev& nd = a.nets[net];
   NeuronRegs<Acc> R;
   neuron_load<Acc, NP>(a, nd, net, i0, t, R);
-  if (a.q_cap)
-    gather_now<Acc>(a, blockIdx.x, t, s_in);
-  else
+  if (!a.q_cap)
     lds_barrier();
+  else if constexpr (WDT != DPSNN_W_F32)
+    gather_now<Acc, kFmtCode>(a, blockIdx.x, t, s_in);
+  else if (sizeof(Acc) == 4 && a.q_packed)
+    gather_now<Acc, kFmtPacked>(a, blockIdx.x, t, s_in);
+  else
+    gather_now<Acc, kFmtWide>(a, blockIdx.x, t, s_in);
   neuron_finish<Acc, NP>(a, nd, i0, t, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
-  if (a.q_cap) route_inbox<Acc>(a, blockIdx.x, t, s_route);  // has barriers
+  if (a.q_cap) route_inbox<Acc, WDT != DPSNN_W_F32>(a, blockIdx.x, t, s_route);  // barriers
   lds_barrier();
   const int n = s_n;
   if (n == 0) return;
@@ -1080,12 +1146,15 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
 // Advance the device step counter after `n` steps; on a switch from the
 // split to the fused schedule, make both spike-log bases current.
 __global__ void k_tick(uint32_t* t_base, uint32_t n, unsigned long long* log_base,
-                       int sync_logs) {
+                       int sync_logs, uint32_t* spk_n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const uint32_t t = t_base[0];
     if (sync_logs) log_base[(t + 1) & 1] = log_base[t & 1];
     t_base[0] = t + n;
   }
+  // spike-list counters of the next step start from zero
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < 2 * kSpkLists; k += blockDim.x) spk_n[k * kSpkStride] = 0u;
 }
 
 // k_drain for one entry format (IE: inbox entries, CE: queue entries).
@@ -1169,21 +1238,36 @@ hipError_t launch_init(const InitArgs& a, hipStream_t st) {
 }
 
 // Dynamic LDS of the delivery kernel: the larger of the tile-count prefix
-// and the routing blocks' RouteLds.
+// (per-tile spike lists) and the routing blocks' RouteLds.
 template <typename Acc>
 static size_t deliver_lds(const StepArgs& a) {
-  const size_t pref = (size_t)a.n_tiles * 4;
+  const size_t pref = a.spk_lists ? 0 : (size_t)a.n_tiles * 4;
   const size_t route = a.route_blocks ? sizeof(RouteLds<Acc>) : 0;
   return pref > route ? pref : route;
 }
 
-template <typename Acc>
-static void launch_neuron(const StepArgs& a, uint32_t t_off, hipStream_t st) {
+template <typename Acc, int FMT>
+static void launch_neuron_fmt(const StepArgs& a, uint32_t t_off, hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
   if (a.P <= 2)
-    hipLaunchKernelGGL((k_neuron<Acc, 2>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_neuron<Acc, 2, FMT>), tiles, block, 0, st, a, t_off);
   else
-    hipLaunchKernelGGL((k_neuron<Acc, 4>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_neuron<Acc, 4, FMT>), tiles, block, 0, st, a, t_off);
+}
+
+template <typename Acc>
+static void launch_neuron(const StepArgs& a, uint32_t t_off, hipStream_t st) {
+  if (a.q_code) {
+    launch_neuron_fmt<Acc, kFmtCode>(a, t_off, st);
+    return;
+  }
+  if constexpr (sizeof(Acc) == 4) {
+    if (a.q_packed) {
+      launch_neuron_fmt<Acc, kFmtPacked>(a, t_off, st);
+      return;
+    }
+  }
+  launch_neuron_fmt<Acc, kFmtWide>(a, t_off, st);
 }
 
 template <typename Acc>
@@ -1318,7 +1402,8 @@ hipError_t launch_stdp_update(const StepArgs& a, int32_t T, hipStream_t st) {
 }
 
 hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t st) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, a.t_base, n, a.log_base, sync_logs);
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, a.t_base, n, a.log_base, sync_logs,
+                     a.spk_n);
   return hipGetLastError();
 }
 

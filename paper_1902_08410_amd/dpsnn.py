@@ -69,7 +69,7 @@ class DpsnnStats(C.Structure):
         ("bytes_total", C.c_int64), ("lds_bytes", C.c_int32), ("schedule", C.c_int32),
         ("n_index", C.c_int64), ("n_nets", C.c_int32), ("queue_cap", C.c_int32),
         ("deliver_blocks", C.c_int32), ("route_blocks", C.c_int32),
-        ("n_pops", C.c_int32), ("queue_entry_bytes", C.c_int32),
+        ("n_pops", C.c_int32), ("queue_entry_bytes", C.c_int32), ("spike_lists", C.c_int32),
     ]
 
 
@@ -179,6 +179,7 @@ def lib():
             "dpsnn_host_table": ([P(DpsnnParams), C.c_char_p, V, C.c_int64], C.c_int64),
             "dpsnn_set_schedule": ([V, C.c_int32], C.c_int),
             "dpsnn_set_graph_steps": ([V, C.c_int64], C.c_int),
+            "dpsnn_set_delivery": ([V, C.c_int32, C.c_int32], C.c_int),
             "dpsnn_autotune": ([V, C.c_int64, P(C.c_int32)], C.c_int),
             "dpsnn_profile_steps": ([V, C.c_int64, V], C.c_int),
             "dpsnn_build_batch": ([P(DpsnnParams), P(C.c_uint64), C.c_int32, P(V)], C.c_int),
@@ -206,7 +207,7 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
            "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps",
            "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts",
-           "dpsnn_read_plasticity"]
+           "dpsnn_read_plasticity", "dpsnn_set_delivery"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -337,6 +338,11 @@ def dpsnn_step(net: Net, n_steps: int) -> None:
 
 def dpsnn_set_schedule(net: Net, sched: int) -> None:
     _check("dpsnn_set_schedule", lib().dpsnn_set_schedule(net.h, int(sched)))
+
+
+def dpsnn_set_delivery(net: Net, deliver_blocks: int = 0, spike_lists: int = -1) -> None:
+    _check("dpsnn_set_delivery",
+           lib().dpsnn_set_delivery(net.h, int(deliver_blocks), int(spike_lists)))
 
 
 def dpsnn_set_graph_steps(net: Net, steps: int) -> None:

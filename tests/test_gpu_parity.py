@@ -294,8 +294,10 @@ def test_graph_replay_and_schedule_switching(L):
         chosen = L.dpsnn_autotune(net, 200)
         st = net.stats()
         assert chosen in (0, 1) and st["schedule"] == chosen
-        # two passes per candidate: the fused schedule and split delivery grids
-        assert (st["t"] - t0) % 400 == 0 and st["t"] - t0 >= 800
+        # runs of 64 steps (the graph length): one untimed run and 200 // 64
+        # timed ones per candidate (the fused schedule; split delivery grids
+        # with both spike-list kinds)
+        assert (st["t"] - t0) % (4 * 64) == 0 and st["t"] - t0 >= 2 * 4 * 64
         assert st["deliver_blocks"] in (256, 512, 1024, 2048)
         orc.step(st["t"] - t0)
         _compare_all(L, net, orc, "after autotune")
@@ -549,6 +551,32 @@ def test_population_batch_matches_solo_runs(L):
         assert len(ss) > 500
         solo.close()
     net.close()
+
+
+def test_spike_list_kinds_and_grids(L):
+    """The split schedule's delivery with per-tile and with appended spike
+    lists and several grids, switched between calls (graphs and direct
+    launches): bit-exact."""
+    import torch
+    _say("spike list kinds")
+    p = W.grid(3, 3, "swa", K=1250, K_out=200)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        net, orc = _pair(p, 9)
+        L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+        for k, (blocks, lists) in enumerate([(0, 1), (7, 0), (256, 1), (1024, 0), (3, 1),
+                                             (512, 1), (256, 0)]):
+            L.dpsnn_set_delivery(net, blocks, lists)
+            st = net.stats()
+            assert st["spike_lists"] == lists
+            assert blocks == 0 or st["deliver_blocks"] == blocks
+            n = 300 if k % 2 else 47      # graph replays and direct launches; direct only
+            L.dpsnn_step(net, n)
+            orc.step(n)
+            assert _compare_all(L, net, orc, f"lists {lists} blocks {blocks}") > 0
+        for bad in [(-1, 0), (0, 2), (0, -2)]:
+            with pytest.raises(L.DpsnnError):
+                L.dpsnn_set_delivery(net, *bad)
+        net.close()
 
 
 def test_queue_entry_formats(L):
