@@ -243,8 +243,9 @@ int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
  * 0 keeps the current one) and the spike lists it reads (0: one list per
  * tile of 1024 neurons, whose counts every delivery block scans, for at most
  * 16000 tiles; 1: lists appended by the tiles through 64 counters; -1 keeps
- * the current kind).  Results do not depend on either.  The default: 1024
- * blocks at most, per-tile lists up to 2048 tiles.  INVAL otherwise. */
+ * the current kind).  Results do not depend on either.  The default: one
+ * block per tile, between 256 and 1024 blocks, and appended lists.  INVAL
+ * otherwise. */
 int dpsnn_set_delivery(dpsnn_net* net, int32_t deliver_blocks, int32_t spike_lists);
 
 /* Steps captured per HIP graph replay (0 disables graphs; graphs are only

@@ -330,7 +330,7 @@ int build_impl(dpsnn_net* n) {
   a.spk = spk;
   a.spk_cap = spk_cap;
   a.blk_cnt = blk_cnt;
-  a.spk_lists = n_tiles > kScanTilesDefault ? 1 : 0;
+  a.spk_lists = 1;  // appended lists; the autotuner also tries per-tile ones
   a.log = log;
   a.log_base = reinterpret_cast<unsigned long long*>(ctl);
   a.n_spikes = reinterpret_cast<unsigned long long*>(ctl + 16);

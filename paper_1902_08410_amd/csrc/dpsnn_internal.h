@@ -18,7 +18,6 @@ constexpr int kDelayShift = 26;  // target word = target | delay index << 26
 constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
 constexpr int kSpkLists = 64;          // appended spike lists per step
 constexpr int kMaxScanTiles = 16000;   // per-tile lists: LDS prefix of the tile counts
-constexpr int kScanTilesDefault = 2048; // per-tile lists by default up to this size
 constexpr int kSpkStride = 16;         // their counters 64 bytes apart
 constexpr int kQueueMaxSlots = 128;   // input queues need D <= 128 slots
 constexpr int kQueueDefaultCap = 4096; // entries per (tile, slot) queue
@@ -172,7 +171,7 @@ struct StepArgs {
   // Spikes of the step (split schedule).  Per-tile lists (spk_lists = 0):
   // tile b writes its spike ids to spk[b * 1024 ...] and their count to
   // blk_cnt[b]; each delivery block scans the counts.  Appended lists
-  // (spk_lists = 1, large networks): tile b appends its ids to list
+  // (spk_lists = 1, the default): tile b appends its ids to list
   // g = b mod kSpkLists, spk[g * spk_cap ...], counted in
   // spk_n[((t & 1) * kSpkLists + g) * kSpkStride]; the delivery of step t
   // zeroes the counters of step t + 1, and so does the step-counter kernel.
