@@ -248,3 +248,14 @@ def test_wave_analysis_rejects_invalid_requests_before_any_device_call():
     wp = L.DpsnnWaveParams(L.ABI_VERSION, 0, 0, 0.5, 1, 2, 2, 1, 0)
     assert lib.dpsnn_waves(None, C.byref(wp), C.byref(res), None, None, None, 0, None, None,
                            None, 0) == E
+
+
+def test_handle_setters_reject_a_null_handle():
+    """The setters check their handle before touching the device."""
+    from paper_1902_08410_amd import dpsnn as L
+    lib = L.lib()
+    E = -1
+    assert lib.dpsnn_set_delivery(None, 0, -1) == E
+    assert lib.dpsnn_set_delivery(None, 256, 1) == E
+    assert lib.dpsnn_set_schedule(None, L.SCHED_SPLIT) == E
+    assert lib.dpsnn_set_graph_steps(None, 64) == E
