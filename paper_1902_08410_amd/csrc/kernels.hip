@@ -777,13 +777,23 @@ __device__ __forceinline__ void stdp_event(const StepArgs& a, int32_t ta, int32_
   t_act = ta;
 }
 
-// 256 synapses (4 per lane) of row s starting at p0 = chunk * 256.  s_b is
-// the wavefront's 256-entry LDS scratch.  Every lane of the wavefront takes
-// part, also past the end of the row.  PLAST: the row's synapses register
-// the activation first when the source is excitatory.
-template <typename Acc, int WDT, bool PLAST = false>
-__device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int p0,
-                                              uint32_t t, int lane, uint32_t* s_b) {
+// One chunk of a row: 256 synapses (4 per lane) of row s from p0 = chunk *
+// 256; targets, fixed-point efficacies and, for code entries, the stored
+// codes.
+template <typename Acc>
+struct Chunk {
+  int32_t s, p0;
+  int tv[4];
+  Acc wv[4];
+  uint32_t cv[4];
+};
+
+// Loads of a chunk (issued, not waited for: the values are used later).
+template <typename Acc, int WDT>
+__device__ __forceinline__ void chunk_load(const StepArgs& a, int32_t s, int p0, int lane,
+                                           Chunk<Acc>& c) {
+  c.s = s;
+  c.p0 = p0;
   const int64_t rb = (int64_t)s * a.row_stride;
   int64_t scale = 0;
   int q_src = 0;  // source population (int8 codes)
@@ -793,47 +803,71 @@ __device__ __forceinline__ void deliver_chunk(const StepArgs& a, int32_t s, int 
     scale = a.sfix[(int64_t)a.P * ms + q_src];
   }
   const int p = p0 + lane * 4;
-  int tv[4] = {0, 0, 0, 0};
-  Acc wv[4] = {0, 0, 0, 0};
-  uint32_t cv[4] = {0, 0, 0, 0};  // efficacy codes of code entries
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    c.tv[j] = 0;
+    c.wv[j] = 0;
+    c.cv[j] = 0;
+  }
   if (p < a.K_out) {  // rows are padded to a multiple of 4 words
     const int4 tg = *reinterpret_cast<const int4*>(a.tgt + rb + p);
-    tv[0] = tg.x; tv[1] = tg.y; tv[2] = tg.z; tv[3] = tg.w;
+    c.tv[0] = tg.x; c.tv[1] = tg.y; c.tv[2] = tg.z; c.tv[3] = tg.w;
     if (WDT == DPSNN_W_F32) {
       const float4 w4 =
           *reinterpret_cast<const float4*>(static_cast<const float*>(a.w) + rb + p);
-      wv[0] = (Acc)__builtin_rintf(w4.x * a.two_q);
-      wv[1] = (Acc)__builtin_rintf(w4.y * a.two_q);
-      wv[2] = (Acc)__builtin_rintf(w4.z * a.two_q);
-      wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
+      c.wv[0] = (Acc)__builtin_rintf(w4.x * a.two_q);
+      c.wv[1] = (Acc)__builtin_rintf(w4.y * a.two_q);
+      c.wv[2] = (Acc)__builtin_rintf(w4.z * a.two_q);
+      c.wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
+        c.wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
         if (WDT == DPSNN_W_F16)
-          cv[j] = static_cast<const uint16_t*>(a.w)[rb + p + j];
+          c.cv[j] = static_cast<const uint16_t*>(a.w)[rb + p + j];
         else
-          cv[j] = (uint32_t)(uint8_t)static_cast<const int8_t*>(a.w)[rb + p + j] |
-                  (uint32_t)q_src << 8;
+          c.cv[j] = (uint32_t)(uint8_t)static_cast<const int8_t*>(a.w)[rb + p + j] |
+                    (uint32_t)q_src << 8;
       }
     }
   }
-  if (PLAST) {
-    int32_t ms;
-    int q;
-    module_pop(a, s, &ms, &q);
-    if (a.nets[a.tile_net[s >> 10]].exc[q] && p < a.K_out) {
-      int4 ta4 = *reinterpret_cast<const int4*>(a.syn_t + rb + p);
-      float4 y4 = *reinterpret_cast<const float4*>(a.syn_y + rb + p);
-      int32_t tav[4] = {ta4.x, ta4.y, ta4.z, ta4.w};
-      float yv[4] = {y4.x, y4.y, y4.z, y4.w};
+}
+
+// Plasticity events of a loaded chunk: when the source is excitatory its
+// synapses register the activation (before the events are delivered).
+template <typename Acc>
+__device__ __forceinline__ void chunk_plasticity(const StepArgs& a, const Chunk<Acc>& c,
+                                                 uint32_t t, int lane) {
+  const int64_t rb = (int64_t)c.s * a.row_stride;
+  const int p = c.p0 + lane * 4;
+  int32_t ms;
+  int q;
+  module_pop(a, c.s, &ms, &q);
+  if (a.nets[a.tile_net[c.s >> 10]].exc[q] && p < a.K_out) {
+    int4 ta4 = *reinterpret_cast<const int4*>(a.syn_t + rb + p);
+    float4 y4 = *reinterpret_cast<const float4*>(a.syn_y + rb + p);
+    int32_t tav[4] = {ta4.x, ta4.y, ta4.z, ta4.w};
+    float yv[4] = {y4.x, y4.y, y4.z, y4.w};
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (p + j < a.K_out) stdp_event(a, (int32_t)t, a.t_post[tv[j] & kTargetMask], tav[j], yv[j]);
-      *reinterpret_cast<int4*>(a.syn_t + rb + p) = make_int4(tav[0], tav[1], tav[2], tav[3]);
-      *reinterpret_cast<float4*>(a.syn_y + rb + p) = make_float4(yv[0], yv[1], yv[2], yv[3]);
-    }
+    for (int j = 0; j < 4; ++j)
+      if (p + j < a.K_out)
+        stdp_event(a, (int32_t)t, a.t_post[c.tv[j] & kTargetMask], tav[j], yv[j]);
+    *reinterpret_cast<int4*>(a.syn_t + rb + p) = make_int4(tav[0], tav[1], tav[2], tav[3]);
+    *reinterpret_cast<float4*>(a.syn_y + rb + p) = make_float4(yv[0], yv[1], yv[2], yv[3]);
   }
+}
+
+// Delivery of a loaded chunk.  s_b is the wavefront's 256-entry LDS
+// scratch.  Every lane of the wavefront takes part, also past the end of
+// the row.
+template <typename Acc, int WDT>
+__device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc>& c,
+                                              uint32_t t, int lane, uint32_t* s_b) {
+  const int p0 = c.p0;
+  const int p = p0 + lane * 4;
+  const int* tv = c.tv;
+  const Acc* wv = c.wv;
+  const uint32_t* cv = c.cv;
   const int slot0 = (int)((t + (uint32_t)a.d_min) % (uint32_t)a.D);
   Acc* slots = static_cast<Acc*>(a.slots);
   if (a.q_cap == 0) {
@@ -1085,12 +1119,25 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   const int64_t items = (int64_t)n_spk * cpr;
   const int64_t wid = (int64_t)blockIdx.x * 4 + (tid >> 6);
   const int64_t nw = (int64_t)a.deliver_blocks * 4;  // delivery wavefronts
-  for (int64_t it = wid; it < items; it += nw) {
+  // item it: chunk it mod cpr of spike number it / cpr.  The next item's
+  // loads are issued before the current item is delivered.
+  auto load_item = [&](int64_t it, Chunk<Acc>& c) {
     const int sidx = (int)(it / cpr);
     const int chunk = (int)(it - (int64_t)sidx * cpr);
     const int32_t s = spike_at(a, sidx, s_pref, incl, excl);
     if (chunk == 0 && lane == 0) record_spike(a, s, t, log0 + (unsigned long long)sidx);
-    deliver_chunk<Acc, WDT, PLAST>(a, s, chunk * 256, t, lane, s_b[tid >> 6]);
+    chunk_load<Acc, WDT>(a, s, chunk * 256, lane, c);
+  };
+  Chunk<Acc> cur;
+  if (wid < items) load_item(wid, cur);
+  for (int64_t it = wid; it < items; it += nw) {
+    Chunk<Acc> nxt;
+    const bool more = it + nw < items;
+    if (more) load_item(it + nw, nxt);
+    if (PLAST) chunk_plasticity<Acc>(a, cur, t, lane);
+    chunk_deliver<Acc, WDT>(a, cur, t, lane, s_b[tid >> 6]);
+    if (!more) break;
+    cur = nxt;
   }
 }
 
@@ -1139,7 +1186,9 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   for (int it = wave; it < n * cpr; it += 4) {
     const int k = it / cpr;
     const int32_t s = __builtin_amdgcn_readfirstlane(s_spk[k]);
-    deliver_chunk<Acc, WDT>(a, s, (it - k * cpr) * 256, t, lane, s_b[wave]);
+    Chunk<Acc> c;
+    chunk_load<Acc, WDT>(a, s, (it - k * cpr) * 256, lane, c);
+    chunk_deliver<Acc, WDT>(a, c, t, lane, s_b[wave]);
   }
 }
 
