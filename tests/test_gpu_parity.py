@@ -553,13 +553,15 @@ def test_population_batch_matches_solo_runs(L):
     net.close()
 
 
-def test_spike_list_kinds_and_grids(L):
+@pytest.mark.parametrize("side,K_out", [(3, 200), (9, 100)])
+def test_spike_list_kinds_and_grids(L, side, K_out):
     """The split schedule's delivery with per-tile and with appended spike
     lists and several grids, switched between calls (graphs and direct
-    launches): bit-exact."""
+    launches): bit-exact; 11 tiles (lists of one tile or none) and 99 tiles
+    (two tiles in some of the 64 lists)."""
     import torch
-    _say("spike list kinds")
-    p = W.grid(3, 3, "swa", K=1250, K_out=200)
+    _say("spike list kinds", side, K_out)
+    p = W.grid(side, side, "swa", K=1250, K_out=K_out)
     with torch.cuda.stream(torch.cuda.Stream()):
         net, orc = _pair(p, 9)
         L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
