@@ -17,7 +17,8 @@ constexpr int kMaxKout = 4096;
 constexpr int kDelayShift = 26;  // target word = target | delay index << 26
 constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
 constexpr int kSpkLists = 64;          // appended spike lists per step
-constexpr int kMaxScanTiles = 16000;   // per-tile lists: LDS prefix of the tile counts
+constexpr int kMaxScanTiles = 15000;   // per-tile lists: LDS prefix of the tile counts
+                                       // (with the static LDS, within 64 KiB per block)
 constexpr int kSpkStride = 16;         // their counters 64 bytes apart
 constexpr int kQueueMaxSlots = 128;   // input queues need D <= 128 slots
 constexpr int kQueueDefaultCap = 4096; // entries per (tile, slot) queue
