@@ -7,30 +7,35 @@
 //             The delay index rides in the top 6 bits of each target word,
 //             so that delivery needs no lookup.
 //  k_init     initial membrane potentials, fatigue and refractory counters.
-//  k_neuron   one step of dt for a tile of 1024 neurons (4 per thread):
-//             input slot read-and-clear, external Poisson drive, Eq. 2 update,
-//             threshold; the tile's spikes go to its own segment of the spike
-//             list (no global counter).
-//  k_deliver  the tile counts are scanned in LDS by every block; then every
-//             wavefront of the grid takes chunks of 256 synapses of spiking
-//             rows (16-byte loads) and adds the fixed-point efficacies into the
-//             target slots with atomics.  Spreading the chunks over the whole
-//             chip keeps every CU issuing atomics.  Also appends the spike log
-//             and the 5 ms population counts.
-//  k_step     fused schedule for small networks: k_neuron followed by the
-//             delivery of the tile's own spikes by its four wavefronts.
-//  k_drain    folds pending local-queue entries into the slots (inspection).
+//  k_neuron   one step of dt for a tile of 1024 neurons (4 per thread): the
+//             tile's queued inputs summed in LDS, the input slot read and
+//             cleared where marked, external Poisson drive, Eq. 2 update,
+//             threshold, 5 ms population counts; the tile's spikes are
+//             appended to one of the step's spike lists (or kept per tile).
+//  k_deliver  delivery blocks: every wavefront takes chunks of 256 synapses
+//             of spiking rows (16-byte loads, the next chunk's loads issued
+//             before the current one is delivered); the events of a chunk to
+//             one tile form a run in the target-sorted row, and one returning
+//             atomic reserves the run's room in that tile's inbox of the
+//             step.  Routing blocks of the same grid move each tile's inbox of
+//             the previous step into its per-slot queues.  Also appends the
+//             spike log.
+//  k_step     fused schedule for small networks: update, routing and the
+//             delivery of the tile's own spikes in one block per tile.
+//  k_drain    folds pending queue entries into the slots (schedule switches
+//             and inspection).
+//  k_stdp_update  the periodic efficacy update of plastic networks.
 //
-// Local-event queues.  Half of a row (the local synapses) targets the
-// source's own module, which spans at most four 1024-neuron tiles.  A
-// wavefront delivering a chunk of 256 synapses groups its local events by
-// (delay, tile) in LDS, reserves room for each group with one atomic on the
-// queue counter of (arrival slot, tile), and appends (in-tile index,
-// fixed-point efficacy) pairs with plain stores.  When a tile consumes a
-// slot it sums that slot's queue into LDS and adds it to the slot value.
-// Events that do not fit a full queue, and all remote events, are atomic
-// adds into the slot.  Every path sums integers, so the result is the same
-// whichever path an event takes.
+// Event queues.  Per 1024-neuron tile: an inbox for each step parity and a
+// queue per input slot.  Delivery of step t appends each event (in-tile
+// index, delay index, efficacy) to its target tile's inbox; at step t + 1
+// the update sums the events that arrive at once (delay d_min = 1) and the
+// queue of the current slot, and the routing blocks move the other events of
+// the inbox into the queues of their arrival slots.  Events that find an
+// inbox, the routing stage or a queue full are added into the slot with an
+// atomic instead, and the (tile, slot) is marked so that the update reads
+// that slot.  Every path sums integers, so the result does not depend on
+// the path or the order.
 //
 // A step reads only slot t mod D and delivery writes only slots t+d_min ..
 // t+d_max, so update and delivery of one step need no grid-wide ordering;
