@@ -83,7 +83,9 @@ typedef struct dpsnn_params {
   double frac_exc;         /* excitatory share of a module [0.8]            */
   double frac_local[2];    /* share of a source's synapses kept local [0.5] */
   double lambda;           /* decay length of Eq. 1 [1]                     */
-  int32_t torus;           /* must be 1: periodic grid                      */
+  int32_t torus;           /* 1: periodic grid [1]; 0: the grid has edges,
+                              and each remote synapse draws among the other
+                              modules that exist (Eq. 1, Sec. 2.2)        */
   int32_t d_min, d_max;    /* delays in steps, 1 <= d_min <= d_max,
                               d_max - d_min < 64 [1, 20]                    */
   double dt_ms;            /* step [0.1]                                    */
@@ -156,7 +158,7 @@ typedef struct dpsnn_params {
   double stdp_w_max;                     /* largest plastic efficacy, mV  */
 } dpsnn_params;
 
-typedef struct dpsnn_stats {
+typedef struct dpsnn_stats_t {
   int64_t t;              /* steps simulated                               */
   int64_t n_neurons;      /* neurons                                       */
   int64_t n_modules;      /* modules                                       */
@@ -182,7 +184,7 @@ typedef struct dpsnn_stats {
                              0 = no queues                                */
   int32_t spike_lists;    /* spike lists of the split schedule (see
                              dpsnn_set_delivery)                          */
-} dpsnn_stats;
+} dpsnn_stats_t;
 
 typedef struct dpsnn_net dpsnn_net; /* opaque handle */
 
@@ -248,6 +250,13 @@ int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
  * otherwise. */
 int dpsnn_set_delivery(dpsnn_net* net, int32_t deliver_blocks, int32_t spike_lists);
 
+/* Grid of the inbox-routing blocks of the split schedule's delivery kernel
+ * (each block moves the inboxes of every route_blocks-th tile into their
+ * per-slot queues): 1 .. number of 1024-neuron tiles, or 0 for the default
+ * (one block per tile, at most 4096).  Results do not depend on it.  INVAL
+ * otherwise; STATE for a handle without input queues. */
+int dpsnn_set_routing(dpsnn_net* net, int32_t route_blocks);
+
 /* Steps captured per HIP graph replay (0 disables graphs; graphs are only
  * used on a non-default stream).  Default 128. */
 int dpsnn_set_graph_steps(dpsnn_net* net, int64_t steps);
@@ -278,14 +287,24 @@ int dpsnn_profile_steps(dpsnn_net* net, int64_t n_steps, double* host_ms);
 int dpsnn_sync(dpsnn_net* net);
 
 /*
- * Drain the device spike log into host_step[] / host_id[] (each of
- * capacity `cap`), sorted by (step, neuron id).  *n_out = number of logged
- * spikes.  With cap < *n_out nothing is copied or drained (query with
- * cap = 0).  Synchronises.  Errors: INVAL, SPIKELOG_FULL (the log
- * overflowed: what was kept is still returned and drained), DEVICE.
+ * Spikes as (time, neuron id) messages, the unit the paper's engine
+ * exchanges and delivers (Sec. 2.1.1, steps 1-2; Sec. 2.1.2).  Drain the
+ * spikes logged since the last read into host_step[] / host_id[] (each of
+ * capacity `cap`), sorted by (step, neuron id); ids are global indices of
+ * the handle.  *n_out = number of spikes available.  With cap < *n_out
+ * nothing is copied or drained (query with cap = 0).  The device log holds
+ * spike_log_cap entries between reads.  Synchronises.  Errors: INVAL,
+ * SPIKELOG_FULL (the device log overflowed: what was kept is still returned
+ * and drained), DEVICE.
  */
 int dpsnn_read_spikes(dpsnn_net* net, int32_t* host_step, int32_t* host_id,
                       int64_t cap, int64_t* n_out);
+
+/* The same for network k of a batch handle only, with network-local neuron
+ * ids (0 .. its neuron count - 1); the spikes of the other networks stay
+ * available to later reads. */
+int dpsnn_read_spikes_net(dpsnn_net* net, int32_t k, int32_t* host_step,
+                          int32_t* host_id, int64_t cap, int64_t* n_out);
 
 /*
  * Drain the completed population-count bins (Sec. 2.3: firing rates per
@@ -297,8 +316,18 @@ int dpsnn_read_spikes(dpsnn_net* net, int32_t* host_step, int32_t* host_id,
 int dpsnn_read_rates(dpsnn_net* net, uint32_t* host_counts, int64_t cap_bins,
                      int64_t* n_bins);
 
-/* Counters and sizes (synchronises). */
-int dpsnn_stats_get(dpsnn_net* net, dpsnn_stats* out);
+/* The same for network k of a batch handle only: host_counts is
+ * [bins][modules of network k][n_pops], from the first bin that network
+ * k has not drained.  dpsnn_read_rates returns every bin some network has
+ * not drained; counts a network has already drained read 0 there. */
+int dpsnn_read_rates_net(dpsnn_net* net, int32_t k, uint32_t* host_counts,
+                         int64_t cap_bins, int64_t* n_bins);
+
+/* Counters and sizes (synchronises): spikes and recurrent synaptic events
+ * (the event count of Sec. 2.4), build time, device bytes.  dpsnn_stats_get
+ * is the same call under its earlier name. */
+int dpsnn_stats(dpsnn_net* net, dpsnn_stats_t* out);
+int dpsnn_stats_get(dpsnn_net* net, dpsnn_stats_t* out);
 
 void dpsnn_free(dpsnn_net* net);
 const char* dpsnn_strerror(int code);

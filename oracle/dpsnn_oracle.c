@@ -294,7 +294,7 @@ static int valid(const orc_params* p) {
       if (!(p->tau_arp[q] >= 0.0) || !(p->nu_ext_hz[q] >= 0.0)) return 0;
       if (!(p->J_sd[q] >= 0.0) || !(p->Jext_sd[q] >= 0.0)) return 0;
     }
-    if (p->torus != 1) return 0;  /* open boundaries: population model */
+    if (p->torus != 0 && p->torus != 1) return 0;
     return 1;
   }
   if (p->n_pops < 2 || p->n_pops > MAXP) return 0;
@@ -357,7 +357,7 @@ static void set_model(orc_net* n) {
       n->n_blk[q] = b;
     }
     n->off_rule = RULE_OTHERS;
-    n->open = 0;
+    n->open = p->torus ? 0 : 1;  /* torus = 0: the grid has edges */
     return;
   }
   n->P = p->n_pops;
@@ -451,10 +451,10 @@ static int build_tables(orc_net* n) {
    *    offsets (ox, oy) in [0,W) x [0,H) row-major without (0,0), d the
    *    Euclidean length of the shortest periodic image.
    *  - RULE_ALL on the torus: the same offsets with (0,0) (d = 0) first.
-   *  - RULE_ALL with open boundaries: plane offsets (dx, dy) in
-   *    [-(W-1), W-1] x [-(H-1), H-1] row-major, d = |(dx, dy)|; a draw that
-   *    leaves the grid is repeated, so that each source draws from exp(-d/l)
-   *    restricted to the modules that exist. */
+   *  - open boundaries: plane offsets (dx, dy) in [-(W-1), W-1] x
+   *    [-(H-1), H-1] row-major, d = |(dx, dy)|, without (0,0) for
+   *    RULE_OTHERS; a draw that leaves the grid is repeated, so that each
+   *    source draws from exp(-d/l) restricted to the modules that exist. */
   const int W = p->grid_w, H = p->grid_h;
   int cnt_off;
   if (n->off_rule == RULE_OTHERS)
@@ -463,6 +463,7 @@ static int build_tables(orc_net* n) {
     cnt_off = n->M;
   else
     cnt_off = (2 * W - 1) * (2 * H - 1);
+  if (n->off_rule == RULE_OTHERS && n->open) cnt_off = (2 * W - 1) * (2 * H - 1) - 1;
   n->n_off = cnt_off;
   if (n->n_off > 0) {
     double* wgt = (double*)malloc(sizeof(double) * n->n_off);
@@ -487,6 +488,7 @@ static int build_tables(orc_net* n) {
     } else {
       for (int dy = -(H - 1); dy <= H - 1; dy++)
         for (int dx = -(W - 1); dx <= W - 1; dx++) {
+          if (dx == 0 && dy == 0 && n->off_rule == RULE_OTHERS) continue;
           double d = sqrt((double)(dx * dx + dy * dy));
           wgt[k] = exp(-d / p->lambda);
           n->off_xy[2 * k] = dx;
@@ -561,7 +563,8 @@ static int build_tables(orc_net* n) {
  * n_blk); it targets a uniform neuron of the block's target range in a
  * module chosen by the block's rule:
  *   RULE_OWN    the source's own module; neuron from word 0;
- *   RULE_OTHERS another module by Eq. 1 (torus offsets without (0,0));
+ *   RULE_OTHERS another module by Eq. 1 (offsets without (0,0); with open
+ *               boundaries a draw outside the grid is repeated as below);
  *   RULE_ALL    any module by Eq. 1 from d = 0; with open boundaries a draw
  *               outside the grid is repeated with counter word 2 = attempt
  *               (at most MAX_ATTEMPTS, then the own module);

@@ -98,6 +98,8 @@ int build_impl(dpsnn_net* n) {
     n->N_total += n->T[k].N;
   }
   n->N_pad = gi;
+  n->rate_first.assign(nn, 0);
+  n->pend.assign(nn, {});
   n->N_index = n->base[nn - 1] + n->T[nn - 1].N;
   n->M_total = (int32_t)gm;
   if (n->N_pad > (int64_t)kTargetMask) return DPSNN_E_INVAL;
@@ -183,6 +185,13 @@ int build_impl(dpsnn_net* n) {
           wfix_dev[q][bb] = (int64_t*)dev_alloc(n, (size_t)kQuantN * 8);
           if (!wfix_dev[q][bb]) return DPSNN_E_NOMEM;
           wf.push_back(fix_table(p, T, q, bb));
+          // a plastic efficacy moves within [0, w_max] after the first
+          // update: bound it by the larger of its start and w_max
+          const bool exc = p.n_pops == 0 ? q == 0 : p.pop_exc[q] != 0;
+          if (p.plastic && exc) {
+            const int64_t wm = (int64_t)llrint(ldexp(p.stdp_w_max, p.q_frac_bits));
+            for (int64_t& v : wf.back()) v = std::max<int64_t>(v < 0 ? -v : v, wm);
+          }
           HIP_OK(hipMemcpyAsync(wfix_dev[q][bb], wf.back().data(), (size_t)kQuantN * 8,
                                 hipMemcpyHostToDevice, st));
         }
@@ -434,8 +443,11 @@ int build_common(const dpsnn_params* p, const uint64_t* seeds, int32_t n_nets,
   n->alloc_ctx = g_ctx;
   const int rc = build_impl(n.get());
   if (rc != DPSNN_OK) {
-    (void)hipStreamSynchronize(n->stream);
-    release_all(n.get());
+    // parameter and range errors come before any device call
+    if (!n->blocks.empty()) {
+      (void)hipStreamSynchronize(n->stream);
+      release_all(n.get());
+    }
     return rc;
   }
   n->build_ms =
@@ -630,12 +642,17 @@ void drop_graph(dpsnn_net* n) {
   n->graph_stream = nullptr;
 }
 
+// First rate bin that some network of the handle has not drained.
+int64_t rate_first_min(const dpsnn_net* n) {
+  return *std::min_element(n->rate_first.begin(), n->rate_first.end());
+}
+
 // Capture graph_steps steps of the current schedule followed by the step
 // counter update; replays then need no host work per step.
 int ensure_graph(dpsnn_net* n) {
   if (n->graph && n->graph_sched == n->sched && n->graph_stream == n->stream &&
       n->graph_blocks == n->sa.deliver_blocks && n->graph_lists == n->sa.spk_lists &&
-      n->graph_K == n->graph_steps)
+      n->graph_routes == n->sa.route_blocks && n->graph_K == n->graph_steps)
     return DPSNN_OK;
   drop_graph(n);
   hipGraph_t g = nullptr;
@@ -659,6 +676,7 @@ int ensure_graph(dpsnn_net* n) {
   n->graph_sched = n->sched;
   n->graph_blocks = n->sa.deliver_blocks;
   n->graph_lists = n->sa.spk_lists;
+  n->graph_routes = n->sa.route_blocks;
   n->graph_stream = n->stream;
   return DPSNN_OK;
 }
@@ -680,6 +698,14 @@ int dpsnn_set_delivery(dpsnn_net* n, int32_t deliver_blocks, int32_t spike_lists
     return DPSNN_E_INVAL;
   if (deliver_blocks > 0) n->sa.deliver_blocks = deliver_blocks;
   if (spike_lists >= 0) n->sa.spk_lists = spike_lists;
+  return DPSNN_OK;
+}
+
+int dpsnn_set_routing(dpsnn_net* n, int32_t route_blocks) {
+  if (!n || route_blocks < 0 || route_blocks > n->sa.n_tiles) return DPSNN_E_INVAL;
+  if (n->sa.q_cap == 0) return DPSNN_E_STATE;
+  n->sa.route_blocks =
+      route_blocks ? route_blocks : (int32_t)std::min<int64_t>(n->sa.n_tiles, 4096);
   return DPSNN_OK;
 }
 
@@ -716,7 +742,7 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
   if (n_steps == 0) return DPSNN_OK;
   if (n->t + n_steps > (n->sa.plastic ? 0x7FFFFFFFll : 0xFFFFFFFFll)) return DPSNN_E_INVAL;
   const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
-  if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
+  if (last_bin - rate_first_min(n) + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
   // the fused schedule advances both spike-log bases: align them after split
   if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
     HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
@@ -816,7 +842,7 @@ int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
   if (!n || n_steps < 1 || !host_ms) return DPSNN_E_INVAL;
   if (n->t + n_steps > (n->sa.plastic ? 0x7FFFFFFFll : 0xFFFFFFFFll)) return DPSNN_E_INVAL;
   const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
-  if (last_bin - n->rate_first + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
+  if (last_bin - rate_first_min(n) + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
   if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
     HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
   n->last_sched = n->sched;
@@ -875,57 +901,127 @@ int dpsnn_sync(dpsnn_net* n) {
   unsigned long long cnt = 0;
   const int rc = log_count(n, &cnt);
   if (rc != DPSNN_OK) return rc;
-  if ((int64_t)cnt > n->p[0].spike_log_cap) return DPSNN_E_SPIKELOG_FULL;
+  if ((int64_t)cnt > n->p[0].spike_log_cap || n->log_overflow) return DPSNN_E_SPIKELOG_FULL;
   return DPSNN_OK;
+}
+
+// Move the device spike log into the per-network host lists and empty it.
+static int drain_log(dpsnn_net* n) {
+  HIP_OK(hipStreamSynchronize(n->stream));
+  unsigned long long cnt = 0;
+  const int rc = log_count(n, &cnt);
+  if (rc != DPSNN_OK) return rc;
+  if ((int64_t)cnt > n->p[0].spike_log_cap) n->log_overflow = true;
+  const int64_t have = std::min<int64_t>((int64_t)cnt, n->p[0].spike_log_cap);
+  if (have == 0) return DPSNN_OK;
+  std::vector<int2> buf((size_t)have);
+  HIP_OK(hipMemcpy(buf.data(), n->sa.log, (size_t)have * 8, hipMemcpyDeviceToHost));
+  for (const int2& e : buf) {
+    // network of a global id: the last base at or below it
+    const size_t k =
+        (size_t)(std::upper_bound(n->base.begin(), n->base.end(), (int64_t)e.y) -
+                 n->base.begin()) - 1;
+    n->pend[k].push_back(e);
+  }
+  HIP_OK(hipMemsetAsync(n->sa.log_base, 0, 16, n->stream));
+  HIP_OK(hipStreamSynchronize(n->stream));
+  return DPSNN_OK;
+}
+
+static bool by_step_id(const int2& a, const int2& b) {
+  return a.x != b.x ? a.x < b.x : a.y < b.y;
+}
+
+// Hand out the pending spikes of networks [k0, k1), ids minus `off`.
+static int hand_out(dpsnn_net* n, int32_t k0, int32_t k1, int64_t off, int32_t* host_step,
+                    int32_t* host_id, int64_t cap, int64_t* n_out) {
+  int64_t have = 0;
+  for (int32_t k = k0; k < k1; ++k) have += (int64_t)n->pend[k].size();
+  *n_out = have;
+  if (cap < have || (have > 0 && (!host_step || !host_id))) return DPSNN_OK;
+  std::vector<int2> buf;
+  buf.reserve((size_t)have);
+  for (int32_t k = k0; k < k1; ++k) {
+    buf.insert(buf.end(), n->pend[k].begin(), n->pend[k].end());
+    std::vector<int2>().swap(n->pend[k]);
+  }
+  std::sort(buf.begin(), buf.end(), by_step_id);
+  for (int64_t i = 0; i < have; ++i) {
+    host_step[i] = buf[(size_t)i].x;
+    host_id[i] = (int32_t)(buf[(size_t)i].y - off);
+  }
+  const bool overflow = n->log_overflow;
+  n->log_overflow = false;
+  return overflow ? DPSNN_E_SPIKELOG_FULL : DPSNN_OK;
 }
 
 int dpsnn_read_spikes(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_t cap,
                       int64_t* n_out) {
   if (!n || !n_out || cap < 0) return DPSNN_E_INVAL;
-  HIP_OK(hipStreamSynchronize(n->stream));
-  unsigned long long cnt = 0;
-  const int rc = log_count(n, &cnt);
+  const int rc = drain_log(n);
   if (rc != DPSNN_OK) return rc;
-  const bool overflow = (int64_t)cnt > n->p[0].spike_log_cap;
-  const int64_t have = std::min<int64_t>((int64_t)cnt, n->p[0].spike_log_cap);
-  *n_out = have;
-  if (cap < have || (have > 0 && (!host_step || !host_id))) return DPSNN_OK;
-  std::vector<int2> buf((size_t)have);
-  if (have > 0)
-    HIP_OK(hipMemcpy(buf.data(), n->sa.log, (size_t)have * 8, hipMemcpyDeviceToHost));
-  std::sort(buf.begin(), buf.end(), [](const int2& a, const int2& b) {
-    return a.x != b.x ? a.x < b.x : a.y < b.y;
-  });
-  for (int64_t k = 0; k < have; ++k) {
-    host_step[k] = buf[k].x;
-    host_id[k] = buf[k].y;
+  return hand_out(n, 0, (int32_t)n->p.size(), 0, host_step, host_id, cap, n_out);
+}
+
+int dpsnn_read_spikes_net(dpsnn_net* n, int32_t k, int32_t* host_step, int32_t* host_id,
+                          int64_t cap, int64_t* n_out) {
+  if (!n || !n_out || cap < 0 || k < 0 || k >= (int32_t)n->p.size()) return DPSNN_E_INVAL;
+  const int rc = drain_log(n);
+  if (rc != DPSNN_OK) return rc;
+  return hand_out(n, k, k + 1, n->base[k], host_step, host_id, cap, n_out);
+}
+
+// Copy (and clear on the device) the counts of modules [m0, m0 + nm) of
+// bins [first, first + nb) of the rate ring into host [nb][nm][P]: at most
+// two 2-D copies (the ring wraps once).
+static int drain_bins(dpsnn_net* n, int64_t first, int64_t nb, int64_t m0, int64_t nm,
+                      uint32_t* host) {
+  const int64_t P = n->sa.P, per = (int64_t)n->M_total * P;
+  const int64_t cap = n->p[0].rate_bins_cap;
+  for (int64_t b = 0; b < nb;) {
+    const int64_t src = (first + b) % cap;
+    const int64_t run = std::min<int64_t>(nb - b, cap - src);
+    unsigned int* d = n->sa.rates + src * per + m0 * P;
+    HIP_OK(hipMemcpy2D(host + b * nm * P, (size_t)(nm * P * 4), d, (size_t)(per * 4),
+                       (size_t)(nm * P * 4), (size_t)run, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemset2DAsync(d, (size_t)(per * 4), 0, (size_t)(nm * P * 4), (size_t)run,
+                            n->stream));
+    b += run;
   }
-  HIP_OK(hipMemsetAsync(n->sa.log_base, 0, 16, n->stream));
   HIP_OK(hipStreamSynchronize(n->stream));
-  return overflow ? DPSNN_E_SPIKELOG_FULL : DPSNN_OK;
+  return DPSNN_OK;
 }
 
 int dpsnn_read_rates(dpsnn_net* n, uint32_t* host_counts, int64_t cap_bins, int64_t* n_bins) {
   if (!n || !n_bins || cap_bins < 0) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
   const int64_t done = n->t / n->p[0].rate_bin_steps;
-  const int64_t nb = done - n->rate_first;
+  const int64_t first = rate_first_min(n);
+  const int64_t nb = done - first;
   *n_bins = nb;
   if (nb <= 0 || cap_bins < nb || !host_counts) return DPSNN_OK;
-  const int64_t per = (int64_t)n->M_total * n->sa.P;
-  const int64_t cap = n->p[0].rate_bins_cap;
-  for (int64_t b = 0; b < nb; ++b) {
-    const int64_t src = (n->rate_first + b) % cap;
-    HIP_OK(hipMemcpy(host_counts + b * per, n->sa.rates + src * per, (size_t)per * 4,
-                     hipMemcpyDeviceToHost));
-    HIP_OK(hipMemsetAsync(n->sa.rates + src * per, 0, (size_t)per * 4, n->stream));
-  }
-  HIP_OK(hipStreamSynchronize(n->stream));
-  n->rate_first = done;
+  const int rc = drain_bins(n, first, nb, 0, n->M_total, host_counts);
+  if (rc != DPSNN_OK) return rc;
+  std::fill(n->rate_first.begin(), n->rate_first.end(), done);
   return DPSNN_OK;
 }
 
-int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
+int dpsnn_read_rates_net(dpsnn_net* n, int32_t k, uint32_t* host_counts, int64_t cap_bins,
+                         int64_t* n_bins) {
+  if (!n || !n_bins || cap_bins < 0 || k < 0 || k >= (int32_t)n->p.size())
+    return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  const int64_t done = n->t / n->p[0].rate_bin_steps;
+  const int64_t nb = done - n->rate_first[k];
+  *n_bins = nb;
+  if (nb <= 0 || cap_bins < nb || !host_counts) return DPSNN_OK;
+  const int rc = drain_bins(n, n->rate_first[k], nb, n->mbase[k], n->T[k].M, host_counts);
+  if (rc != DPSNN_OK) return rc;
+  n->rate_first[k] = done;
+  return DPSNN_OK;
+}
+
+int dpsnn_stats(dpsnn_net* n, dpsnn_stats_t* out) {
   if (!n || !out) return DPSNN_E_INVAL;
   HIP_OK(hipStreamSynchronize(n->stream));
   unsigned long long ns = 0;
@@ -961,6 +1057,8 @@ int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats* out) {
                                                       : (int32_t)sizeof(QEntry<int64_t>));
   return DPSNN_OK;
 }
+
+int dpsnn_stats_get(dpsnn_net* n, dpsnn_stats_t* out) { return dpsnn_stats(n, out); }
 
 void dpsnn_free(dpsnn_net* n) {
   if (!n) return;
@@ -1097,7 +1195,7 @@ int dpsnn_waves(dpsnn_net* n, const dpsnn_wave_params* wp, dpsnn_wave_result* ou
   if (!n || !wp || !out || wp->net < 0 || wp->net >= (int32_t)n->p.size() || wp->n_bins < 0)
     return DPSNN_E_INVAL;
   const int64_t done = n->t / n->p[0].rate_bin_steps;
-  const int64_t avail = done - n->rate_first;
+  const int64_t avail = done - n->rate_first[wp->net];
   if (avail < 1) return DPSNN_E_STATE;
   const int64_t nb = wp->n_bins > 0 ? std::min<int64_t>(wp->n_bins, avail) : avail;
   if (nb > kWaveMaxBins) return DPSNN_E_INVAL;

@@ -74,7 +74,7 @@ constexpr int kMaxPops = 4;     // populations per module
 constexpr int kMaxAttempts = 64; // draws of a module inside open boundaries
 // how a block of a source's synapses picks the target module
 constexpr int kRuleOwn = 0;      // the source's module
-constexpr int kRuleOthers = 1;   // another module by Eq. 1 (torus)
+constexpr int kRuleOthers = 1;   // another module by Eq. 1
 constexpr int kRuleAll = 2;      // any module by Eq. 1 from d = 0
 
 // Everything dpsnn_build derives from the parameters on the host, in
@@ -325,7 +325,9 @@ struct dpsnn_net {
   int64_t bytes_total = 0, bytes_rows = 0, bytes_state = 0;
   double build_ms = 0.0;
   int64_t t = 0;
-  int64_t rate_first = 0;      // first rate bin not yet drained
+  std::vector<int64_t> rate_first;  // per network: first rate bin it has not drained
+  std::vector<std::vector<int2>> pend;  // per network: drained log entries not yet read
+  bool log_overflow = false;   // the device log overflowed since the last read
   dpsnn::StepArgs sa;
   unsigned char* ctl = nullptr;  // log bases, spike total, step counter, spike-list counts
   int sched = DPSNN_SCHED_SPLIT;
@@ -335,6 +337,7 @@ struct dpsnn_net {
   int graph_K = 0, graph_sched = -1;
   int32_t graph_blocks = 0;     // delivery grid captured in the graph
   int32_t graph_lists = 0;      // spike-list kind captured in the graph
+  int32_t graph_routes = 0;     // routing grid captured in the graph
   hipStream_t graph_stream = nullptr;
   int64_t graph_steps = 128;    // steps per captured graph (0 = no graphs)
 };

@@ -113,7 +113,7 @@ int validate(const dpsnn_params& p) {
       const long nloc = llround(p.frac_local[q] * p.K_out);
       if (M == 1 && nloc < p.K_out) return DPSNN_E_INVAL;  // nowhere remote
     }
-    if (p.torus != 1) return DPSNN_E_INVAL;  // open edges: population model
+    if (p.torus != 0 && p.torus != 1) return DPSNN_E_INVAL;
     return DPSNN_OK;
   }
   if (p.n_pops < 2 || p.n_pops > kMaxPops) return DPSNN_E_INVAL;
@@ -182,7 +182,7 @@ void population_model(const dpsnn_params& p, HostTables& T, PopParams* pp) {
       }
       T.n_blk[q] = b;
     }
-    T.open = 0;
+    T.open = p.torus ? 0 : 1;  // torus = 0: the grid has edges
     return;
   }
   T.P = p.n_pops;
@@ -213,6 +213,27 @@ void population_model(const dpsnn_params& p, HostTables& T, PopParams* pp) {
 }
 
 }  // namespace
+
+static int64_t stored_fix(const dpsnn_params& p, const HostTables& T, int q, int b, int i);
+
+// int32 input slots: the parts of the fixed-point range bound that the
+// parameters alone decide (the per-neuron sum over incoming synapses needs
+// the rows and is checked at build): every single efficacy, the largest
+// external sum of one step, and a plastic efficacy's upper clip w_max must
+// each be below 2^31.
+static int range_check(const dpsnn_params& p, const HostTables& T) {
+  if (p.acc_bits != 32) return DPSNN_OK;
+  const int64_t lim = (int64_t)1 << 31;
+  if (T.ext_bound >= lim) return DPSNN_E_RANGE;
+  if (p.plastic && ldexp(p.stdp_w_max, p.q_frac_bits) >= 2147483647.5) return DPSNN_E_RANGE;
+  for (int q = 0; q < T.P; ++q)
+    for (int b = 0; b < T.tables(q); ++b)
+      for (int i = 0; i < kQuantN; ++i) {
+        const int64_t v = stored_fix(p, T, q, b, i);
+        if (v >= lim || v <= -lim) return DPSNN_E_RANGE;
+      }
+  return DPSNN_OK;
+}
 
 int compute_tables(const dpsnn_params& p, HostTables& T) {
   const int rc = validate(p);
@@ -277,9 +298,9 @@ int compute_tables(const dpsnn_params& p, HostTables& T) {
   //  - to other modules on the torus: (ox, oy) row-major over [0,W) x [0,H)
   //    without (0, 0), d the length of the shortest periodic image;
   //  - to any module on the torus: the same with (0, 0);
-  //  - to any module with open edges: (dx, dy) row-major over
-  //    [-(W-1), W-1] x [-(H-1), H-1], d = |(dx, dy)|; the device repeats a
-  //    draw that leaves the grid.
+  //  - with open edges: (dx, dy) row-major over [-(W-1), W-1] x
+  //    [-(H-1), H-1], d = |(dx, dy)|, without (0, 0) to other modules; the
+  //    device repeats a draw that leaves the grid.
   const int W = p.grid_w, H = p.grid_h;
   std::vector<double> wt;
   T.off_xy.clear();
@@ -295,6 +316,7 @@ int compute_tables(const dpsnn_params& p, HostTables& T) {
   } else {
     for (int dy = 1 - H; dy < H; ++dy)
       for (int dx = 1 - W; dx < W; ++dx) {
+        if (!dx && !dy && !all) continue;
         wt.push_back(exp(-sqrt((double)(dx * dx + dy * dy)) / p.lambda));
         T.off_xy.push_back(dx);
         T.off_xy.push_back(dy);
@@ -355,7 +377,7 @@ int compute_tables(const dpsnn_params& p, HostTables& T) {
     const int64_t bnd = (int64_t)(T.n_pois[q] + 1) * jmax;
     T.ext_bound = std::max(T.ext_bound, bnd);
   }
-  return DPSNN_OK;
+  return range_check(p, T);
 }
 
 // Fixed-point value of a stored efficacy, as the device computes it.

@@ -169,7 +169,11 @@ def lib():
             "dpsnn_sync": ([V], C.c_int),
             "dpsnn_read_spikes": ([V, V, V, C.c_int64, P(C.c_int64)], C.c_int),
             "dpsnn_read_rates": ([V, V, C.c_int64, P(C.c_int64)], C.c_int),
+            "dpsnn_stats": ([V, P(DpsnnStats)], C.c_int),
             "dpsnn_stats_get": ([V, P(DpsnnStats)], C.c_int),
+            "dpsnn_read_spikes_net": ([V, C.c_int32, V, V, C.c_int64, P(C.c_int64)], C.c_int),
+            "dpsnn_read_rates_net": ([V, C.c_int32, V, C.c_int64, P(C.c_int64)], C.c_int),
+            "dpsnn_set_routing": ([V, C.c_int32], C.c_int),
             "dpsnn_free": ([V], None),
             "dpsnn_strerror": ([C.c_int], C.c_char_p),
             "dpsnn_read_state": ([V, V, V, V], C.c_int),
@@ -207,7 +211,8 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_read_slots", "dpsnn_read_rows", "dpsnn_host_table", "dpsnn_set_schedule",
            "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps",
            "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts",
-           "dpsnn_read_plasticity", "dpsnn_set_delivery"]
+           "dpsnn_read_plasticity", "dpsnn_set_delivery", "dpsnn_stats",
+           "dpsnn_read_spikes_net", "dpsnn_read_rates_net", "dpsnn_set_routing"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -283,7 +288,7 @@ class Net:
         self.n_del = int(self.params["d_max"]) - int(self.params["d_min"]) + 1
 
     def stats(self) -> dict:
-        return dpsnn_stats_get(self)
+        return dpsnn_stats(self)
 
     def close(self):
         if self.h:
@@ -345,6 +350,10 @@ def dpsnn_set_delivery(net: Net, deliver_blocks: int = 0, spike_lists: int = -1)
            lib().dpsnn_set_delivery(net.h, int(deliver_blocks), int(spike_lists)))
 
 
+def dpsnn_set_routing(net: Net, route_blocks: int = 0) -> None:
+    _check("dpsnn_set_routing", lib().dpsnn_set_routing(net.h, int(route_blocks)))
+
+
 def dpsnn_set_graph_steps(net: Net, steps: int) -> None:
     _check("dpsnn_set_graph_steps", lib().dpsnn_set_graph_steps(net.h, int(steps)))
 
@@ -378,6 +387,19 @@ def dpsnn_read_spikes(net: Net):
     return st, ids
 
 
+def dpsnn_read_spikes_net(net: Net, k: int):
+    """(steps, network-local ids) of network k of a batch handle."""
+    n = C.c_int64(0)
+    rc = lib().dpsnn_read_spikes_net(net.h, int(k), None, None, 0, C.byref(n))
+    if rc not in (0, -5):
+        _check("dpsnn_read_spikes_net", rc)
+    st = np.zeros(n.value, np.int32)
+    ids = np.zeros(n.value, np.int32)
+    rc = lib().dpsnn_read_spikes_net(net.h, int(k), _ptr(st), _ptr(ids), n.value, C.byref(n))
+    _check("dpsnn_read_spikes_net", rc)
+    return st, ids
+
+
 def dpsnn_read_rates(net: Net) -> np.ndarray:
     nb = C.c_int64(0)
     _check("dpsnn_read_rates", lib().dpsnn_read_rates(net.h, None, 0, C.byref(nb)))
@@ -388,10 +410,26 @@ def dpsnn_read_rates(net: Net) -> np.ndarray:
     return out
 
 
-def dpsnn_stats_get(net: Net) -> dict:
+def dpsnn_read_rates_net(net: Net, k: int) -> np.ndarray:
+    """Rate bins [bins][modules of network k][n_pops] of network k."""
+    nb = C.c_int64(0)
+    _check("dpsnn_read_rates_net",
+           lib().dpsnn_read_rates_net(net.h, int(k), None, 0, C.byref(nb)))
+    m = dpsnn_net_info(net, k)["n_modules"]
+    out = np.zeros((max(nb.value, 0), m, net.n_pops), np.uint32)
+    if nb.value > 0:
+        _check("dpsnn_read_rates_net",
+               lib().dpsnn_read_rates_net(net.h, int(k), _ptr(out), nb.value, C.byref(nb)))
+    return out
+
+
+def dpsnn_stats(net: Net) -> dict:
     s = DpsnnStats()
-    _check("dpsnn_stats_get", lib().dpsnn_stats_get(net.h, C.byref(s)))
+    _check("dpsnn_stats", lib().dpsnn_stats(net.h, C.byref(s)))
     return {name: getattr(s, name) for name, _ in DpsnnStats._fields_}
+
+
+dpsnn_stats_get = dpsnn_stats
 
 
 def dpsnn_free(net: Net) -> None:

@@ -3,8 +3,9 @@ mode) on the 2x2 grid of 1250-neuron modules, SWA and AW, seeds
 1-5, 2 s of biological time each: mean rates after a 0.5 s transient,
 up-state and burst frequencies and per-neuron spike-count histograms.
 
-Calls only the oracle and the output analysis; run from the repository
-root:  python tests/golden/make_fp64_stats.py
+Calls only the oracle package (its EXACT64 simulation and the binary64
+reductions of oracle/stats.py); run from the repository root:
+  python tests/golden/make_fp64_stats.py
 """
 import json
 import multiprocessing as mp
@@ -20,14 +21,15 @@ SEEDS = [1, 2, 3, 4, 5]
 
 def one(job):
     import oracle as O
-    from paper_1902_08410_amd import analysis, workloads as W
+    from oracle import stats
+    from paper_1902_08410_amd import workloads as W
     regime, seed = job
     p = W.swa() if regime == "swa" else W.aw()
     o = O.Oracle(p, seed, mode=O.EXACT64, store_rows=True)
     o.step(STEPS)
     st, ids = o.spikes()
     K, Kexc = p["K"], round(p["frac_exc"] * p["K"])
-    s = analysis.summary(o.rates(), st, ids, o.N, K, Kexc, p["rate_bin_steps"] * p["dt_ms"],
+    s = stats.summary(o.rates(), st, ids, o.N, K, Kexc, p["rate_bin_steps"] * p["dt_ms"],
                          p["dt_ms"], STEPS)
     return regime, seed, s
 

@@ -76,7 +76,7 @@ def _compare_rows(L, net, orc, rows, wd):
 
 
 @pytest.mark.parametrize("case", ["2x2_f32", "tiny_f16", "tiny_i8", "ragged_3x3",
-                                  "odd_7x5", "delays64", "single_delay"])
+                                  "odd_7x5", "delays64", "single_delay", "open_6x3"])
 def test_rows_bitwise_equal(L, case):
     p = {"2x2_f32": W.swa(),
          "tiny_f16": W.tiny(w=3, h=2, K=40, K_out=30, weight_dtype="f16"),
@@ -84,7 +84,8 @@ def test_rows_bitwise_equal(L, case):
          "ragged_3x3": W.tiny(w=3, h=3, K=47, K_out=37, d_max=11),
          "odd_7x5": W.grid(7, 5, "swa", K=60, K_out=130, **{"lambda": 1.7}),
          "delays64": W.tiny(w=2, h=2, K=50, K_out=300, d_min=1, d_max=64),
-         "single_delay": W.tiny(w=2, h=2, K=50, K_out=40, d_min=3, d_max=3)}[case]
+         "single_delay": W.tiny(w=2, h=2, K=50, K_out=40, d_min=3, d_max=3),
+         "open_6x3": W.grid(6, 3, "aw", K=50, K_out=90, torus=0, **{"lambda": 1.3})}[case]
     _say("rows", case)
     net, orc = _pair(p, 7, store_rows=False)
     rows = list(range(net.N)) if net.N <= 5000 else list(range(0, net.N, 3))
@@ -163,6 +164,7 @@ RASTER_CASES = {
                                    nu_ext_hz=[3000.0, 3000.0]),
     "const_drive": W.tiny(w=2, h=2, K=30, K_out=20, I_const=[1.3, 2.1],
                           nu_ext_hz=[0.0, 0.0]),
+    "open_edges_f32": W.tiny(w=4, h=3, K=60, K_out=50, torus=0, nu_ext_hz=[3500.0, 3500.0]),
 }
 
 
@@ -618,3 +620,81 @@ def test_queue_entry_formats(L):
                 orc.step(100)
                 assert _compare_all(L, net, orc, f"code entries {wd} {acc} {sched}") > 0
             net.close()
+
+
+def test_per_network_reads(L):
+    """dpsnn_read_spikes_net / dpsnn_read_rates_net return one network's
+    spikes (network-local ids) and rate bins; what the other networks have
+    not read stays for later reads, and the whole-handle reads return the
+    rest (counts already drained read 0)."""
+    _say("per-network reads")
+    params = [dict(p, spike_log_cap=1 << 20, rate_bins_cap=256) for p, _ in BATCH]
+    seeds = [s for _, s in BATCH]
+    net = L.dpsnn_build_batch(params, seeds)
+    orcs = [O.Oracle(p, s) for p, s in zip(params, seeds)]
+    L.dpsnn_step(net, 700)
+    for o in orcs:
+        o.step(700)
+    st1, id1 = L.dpsnn_read_spikes_net(net, 1)
+    ost, oids = orcs[1].spikes()
+    assert len(st1) > 50
+    assert np.array_equal(st1, ost) and np.array_equal(id1, oids)
+    r0 = L.dpsnn_read_rates_net(net, 0)
+    assert np.array_equal(r0, orcs[0].rates()[:r0.shape[0]])
+    assert L.dpsnn_read_spikes_net(net, 1)[0].size == 0       # drained
+    L.dpsnn_step(net, 300)
+    for o in orcs:
+        o.step(300)
+    # network 1 again: only its spikes of the last 300 steps
+    st1b, id1b = L.dpsnn_read_spikes_net(net, 1)
+    ost, oids = orcs[1].spikes()
+    late = ost >= 700
+    assert np.array_equal(st1b, ost[late]) and np.array_equal(id1b, oids[late])
+    # the whole handle: networks 0 and 2 from the start, global ids
+    st, ids = L.dpsnn_read_spikes(net)
+    parts = _split_spikes(L, net, st, ids)
+    for k in (0, 2):
+        s_k, i_k, _ = parts[k]
+        ost, oids = orcs[k].spikes()
+        assert np.array_equal(s_k, ost) and np.array_equal(i_k, oids), k
+    assert parts[1][0].size == 0
+    rates = L.dpsnn_read_rates(net)
+    info0 = L.dpsnn_net_info(net, 0)
+    mb, m = info0["module_base"], info0["n_modules"]
+    nb0 = r0.shape[0]
+    assert np.all(rates[:nb0, mb:mb + m, :] == 0)          # network 0 read them already
+    assert np.array_equal(rates[nb0:, mb:mb + m, :], orcs[0].rates()[nb0:nb0 + rates.shape[0] -
+                                                                        nb0])
+    for k in (1, 2):
+        info = L.dpsnn_net_info(net, k)
+        mb, m = info["module_base"], info["n_modules"]
+        assert np.array_equal(rates[:, mb:mb + m, :], orcs[k].rates()[:rates.shape[0]]), k
+    assert L.dpsnn_read_rates_net(net, 2).shape[0] == 0
+    with pytest.raises(L.DpsnnError):
+        L.dpsnn_read_spikes_net(net, 3)
+    net.close()
+
+
+def test_routing_grid_below_tile_count(L):
+    """Routing blocks that each walk several tiles (1, 3 and 7 blocks for 11
+    tiles; the 96x96 and batched networks have more tiles than the default
+    4096 blocks), switched between graph replays and direct launches: rasters,
+    state and slots equal the oracle's."""
+    import torch
+    p = W.grid(3, 3, "swa", K=1250, K_out=200)
+    _say("routing grid")
+    with torch.cuda.stream(torch.cuda.Stream()):
+        net, orc = _pair(p, 21)
+        L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+        assert net.stats()["route_blocks"] == 11
+        for k, rb in enumerate([1, 3, 7, 0, 2]):
+            L.dpsnn_set_routing(net, rb)
+            assert net.stats()["route_blocks"] == (rb or 11)
+            n = 300 if k % 2 == 0 else 53
+            L.dpsnn_step(net, n)
+            orc.step(n)
+            assert _compare_all(L, net, orc, f"routing {rb}") > 0
+        for bad in (-1, 12):
+            with pytest.raises(L.DpsnnError):
+                L.dpsnn_set_routing(net, bad)
+        net.close()

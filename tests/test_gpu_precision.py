@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from paper_1902_08410_amd import analysis
+from oracle import stats
 from paper_1902_08410_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -65,7 +65,7 @@ def test_long_run_statistics_vs_fp64(L, wd):
         mb, m = info["module_base"], info["n_modules"]
         sel = (ids >= b) & (ids < b + n)
         p = plist[k]
-        got[r][s] = analysis.summary(rates[:, mb:mb + m, :], st[sel], ids[sel] - b, n,
+        got[r][s] = stats.summary(rates[:, mb:mb + m, :], st[sel], ids[sel] - b, n,
                                      p["K"], round(p["frac_exc"] * p["K"]),
                                      p["rate_bin_steps"] * p["dt_ms"], p["dt_ms"], steps)
     net.close()
@@ -81,10 +81,10 @@ def test_long_run_statistics_vs_fp64(L, wd):
             assert abs(b.mean() - a.mean()) <= tol, (wd, r, key, b.mean(), a.mean(), tol)
         ha = [np.array(x["count_hist"]) for x in ref]
         hb = [np.array(x["count_hist"]) for x in mine]
-        seed_ks = max(analysis.ks_from_hists(ha[i], ha[j])
+        seed_ks = max(stats.ks_from_hists(ha[i], ha[j])
                       for i in range(len(ha)) for j in range(i + 1, len(ha)))
         pool = lambda hs: sum(np.pad(h, (0, 4000 - len(h))) for h in hs)  # noqa: E731
-        ks = analysis.ks_from_hists(pool(hb), pool(ha))
+        ks = stats.ks_from_hists(pool(hb), pool(ha))
         report[(r, "ks")] = (ks, 0.0, max(0.05, seed_ks))
         assert ks <= max(0.05, seed_ks), (wd, r, ks, seed_ks)
     for k, v in report.items():

@@ -54,6 +54,7 @@ PARAM_SETS = {
                                           "acc_bits": 64, "q_frac_bits": 32}),
     "tiny_3x2": W.tiny(w=3, h=2, K=16, K_out=8, tau_c=[300.0, 300.0], I_const=[0.5, 0.2]),
     "odd_7x5": W.grid(7, 5, "swa", **{"lambda": 1.7, "J_sd": [0.3, 0.9]}),
+    "open_6x3": W.grid(6, 3, "aw", torus=0, **{"lambda": 1.3}),
 }
 
 
@@ -83,7 +84,7 @@ def test_f16_table_matches_numpy_rounding():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(torus=0), dict(d_min=0), dict(d_max=0), dict(d_min=1, d_max=65),
+    dict(torus=2), dict(d_min=0), dict(d_max=0), dict(d_min=1, d_max=65),
     {"lambda": 0.0}, {"lambda": -1.0}, dict(grid_w=1, grid_h=1), dict(K=3),
     dict(K_out=5000), dict(acc_bits=16), dict(q_frac_bits=31), dict(weight_dtype=3),
     dict(rate_bin_steps=0), dict(rate_bins_cap=0), dict(spike_log_cap=-1),
@@ -131,7 +132,7 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     lines = []
-    for cname, py in (("dpsnn_params", L.DpsnnParams), ("dpsnn_stats", L.DpsnnStats)):
+    for cname, py in (("dpsnn_params", L.DpsnnParams), ("dpsnn_stats_t", L.DpsnnStats)):
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             cf = "lambda" if f == "lambda_" else f
@@ -147,7 +148,7 @@ def test_struct_layout_matches_header(tmp_path):
     for ln in out.splitlines():
         a, b, v = ln.split()
         got[(a, b)] = int(v)
-    for cname, py in (("dpsnn_params", L.DpsnnParams), ("dpsnn_stats", L.DpsnnStats)):
+    for cname, py in (("dpsnn_params", L.DpsnnParams), ("dpsnn_stats_t", L.DpsnnStats)):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
@@ -259,3 +260,29 @@ def test_handle_setters_reject_a_null_handle():
     assert lib.dpsnn_set_delivery(None, 256, 1) == E
     assert lib.dpsnn_set_schedule(None, L.SCHED_SPLIT) == E
     assert lib.dpsnn_set_graph_steps(None, 64) == E
+
+
+@pytest.mark.parametrize("over", [
+    # the external sum of one step leaves int32 at Q = 16
+    dict(Jext_mean=[20000.0, 20000.0], Jext_sd=[0.0, 0.0], nu_ext_hz=[30000.0, 30000.0]),
+    # a single efficacy does not fit int32 at Q = 16
+    dict(J_mean=[40000.0, -2.0]),
+    # a plastic efficacy may grow to w_max = 2^15 mV = 2^31 at Q = 16
+    dict(plastic=1, stdp_update_steps=100, stdp_tau_plus=2.0, stdp_tau_minus=2.0,
+         stdp_tau_y=5.0, stdp_w_max=32768.0),
+])
+def test_fixed_point_range_errors_before_any_device_call(over):
+    """DPSNN_E_RANGE: the int32 bounds that the parameters alone decide are
+    checked on the host (tables and dpsnn_build) before any device work; the
+    same parameters with int64 slots (Q = 32) are valid."""
+    import ctypes as C
+    p = W.swa(rate_bins_cap=16, spike_log_cap=16, **over)
+    with pytest.raises(L.DpsnnError) as e:
+        L.dpsnn_host_table(p, "prop_f64", np.float64)
+    assert e.value.code == -4
+    h = C.c_void_p()
+    assert L.lib().dpsnn_build(C.byref(L.to_struct(p)), C.c_uint64(1), C.byref(h)) == -4
+    assert not h.value
+    if not over.get("plastic"):
+        p64 = dict(p, acc_bits=64, q_frac_bits=32)
+        assert len(L.dpsnn_host_table(p64, "prop_f64", np.float64)) == 8

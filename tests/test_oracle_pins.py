@@ -593,3 +593,108 @@ def test_table_s1_states_give_the_paper_rates():
         st, _ = o.spikes()
         rate = (st >= 1000).sum() / o.N / 0.9
         assert abs(rate - hz) <= 0.25 * hz, (state, rate)
+
+
+# --------------------------------------------------------------------------
+# int8 efficacies (stored codes with one binary32 scale per source
+# population; the paper stores weights in 2 bytes, Table 1): every table
+# entry is checked against what the format definition fixes exactly, with
+# rational arithmetic, not by re-running the oracle's own conversion.
+def _ulp32(x: float) -> float:
+    x = np.float32(abs(x))
+    return float(np.nextafter(x, np.float32(np.inf)) - x)
+
+
+@pytest.mark.parametrize("params", [
+    W.swa(weight_dtype="i8"),
+    W.grid(3, 3, "aw", weight_dtype="i8", J_sd=[0.3, 0.9]),
+    W.grid(2, 2, "swa", weight_dtype="i8", acc_bits=64, q_frac_bits=32),
+    W.fbi(2, 2, "sw", scale=0.1, weight_dtype="i8"),
+])
+def test_int8_codes_scale_and_fixed_point_exact(params):
+    from fractions import Fraction as F
+    o = O.Oracle(params, 3, store_rows=False)
+    P = o.table("s8", np.float32).size
+    s8 = o.table("s8", np.float32)
+    s8fix = o.table("s8fix", np.int64)
+    two_q = F(2) ** params["q_frac_bits"]
+    for q in range(P):
+        names = [f"_{q}"]
+        b = 1
+        while True:  # further blocks of the source population, if any
+            try:
+                o.table(f"wt64_{q}_{b}", np.float64)
+            except Exception:
+                break
+            names.append(f"_{q}_{b}")
+            b += 1
+        w64 = [o.table("wt64" + n, np.float64) for n in names]
+        codes = [o.table("wq8" + n, np.int8).astype(np.int64) for n in names]
+        wfix = [o.table("wfix" + n, np.int64) for n in names]
+        amax = max(float(np.max(np.abs(w))) for w in w64)
+        s = float(s8[q])
+        # the scale is max|w| / 127 rounded once to binary32
+        assert abs(F(s) - F(amax) / 127) <= F(_ulp32(s)) / 2
+        # its fixed-point value is the nearest integer to s * 2^Q
+        assert abs(F(int(s8fix[q])) - F(s) * two_q) <= F(1, 2)
+        for w, c, fx in zip(w64, codes, wfix):
+            assert np.all(np.abs(c) <= 127)
+            # nearest code: |c s - w| <= s / 2 (a floor, a truncation or a
+            # wrong scale breaks this on some entry)
+            err = np.abs(c.astype(np.float64) * s - w)
+            assert np.max(err) <= 0.5 * s * (1 + 1e-12) + 1e-15, (q, np.max(err) / s)
+            # the largest |w| takes the largest code
+            at = np.abs(w) == amax
+            if at.any():
+                assert np.all(np.abs(c[at]) == 127)
+            # the contribution in fixed point is code * rint(s 2^Q) exactly
+            assert np.array_equal(fx, c * int(s8fix[q]))
+
+
+def test_oracle_flags_int32_range_overflow():
+    """A per-step input sum outside int32 sets ORC_E_RANGE (int64 slots do
+    not); the fixed-point bound of the int32 slots is a stated limit."""
+    big = dict(W.tiny(w=2, h=2, K=16, K_out=8), nu_ext_hz=[30000.0, 30000.0],
+               Jext_mean=[20000.0, 20000.0], Jext_sd=[0.0, 0.0])
+    o = O.Oracle(big, 5, store_rows=False)
+    assert o.step(20) == -4
+    assert o.status == -4
+    o64 = O.Oracle(dict(big, acc_bits=64), 5, store_rows=False)
+    assert o64.step(20) == 0
+    small = O.Oracle(W.tiny(w=2, h=2, K=16, K_out=8), 5, store_rows=False)
+    assert small.step(50) == 0
+
+
+@pytest.mark.parametrize("torus", [False, True])
+def test_eq1_remote_modules_two_population_model(torus):
+    """Remote synapses of the two-population model pick another module with
+    probability exp(-d/lambda) over the other modules that exist (open
+    edges, Sec. 2.2) or over the periodic images (torus) — chi-square
+    against the law computed directly, for corner, edge and interior
+    sources; the local block stays in the source's module."""
+    from scipy import stats
+    w, h, lam = 5, 4, 1.3
+    p = W.grid(w, h, "swa", K=40, K_out=60, torus=1 if torus else 0, **{"lambda": lam})
+    o = O.Oracle(p, 9, store_rows=False)
+    K, n_loc = p["K"], 30
+    for src in (0, 2, 7, 19):
+        counts = np.zeros(w * h)
+        for l in range(K):
+            s = src * K + l
+            tgt, dl, wi, _ = o.gen_row(s)
+            mods = tgt // K
+            # rows are sorted by delay: take the draw blocks by counting
+            assert (mods == src).sum() >= n_loc
+            counts += np.bincount(mods, minlength=w * h)
+        counts[src] -= K * n_loc                 # the local block
+        assert counts[src] == 0
+        law = _module_law(w, h, src, lam, torus)
+        law[src] = 0.0
+        exp = law / law.sum() * counts.sum()
+        keep = exp >= 5
+        obs = np.append(counts[keep], counts[~keep].sum())
+        ex = np.append(exp[keep], exp[~keep].sum())
+        if ex[-1] == 0:
+            obs, ex = obs[:-1], ex[:-1]
+        chi2 = ((obs - ex) ** 2 / ex).sum()
+        assert stats.chi2.sf(chi2, len(ex) - 1) > 1e-4, (src, chi2)
