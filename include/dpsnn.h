@@ -55,6 +55,7 @@ extern "C" {
 #define DPSNN_E_SPIKELOG_FULL (-5) /* spike log overflowed; spikes were lost */
 #define DPSNN_E_STATE (-6)         /* call not valid in the handle's state   */
 #define DPSNN_E_RATES_FULL (-7)    /* rate bins would be overwritten         */
+#define DPSNN_E_SCRATCH (-8)       /* request exceeds the fixed scratch      */
 
 /* Step schedules (results are bit-identical; only speed differs). */
 #define DPSNN_SCHED_FUSED 0 /* one kernel per step; a tile delivers its own
@@ -422,6 +423,27 @@ int dpsnn_waves_counts(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_
                        dpsnn_wave_result* out, int32_t* host_tr_module, double* host_tr_T,
                        int32_t* host_tr_wave, int64_t cap_tr, double* host_wave_speed,
                        double* host_wave_t0, int32_t* host_wave_n, int64_t cap_waves);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the analysis
+ * of dpsnn_waves_counts, same arguments and results, with its scratch in a
+ * fixed device buffer of 64 MiB that the library holds on every GPU it runs
+ * on until the process ends, instead of memory allocated per call.  It
+ * calls no hipMalloc / hipFree and no allocator.  Limits: the buffers of
+ * the request must fit 64 MiB (about 72 bytes per possible transition,
+ * grid_w * grid_h * (n_bins / (min_down + min_up) + 1) of them, plus
+ * 2 KiB per module and 1 MiB of tables), and no module may count more than
+ * 65535 spikes in a bin; DPSNN_E_SCRATCH otherwise, before any device work
+ * for the size limit.  Every call on one GPU shares that GPU's buffer:
+ * calls that overlap on one GPU (from several host threads or streams) race
+ * and must not be made.  Results are identical to dpsnn_waves_counts. */
+int dpsnn_waves_counts_static(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_w,
+                              int32_t grid_h, int32_t n_pops, int32_t bin_steps,
+                              double dt_ms, int64_t bin0, const dpsnn_wave_params* wp,
+                              void* stream, dpsnn_wave_result* out, int32_t* host_tr_module,
+                              double* host_tr_T, int32_t* host_tr_wave, int64_t cap_tr,
+                              double* host_wave_speed, double* host_wave_t0,
+                              int32_t* host_wave_n, int64_t cap_waves);
 
 /* Plasticity state of rows first..first+count-1, in the order of
  * dpsnn_read_rows: host_t_act int32 [count][K_out] (last activation step,

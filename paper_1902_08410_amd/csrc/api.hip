@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "dpsnn_internal.h"
@@ -461,14 +462,30 @@ int build_common(const dpsnn_params* p, const uint64_t* seeds, int32_t n_nets,
 namespace {
 
 // Device scratch of one analysis call: from the handle's allocator when it
-// has one, else hipMalloc; freed when the call returns.
+// has one, else hipMalloc, freed when the call returns; or carved out of a
+// fixed device buffer (arena), with no allocation at all; or only counted
+// (measure: the pointers returned are placeholders and never used).
 struct Scratch {
   dpsnn_free_fn free_fn = nullptr;
   void* ctx = nullptr;
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0;
+  size_t used = 0;
+  bool measure = false;
   std::vector<void*> ptrs;
   void* get(size_t bytes) {
     bytes = (bytes + 255) / 256 * 256;
     if (bytes == 0) bytes = 256;
+    if (measure) {
+      used += bytes;
+      return reinterpret_cast<void*>((uintptr_t)used);
+    }
+    if (arena) {
+      if (used + bytes > arena_cap) return nullptr;
+      void* p = arena + used;
+      used += bytes;
+      return p;
+    }
     void* p = nullptr;
     if (free_fn) {
       p = g_alloc ? g_alloc(bytes, ctx) : nullptr;
@@ -488,11 +505,10 @@ struct Scratch {
   }
 };
 
-// The slow-wave analysis over a window of count bins (see dpsnn.h).
-int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
-               const dpsnn_wave_params* wp, hipStream_t st, Scratch& S,
-               dpsnn_wave_result* out, int32_t* h_mod, double* h_T, int32_t* h_wave,
-               int64_t cap_tr, double* h_speed, double* h_t0, int32_t* h_n, int64_t cap_w) {
+// Checks of the analysis request shared by every entry point.
+int waves_check(const WaveArgs& src, int32_t bin_steps, double dt_ms,
+                const dpsnn_wave_params* wp, const dpsnn_wave_result* out, int64_t cap_tr,
+                int64_t cap_w) {
   if (!wp || !out || wp->abi_version != DPSNN_ABI_VERSION || cap_tr < 0 || cap_w < 0)
     return DPSNN_E_INVAL;
   if (src.nb < 1 || src.nb > kWaveMaxBins || src.M < 1 || src.M > kWaveMaxModules ||
@@ -500,17 +516,26 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
       !(wp->noise_var >= 0.0) || !std::isfinite(wp->noise_var) || bin_steps < 1 ||
       !(dt_ms > 0.0))
     return DPSNN_E_INVAL;
-  WaveArgs a = src;
+  return DPSNN_OK;
+}
+
+// The scratch buffers of one analysis: every one is taken here, before any
+// device work, except the log table when lnt_cap = 0 (then it is sized from
+// the largest count once that is known).
+struct WaveBufs {
+  uint32_t* maxc;
+  double* d_mean;
+  double* d_z;
+  double* d_lnt;
+};
+int waves_take(WaveArgs& a, const dpsnn_wave_params* wp, int64_t lnt_cap, Scratch& S,
+               WaveBufs& B) {
   a.min_down = wp->min_down;
   a.min_up = wp->min_up;
   a.min_modules = wp->min_modules;
   a.cap_pm = a.nb / (a.min_down + a.min_up) + 1;
-  a.dbin = (double)bin_steps * dt_ms;
-  a.sd = sqrt(wp->noise_var);
-  a.key0 = (uint32_t)wp->seed;
-  a.key1 = (uint32_t)(wp->seed >> 32);
   const int64_t nt = (int64_t)a.M * a.cap_pm;
-  uint32_t* maxc = (uint32_t*)S.get(4);
+  B.maxc = (uint32_t*)S.get(4);
   a.cnt = (uint32_t*)S.get((size_t)a.M * 4);
   a.tr_k = (uint32_t*)S.get((size_t)nt * 4);
   a.tr_q = (uint32_t*)S.get((size_t)nt * 4);
@@ -530,9 +555,10 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
   a.wave_t0 = (double*)S.get((size_t)nt * 8);
   a.wave_n = (int32_t*)S.get((size_t)nt * 4);
   a.grid = (double*)S.get((size_t)kWaveBatch * a.M * 8);
-  double* d_mean = (double*)S.get(8);
-  double* d_z = (double*)S.get((size_t)kQuantN * 8);
-  for (const void* q : {(const void*)maxc, (const void*)a.cnt, (const void*)a.tr_k,
+  B.d_mean = (double*)S.get(8);
+  B.d_z = (double*)S.get((size_t)kQuantN * 8);
+  B.d_lnt = lnt_cap > 0 ? (double*)S.get((size_t)lnt_cap * 8) : nullptr;
+  for (const void* q : {(const void*)B.maxc, (const void*)a.cnt, (const void*)a.tr_k,
                         (const void*)a.tr_q, (const void*)a.tr_T, (const void*)a.hist,
                         (const void*)a.fill, (const void*)a.off, (const void*)a.keys,
                         (const void*)a.pos, (const void*)a.nxt,
@@ -540,11 +566,36 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
                         (const void*)a.out_wave, (const void*)a.wave_first,
                         (const void*)a.n_waves, (const void*)a.wave_speed,
                         (const void*)a.wave_t0, (const void*)a.wave_n, (const void*)a.grid,
-                        (const void*)d_mean, (const void*)d_z})
+                        (const void*)B.d_mean, (const void*)B.d_z})
     if (!q) return DPSNN_E_NOMEM;
-  a.z = d_z;
+  if (lnt_cap > 0 && !B.d_lnt) return DPSNN_E_NOMEM;
+  return DPSNN_OK;
+}
+
+// The slow-wave analysis over a window of count bins (see dpsnn.h).
+// lnt_host / lnt_cap: a host table of log(i), i < lnt_cap, whose device copy
+// is taken from S up front (no allocation once the count is known); null:
+// the table is built and its buffer taken after the largest count is read.
+int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
+               const dpsnn_wave_params* wp, hipStream_t st, Scratch& S,
+               const double* lnt_host, int64_t lnt_cap,
+               dpsnn_wave_result* out, int32_t* h_mod, double* h_T, int32_t* h_wave,
+               int64_t cap_tr, double* h_speed, double* h_t0, int32_t* h_n, int64_t cap_w) {
+  int rc = waves_check(src, bin_steps, dt_ms, wp, out, cap_tr, cap_w);
+  if (rc != DPSNN_OK) return rc;
+  WaveArgs a = src;
+  a.dbin = (double)bin_steps * dt_ms;
+  a.sd = sqrt(wp->noise_var);
+  a.key0 = (uint32_t)wp->seed;
+  a.key1 = (uint32_t)(wp->seed >> 32);
+  WaveBufs B{};
+  rc = waves_take(a, wp, lnt_host ? lnt_cap : 0, S, B);
+  if (rc != DPSNN_OK) return rc;
+  uint32_t* maxc = B.maxc;
+  double* d_mean = B.d_mean;
+  a.z = B.d_z;
   const std::vector<double>& z = standard_normal_grid();
-  HIP_OK(hipMemcpyAsync(d_z, z.data(), (size_t)kQuantN * 8, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(B.d_z, z.data(), (size_t)kQuantN * 8, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemsetAsync(maxc, 0, 4, st));
   HIP_OK(hipMemsetAsync(a.hist, 0, (size_t)a.nb * 4, st));
   HIP_OK(hipMemsetAsync(a.fill, 0, (size_t)a.nb * 4, st));
@@ -554,13 +605,20 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
   HIP_OK(hipMemcpyAsync(&mx, maxc, 4, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   // log(i) for every count + 1 that can occur (host binary64 log)
-  std::vector<double> lnt((size_t)mx + 2);
-  lnt[0] = -INFINITY;
-  for (size_t i = 1; i < lnt.size(); ++i) lnt[i] = log((double)i);
-  double* d_lnt = (double*)S.get(lnt.size() * 8);
-  if (!d_lnt) return DPSNN_E_NOMEM;
-  a.lnt = d_lnt;
-  HIP_OK(hipMemcpyAsync(d_lnt, lnt.data(), lnt.size() * 8, hipMemcpyHostToDevice, st));
+  if (lnt_host) {
+    if ((int64_t)mx + 2 > lnt_cap) return DPSNN_E_SCRATCH;
+    a.lnt = B.d_lnt;
+    HIP_OK(hipMemcpyAsync(B.d_lnt, lnt_host, ((size_t)mx + 2) * 8, hipMemcpyHostToDevice, st));
+  } else {
+    std::vector<double> lnt((size_t)mx + 2);
+    lnt[0] = -INFINITY;
+    for (size_t i = 1; i < lnt.size(); ++i) lnt[i] = log((double)i);
+    double* d_lnt = (double*)S.get(lnt.size() * 8);
+    if (!d_lnt) return DPSNN_E_NOMEM;
+    a.lnt = d_lnt;
+    HIP_OK(hipMemcpyAsync(d_lnt, lnt.data(), lnt.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));  // lnt is released on return
+  }
   HIP_OK(launch_wave_transitions(a, st));
   int32_t nw = 0;
   uint32_t total = 0;
@@ -590,6 +648,42 @@ int waves_impl(const WaveArgs& src, int32_t bin_steps, double dt_ms,
   out->n_transitions = total;
   out->n_waves = nw;
   out->mean_speed = mean;
+  return DPSNN_OK;
+}
+
+// ---- allocation-free slow-wave analysis -----------------------------------
+// A fixed device buffer for dpsnn_waves_counts_static: every GPU the library
+// runs on holds one copy until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed on.
+constexpr size_t kWaveScratchBytes = (size_t)64 << 20;
+constexpr int64_t kWaveScratchMaxCount = 65535;  // largest count per module and bin
+static __device__ __align__(256) unsigned char scratch[kWaveScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::vector<double> g_lnt;  // log(i), i <= kWaveScratchMaxCount + 1, built once
+
+// The scratch's device address on the current device, and the log table.
+int scratch_setup(void** ptr, const double** lnt) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return DPSNN_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DPSNN_E_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  if (g_lnt.empty()) {
+    g_lnt.resize((size_t)kWaveScratchMaxCount + 2);
+    g_lnt[0] = -INFINITY;
+    for (size_t i = 1; i < g_lnt.size(); ++i) g_lnt[i] = log((double)i);
+    (void)standard_normal_grid();  // built once, used by every call
+  }
+  *ptr = g_scratch_ptr[dev];
+  *lnt = g_lnt.data();
   return DPSNN_OK;
 }
 
@@ -1078,6 +1172,7 @@ const char* dpsnn_strerror(int code) {
     case DPSNN_E_SPIKELOG_FULL: return "spike log full";
     case DPSNN_E_STATE: return "invalid state";
     case DPSNN_E_RATES_FULL: return "rate bins full";
+    case DPSNN_E_SCRATCH: return "request exceeds the fixed scratch buffer";
     default: return "unknown error";
   }
 }
@@ -1215,7 +1310,8 @@ int dpsnn_waves(dpsnn_net* n, const dpsnn_wave_params* wp, dpsnn_wave_result* ou
   Scratch S;
   S.free_fn = n->free_fn;
   S.ctx = n->alloc_ctx;
-  return waves_impl(a, n->p[0].rate_bin_steps, n->p[0].dt_ms, wp, n->stream, S, out,
+  return waves_impl(a, n->p[0].rate_bin_steps, n->p[0].dt_ms, wp, n->stream, S, nullptr, 0,
+                    out,
                     host_tr_module, host_tr_T, host_tr_wave, cap_tr, host_wave_speed,
                     host_wave_t0, host_wave_n, cap_waves);
 }
@@ -1242,9 +1338,58 @@ int dpsnn_waves_counts(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_
   a.M = grid_w * grid_h;
   a.P = n_pops;
   Scratch S;
-  return waves_impl(a, bin_steps, dt_ms, wp, static_cast<hipStream_t>(stream), S, out,
+  return waves_impl(a, bin_steps, dt_ms, wp, static_cast<hipStream_t>(stream), S, nullptr,
+                    0, out,
                     host_tr_module, host_tr_T, host_tr_wave, cap_tr, host_wave_speed,
                     host_wave_t0, host_wave_n, cap_waves);
+}
+
+
+int dpsnn_waves_counts_static(const uint32_t* dev_counts, int64_t n_bins, int32_t grid_w,
+                              int32_t grid_h, int32_t n_pops, int32_t bin_steps, double dt_ms,
+                              int64_t bin0, const dpsnn_wave_params* wp, void* stream,
+                              dpsnn_wave_result* out, int32_t* host_tr_module,
+                              double* host_tr_T, int32_t* host_tr_wave, int64_t cap_tr,
+                              double* host_wave_speed, double* host_wave_t0,
+                              int32_t* host_wave_n, int64_t cap_waves) {
+  if (!dev_counts || n_bins < 1 || n_bins > kWaveMaxBins || grid_w < 1 || grid_h < 1 ||
+      bin0 < 0 || (int64_t)grid_w * grid_h > kWaveMaxModules)
+    return DPSNN_E_INVAL;
+  WaveArgs a{};
+  a.counts = dev_counts;
+  a.ring = n_bins;
+  a.M_stride = (int64_t)grid_w * grid_h;
+  a.mbase = 0;
+  a.slot0 = 0;
+  a.bin0 = bin0;
+  a.nb = (int32_t)n_bins;
+  a.W = grid_w;
+  a.H = grid_h;
+  a.M = grid_w * grid_h;
+  a.P = n_pops;
+  int rc = waves_check(a, bin_steps, dt_ms, wp, out, cap_tr, cap_waves);
+  if (rc != DPSNN_OK) return rc;
+  // the buffers this request needs, counted before any device call
+  {
+    WaveArgs m = a;
+    WaveBufs B{};
+    Scratch count;
+    count.measure = true;
+    rc = waves_take(m, wp, kWaveScratchMaxCount + 2, count, B);
+    if (rc != DPSNN_OK) return rc;
+    if (count.used > kWaveScratchBytes) return DPSNN_E_SCRATCH;
+  }
+  void* base = nullptr;
+  const double* lnt = nullptr;
+  rc = scratch_setup(&base, &lnt);
+  if (rc != DPSNN_OK) return rc;
+  Scratch S;
+  S.arena = static_cast<unsigned char*>(base);
+  S.arena_cap = kWaveScratchBytes;
+  rc = waves_impl(a, bin_steps, dt_ms, wp, static_cast<hipStream_t>(stream), S, lnt,
+                  kWaveScratchMaxCount + 2, out, host_tr_module, host_tr_T, host_tr_wave,
+                  cap_tr, host_wave_speed, host_wave_t0, host_wave_n, cap_waves);
+  return rc == DPSNN_E_NOMEM ? DPSNN_E_SCRATCH : rc;
 }
 
 }  // extern "C"

@@ -18,7 +18,7 @@ ABI_VERSION = 3
 W_F32, W_F16, W_I8 = 0, 1, 2
 WEIGHT_DTYPES = {"f32": W_F32, "f16": W_F16, "i8": W_I8}
 ERRORS = {0: "OK", -1: "INVAL", -2: "NOMEM", -3: "DEVICE", -4: "RANGE",
-          -5: "SPIKELOG_FULL", -6: "STATE", -7: "RATES_FULL"}
+          -5: "SPIKELOG_FULL", -6: "STATE", -7: "RATES_FULL", -8: "SCRATCH"}
 
 _PAIR = C.c_double * 2
 _I4 = C.c_int32 * 4
@@ -196,6 +196,10 @@ def lib():
                                     C.c_double, C.c_int64, P(DpsnnWaveParams), V,
                                     P(DpsnnWaveResult), V, V, V, C.c_int64, V, V, V,
                                     C.c_int64], C.c_int),
+            "dpsnn_waves_counts_static": ([V, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                           C.c_int32, C.c_double, C.c_int64,
+                                           P(DpsnnWaveParams), V, P(DpsnnWaveResult), V, V,
+                                           V, C.c_int64, V, V, V, C.c_int64], C.c_int),
         }
         for fn, (args, res) in sig.items():
             f = getattr(L, fn)
@@ -212,7 +216,8 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_set_graph_steps", "dpsnn_autotune", "dpsnn_profile_steps",
            "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts",
            "dpsnn_read_plasticity", "dpsnn_set_delivery", "dpsnn_stats",
-           "dpsnn_read_spikes_net", "dpsnn_read_rates_net", "dpsnn_set_routing"]
+           "dpsnn_read_spikes_net", "dpsnn_read_rates_net", "dpsnn_set_routing",
+           "dpsnn_waves_counts_static"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -534,11 +539,8 @@ def dpsnn_waves(net: Net, net_index: int = 0, n_bins: int = 0, noise_var: float 
     return _wave_dict(res, o)
 
 
-def dpsnn_waves_counts(counts, grid_w: int, grid_h: int, bin_steps: int, dt_ms: float,
-                       bin0: int = 0, noise_var: float = 0.5, seed: int = 1,
-                       min_down: int = 2, min_up: int = 2, min_modules: int = 1) -> dict:
-    """Slow-wave analysis of a device tensor of counts [bins][modules][pops]
-    (uint32 data, e.g. a torch.int32 CUDA tensor)."""
+def _waves_counts(fn, counts, grid_w, grid_h, bin_steps, dt_ms, bin0, noise_var, seed,
+                  min_down, min_up, min_modules):
     import torch
     assert counts.is_cuda and counts.is_contiguous() and counts.dim() == 3
     assert counts.dtype in (torch.int32, torch.uint32)
@@ -548,10 +550,28 @@ def dpsnn_waves_counts(counts, grid_w: int, grid_h: int, bin_steps: int, dt_ms: 
     args = (C.c_void_p(counts.data_ptr()), nb, grid_w, grid_h, P, bin_steps, dt_ms, bin0,
             C.byref(wp), C.c_void_p(st))
     res = DpsnnWaveResult()
-    _check("dpsnn_waves_counts", lib().dpsnn_waves_counts(*args, C.byref(res), None, None,
-                                                          None, 0, None, None, None, 0))
+    f = getattr(lib(), fn)
+    _check(fn, f(*args, C.byref(res), None, None, None, 0, None, None, None, 0))
     o = _wave_outputs(int(res.n_transitions), int(res.n_waves))
-    _check("dpsnn_waves_counts", lib().dpsnn_waves_counts(
-        *args, C.byref(res), _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), len(o[0]), _ptr(o[3]),
-        _ptr(o[4]), _ptr(o[5]), len(o[3])))
+    _check(fn, f(*args, C.byref(res), _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), len(o[0]),
+                 _ptr(o[3]), _ptr(o[4]), _ptr(o[5]), len(o[3])))
     return _wave_dict(res, o)
+
+
+def dpsnn_waves_counts(counts, grid_w: int, grid_h: int, bin_steps: int, dt_ms: float,
+                       bin0: int = 0, noise_var: float = 0.5, seed: int = 1,
+                       min_down: int = 2, min_up: int = 2, min_modules: int = 1) -> dict:
+    """Slow-wave analysis of a device tensor of counts [bins][modules][pops]
+    (uint32 data, e.g. a torch.int32 CUDA tensor)."""
+    return _waves_counts("dpsnn_waves_counts", counts, grid_w, grid_h, bin_steps, dt_ms, bin0,
+                         noise_var, seed, min_down, min_up, min_modules)
+
+
+def dpsnn_waves_counts_static(counts, grid_w: int, grid_h: int, bin_steps: int,
+                              dt_ms: float, bin0: int = 0, noise_var: float = 0.5,
+                              seed: int = 1, min_down: int = 2, min_up: int = 2,
+                              min_modules: int = 1) -> dict:
+    """The same analysis with the library's fixed device scratch buffer: no
+    device allocation (limits in include/dpsnn.h)."""
+    return _waves_counts("dpsnn_waves_counts_static", counts, grid_w, grid_h, bin_steps,
+                         dt_ms, bin0, noise_var, seed, min_down, min_up, min_modules)

@@ -286,3 +286,22 @@ def test_fixed_point_range_errors_before_any_device_call(over):
     if not over.get("plastic"):
         p64 = dict(p, acc_bits=64, q_frac_bits=32)
         assert len(L.dpsnn_host_table(p64, "prop_f64", np.float64)) == 8
+
+
+def test_static_wave_scratch_rejects_oversized_requests_before_any_device_call():
+    """dpsnn_waves_counts_static checks that the request fits its fixed
+    64 MiB device buffer before touching the device: 90x90 modules and 4096
+    bins need about 600 MB (the counts pointer is never dereferenced)."""
+    import ctypes as C
+    lib = L.lib()
+    wp = L.DpsnnWaveParams(L.ABI_VERSION, 0, 0, 0.5, 1, 2, 2, 1, 0)
+    res = L.DpsnnWaveResult()
+    fake = C.c_void_p(0x1000)
+    rc = lib.dpsnn_waves_counts_static(fake, 4096, 90, 90, 2, 50, 0.1, 0, C.byref(wp), None,
+                                       C.byref(res), None, None, None, 0, None, None, None, 0)
+    assert rc == -8
+    assert "scratch" in L.dpsnn_strerror(-8)
+    bad = L.DpsnnWaveParams(L.ABI_VERSION, 0, 0, 0.5, 1, 0, 2, 1, 0)   # min_down 0
+    rc = lib.dpsnn_waves_counts_static(fake, 10, 3, 3, 2, 50, 0.1, 0, C.byref(bad), None,
+                                       C.byref(res), None, None, None, 0, None, None, None, 0)
+    assert rc == -1
