@@ -1,20 +1,23 @@
 """Benchmark: synaptic events per second on one MI355X.
 
-Default workload (the configuration the metric is quoted on): a 24x24 grid
-of modules of 1250 LIF-SFA neurons (720k neurons, 0.72G synapses,
+Default workload (the configuration the metric is quoted on): a 48x48 grid
+of modules of 1250 LIF-SFA neurons (2.88M neurons, 2.88G synapses,
 out-degree 1000, half local, Eq. 1 remote connectivity with lambda = 1 on a
-torus, delays 1-20 steps of 0.1 ms), FP32 efficacies, int32 fixed-point
-input slots; one slow-wave (SWA) and one asynchronous-wake (AW) network
-advance side by side.  One benchmark step = 1 s of biological time (10 000
-steps of dt) of both networks.  Inputs are synthetic and seeded; the
-networks are built (connectivity generated on the device) before the timed
-region.
+torus, delays 1-20 steps of 0.1 ms), int32 fixed-point input slots; one
+slow-wave (SWA) and one asynchronous-wake (AW) network advance side by side,
+with binary32 efficacies (the headline value), then with binary16 and with
+int8 efficacies (per source population scale), each weight format timed
+with the same protocol (warm-up, autotune, HIP-graph replay, event-timed
+kernels).  One benchmark step = 4000 steps of dt (0.4 s of biological time)
+of both networks.  Inputs are synthetic and seeded; the networks are built
+(connectivity generated on the device) before the timed region.
 
-Other workloads: --workload sweep64 (64 networks of 4x4 to 16x16 modules in one
-batched handle, FP16 efficacies), --workload grid96 (96x96 modules, 11.52M
-neurons, int8 efficacies, int64 slots), --workload fbi24 (24x24 modules of
-the foreground / background / inhibitory populations of Sec. 2.2 with the
-Table S1 states, open boundaries).
+Other workloads: --workload grid24 (24x24 modules, FP32), sweep64 (64
+networks of 4x4 to 16x16 modules in one batched handle, FP16 efficacies),
+grid96 (96x96 modules, 11.52M neurons, int8 efficacies, int64 slots), fbi24
+(24x24 modules of the foreground / background / inhibitory populations of
+Sec. 2.2 with the Table S1 states, open boundaries), stdp24 (24x24 with
+plasticity).  --lambda sets the decay length of the grid workloads.
 
 Prints one JSON line.
 """
@@ -61,7 +64,12 @@ def bytes_per_event(p) -> float:
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_08410_amd", "csrc", "kernels.hip")
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_deliver_k_neuron_grid24_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
+EXT_TRAINS = 400  # external Poisson trains per neuron of the paper's model (Table S1)
+
+
+def traffic_json(workload: str, wdt: str) -> str:
+    return os.path.join(PROFILES, f"k_deliver_k_neuron_{workload}_{wdt}_traffic.json")
 
 
 def kernels_sha256() -> str:
@@ -69,11 +77,12 @@ def kernels_sha256() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
 
 
-def recorded_traffic():
-    """Per-launch HBM bytes of the kernels from the committed counter runs,
-    or None if the kernel source changed since they were taken."""
+def recorded_traffic(workload: str, wdt: str):
+    """Per-launch HBM bytes of the kernels from the committed counter runs of
+    this workload and weight format, or None if the kernel source changed
+    since they were taken."""
     try:
-        rec = json.load(open(TRAFFIC_JSON))
+        rec = json.load(open(traffic_json(workload, wdt)))
     except (OSError, ValueError):
         return None
     return rec if rec.get("kernels_sha256") == kernels_sha256() else None
@@ -88,7 +97,7 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir
     import statistics
 
     def one(d, pat):
-        f = glob.glob(os.path.join(d, pat))
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
         return list(csv.DictReader(open(f[0]))) if f else []
 
     known_kib = 256 * 1024
@@ -103,7 +112,7 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir
     fe = one(fetch_dir, "*counter_collection.csv")
     wr = one(write_dir, "*counter_collection.csv")
     tr = one(kt_dir, "*kernel_trace.csv")
-    for name in ("k_neuron", "k_deliver", "k_step"):
+    for name in ("k_neuron", "k_deliver", "k_step", "k_persist"):
         a = [float(r["Counter_Value"]) for r in fe if name in r["Kernel_Name"]][-2000:]
         b = [float(r["Counter_Value"]) for r in wr if name in r["Kernel_Name"]][-2000:]
         d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr
@@ -120,9 +129,52 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir
     print(json.dumps(rec, indent=1))
 
 
-def cpu_baseline(params, gpu_net, dpsnn, steps: int, budget_s: float):
-    """The oracle (single thread) re-running a post-transient window of the
-    same workload from the GPU's state: events/s of the CPU implementation."""
+def summarize_counters(dirs, out_json):
+    """Medians per kernel of every counter of rocprofv3 --pmc passes (one
+    directory per pass) over the last 2000 dispatches of each kernel."""
+    import csv
+    import glob
+    import statistics
+    rows = []
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += list(csv.DictReader(open(f)))
+    out = {"kernels_sha256": kernels_sha256(), "kernels": {}}
+    for name in ("k_neuron", "k_deliver", "k_step", "k_persist"):
+        sel = [r for r in rows if name in r["Kernel_Name"]]
+        if not sel:
+            continue
+        by = {}
+        for r in sel:
+            by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        out["kernels"][name] = {c: statistics.median(v[-2000:]) for c, v in sorted(by.items())}
+    json.dump(out, open(out_json, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def host_cpu():
+    """CPU model and the number of host threads this process may use."""
+    model = platform.processor() or platform.machine()
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return model, nproc
+
+
+def cpu_baseline(params, gpu_net, dpsnn, workloads, label: str, steps: int, budget_s: float):
+    """The oracle, single-threaded, (1) re-running a post-transient window of
+    the benchmark network from the GPU's state (rows regenerated from Philox
+    per spike), bounded by budget_s; (2) the whole 2x2 correctness network
+    (5000 neurons, 2 s).  Events/s of the plain CPU implementation: a reported
+    baseline, not the target."""
     import numpy as np
     import oracle
     V, c, r = dpsnn.dpsnn_read_state(gpu_net)
@@ -132,6 +184,7 @@ def cpu_baseline(params, gpu_net, dpsnn, steps: int, budget_s: float):
     orc.set_state(V.astype(np.float64), c.astype(np.float64), r.astype(np.int32))
     orc.set_ring(slots)
     orc.set_time(t)
+    del V, c, r, slots
     done = 0
     t0 = time.perf_counter()
     while done < steps and time.perf_counter() - t0 < budget_s:
@@ -139,63 +192,199 @@ def cpu_baseline(params, gpu_net, dpsnn, steps: int, budget_s: float):
         done += 1
     el = time.perf_counter() - t0
     n_sp = len(orc.spikes()[0])
+    orc.close()
+    p1 = workloads.swa()
+    o1 = oracle.Oracle(p1, 1, store_rows=True)
+    t1 = time.perf_counter()
+    o1.step(20000)
+    el1 = time.perf_counter() - t1
+    n1 = len(o1.spikes()[0])
+    o1.close()
+    model, nproc = host_cpu()
     return {"value": n_sp * params["K_out"] / el, "unit": "synaptic events/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"{done} steps ({done * 0.1:.1f} ms biological) of the 24x24 SWA "
-                       f"network from the GPU state at step {t}; {n_sp} spikes, "
-                       f"{el:.1f} s; rows regenerated from Philox per spike"),
-            "cpu": platform.processor() or platform.machine()}
+            "sample": (f"{done} steps ({done * 0.1:.1f} ms biological) of the {label} "
+                       f"network from the GPU state at step {t}; {n_sp} spikes, {el:.1f} s; "
+                       "rows regenerated from Philox per spike; single thread"),
+            "c1_2x2_2s": {"value": n1 * p1["K_out"] / el1, "spikes": n1, "seconds": el1,
+                          "sample": "the whole 2x2 network (5000 neurons) for 2 s "
+                                    "(20000 steps), stored rows, single thread"},
+            "cpu_model": model, "nproc": nproc}
 
 
 def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_workload(name, dpsnn, workloads, total_bins):
-    """Handles of the workload: {label: (handle, params of its first net)}."""
+def workload_groups(name, workloads, lam, weights):
+    """Groups of networks timed together: {group: {label: params}}.  grid48
+    has one group per weight format (each an SWA and an AW network)."""
+    if name == "grid48":
+        return {wd: {"swa": workloads.grid(48, 48, "swa", weight_dtype=wd, **{"lambda": lam}),
+                     "aw": workloads.grid(48, 48, "aw", weight_dtype=wd, **{"lambda": lam})}
+                for wd in weights}
     if name == "grid24":
-        regs = {"swa": workloads.grid(24, 24, "swa"), "aw": workloads.grid(24, 24, "aw")}
-    elif name == "fbi24":
-        regs = {"sw": workloads.fbi(24, 24, "sw"), "aw88": workloads.fbi(24, 24, "aw88")}
-    elif name == "grid96":
-        regs = {"swa": workloads.grid96("swa"), "aw": workloads.grid96("aw")}
-    elif name == "stdp24":
-        regs = {"swa": workloads.grid(24, 24, "swa", **workloads.stdp()),
-                "aw": workloads.grid(24, 24, "aw", **workloads.stdp())}
-    else:
-        regs = None
+        return {"f32": {"swa": workloads.grid(24, 24, "swa", **{"lambda": lam}),
+                        "aw": workloads.grid(24, 24, "aw", **{"lambda": lam})}}
+    if name == "fbi24":
+        return {"f32": {"sw": workloads.fbi(24, 24, "sw"), "aw88": workloads.fbi(24, 24, "aw88")}}
+    if name == "grid96":
+        return {"i8": {"swa": workloads.grid96("swa"), "aw": workloads.grid96("aw")}}
+    if name == "stdp24":
+        return {"f32": {"swa": workloads.grid(24, 24, "swa", **workloads.stdp()),
+                        "aw": workloads.grid(24, 24, "aw", **workloads.stdp())}}
+    return {"f16": {"sweep": None}}
+
+
+DESCRIPTIONS = {
+    "grid48": ("48x48 modules x 1250 LIF-SFA neurons (2.88M neurons, 2.88G synapses), lambda "
+               "{lam:g}, SWA + AW networks, FP32 efficacies (headline) and FP16 / int8 "
+               "(per source population scale) efficacies timed alike, int32 fixed-point slots"),
+    "grid24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda "
+               "{lam:g}, SWA + AW networks, FP32 efficacies, int32 fixed-point slots"),
+    "sweep64": ("batched sweep: 64 networks of 4x4..16x16 modules (9.5M neurons, 9.5G synapses), "
+                "g_c log-uniform 0.002-0.02, lambda 1 or 2, FP16 efficacies, int32 slots, "
+                "one handle"),
+    "grid96": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
+               "SWA + AW networks, int8 efficacies with per-module scale, int64 fixed-point "
+               "slots (Q = 32)"),
+    "stdp24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
+               "SWA + AW networks, FP32 efficacies, int32 slots, STDP on the synapses of "
+               "excitatory sources (20 ms windows, 1 s filter and update period)"),
+    "fbi24": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
+              "synapses, 1125 per neuron), Table S1 SW and AW 8.8 Hz states, Eq. 1 from "
+              "d = 0 with lambda 0.5, open boundaries, FP32 efficacies, int32 slots"),
+}
+
+
+def build_group(name, group, dpsnn, workloads, total_bins):
+    """Handles of one group: {label: (handle, params of its first net)}."""
     nets = {}
-    if regs is not None:
-        for label, p in regs.items():
-            p.update(spike_log_cap=0, rate_bins_cap=total_bins)
-            nets[label] = (dpsnn.dpsnn_build(p, 1), p)
-            progress(f"built {label}: {nets[label][0].stats()['build_ms']:.0f} ms")
-    else:
+    if name == "sweep64":
         plist, seeds = workloads.sweep()
         for p in plist:
             p.update(spike_log_cap=0, rate_bins_cap=total_bins)
         nets["sweep"] = (dpsnn.dpsnn_build_batch(plist, seeds), plist[0])
         progress(f"built sweep of {len(plist)}: {nets['sweep'][0].stats()['build_ms']:.0f} ms")
+        return nets
+    for label, p in group.items():
+        p.update(spike_log_cap=0, rate_bins_cap=total_bins)
+        nets[label] = (dpsnn.dpsnn_build(p, 1), p)
+        progress(f"built {label} ({p['weight_dtype']}): "
+                 f"{nets[label][0].stats()['build_ms']:.0f} ms")
     return nets
 
 
-DESCRIPTIONS = {
-    "grid24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
-           "SWA + AW networks, FP32 efficacies, int32 fixed-point slots"),
-    "sweep64": ("batched sweep: 64 networks of 4x4..16x16 modules (9.5M neurons, 9.5G synapses), "
-           "g_c log-uniform 0.002-0.02, lambda 1 or 2, FP16 efficacies, int32 slots, "
-           "one handle"),
-    "grid96": ("96x96 modules x 1250 neurons (11.52M neurons, 11.52G synapses), lambda 2, "
-           "SWA + AW networks, int8 efficacies with per-module scale, int64 fixed-point "
-           "slots (Q = 32)"),
-    "stdp24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
-               "SWA + AW networks, FP32 efficacies, int32 slots, STDP on the synapses of "
-               "excitatory sources (20 ms windows, 1 s filter and update period)"),
-    "fbi24": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
-            "synapses, 1125 per neuron), Table S1 SW and AW 8.8 Hz states, Eq. 1 from "
-            "d = 0 with lambda 0.5, open boundaries, FP32 efficacies, int32 slots"),
-}
-DTYPES = {"grid24": "f32", "sweep64": "f16", "grid96": "i8", "fbi24": "f32", "stdp24": "f32"}
+def time_group(nets, dpsnn, torch, stream, args, steps, S):
+    """The timing protocol, the same for every group: warm-up bench steps,
+    autotune, the timed bench steps (graph replay on a non-default stream,
+    bracketed by synchronisation and HIP events), then further real steps
+    with HIP events around each kernel for the roofline."""
+    sched = {}
+    for _ in range(args.warmup):
+        for h, _ in nets.values():
+            dpsnn.dpsnn_step(h, S)
+    for name, (h, _) in nets.items():
+        sched[name] = (dpsnn.dpsnn_autotune(h, min(1000, S // 2)) if args.autotune
+                       else h.stats()["schedule"])
+    torch.cuda.synchronize()
+    sp0 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(steps):
+        for h, _ in nets.values():
+            dpsnn.dpsnn_step(h, S)
+        progress(f"enqueued timed step {k + 1}")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    sp1 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
+    prof = {}
+    for name, (h, _) in nets.items():
+        if args.profile_steps <= 0:
+            continue
+        dpsnn.dpsnn_set_schedule(h, dpsnn.SCHED_SPLIT)
+        k_out = h.params["K_out"]
+        s_a = h.stats()["n_spikes"]
+        upd_ms, del_ms = dpsnn.dpsnn_profile_steps(h, args.profile_steps)
+        prof[name] = (upd_ms, del_ms, (h.stats()["n_spikes"] - s_a) * k_out)
+    return {"sched": sched, "spikes": {k: sp1[k] - sp0[k] for k in nets}, "wall": wall,
+            "gpu_ms": gpu_ms, "prof": prof}
+
+
+def group_record(workload, wdt, nets, res, steps, S, args):
+    """Throughput, rates and rooflines of one timed group."""
+    K_OUT = next(iter(nets.values()))[1]["K_out"]
+    spikes, wall, prof = res["spikes"], res["wall"], res["prof"]
+    events = sum(spikes.values()) * K_OUT
+    p0 = next(iter(nets.values()))[1]
+    Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
+    neurons = {k: h.stats()["n_neurons"] for k, (h, _) in nets.items()}
+    sim_s = steps * S * 0.1e-3
+    n_prof = max(1, args.profile_steps * len(prof))
+    del_us = sum(v[1] for v in prof.values()) * 1e3 / n_prof
+    upd_us = sum(v[0] for v in prof.values()) * 1e3 / n_prof
+    ev_per_launch = sum(v[2] for v in prof.values()) / n_prof
+    alg_del = ev_per_launch * Be
+    achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
+    n_mean = sum(neurons.values()) / len(neurons)
+    # whole-step bound: every neuron-step and every event of the timed window
+    # at its algorithmic bytes, over the wall time of the window
+    step_bytes = sum(neurons[k] * steps * S * bytes_per_neuron_step(nets[k][1])
+                     + spikes[k] * K_OUT * bytes_per_event(nets[k][1]) for k in nets)
+    step_gbs = step_bytes / wall / 1e9
+    rec = recorded_traffic(workload, wdt)
+    traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"] \
+        if rec and "k_deliver" in rec["kernels"] else None
+    syn = {k: h.stats()["n_synapses"] for k, (h, _) in nets.items()}
+    dev_bytes = {k: h.stats()["bytes_total"] for k, (h, _) in nets.items()}
+    value = events / wall
+    return {
+        "events_per_s": value,
+        "ms_per_step": wall * 1e3 / steps,
+        "paper_equivalent_events_per_s": sum(spikes.values()) * (K_OUT + EXT_TRAINS) / wall,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic,
+            "kernel": "k_deliver (spike delivery: one inbox reservation per target-tile run, "
+                      "plus the inbox routers)",
+            "bytes_per_event": Be,
+            "events_per_launch": ev_per_launch,
+            "algorithmic_bytes_per_launch": alg_del,
+            "avg_launch_us": del_us,
+            "events_per_s_in_kernel": ev_per_launch / (del_us * 1e-6) if del_us > 0 else None,
+            "update_kernel": {"kernel": "k_neuron (update, with the queued-input gather)",
+                              "avg_launch_us": upd_us,
+                              "algorithmic_bytes_per_launch": n_mean * Bn,
+                              "achieved_GB_s": n_mean * Bn / (upd_us * 1e-6) / 1e9
+                              if upd_us else None,
+                              "bytes_per_neuron_step": Bn},
+            "step_us": res["gpu_ms"] * 1e3 / (steps * S * len(nets)),
+            "whole_step": {"algorithmic_bytes": step_bytes,
+                           "achieved_GB_s": step_gbs,
+                           "frac": step_gbs / HBM_PEAK_GBS,
+                           "bound_events_per_s": value / (step_gbs / HBM_PEAK_GBS)},
+        },
+        "per_handle": {k: {"spikes": spikes[k],
+                           "rate_hz": spikes[k] / neurons[k] / sim_s,
+                           "events_per_s": spikes[k] * K_OUT / wall,
+                           "build_ms": nets[k][0].stats()["build_ms"],
+                           "bytes_per_synapse": dev_bytes[k] / max(1, syn[k]),
+                           "schedule": "split" if res["sched"][k] == 1 else "fused",
+                           "deliver_blocks": nets[k][0].stats()["deliver_blocks"],
+                           "spike_lists": "appended" if nets[k][0].stats()["spike_lists"]
+                           else "per tile"}
+                       for k in nets},
+        "gpu_ms_timed": res["gpu_ms"],
+    }
 
 
 def wave_bench(dpsnn, workloads, torch):
@@ -246,25 +435,30 @@ def wave_bench(dpsnn, workloads, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["grid24", "sweep64", "grid96", "fbi24", "stdp24"],
-                    default="grid24")
+    ap.add_argument("--workload", choices=["grid48", "grid24", "sweep64", "grid96", "fbi24",
+                                           "stdp24"], default="grid48")
+    ap.add_argument("--lambda", dest="lam", type=float, default=1.0,
+                    help="decay length of Eq. 1 for grid48 and grid24 (default 1)")
+    ap.add_argument("--weights", default="f32,f16,i8",
+                    help="grid48: weight formats timed, the first one is the headline")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 10 for grid24, fbi24 and stdp24, 2 for sweep64 and grid96)")
+                    help="timed steps (default 10; 2 for sweep64 and grid96)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dt-steps", type=int, default=None,
-                    help="dt steps per bench step (default 10000 = 1 s; 2000 for sweep64 and grid96)")
+                    help="dt steps per bench step (default 4000 for grid48, 10000 for the "
+                         "24x24 workloads, 2000 for sweep64 and grid96)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--calibrate", action="store_true",
                     help="only copy 256 MiB device-to-device three times (counter calibration)")
     ap.add_argument("--summarize-rocprof", nargs=6, metavar=("KT", "FETCH", "WRITE",
                     "CAL_FETCH", "CAL_WRITE", "OUT_JSON"),
                     help="fold rocprofv3 CSV directories into per-launch traffic figures")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="medians per kernel of --pmc passes: DIR... OUT_JSON")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps timed per kernel with events for the roofline")
-    ap.add_argument("--variants", type=int, default=1,
-                    help="grid24: also time FP16 and int8 efficacies")
     ap.add_argument("--waves", action="store_true",
                     help="time the slow-wave analysis (Sec. 2.3, Eq. 4) of 3 s of the 24x24 "
                          "F/B/I SW network instead of the step")
@@ -272,16 +466,21 @@ def main():
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof)
         return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[:-1], args.summarize_counters[-1])
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (there is no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
-    small = wl in ("grid24", "fbi24", "stdp24")
-    steps = args.steps if args.steps is not None else (10 if small else 2)
-    S = args.dt_steps if args.dt_steps is not None else (10000 if small else 2000)
-    if not small:
+    big = wl in ("sweep64", "grid96")
+    steps = args.steps if args.steps is not None else (2 if big else 10)
+    S = args.dt_steps if args.dt_steps is not None else (
+        2000 if big else 4000 if wl == "grid48" else 10000)
+    if big:
         args.profile_steps = min(args.profile_steps, 200)
+    weights = [w for w in args.weights.split(",") if w]
 
     import torch
     from paper_1902_08410_amd import dpsnn, workloads
@@ -306,151 +505,56 @@ def main():
     # at most 11 candidates, the per-kernel timing steps
     tune_steps = 22 * min(1000, S // 2) if args.autotune else 0
     total_bins = ((args.warmup + steps) * S + tune_steps + args.profile_steps) // 50 + 100
-    sched = {}
-    variants = {}
-    with torch.cuda.stream(stream):
-        nets = build_workload(wl, dpsnn, workloads, total_bins)
-        K_OUT = next(iter(nets.values()))[1]["K_out"]  # same for every handle
-        for _ in range(args.warmup):
-            for h, _ in nets.values():
-                dpsnn.dpsnn_step(h, S)
-        for name, (h, _) in nets.items():
-            sched[name] = (dpsnn.dpsnn_autotune(h, min(1000, S // 2)) if args.autotune
-                           else h.stats()["schedule"])
-        torch.cuda.synchronize()
-        progress("warmup done")
-        sp0 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        for k in range(steps):
-            for h, _ in nets.values():
-                dpsnn.dpsnn_step(h, S)
-            progress(f"enqueued timed step {k + 1}")
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gpu_ms = ev0.elapsed_time(ev1)
-        sp1 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
-        progress("timed region done")
-        # per-kernel times over further real steps (events around each kernel)
-        prof = {}
-        for name, (h, _) in nets.items():
-            if args.profile_steps <= 0:
-                continue
-            dpsnn.dpsnn_set_schedule(h, dpsnn.SCHED_SPLIT)
-            s_a = h.stats()["n_spikes"]
-            upd_ms, del_ms = dpsnn.dpsnn_profile_steps(h, args.profile_steps)
-            prof[name] = (upd_ms, del_ms, (h.stats()["n_spikes"] - s_a) * K_OUT)
-        progress("kernel timing done")
-        if wl == "grid24" and args.variants:
-            for wd in ("f16", "i8"):
-                for reg in ("swa", "aw"):
-                    q = dict(nets[reg][1], weight_dtype=wd)
-                    vn = dpsnn.dpsnn_build(q, 1)
-                    dpsnn.dpsnn_step(vn, S)
-                    torch.cuda.synchronize()
-                    v0 = vn.stats()["n_spikes"]
-                    ta = time.perf_counter()
-                    dpsnn.dpsnn_step(vn, 2 * S)
-                    torch.cuda.synchronize()
-                    tb = time.perf_counter()
-                    ev = (vn.stats()["n_spikes"] - v0) * K_OUT
-                    variants[f"{wd}_{reg}"] = {"events_per_s": ev / (tb - ta),
-                                               "rate_hz": ev / K_OUT / vn.N / (2 * S * 1e-4)}
-                    vn.close()
-                    progress(f"variant {wd} {reg} done")
-
-    spikes = {k: sp1[k] - sp0[k] for k in nets}
-    events = sum(spikes.values()) * K_OUT
-    value = events / wall
-    n_steps_all = steps * S * len(nets)
-    p0 = next(iter(nets.values()))[1]
-    Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
-    neurons = {k: h.stats()["n_neurons"] for k, (h, _) in nets.items()}
-    sim_s = steps * S * 0.1e-3
-    rates = {k: spikes[k] / neurons[k] / sim_s for k in nets}
-    n_prof = max(1, args.profile_steps * len(prof))
-    del_ms = sum(v[1] for v in prof.values())
-    upd_ms = sum(v[0] for v in prof.values())
-    prof_events = sum(v[2] for v in prof.values())
-    del_us = del_ms * 1e3 / n_prof
-    upd_us = upd_ms * 1e3 / n_prof
-    ev_per_launch = prof_events / n_prof
-    alg_del = ev_per_launch * Be
-    achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
-    n_mean = sum(neurons.values()) / len(neurons)
-    # whole-step bound: every neuron-step and every event of the timed window
-    # at its algorithmic bytes, over the wall time of the window
-    step_bytes = sum(neurons[k] * steps * S * bytes_per_neuron_step(nets[k][1])
-                     + spikes[k] * K_OUT * bytes_per_event(nets[k][1]) for k in nets)
-    step_gbs = step_bytes / wall / 1e9
-    traffic = None
-    rec = recorded_traffic() if wl == "grid24" else None
-    if rec and "k_deliver" in rec["kernels"]:
-        traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"]
+    groups = workload_groups(wl, workloads, args.lam, weights)
+    records = {}
     cpu = None
-    if wl == "grid24" and not args.no_cpu_baseline:
-        cpu = cpu_baseline(nets["swa"][1], nets["swa"][0], dpsnn, 400, args.cpu_budget)
+    with torch.cuda.stream(stream):
+        for gi, (gname, group) in enumerate(groups.items()):
+            nets = build_group(wl, group, dpsnn, workloads, total_bins)
+            res = time_group(nets, dpsnn, torch, stream, args, steps, S)
+            records[gname] = group_record(wl, gname, nets, res, steps, S, args)
+            progress(f"group {gname} timed: {records[gname]['events_per_s']:.3e} events/s")
+            if gi == 0 and not args.no_cpu_baseline and wl in ("grid48", "grid24"):
+                label, (h, p) = next(iter(nets.items()))
+                cpu = cpu_baseline(p, h, dpsnn, workloads,
+                                   f"{p['grid_w']}x{p['grid_h']} {label.upper()}", 200,
+                                   args.cpu_budget)
+                progress("cpu baseline done")
+            for h, _ in nets.values():
+                h.close()
+            del nets
+            torch.cuda.synchronize()
 
+    head_name = next(iter(records))
+    head = records[head_name]
     out = {
         "metric": "synaptic events/sec on 1 MI355X (SWA & AW), FP16/int8 vs FP32 weights",
-        "value": value,
+        "value": head["events_per_s"],
         "unit": "synaptic events/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPES[wl],
+        "dtype": head_name,
         "data": "synthetic",
         "config": {
-            "workload": DESCRIPTIONS[wl],
-            "bench_step": f"{S} steps of dt = 0.1 ms ({S * 1e-4:g} s biological) of every network",
-            "neurons": neurons,
-            "handles": list(nets),
+            "workload": DESCRIPTIONS[wl].format(lam=args.lam),
+            "bench_step": f"{S} steps of dt = 0.1 ms ({S * 1e-4:g} s biological) of every "
+                          "network of the headline group",
+            "events": "recurrent synaptic events = K_out x spikes, counted on the device",
+            "handles": list(head["per_handle"]),
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": traffic,
-            "kernel": "k_deliver (spike delivery: one inbox reservation per target-tile run, "
-                      "plus the inbox routers)",
-            "bytes_per_event": Be,
-            "events_per_launch": ev_per_launch,
-            "algorithmic_bytes_per_launch": alg_del,
-            "avg_launch_us": del_us,
-            "events_per_s_in_kernel": ev_per_launch / (del_us * 1e-6) if del_us > 0 else None,
-            "update_kernel": {"kernel": "k_neuron (update, with the queued-input gather)",
-                              "avg_launch_us": upd_us,
-                              "algorithmic_bytes_per_launch": n_mean * Bn,
-                              "achieved_GB_s": n_mean * Bn / (upd_us * 1e-6) / 1e9
-                              if upd_us else None,
-                              "bytes_per_neuron_step": Bn},
-            "step_us": gpu_ms * 1e3 / (n_steps_all / max(1, len(nets))) / max(1, len(nets)),
-            "whole_step": {"algorithmic_bytes": step_bytes,
-                           "achieved_GB_s": step_gbs,
-                           "frac": step_gbs / HBM_PEAK_GBS,
-                           "bound_events_per_s": value / (step_gbs / HBM_PEAK_GBS)},
-        },
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "per_handle": {k: {"spikes": spikes[k], "rate_hz": rates[k],
-                           "events_per_s": spikes[k] * K_OUT / wall,
-                           "build_ms": nets[k][0].stats()["build_ms"],
-                           "schedule": "split" if sched[k] == 1 else "fused",
-                           "deliver_blocks": nets[k][0].stats()["deliver_blocks"],
-                           "spike_lists": "appended" if nets[k][0].stats()["spike_lists"]
-                           else "per tile"}
-                       for k in nets},
-        "gpu_ms_timed": gpu_ms,
-        "weight_variants": variants,
+        "paper_equivalent_events_per_s": head["paper_equivalent_events_per_s"],
+        "paper_equivalent_events": f"spikes x (K_out + {EXT_TRAINS} external trains "
+                                   "of the paper's model), labelled as such",
+        "per_handle": head["per_handle"],
+        "gpu_ms_timed": head["gpu_ms_timed"],
+        "weight_variants": {k: v for k, v in records.items() if k != head_name},
     }
     print(json.dumps(out), flush=True)
 
