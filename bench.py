@@ -257,22 +257,39 @@ DESCRIPTIONS = {
 }
 
 
-def build_group(name, group, dpsnn, workloads, total_bins):
-    """Handles of one group: {label: (handle, params of its first net)}."""
+def build_group(name, group, dpsnn, workloads, total_bins, batched):
+    """Handles of one group: {handle label: (handle, [params], [network labels])}.
+    batched: the group's networks share one handle (one set of launches per
+    step for all of them); else one handle per network."""
     nets = {}
     if name == "sweep64":
         plist, seeds = workloads.sweep()
         for p in plist:
             p.update(spike_log_cap=0, rate_bins_cap=total_bins)
-        nets["sweep"] = (dpsnn.dpsnn_build_batch(plist, seeds), plist[0])
-        progress(f"built sweep of {len(plist)}: {nets['sweep'][0].stats()['build_ms']:.0f} ms")
+        h = dpsnn.dpsnn_build_batch(plist, seeds)
+        nets["sweep"] = (h, plist, [f"net{k}" for k in range(len(plist))])
+        progress(f"built sweep of {len(plist)}: {h.stats()['build_ms']:.0f} ms")
+        return nets
+    for p in group.values():
+        p.update(spike_log_cap=0, rate_bins_cap=total_bins)
+    if batched and len(group) > 1:
+        labels, plist = list(group), list(group.values())
+        h = dpsnn.dpsnn_build_batch(plist, [1] * len(plist))
+        nets["+".join(labels)] = (h, plist, labels)
+        progress(f"built {'+'.join(labels)} ({plist[0]['weight_dtype']}) in one handle: "
+                 f"{h.stats()['build_ms']:.0f} ms")
         return nets
     for label, p in group.items():
-        p.update(spike_log_cap=0, rate_bins_cap=total_bins)
-        nets[label] = (dpsnn.dpsnn_build(p, 1), p)
-        progress(f"built {label} ({p['weight_dtype']}): "
-                 f"{nets[label][0].stats()['build_ms']:.0f} ms")
+        h = dpsnn.dpsnn_build(p, 1)
+        nets[label] = (h, [p], [label])
+        progress(f"built {label} ({p['weight_dtype']}): {h.stats()['build_ms']:.0f} ms")
     return nets
+
+
+def _net_spikes(dpsnn, h, n_nets):
+    """Spikes of each network of a handle since its rate bins were last
+    drained (the completed 5 ms bins)."""
+    return [int(dpsnn.dpsnn_read_rates_net(h, k).sum()) for k in range(n_nets)]
 
 
 def time_group(nets, dpsnn, torch, stream, args, steps, S):
@@ -282,48 +299,51 @@ def time_group(nets, dpsnn, torch, stream, args, steps, S):
     with HIP events around each kernel for the roofline."""
     sched = {}
     for _ in range(args.warmup):
-        for h, _ in nets.values():
+        for h, _, _ in nets.values():
             dpsnn.dpsnn_step(h, S)
-    for name, (h, _) in nets.items():
+    for name, (h, _, _) in nets.items():
         sched[name] = (dpsnn.dpsnn_autotune(h, min(1000, S // 2)) if args.autotune
                        else h.stats()["schedule"])
     torch.cuda.synchronize()
-    sp0 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
+    sp0 = {k: h.stats()["n_spikes"] for k, (h, _, _) in nets.items()}
+    for h, pl, _ in nets.values():   # rate bins before the window
+        _net_spikes(dpsnn, h, len(pl))
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for k in range(steps):
-        for h, _ in nets.values():
+        for h, _, _ in nets.values():
             dpsnn.dpsnn_step(h, S)
         progress(f"enqueued timed step {k + 1}")
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    sp1 = {k: h.stats()["n_spikes"] for k, (h, _) in nets.items()}
+    sp1 = {k: h.stats()["n_spikes"] for k, (h, _, _) in nets.items()}
+    per_net = {k: _net_spikes(dpsnn, h, len(pl)) for k, (h, pl, _) in nets.items()}
     prof = {}
-    for name, (h, _) in nets.items():
+    for name, (h, pl, _) in nets.items():
         if args.profile_steps <= 0:
             continue
         dpsnn.dpsnn_set_schedule(h, dpsnn.SCHED_SPLIT)
-        k_out = h.params["K_out"]
+        k_out = pl[0]["K_out"]
         s_a = h.stats()["n_spikes"]
         upd_ms, del_ms = dpsnn.dpsnn_profile_steps(h, args.profile_steps)
         prof[name] = (upd_ms, del_ms, (h.stats()["n_spikes"] - s_a) * k_out)
-    return {"sched": sched, "spikes": {k: sp1[k] - sp0[k] for k in nets}, "wall": wall,
-            "gpu_ms": gpu_ms, "prof": prof}
+    return {"sched": sched, "spikes": {k: sp1[k] - sp0[k] for k in nets}, "per_net": per_net,
+            "wall": wall, "gpu_ms": gpu_ms, "prof": prof}
 
 
 def group_record(workload, wdt, nets, res, steps, S, args):
     """Throughput, rates and rooflines of one timed group."""
-    K_OUT = next(iter(nets.values()))[1]["K_out"]
+    from paper_1902_08410_amd import dpsnn
+    K_OUT = next(iter(nets.values()))[1][0]["K_out"]
     spikes, wall, prof = res["spikes"], res["wall"], res["prof"]
     events = sum(spikes.values()) * K_OUT
-    p0 = next(iter(nets.values()))[1]
+    p0 = next(iter(nets.values()))[1][0]
     Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
-    neurons = {k: h.stats()["n_neurons"] for k, (h, _) in nets.items()}
     sim_s = steps * S * 0.1e-3
     n_prof = max(1, args.profile_steps * len(prof))
     del_us = sum(v[1] for v in prof.values()) * 1e3 / n_prof
@@ -331,17 +351,24 @@ def group_record(workload, wdt, nets, res, steps, S, args):
     ev_per_launch = sum(v[2] for v in prof.values()) / n_prof
     alg_del = ev_per_launch * Be
     achieved = alg_del / (del_us * 1e-6) / 1e9 if del_us > 0 else None
-    n_mean = sum(neurons.values()) / len(neurons)
+    handle_neurons = {k: h.stats()["n_neurons"] for k, (h, _, _) in nets.items()}
+    n_mean = sum(handle_neurons.values()) / len(handle_neurons)
     # whole-step bound: every neuron-step and every event of the timed window
     # at its algorithmic bytes, over the wall time of the window
-    step_bytes = sum(neurons[k] * steps * S * bytes_per_neuron_step(nets[k][1])
-                     + spikes[k] * K_OUT * bytes_per_event(nets[k][1]) for k in nets)
+    step_bytes = 0.0
+    per_net = {}
+    for k, (h, pl, labels) in nets.items():
+        for j, (p, lab) in enumerate(zip(pl, labels)):
+            n = dpsnn.dpsnn_net_info(h, j)["n_neurons"]
+            sp = res["per_net"][k][j]
+            step_bytes += n * steps * S * bytes_per_neuron_step(p) + sp * K_OUT * bytes_per_event(p)
+            if len(pl) <= 8:
+                per_net[lab] = {"spikes": sp, "rate_hz": sp / n / sim_s,
+                                "events_per_s": sp * K_OUT / wall}
     step_gbs = step_bytes / wall / 1e9
     rec = recorded_traffic(workload, wdt)
     traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"] \
         if rec and "k_deliver" in rec["kernels"] else None
-    syn = {k: h.stats()["n_synapses"] for k, (h, _) in nets.items()}
-    dev_bytes = {k: h.stats()["bytes_total"] for k, (h, _) in nets.items()}
     value = events / wall
     return {
         "events_per_s": value,
@@ -373,16 +400,16 @@ def group_record(workload, wdt, nets, res, steps, S, args):
                            "frac": step_gbs / HBM_PEAK_GBS,
                            "bound_events_per_s": value / (step_gbs / HBM_PEAK_GBS)},
         },
-        "per_handle": {k: {"spikes": spikes[k],
-                           "rate_hz": spikes[k] / neurons[k] / sim_s,
-                           "events_per_s": spikes[k] * K_OUT / wall,
-                           "build_ms": nets[k][0].stats()["build_ms"],
-                           "bytes_per_synapse": dev_bytes[k] / max(1, syn[k]),
-                           "schedule": "split" if res["sched"][k] == 1 else "fused",
-                           "deliver_blocks": nets[k][0].stats()["deliver_blocks"],
-                           "spike_lists": "appended" if nets[k][0].stats()["spike_lists"]
-                           else "per tile"}
-                       for k in nets},
+        "per_network": per_net,
+        "handles": {k: {"networks": labels,
+                        "neurons": h.stats()["n_neurons"],
+                        "build_ms": h.stats()["build_ms"],
+                        "bytes_per_synapse": h.stats()["bytes_total"] /
+                        max(1, h.stats()["n_synapses"]),
+                        "schedule": "split" if res["sched"][k] == 1 else "fused",
+                        "deliver_blocks": h.stats()["deliver_blocks"],
+                        "spike_lists": "appended" if h.stats()["spike_lists"] else "per tile"}
+                    for k, (h, _, labels) in nets.items()},
         "gpu_ms_timed": res["gpu_ms"],
     }
 
@@ -447,6 +474,9 @@ def main():
     ap.add_argument("--dt-steps", type=int, default=None,
                     help="dt steps per bench step (default 4000 for grid48, 10000 for the "
                          "24x24 workloads, 2000 for sweep64 and grid96)")
+    ap.add_argument("--separate", action="store_true",
+                    help="one handle per network (default: the SWA and AW networks of a "
+                         "group in one batched handle)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--autotune", type=int, default=1)
@@ -510,17 +540,23 @@ def main():
     cpu = None
     with torch.cuda.stream(stream):
         for gi, (gname, group) in enumerate(groups.items()):
-            nets = build_group(wl, group, dpsnn, workloads, total_bins)
+            nets = build_group(wl, group, dpsnn, workloads, total_bins, not args.separate)
             res = time_group(nets, dpsnn, torch, stream, args, steps, S)
             records[gname] = group_record(wl, gname, nets, res, steps, S, args)
             progress(f"group {gname} timed: {records[gname]['events_per_s']:.3e} events/s")
             if gi == 0 and not args.no_cpu_baseline and wl in ("grid48", "grid24"):
-                label, (h, p) = next(iter(nets.items()))
+                h, pl, labels = next(iter(nets.values()))
+                p = pl[0]
+                if len(pl) > 1:   # the first network alone, from its own build
+                    h.close()
+                    h = dpsnn.dpsnn_build(p, 1)
+                    dpsnn.dpsnn_step(h, S)
                 cpu = cpu_baseline(p, h, dpsnn, workloads,
-                                   f"{p['grid_w']}x{p['grid_h']} {label.upper()}", 200,
+                                   f"{p['grid_w']}x{p['grid_h']} {labels[0].upper()}", 200,
                                    args.cpu_budget)
                 progress("cpu baseline done")
-            for h, _ in nets.values():
+                h.close()
+            for h, _, _ in nets.values():
                 h.close()
             del nets
             torch.cuda.synchronize()
@@ -543,16 +579,17 @@ def main():
         "config": {
             "workload": DESCRIPTIONS[wl].format(lam=args.lam),
             "bench_step": f"{S} steps of dt = 0.1 ms ({S * 1e-4:g} s biological) of every "
-                          "network of the headline group",
+                          "network of the headline group" + ("" if args.separate else
+                                                             ", advanced in one batched handle"),
             "events": "recurrent synaptic events = K_out x spikes, counted on the device",
-            "handles": list(head["per_handle"]),
+            "handles": head["handles"],
         },
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "paper_equivalent_events_per_s": head["paper_equivalent_events_per_s"],
         "paper_equivalent_events": f"spikes x (K_out + {EXT_TRAINS} external trains "
                                    "of the paper's model), labelled as such",
-        "per_handle": head["per_handle"],
+        "per_network": head["per_network"],
         "gpu_ms_timed": head["gpu_ms_timed"],
         "weight_variants": {k: v for k, v in records.items() if k != head_name},
     }

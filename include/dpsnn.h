@@ -245,7 +245,7 @@ int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
 /* The split schedule's delivery: grid of the delivery kernel (blocks > 0;
  * 0 keeps the current one) and the spike lists it reads (0: one list per
  * tile of 1024 neurons, whose counts every delivery block scans, for at most
- * 15000 tiles; 1: lists appended by the tiles through 64 counters; -1 keeps
+ * 14000 tiles; 1: lists appended by the tiles through 64 counters; -1 keeps
  * the current kind).  Results do not depend on either.  The default: one
  * block per tile, between 256 and 1024 blocks, and appended lists.  INVAL
  * otherwise. */

@@ -282,6 +282,13 @@ int build_impl(dpsnn_net* n) {
     d.key0 = key0;
     d.key1 = key1;
     for (int q = 0; q < kMaxPops; ++q) d.pop_hi[q] = q < T.P - 1 ? T.pop_hi[q] : p.K;
+    {
+      int sh = 0;
+      while ((2ll << sh) <= p.K) ++sh;  // floor(log2 K)
+      d.kshift = sh;
+      d.kmag = (p.K & (p.K - 1)) == 0 ? 0u
+                                      : (uint32_t)((((uint64_t)1 << (32 + sh)) / (uint64_t)p.K) + 1);
+    }
     for (int q = 0; q < T.P; ++q) {
       d.Pm[q] = T.prop32[q][0];
       d.Pc[q] = T.prop32[q][1];
@@ -374,6 +381,8 @@ int build_impl(dpsnn_net* n) {
     qcap = std::min(qcap, budget / std::max<int64_t>(per_cap, 1));
     if (qcap < 64) qcap = 0;
   }
+  // inbox entries are addressed with 32-bit indices: [2][tiles][2 cap]
+  if (qcap > 0 && (int64_t)4 * n_tiles * qcap >= 0xFFFFFFFFll) return DPSNN_E_INVAL;
   if (qcap > 0) {
     a.q_cap = (int32_t)qcap;
     a.in_cap = (int32_t)(2 * qcap);
@@ -1134,7 +1143,7 @@ int dpsnn_stats(dpsnn_net* n, dpsnn_stats_t* out) {
   {
     const int ab = acc_bytes(n->p[0]);
     out->lds_bytes = n->sched == DPSNN_SCHED_SPLIT
-                         ? n->sa.n_tiles * 4 + 1024 + 4 * 256 * 4
+                         ? (n->sa.spk_lists ? 0 : n->sa.n_tiles * 4) + 8192 + 4 * 256 * 4
                          : 1024 * 4 + 1024 * ab + kQueueMaxSlots * 4 + 4 * 256 * 4 + 16;
   }
   out->schedule = n->sched;

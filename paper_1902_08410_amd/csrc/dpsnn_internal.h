@@ -17,8 +17,9 @@ constexpr int kMaxKout = 4096;
 constexpr int kDelayShift = 26;  // target word = target | delay index << 26
 constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
 constexpr int kSpkLists = 64;          // appended spike lists per step
-constexpr int kMaxScanTiles = 15000;   // per-tile lists: LDS prefix of the tile counts
-                                       // (with the static LDS, within 64 KiB per block)
+constexpr int kMaxScanTiles = 14000;   // per-tile lists: LDS prefix of the tile counts
+                                       // (with the entry staging and the static LDS,
+                                       // within 64 KiB per block)
 constexpr int kSpkStride = 16;         // their counters 64 bytes apart
 constexpr int kQueueMaxSlots = 128;   // input queues need D <= 128 slots
 constexpr int kQueueDefaultCap = 4096; // entries per (tile, slot) queue
@@ -145,6 +146,34 @@ struct NetDev {
   int32_t n_pois[kMaxPops];
   uint32_t pois[kMaxPops][kMaxPois];
   int32_t exc[kMaxPops];    // 1: excitatory population (its synapses are plastic)
+  // module of a network-local index x < 2^31: x / K = umulhi(x, kmag) >> kshift
+  // (kshift = floor(log2 K), kmag = ceil(2^(32 + kshift) / K); kmag = 0 when K
+  // is a power of two: x >> kshift)
+  uint32_t kmag;
+  int32_t kshift;
+};
+
+// Module and module-local index of network-local neuron x (x < 2^31): the
+// multiply-high is exact there because x * (kmag - 2^(32+s)/K) / 2^(32+s)
+// stays below 1/K.
+__host__ __device__ inline uint32_t module_of(const NetDev& nd, uint32_t x) {
+  const uint32_t hi = (uint32_t)(((uint64_t)x * nd.kmag) >> 32);
+  return (nd.kmag ? hi : x) >> nd.kshift;
+}
+
+// Step index and the values the kernels derive from it.  The device keeps
+// them for the step counter t (StepArgs::t_base: t, t mod D, t mod
+// rate_bin_steps, (t / rate_bin_steps) mod rate_bins_cap, written by
+// k_tick); a launch for step t + t_off carries t_off and its own residues
+// (StepOff, computed on the host), so that no kernel divides by D or by the
+// rate-bin sizes.
+struct StepOff {
+  uint32_t t_off, d_slot, d_phase, d_bin;
+};
+struct StepTime {
+  uint32_t t;     // step index
+  uint32_t slot;  // input slot of the step: t mod D
+  uint32_t bin;   // rate bin of the step in the ring
 };
 
 // Arguments of the step kernels (passed by value).
@@ -185,7 +214,7 @@ struct StepArgs {
   unsigned long long* log_base;  // [2]: log entries before step t at [t & 1]
   unsigned int* rates;
   unsigned long long* n_spikes;
-  uint32_t* t_base;        // device step counter
+  uint32_t* t_base;        // device step counter and its residues [4] (StepOff)
   // Event queues (q_cap = 0: none; every event is then an atomic add into
   // its slot).  Delivery appends each event to the inbox of its target tile
   // for the step (parity t & 1); in the next step the tile moves its inbox

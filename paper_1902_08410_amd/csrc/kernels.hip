@@ -71,6 +71,35 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Step index and residues of the launch for step t_base + o.t_off: one
+// 16-byte uniform load, then conditional subtractions (each residue sum is
+// below twice its modulus; the bin sum below 2 cap + 1).
+__device__ __forceinline__ StepTime step_time(const StepArgs& a, const StepOff& o) {
+  const uint4 c = *reinterpret_cast<const uint4*>(a.t_base);
+  StepTime T;
+  T.t = c.x + o.t_off;
+  uint32_t sl = c.y + o.d_slot;
+  if (sl >= (uint32_t)a.D) sl -= (uint32_t)a.D;
+  T.slot = sl;
+  const uint32_t carry = c.z + o.d_phase >= (uint32_t)a.rate_bin_steps ? 1u : 0u;
+  uint32_t b = c.w + o.d_bin + carry;
+  if (b >= (uint32_t)a.rate_bins_cap) b -= (uint32_t)a.rate_bins_cap;
+  if (b >= (uint32_t)a.rate_bins_cap) b -= (uint32_t)a.rate_bins_cap;
+  T.bin = b;
+  return T;
+}
+
+// Module and population of global neuron id.
+__device__ __forceinline__ void module_pop(const StepArgs& a, int32_t id, int32_t* mod,
+                                           int* pop) {
+  const NetDev& nd = a.nets[a.tile_net[id >> 10]];
+  const uint32_t local = (uint32_t)(id - (int32_t)nd.base);
+  const uint32_t m = module_of(nd, local);
+  *mod = nd.mbase + (int32_t)m;
+  const int32_t l = (int32_t)(local - m * (uint32_t)nd.K);
+  *pop = (l >= nd.pop_hi[0]) + (l >= nd.pop_hi[1]) + (l >= nd.pop_hi[2]);
+}
+
 // ------------------------------------------------------------------------
 // Connectivity generation
 __host__ __device__ inline int gen_pow2(int Ko) {
@@ -393,11 +422,12 @@ constexpr int kFmtPacked = 1;
 constexpr int kFmtCode = 2;
 
 template <typename Acc, int FMT>
-__device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t t, Acc* s_in) {
+__device__ __forceinline__ void gather_now(const StepArgs& a, int tile, const StepTime& T,
+                                           Acc* s_in) {
   const int D = a.D;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int cur = (int)(t % (uint32_t)D);
-  const uint32_t par = (t - 1u) & 1u;
+  const int cur = (int)T.slot;
+  const uint32_t par = (T.t - 1u) & 1u;
   const uint32_t qn = a.q_cnt[(int64_t)tile * D + cur];
   const uint32_t n_cur = qn < (uint32_t)a.q_cap ? qn : (uint32_t)a.q_cap;
   uint32_t n_in = 0;
@@ -431,6 +461,14 @@ __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, uint32_t
   }
 }
 
+// Dynamic LDS of the delivery blocks: the prefix of the tile counts
+// (per-tile spike lists), then the staging of the inbox entries, 256 per
+// wavefront.
+constexpr size_t kStageBytes = 4 * 256 * 8;
+__host__ __device__ inline uint32_t stage_offset_words(const StepArgs& a) {
+  return a.spk_lists ? 0u : ((uint32_t)a.n_tiles + 3u) / 4u * 4u;
+}
+
 // LDS of route_inbox.
 template <typename Acc>
 struct RouteLds {
@@ -447,13 +485,13 @@ struct RouteLds {
 // space or a full queue they are added into the slot), and empties the
 // inbox.  The queue of slot t mod D is neither read nor written.
 template <typename Acc, typename IE>
-__device__ __forceinline__ void route_entries(const StepArgs& a, int tile, uint32_t t,
+__device__ __forceinline__ void route_entries(const StepArgs& a, int tile, const StepTime& T,
                                               RouteLds<Acc>& L) {
   constexpr bool CODE = std::is_same<IE, CodeEntry>::value;
   const int D = a.D;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int cur = (int)(t % (uint32_t)D);
-  const uint32_t par = (t - 1u) & 1u;
+  const int cur = (int)T.slot;
+  const uint32_t par = (T.t - 1u) & 1u;
   const int64_t ic = ((int64_t)par * a.n_tiles + tile) * kInboxStride;
   const uint32_t got = a.in_cnt[ic];
   const uint32_t n_in = got < (uint32_t)a.in_cap ? got : (uint32_t)a.in_cap;
@@ -564,12 +602,12 @@ __device__ __forceinline__ void route_entries(const StepArgs& a, int tile, uint3
 
 // CODE: code entries (binary16 and int8 efficacies), else QEntry inboxes.
 template <typename Acc, bool CODE>
-__device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, uint32_t t,
+__device__ __forceinline__ void route_inbox(const StepArgs& a, int tile, const StepTime& T,
                                             RouteLds<Acc>& L) {
   if constexpr (CODE)
-    route_entries<Acc, CodeEntry>(a, tile, t, L);
+    route_entries<Acc, CodeEntry>(a, tile, T, L);
   else
-    route_entries<Acc, QEntry<Acc>>(a, tile, t, L);
+    route_entries<Acc, QEntry<Acc>>(a, tile, T, L);
 }
 
 // Entry q of a four-entry array of uniform values, without indexing; the
@@ -603,14 +641,32 @@ struct NeuronRegs {
   uint32_t r4;
 };
 
+// Where the four neurons of a thread sit: global index i0 of the first,
+// its network-local index il0 (a multiple of 4), and the module and
+// module-local index of il0.
+struct NeuronPos {
+  uint32_t i0, il0, m0;
+  int l0;
+};
+
+__device__ __forceinline__ NeuronPos neuron_pos(const NetDev& nd, int tile, int tid) {
+  NeuronPos P;
+  P.i0 = ((uint32_t)tile * 256u + (uint32_t)tid) * 4u;
+  P.il0 = P.i0 - (uint32_t)nd.base;
+  P.m0 = module_of(nd, P.il0);
+  P.l0 = (int)(P.il0 - P.m0 * (uint32_t)nd.K);
+  return P;
+}
+
 template <typename Acc, int NP>
 __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd, int net,
-                                            int64_t i0, uint32_t t, NeuronRegs<Acc>& R) {
-  const int slot = (int)(t % (uint32_t)a.D);
-  Acc* sl = static_cast<Acc*>(a.slots) + (int64_t)slot * a.N_pad + i0;
+                                            const NeuronPos& P, const StepTime& T,
+                                            NeuronRegs<Acc>& R) {
+  const uint32_t i0 = P.i0, t = T.t;
+  Acc* sl = static_cast<Acc*>(a.slots) + ((size_t)T.slot * (size_t)a.N_pad + i0);
   // with queues the slot holds input only where an event found its queue
   // full (marked per tile and slot); gather_now clears the mark
-  const bool marked = a.q_cap == 0 || a.s_dirty[(i0 >> 10) * a.D + slot] != 0u;
+  const bool marked = a.q_cap == 0 || a.s_dirty[(i0 >> 10) * (uint32_t)a.D + T.slot] != 0u;
   if (!marked) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) R.I[j] = 0;
@@ -634,40 +690,44 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
   // external Poisson drive generated on the fly: counts from word j of
   // (il0/4, t, EXT); efficacies 2b and 2b+1 of neuron j from word j of
   // (il0/4, t, EXTJ | b << 8), high half then low half
-  const int64_t il0 = i0 - nd.base;  // network-local index, a multiple of 4
-  const uint32_t g = (uint32_t)(il0 >> 2);
+  const uint32_t g = P.il0 >> 2;
   const uint4 u = philox10(make_uint4(g, t, 0u, kTagExt), nd.key0, nd.key1);
   const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
-  const int64_t m0 = il0 / nd.K;
-  const int l0 = (int)(il0 - m0 * nd.K);
-  int q[4], k[4];
+  int q[4], k[4], npj[4];
   const int h0 = nd.pop_hi[0], h1 = nd.pop_hi[1], h2 = nd.pop_hi[2];
+  const int np[kMaxPops] = {nd.n_pois[0], nd.n_pois[1], NP > 2 ? nd.n_pois[2] : 0,
+                            NP > 2 ? nd.n_pois[3] : 0};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    int lj = l0 + j;
+    int lj = P.l0 + j;
     if (lj >= nd.K) lj -= nd.K;
     q[j] = pop_index<NP>(lj, h0, h1, h2);
     k[j] = 0;
+    npj[j] = sel<NP>(np, q[j]);
   }
-  // Poisson counts: thresholds are uniform over the block (scalar loads),
-  // each lane picks its population's
-  const int np[kMaxPops] = {nd.n_pois[0], nd.n_pois[1], NP > 2 ? nd.n_pois[2] : 0,
-                            NP > 2 ? nd.n_pois[3] : 0};
-  int npj[4];
+  // Poisson counts: the number of thresholds (increasing, uniform over the
+  // block) not above the draw; the scan of a neuron stops at its first
+  // threshold above the draw, the wavefront's once no lane goes on (most
+  // counts are 0 or 1)
+  bool on[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) npj[j] = sel<NP>(np, q[j]);
-#pragma unroll
+  for (int j = 0; j < 4; ++j) on[j] = true;
   for (int x = 0; x < kMaxPois; ++x) {
     const uint32_t th[kMaxPops] = {nd.pois[0][x], nd.pois[1][x],
                                    NP > 2 ? nd.pois[2][x] : 0u, NP > 2 ? nd.pois[3][x] : 0u};
+    bool any = false;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (x < npj[j] && uu[j] >= sel<NP>(th, q[j])) k[j] += 1;
+    for (int j = 0; j < 4; ++j) {
+      on[j] = on[j] && x < npj[j] && uu[j] >= sel<NP>(th, q[j]);
+      k[j] += on[j] ? 1 : 0;
+      any |= on[j];
+    }
+    if (!__any(any)) break;
   }
   int kmax = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) kmax = k[j] > kmax ? k[j] : kmax;
-  const Acc* jx = static_cast<const Acc*>(a.jx) + (int64_t)net * kMaxPops * kQuantN;
+  const Acc* jx = static_cast<const Acc*>(a.jx) + (size_t)net * kMaxPops * kQuantN;
   for (int b = 0; 2 * b < kmax; ++b) {
     const uint4 v = philox10(make_uint4(g, t, 0u, kTagExtJ | ((uint32_t)b << 8)), nd.key0, nd.key1);
     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
@@ -683,16 +743,16 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
 }
 
 template <typename Acc, int NP>
-__device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& nd, int64_t i0,
-                                              uint32_t t, NeuronRegs<Acc>& R, const Acc* s_in,
+__device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& nd,
+                                              const NeuronPos& P, const StepTime& T,
+                                              NeuronRegs<Acc>& R, const Acc* s_in,
                                               int32_t* s_spk, int* s_n) {
   if (s_in) {  // this thread's four entries of the tile's queue sums
 #pragma unroll
     for (int j = 0; j < 4; ++j) R.I[j] += s_in[4 * threadIdx.x + j];
   }
-  const int64_t il0 = i0 - nd.base;
-  const int64_t m0 = il0 / nd.K;
-  const int l0 = (int)(il0 - m0 * nd.K);
+  const uint32_t i0 = P.i0;
+  const int l0 = P.l0;
   // per-population constants: uniform loads, selected per lane
   const float Pm[kMaxPops] = {nd.Pm[0], nd.Pm[1], nd.Pm[2], nd.Pm[3]};
   const float Pc[kMaxPops] = {nd.Pc[0], nd.Pc[1], nd.Pc[2], nd.Pc[3]};
@@ -711,7 +771,7 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
     if (lj >= nd.K) lj -= nd.K;
     const int qq = pop_index<NP>(lj, h0, h1, h2);
     uint32_t rj = (R.r4 >> (8 * j)) & 0xFFu;
-    if (il0 + j < nd.N) {
+    if ((int64_t)P.il0 + j < nd.N) {
       const float dv = fix_to_f32(R.I[j]) * a.inv2q;
       float Vj = R.V[j], cj = R.c[j];
       const float Pcq = sel<NP>(Pc, qq), Eq = sel<NP>(E, qq);
@@ -741,11 +801,10 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
       if (spk) {
         const int pos = atomicAdd(s_n, 1);
         s_spk[pos] = (int32_t)(i0 + j);
-        if (a.t_post) a.t_post[i0 + j] = (int32_t)t;  // plastic networks
+        if (a.t_post) a.t_post[i0 + j] = (int32_t)T.t;  // plastic networks
         // population count of the rate bin (Sec. 2.3)
-        const int64_t mod = nd.mbase + m0 + (l0 + j >= nd.K ? 1 : 0);
-        const uint32_t bin = (t / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
-        atomicAdd(&a.rates[((int64_t)bin * a.M + mod) * a.P + qq], 1u);
+        const uint32_t mod = (uint32_t)nd.mbase + P.m0 + (l0 + j >= nd.K ? 1u : 0u);
+        atomicAdd(&a.rates[((size_t)T.bin * (uint32_t)a.M + mod) * (uint32_t)a.P + qq], 1u);
       }
     }
     r_out |= rj << (8 * j);
@@ -753,17 +812,6 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
   *reinterpret_cast<float4*>(a.V + i0) = make_float4(R.V[0], R.V[1], R.V[2], R.V[3]);
   *reinterpret_cast<float4*>(a.c + i0) = make_float4(R.c[0], R.c[1], R.c[2], R.c[3]);
   *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
-}
-
-// Global module and population of a (global) neuron id.
-__device__ __forceinline__ void module_pop(const StepArgs& a, int32_t id, int32_t* mod,
-                                           int* pop) {
-  const NetDev& nd = a.nets[a.tile_net[id >> 10]];
-  const int32_t local = id - (int32_t)nd.base;
-  const int32_t m = local / nd.K;
-  *mod = nd.mbase + m;
-  const int32_t l = local - m * nd.K;
-  *pop = (l >= nd.pop_hi[0]) + (l >= nd.pop_hi[1]) + (l >= nd.pop_hi[2]);
 }
 
 // Plasticity event of one synapse (Sec. 2.1): source spike at step ta,
@@ -863,17 +911,21 @@ __device__ __forceinline__ void chunk_plasticity(const StepArgs& a, const Chunk<
 }
 
 // Delivery of a loaded chunk.  s_b is the wavefront's 256-entry LDS
-// scratch.  Every lane of the wavefront takes part, also past the end of
-// the row.
+// scratch, s_e (or null: entries stored from the lanes that hold them) its
+// 256-entry staging of the inbox entries.  Every lane of the wavefront takes
+// part, also past the end of the row.
 template <typename Acc, int WDT>
 __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc>& c,
-                                              uint32_t t, int lane, uint32_t* s_b) {
+                                              const StepTime& T, int lane, uint32_t* s_b,
+                                              unsigned long long* s_e) {
   const int p0 = c.p0;
   const int p = p0 + lane * 4;
   const int* tv = c.tv;
   const Acc* wv = c.wv;
   const uint32_t* cv = c.cv;
-  const int slot0 = (int)((t + (uint32_t)a.d_min) % (uint32_t)a.D);
+  const uint32_t t = T.t;
+  int slot0 = (int)T.slot + a.d_min;  // slot of arrival at t + d_min
+  if (slot0 >= a.D) slot0 -= a.D;
   Acc* slots = static_cast<Acc*>(a.slots);
   if (a.q_cap == 0) {
 #pragma unroll
@@ -950,6 +1002,61 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
     }
   }
   wave_lds_sync();
+  if (s_e) {
+    // Entries are staged in LDS and stored with lane l writing chunk
+    // positions l, l + 64, l + 128, l + 192: consecutive lanes then write
+    // consecutive entries of a run, so the stores coalesce.  Inbox index of
+    // each entry (~0: none, an event past the inbox goes to its slot here).
+    uint32_t off[4];
+    unsigned long long ev[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      off[j] = ~0u;
+      ev[j] = 0ull;
+      if (tl[j] >= 0) {
+        const uint32_t pos = s_b[rs[j] - p0] + (uint32_t)(p + j - rs[j]);
+        const int32_t target = tv[j] & kTargetMask;
+        const uint32_t dk = (uint32_t)tv[j] >> kDelayShift;
+        const uint32_t x = (uint32_t)(target & 1023) | (dk << 10);
+        if (pos < (uint32_t)a.in_cap) {
+          off[j] = ((uint32_t)par * (uint32_t)a.n_tiles + (uint32_t)tl[j]) * (uint32_t)a.in_cap +
+                   pos;
+          if (WDT != DPSNN_W_F32 && a.q_code) {
+            ev[j] = code_entry(cv[j], x);
+          } else {
+            const QEntry<Acc> e = QEntry<Acc>::make(x, wv[j]);
+            ev[j] = *reinterpret_cast<const unsigned long long*>(&e);
+          }
+        } else {
+          int sl = slot0 + (int)dk;
+          if (sl >= a.D) sl -= a.D;
+          atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+          a.s_dirty[(int64_t)tl[j] * a.D + sl] = 1u;
+        }
+      }
+    }
+    wave_lds_sync();  // every lane has read its run bases
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      s_b[4 * lane + j] = off[j];
+      s_e[4 * lane + j] = ev[j];
+    }
+    wave_lds_sync();
+    const bool code = WDT != DPSNN_W_F32 && a.q_code;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t o = s_b[lane + 64 * j];
+      if (o != ~0u) {
+        const unsigned long long e = s_e[lane + 64 * j];
+        if (code)
+          static_cast<uint32_t*>(a.in_q)[o] = (uint32_t)e;
+        else
+          static_cast<unsigned long long*>(a.in_q)[o] = e;
+      }
+    }
+    wave_lds_sync();  // s_b and s_e are written again by the next chunk
+    return;
+  }
   QEntry<Acc>* iq = static_cast<QEntry<Acc>*>(a.in_q);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -983,23 +1090,24 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 // ------------------------------------------------------------------------
 // Split schedule: neuron kernel, then the delivery kernel.
 template <typename Acc, int NP, int FMT>
-__global__ void __launch_bounds__(256) k_neuron(StepArgs a, uint32_t t_off) {
+__global__ void __launch_bounds__(256) k_neuron(StepArgs a, StepOff o) {
   __shared__ int32_t s_spk[1024];
   __shared__ Acc s_in[1024];
   __shared__ int s_n;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
-  const uint32_t t = a.t_base[0] + t_off;
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
+  const StepTime T = step_time(a, o);
+  const uint32_t t = T.t;
   const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
   const NetDev& nd = a.nets[net];
+  const NeuronPos P = neuron_pos(nd, blockIdx.x, tid);
   NeuronRegs<Acc> R;
-  neuron_load<Acc, NP>(a, nd, net, i0, t, R);
+  neuron_load<Acc, NP>(a, nd, net, P, T, R);
   if (a.q_cap)
-    gather_now<Acc, FMT>(a, blockIdx.x, t, s_in);
+    gather_now<Acc, FMT>(a, blockIdx.x, T, s_in);
   else
     lds_barrier();
-  neuron_finish<Acc, NP>(a, nd, i0, t, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
   lds_barrier();
   const int n = s_n;
   if (!a.spk_lists) {  // the tile's own list and count
@@ -1048,7 +1156,7 @@ __device__ __forceinline__ int32_t spike_at(const StepArgs& a, int sidx, const i
 }
 
 template <typename Acc, int WDT, bool PLAST = false>
-__global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
+__global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
   // delivery blocks: inclusive prefix of the tile counts (per-tile lists);
   // routing blocks: their RouteLds
   extern __shared__ __align__(16) int32_t s_dyn[];
@@ -1056,17 +1164,20 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
   __shared__ uint32_t s_b[4][256];
   const int tid = threadIdx.x;
   const int nb = a.n_tiles;
-  const uint32_t t = a.t_base[0] + t_off;
+  const StepTime T = step_time(a, o);
+  const uint32_t t = T.t;
   if ((int)blockIdx.x >= a.deliver_blocks) {
     // routing of the inboxes of step t-1, one tile at a time
     RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_dyn);
     const int nr = (int)gridDim.x - a.deliver_blocks;
     for (int tile = (int)blockIdx.x - a.deliver_blocks; tile < nb; tile += nr)
-      route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, t, L);
+      route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, T, L);
     return;
   }
   const int lane = tid & 63;
   int32_t* s_pref = s_dyn;
+  unsigned long long* s_stage =
+      reinterpret_cast<unsigned long long*>(s_dyn + stage_offset_words(a));
   uint32_t incl = 0, excl = 0;
   int n_spk;
   if (!a.spk_lists) {
@@ -1140,7 +1251,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
     const bool more = it + nw < items;
     if (more) load_item(it + nw, nxt);
     if (PLAST) chunk_plasticity<Acc>(a, cur, t, lane);
-    chunk_deliver<Acc, WDT>(a, cur, t, lane, s_b[tid >> 6]);
+    chunk_deliver<Acc, WDT>(a, cur, T, lane, s_b[tid >> 6], s_stage + (tid >> 6) * 256);
     if (!more) break;
     cur = nxt;
   }
@@ -1149,7 +1260,7 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, uint32_t t_off) {
 // Fused schedule (small networks): the tile's own spikes are delivered by
 // its four wavefronts right after the update.
 template <typename Acc, int WDT, int NP>
-__global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
+__global__ void __launch_bounds__(256) k_step(StepArgs a, StepOff o) {
   __shared__ int32_t s_spk[1024];
   __shared__ Acc s_in[1024];
   __shared__ RouteLds<Acc> s_route;
@@ -1158,22 +1269,23 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
   __shared__ unsigned long long s_logbase;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
-  const uint32_t t = a.t_base[0] + t_off;
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + tid) * 4;
+  const StepTime T = step_time(a, o);
+  const uint32_t t = T.t;
   const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
   const NetDev& nd = a.nets[net];
+  const NeuronPos P = neuron_pos(nd, blockIdx.x, tid);
   NeuronRegs<Acc> R;
-  neuron_load<Acc, NP>(a, nd, net, i0, t, R);
+  neuron_load<Acc, NP>(a, nd, net, P, T, R);
   if (!a.q_cap)
     lds_barrier();
   else if constexpr (WDT != DPSNN_W_F32)
-    gather_now<Acc, kFmtCode>(a, blockIdx.x, t, s_in);
+    gather_now<Acc, kFmtCode>(a, blockIdx.x, T, s_in);
   else if (sizeof(Acc) == 4 && a.q_packed)
-    gather_now<Acc, kFmtPacked>(a, blockIdx.x, t, s_in);
+    gather_now<Acc, kFmtPacked>(a, blockIdx.x, T, s_in);
   else
-    gather_now<Acc, kFmtWide>(a, blockIdx.x, t, s_in);
-  neuron_finish<Acc, NP>(a, nd, i0, t, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
-  if (a.q_cap) route_inbox<Acc, WDT != DPSNN_W_F32>(a, blockIdx.x, t, s_route);  // barriers
+    gather_now<Acc, kFmtWide>(a, blockIdx.x, T, s_in);
+  neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  if (a.q_cap) route_inbox<Acc, WDT != DPSNN_W_F32>(a, blockIdx.x, T, s_route);  // barriers
   lds_barrier();
   const int n = s_n;
   if (n == 0) return;
@@ -1193,18 +1305,23 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, uint32_t t_off) {
     const int32_t s = __builtin_amdgcn_readfirstlane(s_spk[k]);
     Chunk<Acc> c;
     chunk_load<Acc, WDT>(a, s, (it - k * cpr) * 256, lane, c);
-    chunk_deliver<Acc, WDT>(a, c, t, lane, s_b[wave]);
+    chunk_deliver<Acc, WDT>(a, c, T, lane, s_b[wave], nullptr);
   }
 }
 
 // Advance the device step counter after `n` steps; on a switch from the
 // split to the fused schedule, make both spike-log bases current.
 __global__ void k_tick(uint32_t* t_base, uint32_t n, unsigned long long* log_base,
-                       int sync_logs, uint32_t* spk_n) {
+                       int sync_logs, uint32_t* spk_n, uint32_t D, uint32_t rbs, uint32_t cap) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const uint32_t t = t_base[0];
     if (sync_logs) log_base[(t + 1) & 1] = log_base[t & 1];
-    t_base[0] = t + n;
+    const uint32_t t1 = t + n;
+    // the counter and the residues the step kernels start from
+    t_base[0] = t1;
+    t_base[1] = t1 % D;
+    t_base[2] = t1 % rbs;
+    t_base[3] = (t1 / rbs) % cap;
   }
   // spike-list counters of the next step start from zero
   if (blockIdx.x == 0)
@@ -1263,6 +1380,16 @@ __global__ void __launch_bounds__(256) k_drain(StepArgs a, uint32_t t) {
 }
 
 // ------------------------------------------------------------------------
+// The launch for step t_base + t_off: t_off and its residues.
+static StepOff step_off(const StepArgs& a, uint32_t t_off) {
+  StepOff o;
+  o.t_off = t_off;
+  o.d_slot = t_off % (uint32_t)a.D;
+  o.d_phase = t_off % (uint32_t)a.rate_bin_steps;
+  o.d_bin = (t_off / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
+  return o;
+}
+
 hipError_t launch_gen(const GenArgs& a, int wdt, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
   const int per_wave = gen_stage_bytes(a.K_out);
@@ -1295,7 +1422,7 @@ hipError_t launch_init(const InitArgs& a, hipStream_t st) {
 // (per-tile spike lists) and the routing blocks' RouteLds.
 template <typename Acc>
 static size_t deliver_lds(const StepArgs& a) {
-  const size_t pref = a.spk_lists ? 0 : (size_t)a.n_tiles * 4;
+  const size_t pref = (size_t)stage_offset_words(a) * 4 + kStageBytes;
   const size_t route = a.route_blocks ? sizeof(RouteLds<Acc>) : 0;
   return pref > route ? pref : route;
 }
@@ -1304,9 +1431,9 @@ template <typename Acc, int FMT>
 static void launch_neuron_fmt(const StepArgs& a, uint32_t t_off, hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
   if (a.P <= 2)
-    hipLaunchKernelGGL((k_neuron<Acc, 2, FMT>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_neuron<Acc, 2, FMT>), tiles, block, 0, st, a, step_off(a, t_off));
   else
-    hipLaunchKernelGGL((k_neuron<Acc, 4, FMT>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_neuron<Acc, 4, FMT>), tiles, block, 0, st, a, step_off(a, t_off));
 }
 
 template <typename Acc>
@@ -1331,24 +1458,24 @@ static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t
   const size_t lds = deliver_lds<Acc>(a);
   const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
   if (a.plastic)
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32, true>), grid, block, lds, st, a, t_off);
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32, true>), grid, block, lds, st, a, step_off(a, t_off));
   else if (wdt == DPSNN_W_F32)
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32>), grid, block, lds, st, a, step_off(a, t_off));
   else if (wdt == DPSNN_W_F16)
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F16>), grid, block, lds, st, a, step_off(a, t_off));
   else
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_I8>), grid, block, lds, st, a, step_off(a, t_off));
 }
 
 template <typename Acc, int NP>
 static void launch_fused_np(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
   const dim3 tiles((unsigned)a.n_tiles), block(256);
   if (wdt == DPSNN_W_F32)
-    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F32, NP>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F32, NP>), tiles, block, 0, st, a, step_off(a, t_off));
   else if (wdt == DPSNN_W_F16)
-    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F16, NP>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_F16, NP>), tiles, block, 0, st, a, step_off(a, t_off));
   else
-    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_I8, NP>), tiles, block, 0, st, a, t_off);
+    hipLaunchKernelGGL((k_step<Acc, DPSNN_W_I8, NP>), tiles, block, 0, st, a, step_off(a, t_off));
 }
 
 template <typename Acc>
@@ -1388,23 +1515,23 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
       launch_neuron<int64_t>(a, t_off, st);
   } else if (a.plastic) {
     if (acc_bits == 32)
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32, true>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32, true>), grid, block, lds, st, a, step_off(a, t_off));
     else
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32, true>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32, true>), grid, block, lds, st, a, step_off(a, t_off));
   } else if (acc_bits == 32) {
     if (wdt == DPSNN_W_F32)
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32>), grid, block, lds, st, a, step_off(a, t_off));
     else if (wdt == DPSNN_W_F16)
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F16>), grid, block, lds, st, a, step_off(a, t_off));
     else
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_I8>), grid, block, lds, st, a, step_off(a, t_off));
   } else {
     if (wdt == DPSNN_W_F32)
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32>), grid, block, lds, st, a, step_off(a, t_off));
     else if (wdt == DPSNN_W_F16)
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F16>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F16>), grid, block, lds, st, a, step_off(a, t_off));
     else
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_I8>), grid, block, lds, st, a, t_off);
+      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_I8>), grid, block, lds, st, a, step_off(a, t_off));
   }
   return hipGetLastError();
 }
@@ -1435,7 +1562,7 @@ __global__ void __launch_bounds__(256) k_stdp_update(StepArgs a, int32_t T) {
     const NetDev& nd = a.nets[a.tile_net[s >> 10]];
     const int64_t il = s - nd.base;
     if (il >= nd.N) continue;  // padding
-    const int l = (int)(il % nd.K);
+    const int l = (int)((uint32_t)il - module_of(nd, (uint32_t)il) * (uint32_t)nd.K);
     const int q = (l >= nd.pop_hi[0]) + (l >= nd.pop_hi[1]) + (l >= nd.pop_hi[2]);
     if (!nd.exc[q]) continue;
     const int32_t tl = a.syn_t[x];
@@ -1457,7 +1584,8 @@ hipError_t launch_stdp_update(const StepArgs& a, int32_t T, hipStream_t st) {
 
 hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, a.t_base, n, a.log_base, sync_logs,
-                     a.spk_n);
+                     a.spk_n, (uint32_t)a.D, (uint32_t)a.rate_bin_steps,
+                     (uint32_t)a.rate_bins_cap);
   return hipGetLastError();
 }
 
