@@ -348,6 +348,16 @@ int dpsnn_write_state(dpsnn_net* net, const float* host_V,
  * entries are folded into the slots first (the sums are unchanged). */
 int dpsnn_read_slots(dpsnn_net* net, int64_t* host_slots);
 
+/* The device spike log as it stands (not drained, not sorted): the entries
+ * logged since the last dpsnn_read_spikes in the order the device wrote
+ * them.  Each tile lists its spikes in neuron order (a wavefront ballot and
+ * prefix sum); with per-tile spike lists (dpsnn_set_delivery) the split
+ * schedule logs every step in (step, id) order, with appended lists the
+ * tiles' runs follow the order in which the tiles appended them.  With
+ * cap < *n_out nothing is copied. */
+int dpsnn_read_log(dpsnn_net* net, int32_t* host_step, int32_t* host_id, int64_t cap,
+                   int64_t* n_out);
+
 /* Synapse rows first..first+count-1 (Eq. 1 targets, stored efficacies,
  * delays), each sorted by (target, delay, draw index j): host_tgt int32
  * [count][K_out]; host_w [count][K_out] of the stored format (float /

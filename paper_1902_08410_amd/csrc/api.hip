@@ -1230,6 +1230,25 @@ int dpsnn_read_slots(dpsnn_net* n, int64_t* host_slots) {
   return DPSNN_OK;
 }
 
+int dpsnn_read_log(dpsnn_net* n, int32_t* host_step, int32_t* host_id, int64_t cap,
+                   int64_t* n_out) {
+  if (!n || !n_out || cap < 0) return DPSNN_E_INVAL;
+  HIP_OK(hipStreamSynchronize(n->stream));
+  unsigned long long cnt = 0;
+  const int rc = log_count(n, &cnt);
+  if (rc != DPSNN_OK) return rc;
+  const int64_t have = std::min<int64_t>((int64_t)cnt, n->p[0].spike_log_cap);
+  *n_out = have;
+  if (cap < have || have == 0 || !host_step || !host_id) return DPSNN_OK;
+  std::vector<int2> buf((size_t)have);
+  HIP_OK(hipMemcpy(buf.data(), n->sa.log, (size_t)have * 8, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < have; ++k) {
+    host_step[k] = buf[(size_t)k].x;
+    host_id[k] = buf[(size_t)k].y;
+  }
+  return DPSNN_OK;
+}
+
 int dpsnn_read_rows(dpsnn_net* n, int64_t first, int64_t count, int32_t* host_tgt, void* host_w,
                     uint8_t* host_dk) {
   if (!n || first < 0 || count < 0 || first + count > n->N_index) return DPSNN_E_INVAL;

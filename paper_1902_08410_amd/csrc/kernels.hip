@@ -630,8 +630,8 @@ __device__ __forceinline__ int pop_index(int l, int h0, int h1, int h2) {
 // Neuron update of the 4 neurons i0..i0+3 (global indices) of one thread at
 // step t; nd is the tile's network.  neuron_load reads and clears the input
 // slot, reads the state and adds the external drive; neuron_finish adds the
-// queued inputs (s_in, may be null), integrates Eq. 2 and appends spiking
-// neurons to the LDS list s_spk (count s_n).  Counters of the random draws
+// queued inputs (s_in, may be null), integrates Eq. 2 and returns the
+// spiking neurons as a mask (compact_spikes lists them).  Counters of the random draws
 // use the network's own neuron indices, so a network in a batch draws what
 // it draws alone.
 template <typename Acc>
@@ -743,10 +743,9 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
 }
 
 template <typename Acc, int NP>
-__device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& nd,
-                                              const NeuronPos& P, const StepTime& T,
-                                              NeuronRegs<Acc>& R, const Acc* s_in,
-                                              int32_t* s_spk, int* s_n) {
+__device__ __forceinline__ uint32_t neuron_finish(const StepArgs& a, const NetDev& nd,
+                                                  const NeuronPos& P, const StepTime& T,
+                                                  NeuronRegs<Acc>& R, const Acc* s_in) {
   if (s_in) {  // this thread's four entries of the tile's queue sums
 #pragma unroll
     for (int j = 0; j < 4; ++j) R.I[j] += s_in[4 * threadIdx.x + j];
@@ -764,7 +763,7 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
   const float al[kMaxPops] = {nd.alpha[0], nd.alpha[1], nd.alpha[2], nd.alpha[3]};
   const int na[kMaxPops] = {nd.n_arp[0], nd.n_arp[1], nd.n_arp[2], nd.n_arp[3]};
   const int h0 = nd.pop_hi[0], h1 = nd.pop_hi[1], h2 = nd.pop_hi[2];
-  uint32_t r_out = 0;
+  uint32_t r_out = 0, mask = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
@@ -799,8 +798,7 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
       R.V[j] = Vj;
       R.c[j] = cj;
       if (spk) {
-        const int pos = atomicAdd(s_n, 1);
-        s_spk[pos] = (int32_t)(i0 + j);
+        mask |= 1u << j;
         if (a.t_post) a.t_post[i0 + j] = (int32_t)T.t;  // plastic networks
         // population count of the rate bin (Sec. 2.3)
         const uint32_t mod = (uint32_t)nd.mbase + P.m0 + (l0 + j >= nd.K ? 1u : 0u);
@@ -812,6 +810,36 @@ __device__ __forceinline__ void neuron_finish(const StepArgs& a, const NetDev& n
   *reinterpret_cast<float4*>(a.V + i0) = make_float4(R.V[0], R.V[1], R.V[2], R.V[3]);
   *reinterpret_cast<float4*>(a.c + i0) = make_float4(R.c[0], R.c[1], R.c[2], R.c[3]);
   *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
+  return mask;
+}
+
+// Spikes of a block in neuron order: each thread holds up to four (bit j of
+// mask: neuron i0 + j); the prefix within a wavefront comes from three
+// ballots of the per-thread counts, the wavefront totals are exchanged in
+// LDS (s_wt, one per wavefront).  Writes the ids in increasing order to
+// s_spk and returns the block's count (the same in every thread); s_spk is
+// read by other threads only after the next barrier.
+__device__ __forceinline__ int compact_spikes(uint32_t mask, uint32_t i0, int32_t* s_spk,
+                                              int* s_wt) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t c = (uint32_t)__popc(mask);
+  const unsigned long long b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int pre = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
+  if (lane == 0) s_wt[wave] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+  lds_barrier();
+  int base = 0, total = 0;
+  const int nw = (int)(blockDim.x >> 6);
+  for (int w = 0; w < nw; ++w) {
+    const int v = s_wt[w];
+    base += w < wave ? v : 0;
+    total += v;
+  }
+  int k = base + pre;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if ((mask >> j) & 1u) s_spk[k++] = (int32_t)(i0 + j);
+  return total;
 }
 
 // Plasticity event of one synapse (Sec. 2.1): source spike at step ta,
@@ -1093,9 +1121,8 @@ template <typename Acc, int NP, int FMT>
 __global__ void __launch_bounds__(256) k_neuron(StepArgs a, StepOff o) {
   __shared__ int32_t s_spk[1024];
   __shared__ Acc s_in[1024];
-  __shared__ int s_n;
+  __shared__ int s_wt[4];
   const int tid = threadIdx.x;
-  if (tid == 0) s_n = 0;
   const StepTime T = step_time(a, o);
   const uint32_t t = T.t;
   const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
@@ -1107,9 +1134,9 @@ __global__ void __launch_bounds__(256) k_neuron(StepArgs a, StepOff o) {
     gather_now<Acc, FMT>(a, blockIdx.x, T, s_in);
   else
     lds_barrier();
-  neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  const uint32_t mask = neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr);
+  const int n = compact_spikes(mask, P.i0, s_spk, s_wt);
   lds_barrier();
-  const int n = s_n;
   if (!a.spk_lists) {  // the tile's own list and count
     int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
     for (int k = tid; k < n; k += 256) out[k] = s_spk[k];
@@ -1265,10 +1292,9 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, StepOff o) {
   __shared__ Acc s_in[1024];
   __shared__ RouteLds<Acc> s_route;
   __shared__ uint32_t s_b[4][256];
-  __shared__ int s_n;
+  __shared__ int s_wt[4];
   __shared__ unsigned long long s_logbase;
   const int tid = threadIdx.x;
-  if (tid == 0) s_n = 0;
   const StepTime T = step_time(a, o);
   const uint32_t t = T.t;
   const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
@@ -1284,10 +1310,10 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, StepOff o) {
     gather_now<Acc, kFmtPacked>(a, blockIdx.x, T, s_in);
   else
     gather_now<Acc, kFmtWide>(a, blockIdx.x, T, s_in);
-  neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr, s_spk, &s_n);
+  const uint32_t mask = neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr);
+  const int n = compact_spikes(mask, P.i0, s_spk, s_wt);
   if (a.q_cap) route_inbox<Acc, WDT != DPSNN_W_F32>(a, blockIdx.x, T, s_route);  // barriers
   lds_barrier();
-  const int n = s_n;
   if (n == 0) return;
   if (tid == 0) {
     // both log bases advance together in this schedule

@@ -174,6 +174,7 @@ def lib():
             "dpsnn_read_spikes_net": ([V, C.c_int32, V, V, C.c_int64, P(C.c_int64)], C.c_int),
             "dpsnn_read_rates_net": ([V, C.c_int32, V, C.c_int64, P(C.c_int64)], C.c_int),
             "dpsnn_set_routing": ([V, C.c_int32], C.c_int),
+            "dpsnn_read_log": ([V, V, V, C.c_int64, P(C.c_int64)], C.c_int),
             "dpsnn_free": ([V], None),
             "dpsnn_strerror": ([C.c_int], C.c_char_p),
             "dpsnn_read_state": ([V, V, V, V], C.c_int),
@@ -217,7 +218,7 @@ EXPORTS = ["dpsnn_set_allocator", "dpsnn_build", "dpsnn_set_stream", "dpsnn_step
            "dpsnn_build_batch", "dpsnn_net_info", "dpsnn_waves", "dpsnn_waves_counts",
            "dpsnn_read_plasticity", "dpsnn_set_delivery", "dpsnn_stats",
            "dpsnn_read_spikes_net", "dpsnn_read_rates_net", "dpsnn_set_routing",
-           "dpsnn_waves_counts_static"]
+           "dpsnn_waves_counts_static", "dpsnn_read_log"]
 SCHED_FUSED, SCHED_SPLIT = 0, 1
 
 
@@ -389,6 +390,17 @@ def dpsnn_read_spikes(net: Net):
     ids = np.zeros(n.value, np.int32)
     rc = lib().dpsnn_read_spikes(net.h, _ptr(st), _ptr(ids), n.value, C.byref(n))
     _check("dpsnn_read_spikes", rc)
+    return st, ids
+
+
+def dpsnn_read_log(net: Net):
+    """(steps, ids) of the device spike log in device order (no drain)."""
+    n = C.c_int64(0)
+    _check("dpsnn_read_log", lib().dpsnn_read_log(net.h, None, None, 0, C.byref(n)))
+    st = np.zeros(n.value, np.int32)
+    ids = np.zeros(n.value, np.int32)
+    _check("dpsnn_read_log",
+           lib().dpsnn_read_log(net.h, _ptr(st), _ptr(ids), n.value, C.byref(n)))
     return st, ids
 
 

@@ -698,3 +698,32 @@ def test_routing_grid_below_tile_count(L):
             with pytest.raises(L.DpsnnError):
                 L.dpsnn_set_routing(net, bad)
         net.close()
+
+
+def test_spike_order_per_tile_lists_is_deterministic(L):
+    """Each tile lists its spikes in neuron order (wavefront ballot and block
+    prefix sum), so with per-tile spike lists the split schedule writes the
+    device log in (step, id) order, identically on a rerun; with appended
+    lists every tile's run of the log is in id order."""
+    p = W.grid(3, 3, "swa", K=1250, K_out=200, spike_log_cap=1 << 22)
+    _say("spike order")
+    logs = []
+    for lists in (0, 0, 1):
+        net = L.dpsnn_build(p, 5)
+        L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+        L.dpsnn_set_delivery(net, 0, lists)
+        L.dpsnn_step(net, 700)
+        st, ids = L.dpsnn_read_log(net)
+        sst, sids = L.dpsnn_read_spikes(net)      # sorted and drained
+        assert len(st) == len(sst) > 1000
+        key = st.astype(np.int64) * (1 << 32) + ids
+        if lists == 0:
+            assert np.all(np.diff(key) > 0)
+            assert np.array_equal(st, sst) and np.array_equal(ids, sids)
+        else:
+            # within one step and one tile, ids increase along the log
+            same = (st[1:] == st[:-1]) & ((ids[1:] >> 10) == (ids[:-1] >> 10))
+            assert np.all(ids[1:][same] > ids[:-1][same])
+        logs.append((st, ids))
+        net.close()
+    assert np.array_equal(logs[0][0], logs[1][0]) and np.array_equal(logs[0][1], logs[1][1])
