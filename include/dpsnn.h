@@ -62,6 +62,10 @@ extern "C" {
                                spikes (small networks) */
 #define DPSNN_SCHED_SPLIT 1 /* neuron kernel, then a delivery kernel that
                                spreads the spiking rows over the whole GPU */
+#define DPSNN_SCHED_PERSIST 2 /* the split schedule's work for many steps in
+                                 one cooperative launch of resident blocks,
+                                 with a grid synchronisation between update
+                                 and delivery (no graphs) */
 
 /* Stored synaptic efficacy formats. */
 #define DPSNN_W_F32 0
@@ -239,7 +243,7 @@ int dpsnn_set_stream(dpsnn_net* net, void* hip_stream);
 int dpsnn_step(dpsnn_net* net, int64_t n_steps);
 
 /* Choose the step schedule (DPSNN_SCHED_*).  INVAL: an unknown schedule,
- * or FUSED for a plastic network. */
+ * or FUSED or PERSIST for a plastic network. */
 int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
 
 /* The split schedule's delivery: grid of the delivery kernel (blocks > 0;

@@ -789,8 +789,8 @@ int ensure_graph(dpsnn_net* n) {
 extern "C" {
 
 int dpsnn_set_schedule(dpsnn_net* n, int32_t sched) {
-  if (!n || (sched != DPSNN_SCHED_FUSED && sched != DPSNN_SCHED_SPLIT)) return DPSNN_E_INVAL;
-  if (sched == DPSNN_SCHED_FUSED && n->sa.plastic) return DPSNN_E_INVAL;
+  if (!n || sched < DPSNN_SCHED_FUSED || sched > DPSNN_SCHED_PERSIST) return DPSNN_E_INVAL;
+  if (sched != DPSNN_SCHED_SPLIT && n->sa.plastic) return DPSNN_E_INVAL;
   n->sched = sched;
   return DPSNN_OK;
 }
@@ -818,8 +818,21 @@ int dpsnn_set_graph_steps(dpsnn_net* n, int64_t steps) {
   return DPSNN_OK;
 }
 
-// n_steps steps: captured graphs for the bulk, the rest launched directly.
+// n_steps steps: captured graphs for the bulk, the rest launched directly;
+// the persistent schedule: launches of up to kPersistSteps steps.
+constexpr int64_t kPersistSteps = 4096;
 static int run_steps(dpsnn_net* n, int64_t n_steps) {
+  if (n->sched == DPSNN_SCHED_PERSIST) {
+    for (int64_t done = 0; done < n_steps;) {
+      const int64_t k = std::min<int64_t>(n_steps - done, kPersistSteps);
+      HIP_OK(launch_persist(n->sa, n->p[0].weight_dtype, n->p[0].acc_bits, 0, (uint32_t)k,
+                            n->stream));
+      HIP_OK(launch_tick(n->sa, (uint32_t)k, 0, n->stream));
+      done += k;
+    }
+    n->t += n_steps;
+    return DPSNN_OK;
+  }
   int64_t done = 0;
   if (n->stream && n->graph_steps > 0 && n_steps >= n->graph_steps) {
     const int rc = ensure_graph(n);
@@ -846,8 +859,9 @@ int dpsnn_step(dpsnn_net* n, int64_t n_steps) {
   if (n->t + n_steps > (n->sa.plastic ? 0x7FFFFFFFll : 0xFFFFFFFFll)) return DPSNN_E_INVAL;
   const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
   if (last_bin - rate_first_min(n) + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
-  // the fused schedule advances both spike-log bases: align them after split
-  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
+  // the fused schedule advances both spike-log bases: align them after the
+  // split or persistent schedule
+  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched >= 0 && n->last_sched != DPSNN_SCHED_FUSED)
     HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
   n->last_sched = n->sched;
   if (!n->sa.plastic) return run_steps(n, n_steps);
@@ -873,7 +887,10 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
     int32_t lists;
   };
   std::vector<Cand> cands;
-  if (!n->sa.plastic) cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks, n->sa.spk_lists});
+  if (!n->sa.plastic) {
+    cands.push_back({DPSNN_SCHED_FUSED, n->sa.deliver_blocks, n->sa.spk_lists});
+    cands.push_back({DPSNN_SCHED_PERSIST, n->sa.deliver_blocks, 1});
+  }
   const int32_t tiles = n->sa.n_tiles;
   for (int32_t lists : {0, 1}) {
     if (!lists && tiles > kMaxScanTiles) continue;
@@ -909,8 +926,10 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   for (int64_t r = 0; r < rounds && rc == DPSNN_OK; ++r) {
     for (size_t i = 0; i < nc && rc == DPSNN_OK; ++i) {
       use(cands[i]);
-      // the graph is captured before the timed run
-      if (graphs && (rc = ensure_graph(n)) != DPSNN_OK) break;
+      // the graph is captured before the timed run (the persistent schedule
+      // launches directly)
+      if (graphs && n->sched != DPSNN_SCHED_PERSIST && (rc = ensure_graph(n)) != DPSNN_OK)
+        break;
       hipEvent_t* e = &ev[(size_t)2 * (r * nc + i)];
       if (hipEventRecord(e[0], n->stream) != hipSuccess) { rc = DPSNN_E_DEVICE; break; }
       if ((rc = dpsnn_step(n, K)) != DPSNN_OK) break;
@@ -946,7 +965,7 @@ int dpsnn_profile_steps(dpsnn_net* n, int64_t n_steps, double* host_ms) {
   if (n->t + n_steps > (n->sa.plastic ? 0x7FFFFFFFll : 0xFFFFFFFFll)) return DPSNN_E_INVAL;
   const int64_t last_bin = (n->t + n_steps - 1) / n->p[0].rate_bin_steps;
   if (last_bin - rate_first_min(n) + 1 > n->p[0].rate_bins_cap) return DPSNN_E_RATES_FULL;
-  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched == DPSNN_SCHED_SPLIT)
+  if (n->sched == DPSNN_SCHED_FUSED && n->last_sched >= 0 && n->last_sched != DPSNN_SCHED_FUSED)
     HIP_OK(launch_tick(n->sa, 0, 1, n->stream));
   n->last_sched = n->sched;
   std::vector<hipEvent_t> ev((size_t)3 * n_steps);

@@ -279,6 +279,9 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint32_t t_off,
                        hipStream_t s);
 hipError_t launch_tick(const StepArgs& a, uint32_t n, int sync_logs, hipStream_t s);
+// n steps of the persistent schedule in one cooperative launch (no tick).
+hipError_t launch_persist(const StepArgs& a, int wdt, int acc_bits, uint32_t t_off, uint32_t n,
+                          hipStream_t s);
 hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uint32_t t_off,
                         hipStream_t s);
 // Fold every pending queue entry into its slot and empty the queues; t is

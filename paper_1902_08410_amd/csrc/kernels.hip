@@ -41,6 +41,7 @@
 // t+d_max, so update and delivery of one step need no grid-wide ordering;
 // the kernel boundary orders consecutive steps.  The step index is read on
 // the device (t = *t_base + t_off) so that launches can be captured in a graph.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -1117,45 +1118,54 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 
 // ------------------------------------------------------------------------
 // Split schedule: neuron kernel, then the delivery kernel.
+// Update of one tile of 1024 neurons by one block, and the tile's spike
+// list (its own, or appended to list tile mod kSpkLists of the step).
 template <typename Acc, int NP, int FMT>
-__global__ void __launch_bounds__(256) k_neuron(StepArgs a, StepOff o) {
-  __shared__ int32_t s_spk[1024];
-  __shared__ Acc s_in[1024];
-  __shared__ int s_wt[4];
+__device__ __forceinline__ void update_tile(const StepArgs& a, const StepTime& T, int tile,
+                                            int32_t* s_spk, Acc* s_in, int* s_wt,
+                                            uint32_t* s_base) {
   const int tid = threadIdx.x;
-  const StepTime T = step_time(a, o);
   const uint32_t t = T.t;
-  const int net = __builtin_amdgcn_readfirstlane(a.tile_net[blockIdx.x]);
+  const int net = __builtin_amdgcn_readfirstlane(a.tile_net[tile]);
   const NetDev& nd = a.nets[net];
-  const NeuronPos P = neuron_pos(nd, blockIdx.x, tid);
+  const NeuronPos P = neuron_pos(nd, tile, tid);
   NeuronRegs<Acc> R;
   neuron_load<Acc, NP>(a, nd, net, P, T, R);
   if (a.q_cap)
-    gather_now<Acc, FMT>(a, blockIdx.x, T, s_in);
+    gather_now<Acc, FMT>(a, tile, T, s_in);
   else
     lds_barrier();
   const uint32_t mask = neuron_finish<Acc, NP>(a, nd, P, T, R, a.q_cap ? s_in : nullptr);
   const int n = compact_spikes(mask, P.i0, s_spk, s_wt);
   lds_barrier();
   if (!a.spk_lists) {  // the tile's own list and count
-    int32_t* out = a.spk + (int64_t)blockIdx.x * 1024;
+    int32_t* out = a.spk + (int64_t)tile * 1024;
     for (int k = tid; k < n; k += 256) out[k] = s_spk[k];
-    if (tid == 0) a.blk_cnt[blockIdx.x] = n;
+    if (tid == 0) a.blk_cnt[tile] = n;
     return;
   }
   if (n == 0) return;
   // append the tile's spikes to spike list g = tile mod kSpkLists of the
   // step (the counters share the appends)
-  __shared__ uint32_t s_base;
-  const int g = (int)(blockIdx.x % kSpkLists);
+  const int g = tile % kSpkLists;
   if (tid == 0)
-    s_base = atomicAdd(&a.spk_n[((t & 1u) * kSpkLists + g) * kSpkStride], (uint32_t)n);
+    *s_base = atomicAdd(&a.spk_n[((t & 1u) * kSpkLists + g) * kSpkStride], (uint32_t)n);
   lds_barrier();
   // (a list holds every neuron of its tiles: the bound only guards)
-  const int64_t room = a.spk_cap - (int64_t)s_base;
+  const uint32_t base = *s_base;
+  const int64_t room = a.spk_cap - (int64_t)base;
   const int n_w = (int64_t)n < room ? n : (room > 0 ? (int)room : 0);
-  int32_t* out = a.spk + (int64_t)g * a.spk_cap + s_base;
+  int32_t* out = a.spk + (int64_t)g * a.spk_cap + base;
   for (int k = tid; k < n_w; k += 256) out[k] = s_spk[k];
+}
+
+template <typename Acc, int NP, int FMT>
+__global__ void __launch_bounds__(256) k_neuron(StepArgs a, StepOff o) {
+  __shared__ int32_t s_spk[1024];
+  __shared__ Acc s_in[1024];
+  __shared__ int s_wt[4];
+  __shared__ uint32_t s_base;
+  update_tile<Acc, NP, FMT>(a, step_time(a, o), blockIdx.x, s_spk, s_in, s_wt, &s_base);
 }
 
 // Spike number sidx of the step: per-tile lists, the tile found by binary
@@ -1182,25 +1192,19 @@ __device__ __forceinline__ int32_t spike_at(const StepArgs& a, int sidx, const i
       a.spk[(int64_t)g * a.spk_cap + ((uint32_t)sidx - first)]);
 }
 
-template <typename Acc, int WDT, bool PLAST = false>
-__global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
-  // delivery blocks: inclusive prefix of the tile counts (per-tile lists);
-  // routing blocks: their RouteLds
-  extern __shared__ __align__(16) int32_t s_dyn[];
-  __shared__ int32_t s_part[8];
-  __shared__ uint32_t s_b[4][256];
+// Delivery of the step's spikes by one block (every thread takes part):
+// wavefront wid of nw delivery wavefronts takes work items wid, wid + nw,
+// ...  s_dyn: the dynamic LDS (tile-count prefix and entry staging), s_part
+// and s_b: the block's small LDS arrays.  Block `lead` also advances the
+// spike-log bases and clears the spike-list counters of the next step.
+template <typename Acc, int WDT, bool PLAST>
+__device__ __forceinline__ void deliver_spikes(const StepArgs& a, const StepTime& T,
+                                               int64_t wid, int64_t nw, bool lead,
+                                               int32_t* s_dyn, int32_t* s_part,
+                                               uint32_t (*s_b)[256]) {
   const int tid = threadIdx.x;
   const int nb = a.n_tiles;
-  const StepTime T = step_time(a, o);
   const uint32_t t = T.t;
-  if ((int)blockIdx.x >= a.deliver_blocks) {
-    // routing of the inboxes of step t-1, one tile at a time
-    RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_dyn);
-    const int nr = (int)gridDim.x - a.deliver_blocks;
-    for (int tile = (int)blockIdx.x - a.deliver_blocks; tile < nb; tile += nr)
-      route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, T, L);
-    return;
-  }
   const int lane = tid & 63;
   int32_t* s_pref = s_dyn;
   unsigned long long* s_stage =
@@ -1250,18 +1254,16 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
     n_spk = (int)__shfl(incl, 63);
   }
   const unsigned long long log0 = a.log_base[t & 1];
-  if (blockIdx.x == 0 && tid == 0) {
+  if (lead && tid == 0) {
     a.log_base[(t + 1) & 1] = log0 + (unsigned long long)n_spk;
     a.n_spikes[0] += (unsigned long long)n_spk;
   }
   // the list counters of the next step start from zero (nothing else reads
   // them in this step)
-  if (a.spk_lists && blockIdx.x == 0 && tid < kSpkLists)
+  if (a.spk_lists && lead && tid < kSpkLists)
     a.spk_n[(((t + 1u) & 1u) * kSpkLists + tid) * kSpkStride] = 0u;
   const int cpr = (a.K_out + 255) / 256;  // chunks per row
   const int64_t items = (int64_t)n_spk * cpr;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + (tid >> 6);
-  const int64_t nw = (int64_t)a.deliver_blocks * 4;  // delivery wavefronts
   // item it: chunk it mod cpr of spike number it / cpr.  The next item's
   // loads are issued before the current item is delivered.
   auto load_item = [&](int64_t it, Chunk<Acc>& c) {
@@ -1282,6 +1284,27 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
     if (!more) break;
     cur = nxt;
   }
+}
+
+template <typename Acc, int WDT, bool PLAST = false>
+__global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
+  // delivery blocks: inclusive prefix of the tile counts (per-tile lists)
+  // and entry staging; routing blocks: their RouteLds
+  extern __shared__ __align__(16) int32_t s_dyn[];
+  __shared__ int32_t s_part[8];
+  __shared__ uint32_t s_b[4][256];
+  const StepTime T = step_time(a, o);
+  if ((int)blockIdx.x >= a.deliver_blocks) {
+    // routing of the inboxes of step t-1, one tile at a time
+    RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_dyn);
+    const int nr = (int)gridDim.x - a.deliver_blocks;
+    for (int tile = (int)blockIdx.x - a.deliver_blocks; tile < a.n_tiles; tile += nr)
+      route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, T, L);
+    return;
+  }
+  deliver_spikes<Acc, WDT, PLAST>(a, T, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6),
+                                  (int64_t)a.deliver_blocks * 4, blockIdx.x == 0, s_dyn,
+                                  s_part, s_b);
 }
 
 // Fused schedule (small networks): the tile's own spikes are delivered by
@@ -1332,6 +1355,54 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, StepOff o) {
     Chunk<Acc> c;
     chunk_load<Acc, WDT>(a, s, (it - k * cpr) * 256, lane, c);
     chunk_deliver<Acc, WDT>(a, c, T, lane, s_b[wave], nullptr);
+  }
+}
+
+// Residues of step t_base + t_off computed on the device (the persistent
+// schedule's steps inside one launch).
+__device__ __forceinline__ StepOff step_off_dev(const StepArgs& a, uint32_t t_off) {
+  StepOff o;
+  o.t_off = t_off;
+  o.d_slot = t_off % (uint32_t)a.D;
+  o.d_phase = t_off % (uint32_t)a.rate_bin_steps;
+  o.d_bin = (t_off / (uint32_t)a.rate_bin_steps) % (uint32_t)a.rate_bins_cap;
+  return o;
+}
+
+// Persistent schedule: n_steps steps in one cooperative launch of blocks
+// that are all resident at once (G of them).  Each step: block b updates
+// tiles b, b + G, ...; the grid synchronises; every block delivers (its
+// wavefronts take delivery items over all 4 G wavefronts) and then routes
+// the previous step's inboxes of tiles b, b + G, ...; the grid
+// synchronises.  This is the split schedule's sequence of work, so the
+// results are the same.
+template <typename Acc, int WDT, int NP, int FMT>
+__global__ void __launch_bounds__(256) k_persist(StepArgs a, StepOff o, uint32_t n_steps) {
+  extern __shared__ __align__(16) int32_t s_dyn[];
+  __shared__ int32_t s_spk[1024];
+  __shared__ Acc s_in[1024];
+  __shared__ int s_wt[4];
+  __shared__ uint32_t s_base;
+  __shared__ int32_t s_part[8];
+  __shared__ uint32_t s_b[4][256];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int G = (int)gridDim.x;
+  for (uint32_t k = 0; k < n_steps; ++k) {
+    const StepTime T = step_time(a, step_off_dev(a, o.t_off + k));
+    for (int tile = (int)blockIdx.x; tile < a.n_tiles; tile += G) {
+      update_tile<Acc, NP, FMT>(a, T, tile, s_spk, s_in, s_wt, &s_base);
+      lds_barrier();  // the tile's LDS is reused by the next one
+    }
+    grid.sync();
+    deliver_spikes<Acc, WDT, false>(a, T, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6),
+                                    (int64_t)G * 4, blockIdx.x == 0, s_dyn, s_part, s_b);
+    if (a.q_cap) {
+      lds_barrier();  // the dynamic LDS holds the routing stage from here
+      RouteLds<Acc>& L = *reinterpret_cast<RouteLds<Acc>*>(s_dyn);
+      for (int tile = (int)blockIdx.x; tile < a.n_tiles; tile += G)
+        route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, T, L);
+    }
+    grid.sync();
   }
 }
 
@@ -1512,8 +1583,50 @@ static void launch_fused(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t
     launch_fused_np<Acc, 4>(a, wdt, t_off, st);
 }
 
+template <typename Acc, int WDT, int NP, int FMT>
+static hipError_t launch_persist_t(const StepArgs& a, uint32_t t_off, uint32_t n,
+                                   hipStream_t st) {
+  const void* fn = reinterpret_cast<const void*>(&k_persist<Acc, WDT, NP, FMT>);
+  const size_t pref = (size_t)stage_offset_words(a) * 4 + kStageBytes;
+  const size_t route = a.q_cap ? sizeof(RouteLds<Acc>) : 0;
+  const size_t lds = pref > route ? pref : route;
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, &k_persist<Acc, WDT, NP, FMT>, 256, lds);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1 || cus < 1) return hipErrorLaunchFailure;
+  StepArgs aa = a;
+  StepOff o = step_off(a, t_off);
+  uint32_t nn = n;
+  void* args[] = {&aa, &o, &nn};
+  return hipLaunchCooperativeKernel(fn, dim3((unsigned)(per_cu * cus)), dim3(256), args,
+                                    (unsigned)lds, st);
+}
+
+template <typename Acc, int NP>
+static hipError_t launch_persist_np(const StepArgs& a, int wdt, uint32_t t_off, uint32_t n,
+                                    hipStream_t st) {
+  if (wdt == DPSNN_W_F16) return launch_persist_t<Acc, DPSNN_W_F16, NP, kFmtCode>(a, t_off, n, st);
+  if (wdt == DPSNN_W_I8) return launch_persist_t<Acc, DPSNN_W_I8, NP, kFmtCode>(a, t_off, n, st);
+  if constexpr (sizeof(Acc) == 4)
+    if (a.q_packed) return launch_persist_t<Acc, DPSNN_W_F32, NP, kFmtPacked>(a, t_off, n, st);
+  return launch_persist_t<Acc, DPSNN_W_F32, NP, kFmtWide>(a, t_off, n, st);
+}
+
+hipError_t launch_persist(const StepArgs& a, int wdt, int acc_bits, uint32_t t_off, uint32_t n,
+                          hipStream_t st) {
+  if (acc_bits == 32)
+    return a.P <= 2 ? launch_persist_np<int32_t, 2>(a, wdt, t_off, n, st)
+                    : launch_persist_np<int32_t, 4>(a, wdt, t_off, n, st);
+  return a.P <= 2 ? launch_persist_np<int64_t, 2>(a, wdt, t_off, n, st)
+                  : launch_persist_np<int64_t, 4>(a, wdt, t_off, n, st);
+}
+
 hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint32_t t_off,
                        hipStream_t st) {
+  if (sched == DPSNN_SCHED_PERSIST) return launch_persist(a, wdt, acc_bits, t_off, 1, st);
   if (sched == DPSNN_SCHED_SPLIT) {
     if (acc_bits == 32)
       launch_split<int32_t>(a, wdt, t_off, st);

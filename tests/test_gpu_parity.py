@@ -727,3 +727,46 @@ def test_spike_order_per_tile_lists_is_deterministic(L):
         logs.append((st, ids))
         net.close()
     assert np.array_equal(logs[0][0], logs[1][0]) and np.array_equal(logs[0][1], logs[1][1])
+
+
+@pytest.mark.parametrize("case", ["tiny_f32_acc32", "tiny_i8_acc64", "tiny_f16_acc32",
+                                  "mid_f32_strong_adapt"])
+def test_persistent_schedule_bit_exact(L, case):
+    """The persistent schedule (many steps per cooperative launch, grid
+    synchronisation between update and delivery) against the oracle, with
+    switches to the split and fused schedules between chunks."""
+    p = RASTER_CASES[case]
+    _say("persistent", case)
+    net, orc = _pair(p, 8)
+    n = 0
+    for k, (sched, steps) in enumerate([(2, 300), (1, 130), (2, 1), (0, 77), (2, 700)]):
+        L.dpsnn_set_schedule(net, sched)
+        assert net.stats()["schedule"] == sched
+        L.dpsnn_step(net, steps)
+        orc.step(steps)
+        n += _compare_all(L, net, orc, (case, k, sched))
+    assert n > 50
+    assert np.array_equal(L.dpsnn_read_rates(net), orc.rates()[: 1208 // p["rate_bin_steps"]])
+    net.close()
+
+
+def test_persistent_schedule_population_model_and_batch(L):
+    """Persistent schedule on a batch of F/B/I networks (three populations)
+    against each network's solo run with the split schedule."""
+    plist = [W.fbi(3, 3, "sw", scale=0.1), W.fbi(2, 4, "aw88", scale=0.1, lam=0.7)]
+    seeds = [3, 4]
+    _say("persistent batch")
+    net = L.dpsnn_build_batch(plist, seeds)
+    L.dpsnn_set_schedule(net, 2)
+    L.dpsnn_step(net, 1500)
+    st, ids = L.dpsnn_read_spikes(net)
+    parts = _split_spikes(L, net, st, ids)
+    for (s_k, i_k, info), p, sd in zip(parts, plist, seeds):
+        solo = L.dpsnn_build(p, sd)
+        L.dpsnn_set_schedule(solo, 1)
+        L.dpsnn_step(solo, 1500)
+        ss, si = L.dpsnn_read_spikes(solo)
+        assert np.array_equal(s_k, ss) and np.array_equal(i_k, si)
+        assert len(ss) > 300
+        solo.close()
+    net.close()
