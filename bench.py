@@ -88,10 +88,34 @@ def recorded_traffic(workload: str, wdt: str):
     return rec if rec.get("kernels_sha256") == kernels_sha256() else None
 
 
-def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, out_json):
-    """Fold rocprofv3 CSV output (kernel trace/stats and FETCH_SIZE / WRITE_SIZE
-    passes of this benchmark, plus the same counters for a 256 MiB copy) into
-    per-launch figures: medians over the last 2000 dispatches of each kernel."""
+WDT_NAMES = {0: "f32", 1: "f16", 2: "i8"}
+
+
+def _kernel_group(name: str):
+    """(kernel, weight format) of a traced step-kernel instantiation, e.g.
+    'dpsnn::k_deliver<int, 0, false>(...)' -> ('k_deliver', 'f32'); None for
+    other kernels.  k_deliver and k_step take the weight format as their
+    second template argument; k_neuron takes the entry format instead, so
+    its group is assigned from the k_deliver launches around it."""
+    base = name.split("(")[0].replace("void ", "")
+    for k in ("k_deliver", "k_neuron", "k_step", "k_persist"):
+        if base.startswith(f"dpsnn::{k}<"):
+            args = base[len(f"dpsnn::{k}<"):].rstrip(">").split(",")
+            if k == "k_neuron":
+                return k, None
+            return k, WDT_NAMES.get(int(args[1])) if len(args) > 1 else None
+    return None
+
+
+def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload,
+                      window):
+    """Fold rocprofv3 CSV output (a kernel trace of the benchmark command,
+    FETCH_SIZE / WRITE_SIZE passes, and the same counters for a 256 MiB copy)
+    into per-launch figures of each weight format's kernels over the window
+    the benchmark times them in: the last `window` dispatches of each kernel
+    of that format (the event-timed steps; one dispatch per step and batched
+    handle).  Writes k_deliver_k_neuron_<workload>_<format>_traffic.json
+    under profiles/ for every format present."""
     import csv
     import glob
     import statistics
@@ -100,6 +124,24 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir
         f = glob.glob(os.path.join(d, "**", pat), recursive=True)
         return list(csv.DictReader(open(f[0]))) if f else []
 
+    def by_group(rows, value):
+        """{(kernel, format): [values in dispatch order]}; a k_neuron launch
+        takes the format of the next k_deliver / k_step launch."""
+        out, pend = {}, []
+        for r in rows:
+            g = _kernel_group(r["Kernel_Name"])
+            if g is None:
+                continue
+            if g[0] == "k_neuron":
+                pend.append(value(r))
+                continue
+            out.setdefault(g, []).append(value(r))
+            if pend:
+                out.setdefault(("k_neuron", g[1]), []).extend(pend)
+                pend = []
+        return out
+
+    window = int(window)
     known_kib = 256 * 1024
     cf = [float(r["Counter_Value"]) for r in one(cal_fetch_dir, "*counter_collection.csv")
           if "copyBuffer" in r["Kernel_Name"]]
@@ -107,26 +149,37 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir
           if "copyBuffer" in r["Kernel_Name"]]
     f_fetch = known_kib / statistics.mean(cf)
     f_write = known_kib / statistics.mean(cw)
-    rec = {"kernels_sha256": kernels_sha256(), "fetch_scale": f_fetch, "write_scale": f_write,
-           "kernels": {}}
-    fe = one(fetch_dir, "*counter_collection.csv")
-    wr = one(write_dir, "*counter_collection.csv")
-    tr = one(kt_dir, "*kernel_trace.csv")
-    for name in ("k_neuron", "k_deliver", "k_step", "k_persist"):
-        a = [float(r["Counter_Value"]) for r in fe if name in r["Kernel_Name"]][-2000:]
-        b = [float(r["Counter_Value"]) for r in wr if name in r["Kernel_Name"]][-2000:]
-        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tr
-             if name in r["Kernel_Name"]][-4000:]
-        if not a or not b:
+    def ordered(rows):
+        return sorted(rows, key=lambda r: int(r.get("Dispatch_Id") or 0))
+
+    cval = lambda r: float(r["Counter_Value"])
+    fe = by_group(ordered(one(fetch_dir, "*counter_collection.csv")), cval)
+    wr = by_group(ordered(one(write_dir, "*counter_collection.csv")), cval)
+    tr = by_group(ordered(one(kt_dir, "*kernel_trace.csv")),
+                  lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    recs = {}
+    for (k, wdt), a in fe.items():
+        b = wr.get((k, wdt), [])
+        d = tr.get((k, wdt), [])[-window:]
+        a = a[-window:]
+        b = b[-window:]
+        if not a or not b or wdt is None:
             continue
-        fetch_b = statistics.median(a) * 1024 * f_fetch
-        write_b = statistics.median(b) * 1024 * f_write
-        rec["kernels"][name] = {"fetch_bytes": fetch_b, "write_bytes": write_b,
-                                "bytes_per_launch": fetch_b + write_b,
-                                "median_duration_us": statistics.median(d) / 1e3 if d else None,
-                                "dispatches": len(a)}
-    json.dump(rec, open(out_json, "w"), indent=1)
-    print(json.dumps(rec, indent=1))
+        rec = recs.setdefault(wdt, {"kernels_sha256": kernels_sha256(), "workload": workload,
+                                    "fetch_scale": f_fetch, "write_scale": f_write,
+                                    "window_dispatches": window, "kernels": {}})
+        fetch_b = statistics.mean(a) * 1024 * f_fetch
+        write_b = statistics.mean(b) * 1024 * f_write
+        rec["kernels"][k] = {
+            "fetch_bytes": fetch_b, "write_bytes": write_b, "bytes_per_launch": fetch_b + write_b,
+            "median_bytes_per_launch": (statistics.median(a) * f_fetch +
+                                        statistics.median(b) * f_write) * 1024,
+            "mean_duration_us": statistics.mean(d) / 1e3 if d else None,
+            "median_duration_us": statistics.median(d) / 1e3 if d else None,
+            "trace_dispatches": len(d), "counter_dispatches": len(a)}
+    for wdt, rec in recs.items():
+        json.dump(rec, open(traffic_json(workload, wdt), "w"), indent=1)
+    print(json.dumps(recs, indent=1))
 
 
 def summarize_counters(dirs, out_json):
@@ -169,20 +222,26 @@ def host_cpu():
     return model, nproc
 
 
-def cpu_baseline(params, gpu_net, dpsnn, workloads, label: str, steps: int, budget_s: float):
+def cpu_baseline(params, seed, gpu_net, k, dpsnn, workloads, label: str, steps: int,
+                 budget_s: float):
     """The oracle, single-threaded, (1) re-running a post-transient window of
-    the benchmark network from the GPU's state (rows regenerated from Philox
-    per spike), bounded by budget_s; (2) the whole 2x2 correctness network
-    (5000 neurons, 2 s).  Events/s of the plain CPU implementation: a reported
-    baseline, not the target."""
+    network k of the benchmark handle from the GPU's state (rows regenerated
+    from Philox per spike), bounded by budget_s; (2) the whole 2x2
+    correctness network (5000 neurons, 2 s).  Events/s of the plain CPU
+    implementation: a reported baseline, not the target.  The handle is only
+    read (its queued inputs are moved into the slots), so no step kernel runs
+    after the timed and profiled steps."""
     import numpy as np
     import oracle
+    info = dpsnn.dpsnn_net_info(gpu_net, k)
+    b, n = info["base"], info["n_neurons"]
     V, c, r = dpsnn.dpsnn_read_state(gpu_net)
     slots = dpsnn.dpsnn_read_slots(gpu_net)
     t = gpu_net.stats()["t"]
-    orc = oracle.Oracle(params, gpu_net.seed, store_rows=False)
-    orc.set_state(V.astype(np.float64), c.astype(np.float64), r.astype(np.int32))
-    orc.set_ring(slots)
+    orc = oracle.Oracle(params, seed, store_rows=False)
+    orc.set_state(V[b:b + n].astype(np.float64), c[b:b + n].astype(np.float64),
+                  r[b:b + n].astype(np.int32))
+    orc.set_ring(np.ascontiguousarray(slots[:, b:b + n]))
     orc.set_time(t)
     del V, c, r, slots
     done = 0
@@ -367,8 +426,10 @@ def group_record(workload, wdt, nets, res, steps, S, args):
                                 "events_per_s": sp * K_OUT / wall}
     step_gbs = step_bytes / wall / 1e9
     rec = recorded_traffic(workload, wdt)
-    traffic = rec["kernels"]["k_deliver"]["bytes_per_launch"] \
-        if rec and "k_deliver" in rec["kernels"] else None
+    rk = rec["kernels"] if rec else {}
+    traffic = rk["k_deliver"]["bytes_per_launch"] if "k_deliver" in rk else None
+    # the committed kernel trace of this command: mean duration over the same window
+    trace_us = rk["k_deliver"].get("mean_duration_us") if "k_deliver" in rk else None
     value = events / wall
     return {
         "events_per_s": value,
@@ -387,13 +448,18 @@ def group_record(workload, wdt, nets, res, steps, S, args):
             "events_per_launch": ev_per_launch,
             "algorithmic_bytes_per_launch": alg_del,
             "avg_launch_us": del_us,
+            "profile_avg_launch_us": trace_us,
             "events_per_s_in_kernel": ev_per_launch / (del_us * 1e-6) if del_us > 0 else None,
             "update_kernel": {"kernel": "k_neuron (update, with the queued-input gather)",
                               "avg_launch_us": upd_us,
                               "algorithmic_bytes_per_launch": n_mean * Bn,
                               "achieved_GB_s": n_mean * Bn / (upd_us * 1e-6) / 1e9
                               if upd_us else None,
-                              "bytes_per_neuron_step": Bn},
+                              "bytes_per_neuron_step": Bn,
+                              "traffic": rk["k_neuron"]["bytes_per_launch"]
+                              if "k_neuron" in rk else None,
+                              "profile_avg_launch_us": rk["k_neuron"].get("mean_duration_us")
+                              if "k_neuron" in rk else None},
             "step_us": res["gpu_ms"] * 1e3 / (steps * S * len(nets)),
             "whole_step": {"algorithmic_bytes": step_bytes,
                            "achieved_GB_s": step_gbs,
@@ -482,9 +548,9 @@ def main():
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--calibrate", action="store_true",
                     help="only copy 256 MiB device-to-device three times (counter calibration)")
-    ap.add_argument("--summarize-rocprof", nargs=6, metavar=("KT", "FETCH", "WRITE",
-                    "CAL_FETCH", "CAL_WRITE", "OUT_JSON"),
-                    help="fold rocprofv3 CSV directories into per-launch traffic figures")
+    ap.add_argument("--summarize-rocprof", nargs=7, metavar=("KT", "FETCH", "WRITE", "CAL_FETCH",
+                                                           "CAL_WRITE", "WORKLOAD", "WINDOW"),
+                    help="fold rocprofv3 output into profiles/*_traffic.json")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="medians per kernel of --pmc passes: DIR... OUT_JSON")
     ap.add_argument("--profile-steps", type=int, default=2000,
@@ -547,15 +613,10 @@ def main():
             if gi == 0 and not args.no_cpu_baseline and wl in ("grid48", "grid24"):
                 h, pl, labels = next(iter(nets.values()))
                 p = pl[0]
-                if len(pl) > 1:   # the first network alone, from its own build
-                    h.close()
-                    h = dpsnn.dpsnn_build(p, 1)
-                    dpsnn.dpsnn_step(h, S)
-                cpu = cpu_baseline(p, h, dpsnn, workloads,
+                cpu = cpu_baseline(p, 1, h, 0, dpsnn, workloads,
                                    f"{p['grid_w']}x{p['grid_h']} {labels[0].upper()}", 200,
                                    args.cpu_budget)
                 progress("cpu baseline done")
-                h.close()
             for h, _, _ in nets.values():
                 h.close()
             del nets
