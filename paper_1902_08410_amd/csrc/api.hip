@@ -118,7 +118,11 @@ int build_impl(dpsnn_net* n) {
   void* slots = dev_alloc(n, (size_t)T0.D * Np * ab);
   n->bytes_state = Np * 9 + (int64_t)T0.D * Np * ab;
   const int64_t n_tiles = Np / 1024;
-  const int64_t spk_cap = (n_tiles + kSpkLists - 1) / kSpkLists * 1024;
+  // appended lists: list g takes the runs g, g + kSpkLists, ... of
+  // 2^kSpkListShift consecutive tiles, and room for every neuron of them
+  const int64_t tile_runs = (n_tiles + (1 << kSpkListShift) - 1) >> kSpkListShift;
+  const int64_t spk_cap =
+      (tile_runs + kSpkLists - 1) / kSpkLists * ((int64_t)1024 << kSpkListShift);
   int32_t* spk = (int32_t*)dev_alloc(n, (size_t)(kSpkLists * spk_cap) * 4);
   int32_t* blk_cnt = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
   int32_t* tile_net = (int32_t*)dev_alloc(n, (size_t)n_tiles * 4);
@@ -1162,7 +1166,7 @@ int dpsnn_stats(dpsnn_net* n, dpsnn_stats_t* out) {
   {
     const int ab = acc_bytes(n->p[0]);
     out->lds_bytes = n->sched == DPSNN_SCHED_SPLIT
-                         ? (n->sa.spk_lists ? 0 : n->sa.n_tiles * 4) + 8192 + 4 * 256 * 4
+                         ? (int32_t)deliver_lds_bytes(n->sa, ab * 8)
                          : 1024 * 4 + 1024 * ab + kQueueMaxSlots * 4 + 4 * 256 * 4 + 16;
   }
   out->schedule = n->sched;

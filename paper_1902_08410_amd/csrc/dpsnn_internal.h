@@ -17,6 +17,7 @@ constexpr int kMaxKout = 4096;
 constexpr int kDelayShift = 26;  // target word = target | delay index << 26
 constexpr int32_t kTargetMask = (1 << kDelayShift) - 1;
 constexpr int kSpkLists = 64;          // appended spike lists per step
+constexpr int kSpkListShift = 4;       // runs of 16 consecutive tiles share a list
 constexpr int kMaxScanTiles = 14000;   // per-tile lists: LDS prefix of the tile counts
                                        // (with the entry staging and the static LDS,
                                        // within 64 KiB per block)
@@ -287,6 +288,8 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
 // Fold every pending queue entry into its slot and empty the queues; t is
 // the number of steps taken.
 hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t s);
+// LDS per block of the split schedule's delivery kernel (static and dynamic).
+size_t deliver_lds_bytes(const StepArgs& a, int acc_bits);
 // Periodic efficacy update of the plastic synapses after T steps.
 hipError_t launch_stdp_update(const StepArgs& a, int32_t T, hipStream_t s);
 hipError_t launch_absum_max(const unsigned long long* absum, int64_t n,

@@ -15,11 +15,14 @@
 //  k_deliver  delivery blocks: every wavefront takes chunks of 256 synapses
 //             of spiking rows (16-byte loads, the next chunk's loads issued
 //             before the current one is delivered); the events of a chunk to
-//             one tile form a run in the target-sorted row, and one returning
-//             atomic reserves the run's room in that tile's inbox of the
-//             step.  Routing blocks of the same grid move each tile's inbox of
-//             the previous step into its per-slot queues.  Also appends the
-//             spike log.
+//             one tile form a run in the target-sorted row.  With appended
+//             spike lists the four wavefronts of a block take the same chunk
+//             of four consecutive spikes together, and one returning atomic
+//             per target tile reserves the runs of all four in that tile's
+//             inbox of the step (an LDS hash merges them); otherwise one
+//             atomic per run.  Routing blocks of the same grid move each
+//             tile's inbox of the previous step into its per-slot queues.
+//             Also appends the spike log.
 //  k_step     fused schedule for small networks: update, routing and the
 //             delivery of the tile's own spikes in one block per tile.
 //  k_drain    folds pending queue entries into the slots (schedule switches
@@ -466,6 +469,14 @@ __device__ __forceinline__ void gather_now(const StepArgs& a, int tile, const St
 // (per-tile spike lists), then the staging of the inbox entries, 256 per
 // wavefront.
 constexpr size_t kStageBytes = 4 * 256 * 8;
+// Block-merged reservations: an LDS hash of the target tiles of the four
+// chunks a delivery block handles at once (key, events, inbox base).
+constexpr int kHashBits = 10;
+constexpr int kHash = 1 << kHashBits;      // >= the runs of 4 chunks (4 x 256)
+constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
+constexpr size_t kHashBytes = 3 * kHash * 4;
+constexpr bool kMergeReserve = true;
+static_assert(kHash == 4 * 256, "one uint4 of hash keys per thread of a 256-thread block");
 __host__ __device__ inline uint32_t stage_offset_words(const StepArgs& a) {
   return a.spk_lists ? 0u : ((uint32_t)a.n_tiles + 3u) / 4u * 4u;
 }
@@ -946,7 +957,8 @@ __device__ __forceinline__ void chunk_plasticity(const StepArgs& a, const Chunk<
 template <typename Acc, int WDT>
 __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc>& c,
                                               const StepTime& T, int lane, uint32_t* s_b,
-                                              unsigned long long* s_e) {
+                                              unsigned long long* s_e,
+                                              uint32_t* s_hash = nullptr, bool valid = true) {
   const int p0 = c.p0;
   const int p = p0 + lane * 4;
   const int* tv = c.tv;
@@ -957,6 +969,7 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
   if (slot0 >= a.D) slot0 -= a.D;
   Acc* slots = static_cast<Acc*>(a.slots);
   if (a.q_cap == 0) {
+    if (!valid) return;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (p + j < a.K_out) {
@@ -974,7 +987,7 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
   const int end = p0 + 256 < a.K_out ? p0 + 256 : a.K_out;
   int tl[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) tl[j] = p + j < end ? (tv[j] & kTargetMask) >> 10 : -1;
+  for (int j = 0; j < 4; ++j) tl[j] = valid && p + j < end ? (tv[j] & kTargetMask) >> 10 : -1;
   int prev = __shfl_up(tl[3], 1);
   if (lane == 0) prev = -2;
   bool f[4];
@@ -1016,19 +1029,76 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
     }
   }
   const uint32_t par = t & 1u;
-  // reservations: one returning atomic per run
+  uint32_t len[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
+    len[j] = 0;
     if (f[j]) {
       int ne = nxt;
 #pragma unroll
       for (int k = 3; k > j; --k)
         if (f[k]) ne = p + k;
       if (ne > end) ne = end;
-      const uint32_t len = (uint32_t)(ne - (p + j));
-      s_b[p + j - p0] =
-          atomicAdd(&a.in_cnt[((int64_t)par * a.n_tiles + tl[j]) * kInboxStride], len);
+      len[j] = (uint32_t)(ne - (p + j));
     }
+  }
+  if (s_hash) {
+    // Reservations merged over the block's four chunks (the same chunk of
+    // four spikes in a row of the spike list, whose rows share target
+    // tiles): each run enters its tile in the LDS hash and takes its rank
+    // among the block's events to that tile; one returning atomic per tile
+    // then reserves them all, and each run's base is that reservation plus
+    // its rank.  Every wavefront of the block passes both barriers.
+    uint32_t* s_hk = s_hash;
+    uint32_t* s_hc = s_hash + kHash;
+    uint32_t* s_hb = s_hash + 2 * kHash;
+    // each run's hash entry and rank (< 2^11) wait in the wavefront's
+    // scratch across the barriers, not in registers
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (f[j]) {
+        const uint32_t key = (uint32_t)tl[j];
+        uint32_t h = (key * 2654435761u) >> (32 - kHashBits);
+        // at most kHash distinct tiles per round: a free or matching
+        // entry is always found
+        for (;;) {
+          const uint32_t old = atomicCAS(&s_hk[h], kHashEmpty, key);
+          if (old == kHashEmpty || old == key) break;
+          h = (h + 1) & (uint32_t)(kHash - 1);
+        }
+        s_b[p + j - p0] = h << 16 | atomicAdd(&s_hc[h], len[j]);
+      }
+    }
+    lds_barrier();
+    {
+      const int h0 = (int)threadIdx.x * 4;  // kHash == 4 * blockDim.x
+      const uint4 k4 = *reinterpret_cast<const uint4*>(s_hk + h0);
+      const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (kk[u] != kHashEmpty) {
+          s_hb[h0 + u] = atomicAdd(&a.in_cnt[((int64_t)par * a.n_tiles + kk[u]) * kInboxStride],
+                                   s_hc[h0 + u]);
+          s_hk[h0 + u] = kHashEmpty;
+          s_hc[h0 + u] = 0;
+        }
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (f[j]) {
+        const uint32_t v = s_b[p + j - p0];
+        s_b[p + j - p0] = s_hb[v >> 16] + (v & 0xFFFFu);
+      }
+    }
+  } else {
+    // reservations: one returning atomic per run
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (f[j])
+        s_b[p + j - p0] =
+            atomicAdd(&a.in_cnt[((int64_t)par * a.n_tiles + tl[j]) * kInboxStride], len[j]);
   }
   wave_lds_sync();
   if (s_e) {
@@ -1119,7 +1189,7 @@ __device__ __forceinline__ void record_spike(const StepArgs& a, int32_t id, uint
 // ------------------------------------------------------------------------
 // Split schedule: neuron kernel, then the delivery kernel.
 // Update of one tile of 1024 neurons by one block, and the tile's spike
-// list (its own, or appended to list tile mod kSpkLists of the step).
+// list (its own, or appended to one of the kSpkLists lists of the step).
 template <typename Acc, int NP, int FMT>
 __device__ __forceinline__ void update_tile(const StepArgs& a, const StepTime& T, int tile,
                                             int32_t* s_spk, Acc* s_in, int* s_wt,
@@ -1145,9 +1215,11 @@ __device__ __forceinline__ void update_tile(const StepArgs& a, const StepTime& T
     return;
   }
   if (n == 0) return;
-  // append the tile's spikes to spike list g = tile mod kSpkLists of the
-  // step (the counters share the appends)
-  const int g = tile % kSpkLists;
+  // append the tile's spikes to spike list g = (tile >> kSpkListShift) mod
+  // kSpkLists of the step: the counters share the appends, and neighbouring
+  // tiles, whose rows reach the same target tiles, follow each other in a
+  // list (the merged reservations of delivery gain from that)
+  const int g = (tile >> kSpkListShift) % kSpkLists;
   if (tid == 0)
     *s_base = atomicAdd(&a.spk_n[((t & 1u) * kSpkLists + g) * kSpkStride], (uint32_t)n);
   lds_barrier();
@@ -1197,11 +1269,12 @@ __device__ __forceinline__ int32_t spike_at(const StepArgs& a, int sidx, const i
 // ...  s_dyn: the dynamic LDS (tile-count prefix and entry staging), s_part
 // and s_b: the block's small LDS arrays.  Block `lead` also advances the
 // spike-log bases and clears the spike-list counters of the next step.
-template <typename Acc, int WDT, bool PLAST>
+template <typename Acc, int WDT, bool PLAST, bool MERGE = false>
 __device__ __forceinline__ void deliver_spikes(const StepArgs& a, const StepTime& T,
                                                int64_t wid, int64_t nw, bool lead,
                                                int32_t* s_dyn, int32_t* s_part,
-                                               uint32_t (*s_b)[256]) {
+                                               uint32_t (*s_b)[256],
+                                               uint32_t* s_hash = nullptr) {
   const int tid = threadIdx.x;
   const int nb = a.n_tiles;
   const uint32_t t = T.t;
@@ -1263,6 +1336,47 @@ __device__ __forceinline__ void deliver_spikes(const StepArgs& a, const StepTime
   if (a.spk_lists && lead && tid < kSpkLists)
     a.spk_n[(((t + 1u) & 1u) * kSpkLists + tid) * kSpkStride] = 0u;
   const int cpr = (a.K_out + 255) / 256;  // chunks per row
+  if constexpr (MERGE) {
+    // (with queues and appended spike lists only)
+    // Block items: chunk bi mod cpr of the four spikes 4 (bi / cpr) + w,
+    // wavefront w taking one; the block's wavefronts run the same rounds.
+    const int wave = tid >> 6;
+    const int64_t b = wid >> 2, nb = nw >> 2;
+    const int64_t bitems = ((int64_t)n_spk + 3) / 4 * cpr;
+    for (int h = tid; h < kHash; h += 256) {
+      s_hash[h] = kHashEmpty;
+      s_hash[kHash + h] = 0u;
+    }
+    lds_barrier();
+    auto load_block_item = [&](int64_t bi, Chunk<Acc>& c) -> bool {
+      const int64_t g = bi / cpr;
+      const int chunk = (int)(bi - g * cpr);
+      const int64_t sidx = 4 * g + wave;
+      if (sidx >= n_spk) {
+        c.s = 0;
+        c.p0 = 0;
+        return false;
+      }
+      const int32_t s = spike_at(a, (int)sidx, s_pref, incl, excl);
+      if (chunk == 0 && lane == 0) record_spike(a, s, t, log0 + (unsigned long long)sidx);
+      chunk_load<Acc, WDT>(a, s, chunk * 256, lane, c);
+      return true;
+    };
+    Chunk<Acc> cur;
+    bool v_cur = false;
+    if (b < bitems) v_cur = load_block_item(b, cur);
+    for (int64_t bi = b; bi < bitems; bi += nb) {
+      Chunk<Acc> nxt;
+      bool v_nxt = false;
+      const bool more = bi + nb < bitems;
+      if (more) v_nxt = load_block_item(bi + nb, nxt);
+      if (PLAST && v_cur) chunk_plasticity<Acc>(a, cur, t, lane);
+      chunk_deliver<Acc, WDT>(a, cur, T, lane, s_b[wave], s_stage + wave * 256, s_hash, v_cur);
+      if (!more) break;
+      cur = nxt;
+      v_cur = v_nxt;
+    }
+  } else {
   const int64_t items = (int64_t)n_spk * cpr;
   // item it: chunk it mod cpr of spike number it / cpr.  The next item's
   // loads are issued before the current item is delivered.
@@ -1284,9 +1398,10 @@ __device__ __forceinline__ void deliver_spikes(const StepArgs& a, const StepTime
     if (!more) break;
     cur = nxt;
   }
+  }
 }
 
-template <typename Acc, int WDT, bool PLAST = false>
+template <typename Acc, int WDT, bool PLAST = false, bool MERGE = false>
 __global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
   // delivery blocks: inclusive prefix of the tile counts (per-tile lists)
   // and entry staging; routing blocks: their RouteLds
@@ -1302,9 +1417,11 @@ __global__ void __launch_bounds__(256) k_deliver(StepArgs a, StepOff o) {
       route_inbox<Acc, WDT != DPSNN_W_F32>(a, tile, T, L);
     return;
   }
-  deliver_spikes<Acc, WDT, PLAST>(a, T, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6),
-                                  (int64_t)a.deliver_blocks * 4, blockIdx.x == 0, s_dyn,
-                                  s_part, s_b);
+  deliver_spikes<Acc, WDT, PLAST, MERGE>(
+      a, T, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), (int64_t)a.deliver_blocks * 4,
+      blockIdx.x == 0, s_dyn, s_part, s_b,
+      MERGE ? reinterpret_cast<uint32_t*>(s_dyn + stage_offset_words(a) + kStageBytes / 4)
+            : nullptr);
 }
 
 // Fused schedule (small networks): the tile's own spikes are delivered by
@@ -1515,11 +1632,18 @@ hipError_t launch_init(const InitArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Merged reservations in the delivery kernel: with queues and appended
+// spike lists.
+static bool merge_reserve(const StepArgs& a) { return kMergeReserve && a.q_cap && a.spk_lists; }
+
 // Dynamic LDS of the delivery kernel: the larger of the tile-count prefix
 // (per-tile spike lists) and the routing blocks' RouteLds.
 template <typename Acc>
 static size_t deliver_lds(const StepArgs& a) {
-  const size_t pref = (size_t)stage_offset_words(a) * 4 + kStageBytes;
+  // (the merged reservations' hash only with appended spike lists, whose
+  // blocks keep no tile-count prefix)
+  const size_t pref =
+      (size_t)stage_offset_words(a) * 4 + kStageBytes + (merge_reserve(a) ? kHashBytes : 0);
   const size_t route = a.route_blocks ? sizeof(RouteLds<Acc>) : 0;
   return pref > route ? pref : route;
 }
@@ -1548,20 +1672,34 @@ static void launch_neuron(const StepArgs& a, uint32_t t_off, hipStream_t st) {
   launch_neuron_fmt<Acc, kFmtWide>(a, t_off, st);
 }
 
+template <typename Acc, bool MERGE>
+static void launch_deliver(const StepArgs& a, int wdt, dim3 grid, size_t lds, uint32_t t_off,
+                           hipStream_t st) {
+  const dim3 block(256);
+  if (a.plastic)
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32, true, MERGE>), grid, block, lds, st, a,
+                       step_off(a, t_off));
+  else if (wdt == DPSNN_W_F32)
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32, false, MERGE>), grid, block, lds, st, a,
+                       step_off(a, t_off));
+  else if (wdt == DPSNN_W_F16)
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F16, false, MERGE>), grid, block, lds, st, a,
+                       step_off(a, t_off));
+  else
+    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_I8, false, MERGE>), grid, block, lds, st, a,
+                       step_off(a, t_off));
+}
+
 template <typename Acc>
 static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
   const dim3 block(256);
   launch_neuron<Acc>(a, t_off, st);
   const size_t lds = deliver_lds<Acc>(a);
   const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
-  if (a.plastic)
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32, true>), grid, block, lds, st, a, step_off(a, t_off));
-  else if (wdt == DPSNN_W_F32)
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F32>), grid, block, lds, st, a, step_off(a, t_off));
-  else if (wdt == DPSNN_W_F16)
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_F16>), grid, block, lds, st, a, step_off(a, t_off));
+  if (merge_reserve(a))
+    launch_deliver<Acc, true>(a, wdt, grid, lds, t_off, st);
   else
-    hipLaunchKernelGGL((k_deliver<Acc, DPSNN_W_I8>), grid, block, lds, st, a, step_off(a, t_off));
+    launch_deliver<Acc, false>(a, wdt, grid, lds, t_off, st);
 }
 
 template <typename Acc, int NP>
@@ -1652,27 +1790,28 @@ hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uin
       launch_neuron<int32_t>(a, t_off, st);
     else
       launch_neuron<int64_t>(a, t_off, st);
-  } else if (a.plastic) {
-    if (acc_bits == 32)
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32, true>), grid, block, lds, st, a, step_off(a, t_off));
-    else
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32, true>), grid, block, lds, st, a, step_off(a, t_off));
-  } else if (acc_bits == 32) {
-    if (wdt == DPSNN_W_F32)
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F32>), grid, block, lds, st, a, step_off(a, t_off));
-    else if (wdt == DPSNN_W_F16)
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_F16>), grid, block, lds, st, a, step_off(a, t_off));
-    else
-      hipLaunchKernelGGL((k_deliver<int32_t, DPSNN_W_I8>), grid, block, lds, st, a, step_off(a, t_off));
   } else {
-    if (wdt == DPSNN_W_F32)
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F32>), grid, block, lds, st, a, step_off(a, t_off));
-    else if (wdt == DPSNN_W_F16)
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_F16>), grid, block, lds, st, a, step_off(a, t_off));
-    else
-      hipLaunchKernelGGL((k_deliver<int64_t, DPSNN_W_I8>), grid, block, lds, st, a, step_off(a, t_off));
+    // the delivery launch of the split schedule, as launch_split makes it
+    const bool m = merge_reserve(a);
+    if (acc_bits == 32) {
+      if (m)
+        launch_deliver<int32_t, true>(a, wdt, grid, lds, t_off, st);
+      else
+        launch_deliver<int32_t, false>(a, wdt, grid, lds, t_off, st);
+    } else {
+      if (m)
+        launch_deliver<int64_t, true>(a, wdt, grid, lds, t_off, st);
+      else
+        launch_deliver<int64_t, false>(a, wdt, grid, lds, t_off, st);
+    }
   }
   return hipGetLastError();
+}
+
+size_t deliver_lds_bytes(const StepArgs& a, int acc_bits) {
+  // dynamic part, plus the wavefront scratch s_b and s_part
+  return (acc_bits == 32 ? deliver_lds<int32_t>(a) : deliver_lds<int64_t>(a)) +
+         sizeof(uint32_t) * 4 * 256 + sizeof(int32_t) * 8;
 }
 
 hipError_t launch_drain(const StepArgs& a, int acc_bits, uint32_t t, hipStream_t st) {
