@@ -191,7 +191,7 @@ def summarize_counters(dirs, out_json):
     rows = []
     for d in dirs:
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            rows += list(csv.DictReader(open(f)))
+            rows += sorted(csv.DictReader(open(f)), key=lambda r: int(r.get("Dispatch_Id") or 0))
     out = {"kernels_sha256": kernels_sha256(), "kernels": {}}
     for name in ("k_neuron", "k_deliver", "k_step", "k_persist"):
         sel = [r for r in rows if name in r["Kernel_Name"]]
@@ -357,10 +357,19 @@ def time_group(nets, dpsnn, torch, stream, args, steps, S):
     bracketed by synchronisation and HIP events), then further real steps
     with HIP events around each kernel for the roofline."""
     sched = {}
+    if args.graph_steps is not None:
+        for h, _, _ in nets.values():
+            dpsnn.dpsnn_set_graph_steps(h, args.graph_steps)
     for _ in range(args.warmup):
         for h, _, _ in nets.values():
             dpsnn.dpsnn_step(h, S)
     for name, (h, _, _) in nets.items():
+        if not args.autotune and args.delivery:
+            # a fixed launch configuration (as an autotuned run chose it),
+            # for profiler passes that cannot run the autotuner
+            sc, b, li = args.delivery.split(":")
+            dpsnn.dpsnn_set_schedule(h, {"split": dpsnn.SCHED_SPLIT, "fused": dpsnn.SCHED_FUSED}[sc])
+            dpsnn.dpsnn_set_delivery(h, int(b), int(li))
         sched[name] = (dpsnn.dpsnn_autotune(h, min(1000, S // 2)) if args.autotune
                        else h.stats()["schedule"])
     torch.cuda.synchronize()
@@ -383,6 +392,7 @@ def time_group(nets, dpsnn, torch, stream, args, steps, S):
     sp1 = {k: h.stats()["n_spikes"] for k, (h, _, _) in nets.items()}
     per_net = {k: _net_spikes(dpsnn, h, len(pl)) for k, (h, pl, _) in nets.items()}
     prof = {}
+    bracket = event_bracket_us(torch, stream) if args.profile_steps > 0 else None
     for name, (h, pl, _) in nets.items():
         if args.profile_steps <= 0:
             continue
@@ -392,7 +402,29 @@ def time_group(nets, dpsnn, torch, stream, args, steps, S):
         upd_ms, del_ms = dpsnn.dpsnn_profile_steps(h, args.profile_steps)
         prof[name] = (upd_ms, del_ms, (h.stats()["n_spikes"] - s_a) * k_out)
     return {"sched": sched, "spikes": {k: sp1[k] - sp0[k] for k in nets}, "per_net": per_net,
-            "wall": wall, "gpu_ms": gpu_ms, "prof": prof}
+            "wall": wall, "gpu_ms": gpu_ms, "prof": prof, "bracket_us": bracket}
+
+
+def event_bracket_us(torch, stream, n: int = 200) -> float:
+    """What a pair of HIP events around one launch adds to the launch's own
+    duration: the median interval of event pairs around a one-element
+    kernel on the same stream (its dispatch and completion, plus the tiny
+    kernel itself)."""
+    import statistics
+    x = torch.zeros(1, device="cuda")
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(n)]
+    with torch.cuda.stream(stream):
+        # a busy GPU while the pairs are enqueued, so that the intervals hold
+        # no host-side submission gaps (as in the per-kernel timing steps,
+        # whose launches queue up behind long kernels)
+        torch.cuda._sleep(50_000_000)
+        for a, b in pairs:
+            a.record(stream)
+            x.add_(1.0)
+            b.record(stream)
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in pairs) * 1e3
 
 
 def group_record(workload, wdt, nets, res, steps, S, args):
@@ -448,6 +480,7 @@ def group_record(workload, wdt, nets, res, steps, S, args):
             "events_per_launch": ev_per_launch,
             "algorithmic_bytes_per_launch": alg_del,
             "avg_launch_us": del_us,
+            "event_bracket_us": res["bracket_us"],
             "profile_avg_launch_us": trace_us,
             "events_per_s_in_kernel": ev_per_launch / (del_us * 1e-6) if del_us > 0 else None,
             "update_kernel": {"kernel": "k_neuron (update, with the queued-input gather)",
@@ -472,9 +505,15 @@ def group_record(workload, wdt, nets, res, steps, S, args):
                         "build_ms": h.stats()["build_ms"],
                         "bytes_per_synapse": h.stats()["bytes_total"] /
                         max(1, h.stats()["n_synapses"]),
-                        "schedule": "split" if res["sched"][k] == 1 else "fused",
+                        "schedule": {0: "fused", 1: "split", 2: "persistent"}[res["sched"][k]],
                         "deliver_blocks": h.stats()["deliver_blocks"],
-                        "spike_lists": "appended" if h.stats()["spike_lists"] else "per tile"}
+                        "spike_lists": {0: "per tile", 1: "appended",
+                                        2: "appended, merged reservations"}[
+                            h.stats()["spike_lists"]],
+                        # the same launches without the autotuner: --autotune 0 --delivery
+                        "delivery": "{}:{}:{}".format(
+                            {0: "fused", 1: "split", 2: "split"}[res["sched"][k]],
+                            h.stats()["deliver_blocks"], h.stats()["spike_lists"])}
                     for k, (h, _, labels) in nets.items()},
         "gpu_ms_timed": res["gpu_ms"],
     }
@@ -546,6 +585,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--graph-steps", type=int, default=None,
+                    help="steps per captured HIP graph (0: direct launches, as profiler "
+                         "counter passes need); default: the library's")
+    ap.add_argument("--delivery", default=None, metavar="SCHED:BLOCKS:LISTS",
+                    help="with --autotune 0: schedule (split or fused), delivery blocks "
+                         "and spike-list kind of every handle, e.g. split:1024:2")
     ap.add_argument("--calibrate", action="store_true",
                     help="only copy 256 MiB device-to-device three times (counter calibration)")
     ap.add_argument("--summarize-rocprof", nargs=7, metavar=("KT", "FETCH", "WRITE", "CAL_FETCH",
@@ -598,8 +643,8 @@ def main():
         return
     stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
     # rate bins: warm-up and timed steps, the autotuner's two passes over
-    # at most 11 candidates, the per-kernel timing steps
-    tune_steps = 22 * min(1000, S // 2) if args.autotune else 0
+    # at most 17 candidates, the per-kernel timing steps
+    tune_steps = 34 * min(1000, S // 2) if args.autotune else 0
     total_bins = ((args.warmup + steps) * S + tune_steps + args.profile_steps) // 50 + 100
     groups = workload_groups(wl, workloads, args.lam, weights)
     records = {}

@@ -249,10 +249,13 @@ int dpsnn_set_schedule(dpsnn_net* net, int32_t sched);
 /* The split schedule's delivery: grid of the delivery kernel (blocks > 0;
  * 0 keeps the current one) and the spike lists it reads (0: one list per
  * tile of 1024 neurons, whose counts every delivery block scans, for at most
- * 14000 tiles; 1: lists appended by the tiles through 64 counters; -1 keeps
- * the current kind).  Results do not depend on either.  The default: one
- * block per tile, between 256 and 1024 blocks, and appended lists.  INVAL
- * otherwise. */
+ * 14000 tiles; 1: lists appended by the tiles through 64 counters; 2: the
+ * appended lists, with the four wavefronts of a delivery block taking the
+ * same chunk of four consecutive spikes and reserving inbox room once per
+ * target tile for all four instead of once per run (acts as 1 without
+ * input queues); -1 keeps the current kind).  Results do not depend on
+ * either.  The default: one block per tile, between 256 and 1024 blocks,
+ * and kind 2 (kind 1 for a handle without queues).  INVAL otherwise. */
 int dpsnn_set_delivery(dpsnn_net* net, int32_t deliver_blocks, int32_t spike_lists);
 
 /* Grid of the inbox-routing blocks of the split schedule's delivery kernel

@@ -351,7 +351,8 @@ int build_impl(dpsnn_net* n) {
   a.spk = spk;
   a.spk_cap = spk_cap;
   a.blk_cnt = blk_cnt;
-  a.spk_lists = 1;  // appended lists; the autotuner also tries per-tile ones
+  a.spk_lists = 1;  // appended lists (merged reservations once queues exist);
+                    // the autotuner also tries the other kinds
   a.log = log;
   a.log_base = reinterpret_cast<unsigned long long*>(ctl);
   a.n_spikes = reinterpret_cast<unsigned long long*>(ctl + 16);
@@ -407,6 +408,7 @@ int build_impl(dpsnn_net* n) {
     // largest value) fits 21 bits
     a.q_packed = ab == 4 && max_fix < (1 << 21) && wmax_fix < (1 << 21);
     a.q_code = q_code;
+    a.spk_lists = 2;  // appended lists, reservations merged per delivery block
     n->bytes_state += (int64_t)((n_in + n_q) * eb) +
                       (2 * n_tiles * kInboxStride + 2 * n_tiles * T0.D) * 4;
   }
@@ -801,7 +803,7 @@ int dpsnn_set_schedule(dpsnn_net* n, int32_t sched) {
 
 int dpsnn_set_delivery(dpsnn_net* n, int32_t deliver_blocks, int32_t spike_lists) {
   if (!n || deliver_blocks < 0 || deliver_blocks > (1 << 20) || spike_lists < -1 ||
-      spike_lists > 1 || (spike_lists == 0 && n->sa.n_tiles > kMaxScanTiles))
+      spike_lists > 2 || (spike_lists == 0 && n->sa.n_tiles > kMaxScanTiles))
     return DPSNN_E_INVAL;
   if (deliver_blocks > 0) n->sa.deliver_blocks = deliver_blocks;
   if (spike_lists >= 0) n->sa.spk_lists = spike_lists;
@@ -885,6 +887,7 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
   if (!n || probe_steps < 1) return DPSNN_E_INVAL;
   // candidates: the fused schedule, and the split one with several grids of
   // the delivery kernel, each with per-tile and with appended spike lists
+  // (with and without merged reservations)
   struct Cand {
     int sched;
     int32_t blocks;
@@ -896,8 +899,9 @@ int dpsnn_autotune(dpsnn_net* n, int64_t probe_steps, int32_t* chosen) {
     cands.push_back({DPSNN_SCHED_PERSIST, n->sa.deliver_blocks, 1});
   }
   const int32_t tiles = n->sa.n_tiles;
-  for (int32_t lists : {0, 1}) {
+  for (int32_t lists : {0, 1, 2}) {
     if (!lists && tiles > kMaxScanTiles) continue;
+    if (lists == 2 && !n->sa.q_cap) continue;  // merged reservations need queues
     for (int32_t b : {std::min<int32_t>(1024, std::max<int32_t>(256, tiles)), 256, 512, 1024,
                       2048}) {
       bool seen = false;

@@ -202,13 +202,15 @@ struct StepArgs {
   // Spikes of the step (split schedule).  Per-tile lists (spk_lists = 0):
   // tile b writes its spike ids to spk[b * 1024 ...] and their count to
   // blk_cnt[b]; each delivery block scans the counts.  Appended lists
-  // (spk_lists = 1, the default): tile b appends its ids to list
-  // g = b mod kSpkLists, spk[g * spk_cap ...], counted in
-  // spk_n[((t & 1) * kSpkLists + g) * kSpkStride]; the delivery of step t
-  // zeroes the counters of step t + 1, and so does the step-counter kernel.
+  // (spk_lists = 1, the default; 2: the same lists, delivered with
+  // reservations merged over each block's four chunks): tile b appends its
+  // ids to list g = (b >> kSpkListShift) mod kSpkLists, spk[g * spk_cap ...],
+  // counted in spk_n[((t & 1) * kSpkLists + g) * kSpkStride]; the delivery
+  // of step t zeroes the counters of step t + 1, and so does the
+  // step-counter kernel.
   int32_t spk_lists;
   int32_t* spk;            // [kSpkLists][spk_cap] (>= n_tiles * 1024)
-  int64_t spk_cap;         // ceil(n_tiles / kSpkLists) * 1024
+  int64_t spk_cap;         // room for every neuron of the tiles of one list
   int32_t* blk_cnt;        // [n_tiles]
   uint32_t* spk_n;         // [2][kSpkLists][kSpkStride]
   int2* log;

@@ -69,6 +69,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Workgroup barrier that orders LDS only: global loads and stores issued
 // before it stay in flight (a full __syncthreads waits for all of them).
 // Used where threads share data through LDS alone.
+// Clang vector types for the non-temporal loads and stores.
+typedef float NtF4 __attribute__((ext_vector_type(4)));
+typedef int NtI4 __attribute__((ext_vector_type(4)));
+typedef unsigned short NtU16x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -289,19 +294,6 @@ __device__ __forceinline__ void atomic_add_fix<int64_t>(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 
-template <typename Acc, int WDT>
-__device__ __forceinline__ Acc stored_to_fix(const void* w, int64_t o, float two_q,
-                                             int64_t scale) {
-  if (WDT == DPSNN_W_F32) {
-    return (Acc)__builtin_rintf(static_cast<const float*>(w)[o] * two_q);
-  } else if (WDT == DPSNN_W_F16) {
-    const __half h = static_cast<const __half*>(w)[o];
-    return (Acc)__builtin_rintf(__half2float(h) * two_q);
-  } else {
-    return (Acc)static_cast<const int8_t*>(w)[o] * (Acc)scale;
-  }
-}
-
 template <typename Acc>
 __device__ __forceinline__ void lds_add(Acc* p, Acc v);
 template <>
@@ -475,7 +467,6 @@ constexpr int kHashBits = 10;
 constexpr int kHash = 1 << kHashBits;      // >= the runs of 4 chunks (4 x 256)
 constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
 constexpr size_t kHashBytes = 3 * kHash * 4;
-constexpr bool kMergeReserve = true;
 static_assert(kHash == 4 * 256, "one uint4 of hash keys per thread of a 256-thread block");
 __host__ __device__ inline uint32_t stage_offset_words(const StepArgs& a) {
   return a.spk_lists ? 0u : ((uint32_t)a.n_tiles + 3u) / 4u * 4u;
@@ -693,9 +684,11 @@ __device__ __forceinline__ void neuron_load(const StepArgs& a, const NetDev& nd,
       sl[j] = 0;
     }
   }
-  const float4 V4 = *reinterpret_cast<const float4*>(a.V + i0);
-  const float4 c4 = *reinterpret_cast<const float4*>(a.c + i0);
-  R.r4 = *reinterpret_cast<const uint32_t*>(a.ref + i0);
+  // the state streams through once per step: non-temporal loads and
+  // stores keep it from displacing the tables and entries in L2
+  const NtF4 V4 = __builtin_nontemporal_load(reinterpret_cast<const NtF4*>(a.V + i0));
+  const NtF4 c4 = __builtin_nontemporal_load(reinterpret_cast<const NtF4*>(a.c + i0));
+  R.r4 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(a.ref + i0));
   R.V[0] = V4.x; R.V[1] = V4.y; R.V[2] = V4.z; R.V[3] = V4.w;
   R.c[0] = c4.x; R.c[1] = c4.y; R.c[2] = c4.z; R.c[3] = c4.w;
 
@@ -819,9 +812,11 @@ __device__ __forceinline__ uint32_t neuron_finish(const StepArgs& a, const NetDe
     }
     r_out |= rj << (8 * j);
   }
-  *reinterpret_cast<float4*>(a.V + i0) = make_float4(R.V[0], R.V[1], R.V[2], R.V[3]);
-  *reinterpret_cast<float4*>(a.c + i0) = make_float4(R.c[0], R.c[1], R.c[2], R.c[3]);
-  *reinterpret_cast<uint32_t*>(a.ref + i0) = r_out;
+  __builtin_nontemporal_store(NtF4{R.V[0], R.V[1], R.V[2], R.V[3]},
+                              reinterpret_cast<NtF4*>(a.V + i0));
+  __builtin_nontemporal_store(NtF4{R.c[0], R.c[1], R.c[2], R.c[3]},
+                              reinterpret_cast<NtF4*>(a.c + i0));
+  __builtin_nontemporal_store(r_out, reinterpret_cast<uint32_t*>(a.ref + i0));
   return mask;
 }
 
@@ -871,15 +866,30 @@ __device__ __forceinline__ void stdp_event(const StepArgs& a, int32_t ta, int32_
 }
 
 // One chunk of a row: 256 synapses (4 per lane) of row s from p0 = chunk *
-// 256; targets, fixed-point efficacies and, for code entries, the stored
-// codes.
+// 256; targets, and the fixed-point efficacies (binary32 rows) or the
+// stored codes (binary16 and int8 rows, decoded where a fixed-point value
+// is needed, with the int8 scale of the source population), so that a
+// code chunk holds no more registers than it needs.
 template <typename Acc>
 struct Chunk {
   int32_t s, p0;
   int tv[4];
   Acc wv[4];
   uint32_t cv[4];
+  Acc scale;
 };
+
+// Fixed-point efficacy j of a loaded chunk.
+template <typename Acc, int WDT>
+__device__ __forceinline__ Acc chunk_fix(const StepArgs& a, const Chunk<Acc>& c, int j) {
+  if constexpr (WDT == DPSNN_W_F32)
+    return c.wv[j];
+  else if constexpr (WDT == DPSNN_W_F16)
+    return (Acc)__builtin_rintf(__half2float(__ushort_as_half((unsigned short)c.cv[j])) *
+                                a.two_q);
+  else
+    return (Acc)(int8_t)(uint8_t)c.cv[j] * c.scale;
+}
 
 // Loads of a chunk (issued, not waited for: the values are used later).
 template <typename Acc, int WDT>
@@ -896,32 +906,39 @@ __device__ __forceinline__ void chunk_load(const StepArgs& a, int32_t s, int p0,
     scale = a.sfix[(int64_t)a.P * ms + q_src];
   }
   const int p = p0 + lane * 4;
+  c.scale = (Acc)scale;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     c.tv[j] = 0;
-    c.wv[j] = 0;
-    c.cv[j] = 0;
+    if (WDT == DPSNN_W_F32)
+      c.wv[j] = 0;
+    else
+      c.cv[j] = 0;
   }
   if (p < a.K_out) {  // rows are padded to a multiple of 4 words
-    const int4 tg = *reinterpret_cast<const int4*>(a.tgt + rb + p);
+    // a row is read once per spike: non-temporal loads, so that the
+    // inboxes and queues written now and read in the next step stay cached
+    const NtI4 tg = __builtin_nontemporal_load(reinterpret_cast<const NtI4*>(a.tgt + rb + p));
     c.tv[0] = tg.x; c.tv[1] = tg.y; c.tv[2] = tg.z; c.tv[3] = tg.w;
     if (WDT == DPSNN_W_F32) {
-      const float4 w4 =
-          *reinterpret_cast<const float4*>(static_cast<const float*>(a.w) + rb + p);
+      const NtF4 w4 = __builtin_nontemporal_load(
+          reinterpret_cast<const NtF4*>(static_cast<const float*>(a.w) + rb + p));
       c.wv[0] = (Acc)__builtin_rintf(w4.x * a.two_q);
       c.wv[1] = (Acc)__builtin_rintf(w4.y * a.two_q);
       c.wv[2] = (Acc)__builtin_rintf(w4.z * a.two_q);
       c.wv[3] = (Acc)__builtin_rintf(w4.w * a.two_q);
-    } else {
+    } else if (WDT == DPSNN_W_F16) {
+      const NtU16x4 h4 = __builtin_nontemporal_load(
+          reinterpret_cast<const NtU16x4*>(static_cast<const uint16_t*>(a.w) + rb + p));
+      const uint32_t hv[4] = {h4.x, h4.y, h4.z, h4.w};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        c.wv[j] = stored_to_fix<Acc, WDT>(a.w, rb + p + j, a.two_q, scale);
-        if (WDT == DPSNN_W_F16)
-          c.cv[j] = static_cast<const uint16_t*>(a.w)[rb + p + j];
-        else
-          c.cv[j] = (uint32_t)(uint8_t)static_cast<const int8_t*>(a.w)[rb + p + j] |
-                    (uint32_t)q_src << 8;
-      }
+      for (int j = 0; j < 4; ++j) c.cv[j] = hv[j];
+    } else {
+      const uint32_t b4 = __builtin_nontemporal_load(
+          reinterpret_cast<const uint32_t*>(static_cast<const int8_t*>(a.w) + rb + p));
+#pragma unroll
+      for (int j = 0; j < 4; ++j)  // element p + j is byte j
+        c.cv[j] = (b4 >> (8 * j) & 0xFFu) | (uint32_t)q_src << 8;
     }
   }
 }
@@ -962,7 +979,6 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
   const int p0 = c.p0;
   const int p = p0 + lane * 4;
   const int* tv = c.tv;
-  const Acc* wv = c.wv;
   const uint32_t* cv = c.cv;
   const uint32_t t = T.t;
   int slot0 = (int)T.slot + a.d_min;  // slot of arrival at t + d_min
@@ -976,7 +992,7 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
         int sl = slot0 + (int)((uint32_t)tv[j] >> kDelayShift);
         if (sl >= a.D) sl -= a.D;
         const int32_t target = tv[j] & kTargetMask;
-        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, chunk_fix<Acc, WDT>(a, c, j));
       }
     }
     return;
@@ -1123,13 +1139,13 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
           if (WDT != DPSNN_W_F32 && a.q_code) {
             ev[j] = code_entry(cv[j], x);
           } else {
-            const QEntry<Acc> e = QEntry<Acc>::make(x, wv[j]);
+            const QEntry<Acc> e = QEntry<Acc>::make(x, chunk_fix<Acc, WDT>(a, c, j));
             ev[j] = *reinterpret_cast<const unsigned long long*>(&e);
           }
         } else {
           int sl = slot0 + (int)dk;
           if (sl >= a.D) sl -= a.D;
-          atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+          atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, chunk_fix<Acc, WDT>(a, c, j));
           a.s_dirty[(int64_t)tl[j] * a.D + sl] = 1u;
         }
       }
@@ -1169,11 +1185,11 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
         if (WDT != DPSNN_W_F32 && a.q_code)
           static_cast<uint32_t*>(a.in_q)[o] = code_entry(cv[j], x);
         else
-          iq[o] = QEntry<Acc>::make(x, wv[j]);
+          iq[o] = QEntry<Acc>::make(x, chunk_fix<Acc, WDT>(a, c, j));
       } else {
         int sl = slot0 + (int)dk;
         if (sl >= a.D) sl -= a.D;
-        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, wv[j]);
+        atomic_add_fix<Acc>(slots + (int64_t)sl * a.N_pad + target, chunk_fix<Acc, WDT>(a, c, j));
         a.s_dirty[(int64_t)tl[j] * a.D + sl] = 1u;
       }
     }
@@ -1632,9 +1648,9 @@ hipError_t launch_init(const InitArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Merged reservations in the delivery kernel: with queues and appended
-// spike lists.
-static bool merge_reserve(const StepArgs& a) { return kMergeReserve && a.q_cap && a.spk_lists; }
+// Merged reservations in the delivery kernel: spike lists of kind 2 (the
+// appended lists) with queues.
+static bool merge_reserve(const StepArgs& a) { return a.q_cap && a.spk_lists == 2; }
 
 // Dynamic LDS of the delivery kernel: the larger of the tile-count prefix
 // (per-tile spike lists) and the routing blocks' RouteLds.
@@ -1692,7 +1708,6 @@ static void launch_deliver(const StepArgs& a, int wdt, dim3 grid, size_t lds, ui
 
 template <typename Acc>
 static void launch_split(const StepArgs& a, int wdt, uint32_t t_off, hipStream_t st) {
-  const dim3 block(256);
   launch_neuron<Acc>(a, t_off, st);
   const size_t lds = deliver_lds<Acc>(a);
   const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
@@ -1782,7 +1797,6 @@ hipError_t launch_step(const StepArgs& a, int wdt, int acc_bits, int sched, uint
 // One phase of the split schedule on its own (0 = neuron update, 1 = delivery).
 hipError_t launch_phase(const StepArgs& a, int wdt, int acc_bits, int phase, uint32_t t_off,
                         hipStream_t st) {
-  const dim3 tiles((unsigned)a.n_tiles), block(256);
   const dim3 grid((unsigned)(a.deliver_blocks + a.route_blocks));
   const size_t lds = acc_bits == 32 ? deliver_lds<int32_t>(a) : deliver_lds<int64_t>(a);
   if (phase == 0) {

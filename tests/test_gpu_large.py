@@ -78,10 +78,11 @@ def _grid96():
 
 @pytest.mark.timeout(420)
 def test_96x96_full_size_start_and_teacher_forced_step(L):
-    """96x96 in the benchmark's launch configuration (split schedule,
-    appended spike lists): 300 sampled rows bit-exact, the first 4 steps
-    bit-exact from the start (spikes, state, every slot), then after 1000
-    more steps one step re-run by the oracle from the GPU's state."""
+    """96x96 in the split schedule with appended spike lists and merged
+    reservations (the delivery the autotuner picks at this size): 300
+    sampled rows bit-exact, the first 4 steps bit-exact from the start
+    (spikes, state, every slot), then after 1000 more steps one step re-run
+    by the oracle from the GPU's state."""
     p = _grid96()
     _say("96x96 build")
     net = L.dpsnn_build(p, 1)
@@ -89,7 +90,7 @@ def test_96x96_full_size_start_and_teacher_forced_step(L):
     assert st["n_neurons"] == 11_520_000 and st["route_blocks"] == 4096
     assert st["queue_entry_bytes"] == 4
     L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
-    L.dpsnn_set_delivery(net, 0, 1)
+    L.dpsnn_set_delivery(net, 0, 2)
     orc = O.Oracle(p, 1, store_rows=False)
     rng = np.random.default_rng(5)
     d_min = p["d_min"]

@@ -558,17 +558,18 @@ def test_population_batch_matches_solo_runs(L):
 @pytest.mark.parametrize("side,K_out", [(3, 200), (9, 100)])
 def test_spike_list_kinds_and_grids(L, side, K_out):
     """The split schedule's delivery with per-tile and with appended spike
-    lists and several grids, switched between calls (graphs and direct
-    launches): bit-exact; 11 tiles (lists of one tile or none) and 99 tiles
-    (two tiles in some of the 64 lists)."""
+    lists (with and without merged reservations) and several grids,
+    switched between calls (graphs and direct launches): bit-exact; 11
+    tiles (lists of one tile or none) and 99 tiles (several tiles in some of
+    the 64 lists)."""
     import torch
     _say("spike list kinds", side, K_out)
     p = W.grid(side, side, "swa", K=1250, K_out=K_out)
     with torch.cuda.stream(torch.cuda.Stream()):
         net, orc = _pair(p, 9)
         L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
-        for k, (blocks, lists) in enumerate([(0, 1), (7, 0), (256, 1), (1024, 0), (3, 1),
-                                             (512, 1), (256, 0)]):
+        for k, (blocks, lists) in enumerate([(0, 1), (7, 0), (256, 2), (1024, 0), (3, 1),
+                                             (512, 2), (256, 0), (5, 2), (1024, 1)]):
             L.dpsnn_set_delivery(net, blocks, lists)
             st = net.stats()
             assert st["spike_lists"] == lists
@@ -577,7 +578,7 @@ def test_spike_list_kinds_and_grids(L, side, K_out):
             L.dpsnn_step(net, n)
             orc.step(n)
             assert _compare_all(L, net, orc, f"lists {lists} blocks {blocks}") > 0
-        for bad in [(-1, 0), (0, 2), (0, -2)]:
+        for bad in [(-1, 0), (0, 3), (0, -2)]:
             with pytest.raises(L.DpsnnError):
                 L.dpsnn_set_delivery(net, *bad)
         net.close()
@@ -704,11 +705,11 @@ def test_spike_order_per_tile_lists_is_deterministic(L):
     """Each tile lists its spikes in neuron order (wavefront ballot and block
     prefix sum), so with per-tile spike lists the split schedule writes the
     device log in (step, id) order, identically on a rerun; with appended
-    lists every tile's run of the log is in id order."""
+    lists (either delivery) every tile's run of the log is in id order."""
     p = W.grid(3, 3, "swa", K=1250, K_out=200, spike_log_cap=1 << 22)
     _say("spike order")
     logs = []
-    for lists in (0, 0, 1):
+    for lists in (0, 0, 1, 2):
         net = L.dpsnn_build(p, 5)
         L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
         L.dpsnn_set_delivery(net, 0, lists)
