@@ -1,0 +1,73 @@
+"""Host logic of bench.py's profiler summaries (CPU): kernel names to
+(kernel, weight format), the pairing of update launches with the delivery
+launch after them, the event-timed window, and the counter calibration."""
+import csv
+import json
+import os
+
+import pytest
+
+import bench
+
+
+def test_kernel_group_names():
+    g = bench._kernel_group
+    assert g("void dpsnn::k_deliver<int, 0, false, true>(dpsnn::StepArgs, dpsnn::StepOff)") == \
+        ("k_deliver", "f32")
+    assert g("dpsnn::k_deliver<long, 2, false, false>(x)") == ("k_deliver", "i8")
+    assert g("dpsnn::k_step<int, 1, 2>(x)") == ("k_step", "f16")
+    assert g("dpsnn::k_persist<long, 2, 2, 2>(x)") == ("k_persist", "i8")
+    assert g("dpsnn::k_neuron<int, 2, 1>(x)") == ("k_neuron", None)
+    assert g("dpsnn::k_gen<0>(x)") is None
+    assert g("__amd_rocclr_copyBuffer") is None
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_ALL)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_summarize_rocprof_windows_and_scales(tmp_path, monkeypatch):
+    """Two weight formats timed one after the other: each format's window
+    is its own last N dispatches, update launches take the format of the
+    delivery launch after them, dispatch ids order the rows (the CSV is
+    shuffled), and the copy calibration scales the counters."""
+    names = {"f32": ("dpsnn::k_neuron<int, 2, 1>(a)", "dpsnn::k_deliver<int, 0, false, true>(a)"),
+             "f16": ("dpsnn::k_neuron<int, 2, 2>(a)", "dpsnn::k_deliver<int, 1, false, true>(a)")}
+    trace, fetch, write = [], [], []
+    did = 0
+    for fmt, base in (("f32", 100), ("f16", 200)):
+        for k in range(6):       # 6 steps; the window below is the last 4
+            for kern, dur in ((0, base + k), (1, 2 * base + k)):
+                did += 1
+                trace.append([did, names[fmt][kern], 1000 * did, 1000 * did + dur * 1000])
+                fetch.append([did, names[fmt][kern], "FETCH_SIZE", 10.0 * (kern + 1) + k])
+                write.append([did, names[fmt][kern], "WRITE_SIZE", 5.0 * (kern + 1)])
+    trace.reverse()
+    d = str(tmp_path)
+    _write(f"{d}/kt/x_kernel_trace.csv",
+           ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], trace)
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write(f"{d}/fe/x_counter_collection.csv", hdr, fetch[::-1])
+    _write(f"{d}/wr/x_counter_collection.csv", hdr, write)
+    _write(f"{d}/cf/x_counter_collection.csv", hdr, [[1, "__amd_rocclr_copyBuffer", "FETCH_SIZE",
+                                                      256 * 1024 / 2]])
+    _write(f"{d}/cw/x_counter_collection.csv", hdr, [[1, "__amd_rocclr_copyBuffer", "WRITE_SIZE",
+                                                      256 * 1024]])
+    monkeypatch.setattr(bench, "PROFILES", d)
+    bench.summarize_rocprof(f"{d}/kt", f"{d}/fe", f"{d}/wr", f"{d}/cf", f"{d}/cw", "wl", 4)
+    for fmt, base in (("f32", 100), ("f16", 200)):
+        rec = json.load(open(os.path.join(d, f"k_deliver_k_neuron_wl_{fmt}_traffic.json")))
+        assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == 1.0
+        kn, kd = rec["kernels"]["k_neuron"], rec["kernels"]["k_deliver"]
+        # steps 2..5 of the format: durations base + k and 2 base + k
+        assert kn["mean_duration_us"] == pytest.approx(base + 3.5)
+        assert kd["mean_duration_us"] == pytest.approx(2 * base + 3.5)
+        assert kn["trace_dispatches"] == kd["counter_dispatches"] == 4
+        # FETCH 10 (kern + 1) + k KiB, doubled by the calibration; WRITE 5 (kern + 1)
+        assert kn["fetch_bytes"] == pytest.approx(2 * (10 + 3.5) * 1024)
+        assert kd["write_bytes"] == pytest.approx(10 * 1024)
+        assert kd["bytes_per_launch"] == pytest.approx(2 * (20 + 3.5) * 1024 + 10 * 1024)
