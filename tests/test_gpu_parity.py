@@ -771,3 +771,27 @@ def test_persistent_schedule_population_model_and_batch(L):
         assert len(ss) > 300
         solo.close()
     net.close()
+
+
+@pytest.mark.timeout(300)
+def test_merged_reservations_under_hash_pressure(L):
+    """Merged reservations with most of the LDS hash in use: 30x30 modules
+    (1099 tiles), every synapse remote and its module drawn almost
+    uniformly (lambda = 100), 256 synapses per row, so the four chunks of a
+    block reach ~660 distinct tiles per round (linear probing in a
+    1024-entry table).  Bit-exact against the oracle with the merged
+    delivery, then with the per-run one on the same handle."""
+    _say("merged reservations, hash pressure")
+    p = W.grid(30, 30, "swa", K=1250, K_out=256, frac_local=[0.0, 0.0], **{"lambda": 100.0})
+    net, orc = _pair(p, 21, store_rows=False)
+    assert -(-net.N // 1024) == 1099
+    L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+    L.dpsnn_set_delivery(net, 1024, 2)
+    # the start: thousands of spikes per step (the oracle is the slow side)
+    for k, (lists, n) in enumerate([(2, 12), (2, 17), (1, 9)]):
+        L.dpsnn_set_delivery(net, 0, lists)
+        L.dpsnn_step(net, n)
+        orc.step(n)
+        assert _compare_all(L, net, orc, f"hash pressure {k}") > 100
+    net.close()
+    orc.close()
