@@ -1019,22 +1019,26 @@ __device__ __forceinline__ void chunk_deliver(const StepArgs& a, const Chunk<Acc
       first = first < p + j ? first : p + j;
     }
   }
-  int incl = last;  // max-scan over lanes
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off);
-    if (lane >= off) incl = incl > v ? incl : v;
-  }
-  int carry = __shfl_up(incl, 1);
-  if (lane == 0) carry = -1;
-  int after = first;  // min-scan over the later lanes
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_down(after, off);
-    if (lane + off < 64) after = after < v ? after : v;
-  }
-  int nxt = __shfl_down(after, 1);
-  if (lane == 63) nxt = 1 << 30;
+  // Run starts increase with the lane, so the last start before this lane
+  // is the last start of the nearest lower lane that has one, and the
+  // first start after it the first start of the nearest higher such lane:
+  // one ballot and two lane reads.
+  const uint64_t heads = __ballot(last >= 0);  // uniform
+  const uint32_t h_lo = (uint32_t)heads, h_hi = (uint32_t)(heads >> 32);
+  const uint32_t l5 = (uint32_t)lane & 31u;
+  const uint32_t m_lt = (1u << l5) - 1u, m_gt = ~((2u << l5) - 1u);  // l5 = 31: 2 << 31 = 0
+  // nearest lower lane with a start (-1: none)
+  const uint32_t b_own = (lane < 32 ? h_lo : h_hi) & m_lt;
+  const int lo_lane = b_own ? (lane & 32) + 31 - __clz(b_own)
+                            : (lane >= 32 && h_lo ? 31 - __clz(h_lo) : -1);
+  // nearest higher lane with a start (64: none)
+  const uint32_t a_own = (lane < 32 ? h_lo : h_hi) & (l5 == 31u ? 0u : m_gt);
+  const int hi_lane = a_own ? (lane & 32) + __ffs(a_own) - 1
+                            : (lane < 32 && h_hi ? 32 + __ffs(h_hi) - 1 : 64);
+  const int lo_last = __shfl(last, lo_lane < 0 ? lane : lo_lane);
+  const int hi_first = __shfl(first, hi_lane > 63 ? lane : hi_lane);
+  const int carry = lo_lane < 0 ? -1 : lo_last;
+  const int nxt = hi_lane > 63 ? 1 << 30 : hi_first;
   int rs[4];
   {
     int c = carry;
