@@ -20,7 +20,9 @@
  * in which concurrent additions land cannot change any result.  Rows are
  * stored sorted by target, so the events of a spike to one 1024-neuron tile
  * are contiguous: delivery reserves room for each such run in the tile's
- * inbox with one atomic and appends the events; in the next step the tile
+ * inbox with one atomic (by default one atomic per target tile for the runs
+ * of four spikes delivered together) and appends the events; in the next
+ * step the tile
  * moves them into its per-slot queues, and sums the queue of the current
  * slot when it reaches it.  Events that find a queue full are added into
  * the slot directly.

@@ -121,3 +121,73 @@ def test_short_horizon_membrane_error_vs_fp64(L, wd):
           f"difference, max |dV| {worst:.3e} mV, max RMS {rms:.3e} mV", flush=True)
     assert steps_ok >= 3
     assert worst < bound
+
+
+GOLD48 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "fp64_stats_48x48.json")
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("wd", ["f32", "f16", "i8"])
+def test_48x48_statistics_vs_fp64(L, wd):
+    """The 48x48 grid (2.88M neurons per network), lambda in {0.5, 1, 2, 4},
+    SWA and AW, seeds 1 and 2, 1.5 s each, against the binary64 oracle's
+    statistics (tests/golden/fp64_stats_48x48.json, written from the oracle
+    only), each averaged over the two seeds on both sides: mean excitatory
+    and inhibitory rates within max(2 %, 2 sigma_seed), population-burst
+    frequency within max(5 %, 2 sigma_seed, 0.1 Hz), Up-state frequency
+    within max(10 %, 2 sigma_seed, 0.1 Hz), and the per-neuron spike-count
+    distribution of the last 1.0 s within KS max(0.01, twice the
+    seed-to-seed KS of the binary64 runs).  sigma_seed is the spread of the
+    two binary64 seeds of the same (regime, lambda)."""
+    if not os.path.exists(GOLD48):
+        pytest.skip("48x48 binary64 statistics not generated")
+    gold = json.load(open(GOLD48))
+    steps, seeds, skip_s = gold["steps"], gold["seeds"], gold["skip_s"]
+    t0 = int(round(skip_s * 1e3 / 0.1))
+    report = []
+    for lam in gold["lambdas"]:
+        lk = f"{lam:g}"
+        jobs = [(r, s) for r in ("swa", "aw") for s in seeds]
+        _say("48x48 precision", wd, "lambda", lk)
+        plist = [dict(W.grid(48, 48, r, **{"lambda": lam}), weight_dtype=wd,
+                      spike_log_cap=1 << 29, rate_bins_cap=512) for r, _ in jobs]
+        net = L.dpsnn_build_batch(plist, [s for _, s in jobs])
+        L.dpsnn_step(net, steps)
+        st, ids = L.dpsnn_read_log(net)        # every spike, device order
+        got = {}
+        for k, (r, s) in enumerate(jobs):
+            info = L.dpsnn_net_info(net, k)
+            b, n = info["base"], info["n_neurons"]
+            sel = (ids >= b) & (ids < b + n) & (st >= t0)
+            rates = L.dpsnn_read_rates_net(net, k)
+            p = plist[k]
+            got[(r, s)] = stats.summary(rates, st[sel], ids[sel] - b, n, p["K"],
+                                        round(p["frac_exc"] * p["K"]),
+                                        p["rate_bin_steps"] * p["dt_ms"], p["dt_ms"], steps,
+                                        skip_s=skip_s)
+        del st, ids
+        net.close()
+        for r in ("swa", "aw"):
+            ref = [gold["runs"][r][lk][str(s)] for s in seeds]
+            mine = [got[(r, s)] for s in seeds]
+            for key, rel, floor in (("rate_exc_hz", 0.02, 0.0), ("rate_inh_hz", 0.02, 0.0),
+                                    ("burst_freq_hz", 0.05, 0.1), ("up_freq_hz", 0.10, 0.1)):
+                a = np.array([x[key] for x in ref])
+                b = np.array([x[key] for x in mine])
+                tol = max(rel * a.mean(), 2 * a.std(ddof=1), floor)
+                report.append((lk, r, key, b.mean(), a.mean(), tol))
+            ha = [np.array(x["count_hist"]) for x in ref]
+            hb = [np.array(x["count_hist"]) for x in mine]
+            seed_ks = stats.ks_from_hists(ha[0], ha[1])
+            ks = stats.ks_from_hists(sum(np.pad(h, (0, 2001 - len(h))) for h in hb),
+                                     sum(np.pad(h, (0, 2001 - len(h))) for h in ha))
+            report.append((lk, r, "ks", ks, 0.0, max(0.01, 2 * seed_ks)))
+    # every comparison is printed before any is asserted
+    bad = []
+    for lk, r, key, g, f, tol in report:
+        print(f"[precision 48x48 {wd}] lambda {lk} {r} {key}: gpu {g:.4f} fp64 {f:.4f} "
+              f"tol {tol:.4f}", flush=True)
+        if abs(g - f) > tol:
+            bad.append((lk, r, key, g, f, tol))
+    assert not bad, (wd, bad)
