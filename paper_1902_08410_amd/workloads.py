@@ -94,19 +94,27 @@ def grid96(regime: str) -> dict:
 # row's inhibitory entries repeat the external-rate row (garbled) and are
 # read as the AW rows' -1.5 mV.  External drive: 400 Poisson trains of
 # 3.17 / 3.17 / 3.0 Hz with the J_{t,ext} of the state.
+# "swv" is not a state of Table S1: the SW row with the excitatory
+# efficacies x1.15, inhibitory ones of -0.8 mV and g_w/C_m = 0.01 1/ms, a
+# state whose modules alternate between Down and Up states and whose Up
+# states travel across the grid as waves (found by a parameter search; the
+# paper does not print the parameters of its wave simulations).
 _FBI_J = {
     #        F<-F   B<-F   I<-F   F<-B   B<-B   I<-B   F<-I  B<-I  I<-I
     "sw": [0.600, 0.382, 0.560, 0.382, 0.429, 0.560, -1.5, -1.5, -1.5],
     "aw28": [0.515, 0.412, 0.560, 0.412, 0.429, 0.560, -1.5, -1.5, -1.5],
     "aw88": [0.515, 0.412, 0.560, 0.412, 0.429, 0.560, -1.5, -1.5, -1.5],
+    "swv": [0.690, 0.4393, 0.644, 0.4393, 0.49335, 0.644, -0.8, -0.8, -0.8],
 }
 _FBI_JEXT = {"sw": [0.832, 0.858, 1.120], "aw28": [0.858, 0.858, 1.120],
-             "aw88": [1.416, 1.416, 1.120]}
+             "aw88": [1.416, 1.416, 1.120], "swv": [0.832, 0.858, 1.120]}
+_FBI_GC = {"swv": 0.01}  # g_w / C_m of F and B (1/ms); Table S1: 0.02
 
 
 def fbi(w: int, h: int, state: str = "sw", lam: float = 0.5, scale: float = 1.0,
         **over) -> dict:
-    """The F/B/I network of w x h modules in state "sw", "aw28" or "aw88";
+    """The F/B/I network of w x h modules in state "sw", "aw28", "aw88" or
+    "swv" (propagating slow waves, see above);
     scale < 1 shrinks the populations (and out-degrees) for quick tests."""
     j = _FBI_J[state]
     # J_mean_ts[t][s]: target t, source s (order F, B, I)
@@ -122,7 +130,8 @@ def fbi(w: int, h: int, state: str = "sw", lam: float = 0.5, scale: float = 1.0,
             p_Jext_sd=[0.25 * x for x in _FBI_JEXT[state]],
             p_tau_m=[20.0, 20.0, 10.0], p_E=[0.0, 0.0, 0.0], p_V_th=[20.0] * 3,
             p_V_r=[15.0] * 3, p_tau_arp=[2.0, 2.0, 1.0], p_alpha_c=[1.0, 1.0, 0.0],
-            p_tau_c=[1000.0] * 3, p_gc=[0.02, 0.02, 0.0], p_I_const=[0.0] * 3)
+            p_tau_c=[1000.0] * 3, p_gc=[_FBI_GC.get(state, 0.02)] * 2 + [0.0],
+            p_I_const=[0.0] * 3)
     p["lambda"] = lam
     p.update(over)
     return p

@@ -157,3 +157,32 @@ def test_batch_network_index(L):
     mb, m = info["module_base"], info["n_modules"]
     ref = O.waves(rates[:, mb:mb + m, :], 4, 5, BIN_STEPS, DT, noise_var=0.5, seed=4)
     _compare(got, ref)
+
+
+@pytest.mark.timeout(300)
+def test_slow_waves_speed_grows_with_lambda(L):
+    """The F/B/I "swv" state on 24x24 modules: after 1 s of transient, 8 s
+    hold Up states that cross the whole grid as waves (about one every
+    3 s), and their speed (Eq. 4 averaged over the modules, Sec. 2.3) grows
+    with the decay length lambda of Eq. 1, as Sec. 3.3.2 reports.  Analysis
+    without added noise, Down and Up dwell of 4 bins, waves of at least 50
+    modules."""
+    import torch
+
+    def waves(state, lam, seed=1):
+        with torch.cuda.stream(torch.cuda.Stream()):
+            net = L.dpsnn_build(W.fbi(24, 24, state, lam=lam, rate_bins_cap=2048), seed)
+            L.dpsnn_step(net, 10000)
+            L.dpsnn_read_rates(net)
+            L.dpsnn_step(net, 80000)
+            r = L.dpsnn_waves(net, noise_var=0.0, seed=1, min_down=4, min_up=4, min_modules=50)
+            net.close()
+        measured = r["speed"] > 0 if r["n_waves"] else np.zeros(0, bool)
+        _say("waves", state, lam, r["n_transitions"], r["n_waves"], int(measured.sum()),
+             float(r["mean_speed"]))
+        return int(measured.sum()), float(r["mean_speed"])
+
+    n4, v4 = waves("swv", 0.4)
+    n7, v7 = waves("swv", 0.7)
+    assert n4 >= 2 and n7 >= 2
+    assert v7 > 2.0 * v4 > 0.0
