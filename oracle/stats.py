@@ -5,8 +5,8 @@ statistics and the precision tests reduce spike rasters and rate bins with
 these functions, on the oracle's output and on the library's alike.
 
 What they compute:
-  - population rates in bins of 5 ms (Sec. 2.3: firing rates per
-    sub-population);
+  - population rates in bins of 5 ms and their means (Sec. 2.3: firing
+    rates per sub-population);
   - an Up/Down detector on the multi-unit activity of each module (Sec. 2.3:
     in the slow-wave state the module activity alternates between high and
     low states; the Down-to-Up transition is found with a threshold the paper
@@ -27,6 +27,16 @@ def module_rates_hz(counts: np.ndarray, n_exc: int, n_inh: int, bin_ms: float):
     c = counts.astype(np.float64)
     s = bin_ms * 1e-3
     return c[:, :, 0] / n_exc / s, c[:, :, 1] / n_inh / s
+
+
+def population_rates_hz(counts: np.ndarray, sizes, bin_ms: float, skip_s: float = 0.5):
+    """counts [bins][modules][P], sizes[P] neurons per module -> mean rate
+    (Hz) of each population over all modules after the first skip_s."""
+    k0 = int(round(skip_s * 1e3 / bin_ms))
+    c = counts[k0:].astype(np.float64)
+    dur_s = c.shape[0] * bin_ms * 1e-3
+    tot = c.sum(axis=(0, 1))
+    return [float(tot[q] / (sizes[q] * c.shape[1]) / dur_s) for q in range(c.shape[2])]
 
 
 def up_states(x: np.ndarray, min_up: int, hyst: float = 0.2):

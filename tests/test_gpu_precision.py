@@ -191,3 +191,69 @@ def test_48x48_statistics_vs_fp64(L, wd):
         if abs(g - f) > tol:
             bad.append((lk, r, key, g, f, tol))
     assert not bad, (wd, bad)
+
+
+GOLDSWV = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "fp64_stats_swv4x4.json")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("wd", ["f32", "f16", "i8"])
+def test_swv_4x4_slow_waves_vs_fp64(L, wd):
+    """The F/B/I population model in its slow-wave state ("swv": Up states of
+    ~0.3 s at ~0.4 Hz) on 4x4 modules, seeds 1-4, 6 s, against the binary64
+    oracle (tests/golden/fp64_stats_swv4x4.json, written from the oracle
+    only), averaged over the seeds on both sides: the rate of each
+    population within max(3 %, 2 sigma_seed), the Up-state frequency, mean
+    Up duration and Up fraction within max(10 %, 2 sigma_seed), and the
+    per-neuron spike-count distribution within KS max(0.02, twice the mean
+    seed-to-seed KS of the binary64 runs)."""
+    if not os.path.exists(GOLDSWV):
+        pytest.skip("swv binary64 statistics not generated")
+    gold = json.load(open(GOLDSWV))
+    seeds, steps, skip_s = gold["seeds"], gold["steps"], gold["skip_s"]
+    _say("swv 4x4 precision", wd)
+    plist = [dict(W.fbi(gold["side"], gold["side"], "swv"), weight_dtype=wd,
+                  spike_log_cap=1 << 26, rate_bins_cap=2048) for _ in seeds]
+    net = L.dpsnn_build_batch(plist, seeds)
+    L.dpsnn_step(net, steps)
+    st, ids = L.dpsnn_read_log(net)
+    t0 = int(round(skip_s * 1e3 / plist[0]["dt_ms"]))
+    bin_ms = plist[0]["rate_bin_steps"] * plist[0]["dt_ms"]
+    mine = []
+    for k in range(len(seeds)):
+        info = L.dpsnn_net_info(net, k)
+        b, n = info["base"], info["n_neurons"]
+        counts = L.dpsnn_read_rates_net(net, k)
+        sel = (ids >= b) & (ids < b + n) & (st >= t0)
+        up = stats.up_state_stats(counts, bin_ms, skip_s, 50.0)
+        mine.append({"rates_hz": stats.population_rates_hz(counts, plist[k]["pop_size"], bin_ms,
+                                                           skip_s),
+                     "up_freq_hz": up["freq_hz"], "mean_up_ms": up["mean_up_ms"],
+                     "up_fraction": up["up_fraction"],
+                     "count_hist": stats.neuron_rate_hist(ids[sel] - b, n)})
+    net.close()
+    ref = [gold["runs"][str(s)] for s in seeds]
+    report = []
+    for q, name in enumerate(("F", "B", "I")):
+        a = np.array([r["rates_hz"][q] for r in ref])
+        g = np.array([m["rates_hz"][q] for m in mine])
+        report.append((f"rate {name}", g.mean(), a.mean(), max(0.03 * a.mean(), 2 * a.std(ddof=1))))
+    for key in ("up_freq_hz", "mean_up_ms", "up_fraction"):
+        a = np.array([r[key] for r in ref])
+        g = np.array([m[key] for m in mine])
+        report.append((key, g.mean(), a.mean(), max(0.10 * a.mean(), 2 * a.std(ddof=1))))
+    ha = [np.array(r["count_hist"]) for r in ref]
+    seed_ks = np.mean([stats.ks_from_hists(ha[i], ha[j]) for i in range(len(ha))
+                       for j in range(i + 1, len(ha))])
+    pool = lambda hs: sum(np.pad(h, (0, 2001 - len(h))) for h in hs)
+    ks = stats.ks_from_hists(pool([m["count_hist"] for m in mine]), pool(ha))
+    report.append(("ks", ks, 0.0, max(0.02, 2 * seed_ks)))
+    bad = []
+    for key, g, f, tol in report:
+        print(f"[precision swv 4x4 {wd}] {key}: gpu {g:.4f} fp64 {f:.4f} tol {tol:.4f}",
+              flush=True)
+        if abs(g - f) > tol:
+            bad.append((key, g, f, tol))
+    assert mine[0]["up_freq_hz"] > 0.1     # a slow-wave state
+    assert not bad, (wd, bad)

@@ -61,6 +61,23 @@ def test_module_rates():
     assert np.all(e[:, 0] == 0) and np.all(i[:, 1] == 0)
 
 
+def test_population_rates_brute_force():
+    """Mean rate of each population after the skipped bins, against a loop
+    over bins and modules."""
+    rng = np.random.default_rng(4)
+    counts = rng.integers(0, 40, size=(300, 5, 3)).astype(np.uint32)
+    sizes = [250, 750, 250]
+    got = stats.population_rates_hz(counts, sizes, 5.0, skip_s=0.5)
+    for q in range(3):
+        spikes, bins = 0, 0
+        for b in range(100, 300):          # 0.5 s = 100 bins of 5 ms skipped
+            bins += 1
+            for m in range(5):
+                spikes += int(counts[b, m, q])
+        want = spikes / (sizes[q] * 5) / (bins * 5e-3)
+        assert got[q] == pytest.approx(want, rel=1e-12)
+
+
 def test_neuron_rate_hist_brute_force():
     rng = np.random.default_rng(3)
     ids = rng.integers(0, 50, size=700)
