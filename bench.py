@@ -287,6 +287,10 @@ def workload_groups(name, workloads, lam, weights):
                         "aw": workloads.grid(24, 24, "aw", **{"lambda": lam})}}
     if name == "fbi24":
         return {"f32": {"sw": workloads.fbi(24, 24, "sw"), "aw88": workloads.fbi(24, 24, "aw88")}}
+    if name == "fbi48":
+        return {wd: {"swv": workloads.fbi(48, 48, "swv", weight_dtype=wd, lam=lam),
+                     "aw88": workloads.fbi(48, 48, "aw88", weight_dtype=wd, lam=lam)}
+                for wd in weights}
     if name == "grid96":
         return {"i8": {"swa": workloads.grid96("swa"), "aw": workloads.grid96("aw")}}
     if name == "stdp24":
@@ -310,6 +314,11 @@ DESCRIPTIONS = {
     "stdp24": ("24x24 modules x 1250 LIF-SFA neurons (720k neurons, 0.72G synapses), lambda 1, "
                "SWA + AW networks, FP32 efficacies, int32 slots, STDP on the synapses of "
                "excitatory sources (20 ms windows, 1 s filter and update period)"),
+    "fbi48": ("48x48 modules x (250 F + 750 B + 250 I) neurons (2.88M neurons, 3.24G "
+              "synapses, 1125 per neuron), the slow-wave state (swv: Up states of 0.35 s "
+              "travelling across the grid at 0.35 Hz) and Table S1's AW 8.8 Hz state, Eq. 1 "
+              "from d = 0 with lambda {lam:g}, open boundaries, FP32 (headline), FP16 and "
+              "int8 efficacies timed alike, int32 slots"),
     "fbi24": ("24x24 modules x (250 F + 750 B + 250 I) neurons (720k neurons, 0.81G "
               "synapses, 1125 per neuron), Table S1 SW and AW 8.8 Hz states, Eq. 1 from "
               "d = 0 with lambda 0.5, open boundaries, FP32 efficacies, int32 slots"),
@@ -568,9 +577,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["grid48", "grid24", "sweep64", "grid96", "fbi24",
-                                           "stdp24"], default="grid48")
-    ap.add_argument("--lambda", dest="lam", type=float, default=1.0,
-                    help="decay length of Eq. 1 for grid48 and grid24 (default 1)")
+                                           "fbi48", "stdp24"], default="grid48")
+    ap.add_argument("--lambda", dest="lam", type=float, default=None,
+                    help="decay length of Eq. 1 for grid48, grid24 (default 1) and fbi48 "
+                         "(default 0.5)")
     ap.add_argument("--weights", default="f32,f16,i8",
                     help="grid48: weight formats timed, the first one is the headline")
     ap.add_argument("--steps", type=int, default=None,
@@ -615,10 +625,12 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
+    if args.lam is None:
+        args.lam = 0.5 if wl == "fbi48" else 1.0
     big = wl in ("sweep64", "grid96")
     steps = args.steps if args.steps is not None else (2 if big else 10)
     S = args.dt_steps if args.dt_steps is not None else (
-        2000 if big else 4000 if wl == "grid48" else 10000)
+        2000 if big else 4000 if wl in ("grid48", "fbi48") else 10000)
     if big:
         args.profile_steps = min(args.profile_steps, 200)
     weights = [w for w in args.weights.split(",") if w]
