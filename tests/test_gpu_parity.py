@@ -472,6 +472,7 @@ POP_CASES = {
     "fbi_aw28_open_f16": W.fbi(3, 4, "aw28", scale=0.1, weight_dtype="f16", lam=0.4),
     "fbi_aw88_open_i8_q32": W.fbi(4, 2, "aw88", scale=0.1, weight_dtype="i8",
                                   acc_bits=64, q_frac_bits=32),
+    "fbi_swv_open_f16": W.fbi(4, 4, "swv", scale=0.1, weight_dtype="f16", lam=0.6),
 }
 
 
