@@ -528,6 +528,113 @@ def group_record(workload, wdt, nets, res, steps, S, args):
     }
 
 
+def _module_onsets(mua, hold=10):
+    """Up onsets of each module, in bins: the MUA smoothed over 3 bins
+    crossing upward the midpoint of its 10th and 90th percentiles and staying
+    above it for `hold` bins, the crossing placed by linear interpolation."""
+    import numpy as np
+    out = []
+    for m in range(mua.shape[1]):
+        x = np.convolve(mua[:, m], np.ones(3) / 3, mode="same")
+        lo, hi = np.percentile(x, [10, 90])
+        th = 0.5 * (lo + hi)
+        above = x > th
+        on, b = [], 1
+        while b < len(x) - hold:
+            if above[b] and not above[b - 1] and above[b:b + hold].all():
+                on.append(b - 1 + (th - x[b - 1]) / (x[b] - x[b - 1]))
+                b += hold
+            else:
+                b += 1
+        out.append(np.array(on))
+    return out
+
+
+def onset_speeds(counts, w, h, bin_ms, window_bins=40, full=0.868):
+    """Second estimate of the wave speed from the rate bins alone: the Up
+    onsets of the grid total define the events; each module's onset nearest
+    to an event (within window_bins) gives its passage time T; an event that
+    reaches at least `full` of the modules gives the median over interior
+    modules of 1/|grad T| (central differences, inter-module distances per
+    second).  Returns (events, full events, median speed per full event)."""
+    import numpy as np
+    mua = counts.sum(axis=2).astype(np.float64)
+    per = _module_onsets(mua)
+    events = _module_onsets(mua.sum(axis=1)[:, None])[0]
+    speeds, n_full = [], 0
+    for g in events:
+        T = np.full(w * h, np.nan)
+        for m, o in enumerate(per):
+            if len(o):
+                k = int(np.argmin(np.abs(o - g)))
+                if abs(o[k] - g) < window_bins:
+                    T[m] = o[k]
+        if np.count_nonzero(~np.isnan(T)) < full * w * h:
+            continue
+        n_full += 1
+        Tg = T.reshape(h, w) * bin_ms * 1e-3
+        gx = 0.5 * (Tg[1:-1, 2:] - Tg[1:-1, :-2])
+        gy = 0.5 * (Tg[2:, 1:-1] - Tg[:-2, 1:-1])
+        gn = np.hypot(gx, gy)
+        v = 1.0 / gn[np.isfinite(gn) & (gn > 0)]
+        if len(v):
+            speeds.append(float(np.median(v)))
+    return len(events), n_full, speeds
+
+
+def wave_speed(dpsnn, workloads, torch):
+    """Speed of the slow waves of the F/B/I swv state against the decay
+    length lambda of Eq. 1 (Sec. 3.3.2): 24x24 modules, 1 s of transient
+    drained, then 20 s analysed in place by dpsnn_waves (Eq. 4 averaged over
+    the modules of each wave, waves of at least 50 modules, dwell 4 bins),
+    without added noise and with the noise of variance 0.5, and from the
+    modules' own onsets (onset_speeds).  One JSON line."""
+    import numpy as np
+    lams, seeds = (0.4, 0.5, 0.6, 0.7), (1, 2, 3, 4)
+    rows = []
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for lam in lams:
+            for seed in seeds:
+                p = dict(workloads.fbi(24, 24, "swv", lam=lam), rate_bins_cap=4200)
+                net = dpsnn.dpsnn_build(p, seed)
+                dpsnn.dpsnn_step(net, 10000)
+                dpsnn.dpsnn_read_rates(net)
+                dpsnn.dpsnn_step(net, 200000)
+                row = {"lambda": lam, "seed": seed}
+                for nv in (0.0, 0.5):
+                    r = dpsnn.dpsnn_waves(net, noise_var=nv, seed=1, min_down=4, min_up=4,
+                                          min_modules=50)
+                    row[f"eq4_noise{nv:g}"] = {
+                        "transitions": int(r["n_transitions"]),
+                        "waves": int((r["speed"] > 0).sum()) if r["n_waves"] else 0,
+                        "mean_speed": round(float(r["mean_speed"]), 1)}
+                counts = dpsnn.dpsnn_read_rates(net)
+                net.close()
+                ev, full, sp = onset_speeds(counts, 24, 24, 5.0)
+                row["onsets"] = {"events": ev, "full_events": full,
+                                 "median_speed": round(float(np.median(sp)), 1) if sp else None}
+                rows.append(row)
+                progress(f"lambda {lam} seed {seed}: Eq. 4 {row['eq4_noise0']['mean_speed']} "
+                         f"imd/s, onsets {row['onsets']['median_speed']} imd/s")
+
+    def mean_of(key, sub):
+        out = {}
+        for lam in lams:
+            v = [r[key][sub] for r in rows if r["lambda"] == lam and r[key][sub] is not None]
+            out[f"{lam:g}"] = round(float(np.mean(v)), 1) if v else None
+        return out
+    print(json.dumps({"metric": "slow-wave speed against lambda (Sec. 3.3.2, Eq. 4)",
+                      "unit": "inter-module distances per second", "n_gpus": 1,
+                      "data": "synthetic",
+                      "config": {"workload": "24x24 modules x (250 F + 750 B + 250 I) neurons, "
+                                             "swv state, lambda 0.4-0.7, seeds 1-4, 20 s "
+                                             "after 1 s of transient, FP32 efficacies"},
+                      "eq4_noise0": mean_of("eq4_noise0", "mean_speed"),
+                      "eq4_noise0.5": mean_of("eq4_noise0.5", "mean_speed"),
+                      "onsets": mean_of("onsets", "median_speed"), "runs": rows}), flush=True)
+
+
 def wave_bench(dpsnn, workloads, torch):
     """Slow-wave analysis of the 24x24 F/B/I network in the SW state
     (lambda = 0.5): 1 s of transient drained, then 3 s (600 bins of 5 ms)
@@ -613,6 +720,10 @@ def main():
     ap.add_argument("--waves", action="store_true",
                     help="time the slow-wave analysis (Sec. 2.3, Eq. 4) of 3 s of the 24x24 "
                          "F/B/I SW network instead of the step")
+    ap.add_argument("--wave-speed", action="store_true",
+                    help="slow-wave speed against lambda (Sec. 3.3.2): the 24x24 F/B/I swv "
+                         "state, lambda 0.4-0.7, seeds 1-4, 20 s each, analysed by "
+                         "dpsnn_waves")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(*args.summarize_rocprof)
@@ -652,6 +763,9 @@ def main():
         return
     if args.waves:
         wave_bench(dpsnn, workloads, torch)
+        return
+    if args.wave_speed:
+        wave_speed(dpsnn, workloads, torch)
         return
     stream = torch.cuda.Stream()        # default priority; graphs need a non-default stream
     # rate bins: warm-up and timed steps, the autotuner's two passes over

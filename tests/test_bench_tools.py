@@ -71,3 +71,47 @@ def test_summarize_rocprof_windows_and_scales(tmp_path, monkeypatch):
         assert kn["fetch_bytes"] == pytest.approx(2 * (10 + 3.5) * 1024)
         assert kd["write_bytes"] == pytest.approx(10 * 1024)
         assert kd["bytes_per_launch"] == pytest.approx(2 * (20 + 3.5) * 1024 + 10 * 1024)
+
+
+def test_onset_speeds_planted_plane_wave():
+    """A plane wave planted in rate bins: Up states of 300 ms that start at
+    t0 + x / v at module column x (two 5 ms bins per module), four events
+    2 s apart, 24x24 modules, background noise.  The onset estimate gives
+    back v, and every event reaches every module."""
+    import numpy as np
+    w = h = 24
+    v = 100.0                                    # inter-module distances per second
+    bins = 1800
+    counts = np.zeros((bins, w * h, 3), np.int32)
+    rng = np.random.default_rng(3)
+    counts[:, :, 1] = rng.integers(0, 3, size=(bins, w * h))
+    for ev in range(4):
+        t0 = 1.0 + 2.0 * ev
+        for y in range(h):
+            for x in range(w):
+                b0 = int(round((t0 + x / v) / 5e-3))
+                counts[b0:b0 + 60, y * w + x, 1] += 40
+    events, full, speeds = bench.onset_speeds(counts, w, h, 5.0)
+    assert events == 4 and full == 4
+    assert np.allclose(speeds, v, rtol=0.02)
+
+
+def test_onset_speeds_diagonal_wave_scales_by_sqrt2():
+    """A wave front moving along the diagonal with the delay 1 / v per
+    module in x and in y (one bin): |grad T| = sqrt(2) / v, the speed
+    v / sqrt(2)."""
+    import numpy as np
+    w = h = 24
+    v = 200.0
+    bins = 1000
+    counts = np.zeros((bins, w * h, 3), np.int32)
+    for ev in range(2):
+        t0 = 0.5 + 2.0 * ev
+        for y in range(h):
+            for x in range(w):
+                b0 = int(round((t0 + (x + y) / v) / 5e-3))
+                counts[b0:b0 + 60, y * w + x, 0] += 30
+    counts[:, :, 2] += 1
+    events, full, speeds = bench.onset_speeds(counts, w, h, 5.0)
+    assert events == 2 and full == 2
+    assert np.allclose(speeds, v / np.sqrt(2), rtol=0.02)
