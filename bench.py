@@ -444,6 +444,7 @@ def group_record(workload, wdt, nets, res, steps, S, args):
     events = sum(spikes.values()) * K_OUT
     p0 = next(iter(nets.values()))[1][0]
     Bn, Be = bytes_per_neuron_step(p0), bytes_per_event(p0)
+    stream_b = 4 + {"f32": 4, "f16": 2, "i8": 1}[p0["weight_dtype"]]
     sim_s = steps * S * 0.1e-3
     n_prof = max(1, args.profile_steps * len(prof))
     del_us = sum(v[1] for v in prof.values()) * 1e3 / n_prof
@@ -492,6 +493,10 @@ def group_record(workload, wdt, nets, res, steps, S, args):
             "event_bracket_us": res["bracket_us"],
             "profile_avg_launch_us": trace_us,
             "events_per_s_in_kernel": ev_per_launch / (del_us * 1e-6) if del_us > 0 else None,
+            # the synapse stream alone (target word and stored efficacy per event)
+            "synapse_stream": {"bytes_per_event": stream_b,
+                               "achieved_GB_s": ev_per_launch * stream_b / (del_us * 1e-6) / 1e9
+                               if del_us > 0 else None},
             "update_kernel": {"kernel": "k_neuron (update, with the queued-input gather)",
                               "avg_launch_us": upd_us,
                               "algorithmic_bytes_per_launch": n_mean * Bn,

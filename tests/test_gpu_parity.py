@@ -186,6 +186,32 @@ def test_raster_bit_exact(L, case, sched):
     net.close()
 
 
+@pytest.mark.parametrize("sched", [0, 1, 2])
+def test_degenerate_networks_bit_exact(L, sched):
+    """Edge cases of the step: a network that never fires (no external drive,
+    no constant current: empty spike lists, nothing delivered, every bin
+    zero, the leak alone moving the state), and the smallest network, one
+    module of 5 neurons (4 excitatory, 1 inhibitory) with 4 local synapses
+    each, driven hard (ragged tile, runs of one event)."""
+    cases = {"silent": (W.tiny(w=2, h=2, K=30, K_out=20, nu_ext_hz=[0.0, 0.0]), False),
+             "minimal_1x1": (W.tiny(w=1, h=1, K=5, K_out=4, frac_local=[1.0, 1.0],
+                                    nu_ext_hz=[6000.0, 6000.0]), True)}
+    for case, (p, fires) in cases.items():
+        _say("degenerate", case, "schedule", sched)
+        net, orc = _pair(p, 3)
+        L.dpsnn_set_schedule(net, sched)
+        n = 0
+        for k, steps in enumerate((1, 127, 900, 972)):
+            L.dpsnn_step(net, steps)
+            orc.step(steps)
+            n += _compare_all(L, net, orc, (case, k))
+        rates = L.dpsnn_read_rates(net)
+        assert np.array_equal(rates, orc.rates()[: 2000 // p["rate_bin_steps"]])
+        assert (n > 100) == fires and (rates.sum() > 0) == fires, (case, n)
+        assert orc.status == 0
+        net.close()
+
+
 def test_raster_bit_exact_2x2_two_seconds(L):
     """2x2 grid of 1250-neuron modules (5000 neurons), FP32 weights, SWA, 2 s =
     20000 steps."""
