@@ -154,6 +154,7 @@ int build_impl(dpsnn_net* n) {
   void* jx_all = dev_alloc(n, (size_t)nn * kMaxPops * kQuantN * ab);
   if (!jx_all) return DPSNN_E_NOMEM;
   std::vector<NetDev> nd(nn);
+  bool all_two = P > 2;  // two classes of Eq. 2 constants in every network
   std::vector<int32_t> tn((size_t)n_tiles);
   std::vector<int64_t> sf((size_t)M * P);
   for (int k = 0; k < nn; ++k) {
@@ -307,6 +308,22 @@ int build_impl(dpsnn_net* n) {
       for (int x = 0; x < kMaxPois; ++x) d.pois[q][x] = T.pois[q][x];
       d.exc[q] = p.n_pops == 0 ? (q == 0) : (p.pop_exc[q] != 0);
     }
+    // classes of equal Eq. 2 constants: a prefix of populations like
+    // population 0 and the rest like the first population after it
+    auto same = [&](int q, int r) {
+      return memcmp(&d.Pm[q], &d.Pm[r], 4) == 0 && memcmp(&d.Pc[q], &d.Pc[r], 4) == 0 &&
+             memcmp(&d.PVc[q], &d.PVc[r], 4) == 0 && memcmp(&d.Iterm[q], &d.Iterm[r], 4) == 0 &&
+             memcmp(&d.E[q], &d.E[r], 4) == 0 && memcmp(&d.Vth[q], &d.Vth[r], 4) == 0 &&
+             memcmp(&d.Vr[q], &d.Vr[r], 4) == 0 && memcmp(&d.alpha[q], &d.alpha[r], 4) == 0 &&
+             d.n_arp[q] == d.n_arp[r];
+    };
+    int rep = 1;
+    while (rep < T.P && same(rep, 0)) ++rep;
+    bool two = true;
+    for (int q = rep + 1; q < T.P; ++q) two = two && same(q, rep);
+    d.cls_rep = rep < T.P ? rep : 0;
+    d.cls_hi = rep < T.P ? d.pop_hi[rep - 1] : p.K;
+    all_two = all_two && two;
   }
   HIP_OK(hipMemcpyAsync(nets, nd.data(), sizeof(NetDev) * nn, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(tile_net, tn.data(), tn.size() * 4, hipMemcpyHostToDevice, st));
@@ -331,6 +348,7 @@ int build_impl(dpsnn_net* n) {
   a.d_min = p0.d_min;
   a.M = (int32_t)M;
   a.P = P;
+  a.two_cls = all_two ? 1 : 0;
   a.n_tiles = (int32_t)n_tiles;
   a.deliver_blocks = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(256, n_tiles));
   a.rate_bin_steps = p0.rate_bin_steps;

@@ -152,6 +152,12 @@ struct NetDev {
   // is a power of two: x >> kshift)
   uint32_t kmag;
   int32_t kshift;
+  // Populations whose Eq. 2 constants are equal bit for bit form classes;
+  // when the populations [0, cls_rep) share one set and [cls_rep, P) another
+  // (F and B against I in the three-population model), class 1 starts at
+  // module-local index cls_hi and takes the constants of population cls_rep
+  // (one class: cls_hi = K, cls_rep = 0).
+  int32_t cls_hi, cls_rep;
 };
 
 // Module and module-local index of network-local neuron x (x < 2^31): the
@@ -182,6 +188,8 @@ struct StepArgs {
   int64_t N_pad;           // size of the global index space
   int32_t K_out, row_stride, D, n_del, d_min, M;  // M: modules of all networks
   int32_t P;               // populations per module (rate-bin and scale stride)
+  int32_t two_cls;         // P > 2 and every network's Eq. 2 constants fall
+                           // into two contiguous classes (NetDev::cls_hi)
   int32_t n_tiles;         // neuron tiles of 1024 = N_pad / 1024
   int32_t deliver_blocks;  // delivery blocks of the delivery kernel
   int32_t route_blocks;    // inbox-routing blocks that follow them

@@ -757,46 +757,52 @@ __device__ __forceinline__ uint32_t neuron_finish(const StepArgs& a, const NetDe
   }
   const uint32_t i0 = P.i0;
   const int l0 = P.l0;
-  // per-population constants: uniform loads, selected per lane
-  const float Pm[kMaxPops] = {nd.Pm[0], nd.Pm[1], nd.Pm[2], nd.Pm[3]};
-  const float Pc[kMaxPops] = {nd.Pc[0], nd.Pc[1], nd.Pc[2], nd.Pc[3]};
-  const float PVc[kMaxPops] = {nd.PVc[0], nd.PVc[1], nd.PVc[2], nd.PVc[3]};
-  const float It[kMaxPops] = {nd.Iterm[0], nd.Iterm[1], nd.Iterm[2], nd.Iterm[3]};
-  const float E[kMaxPops] = {nd.E[0], nd.E[1], nd.E[2], nd.E[3]};
-  const float Vth[kMaxPops] = {nd.Vth[0], nd.Vth[1], nd.Vth[2], nd.Vth[3]};
-  const float Vr[kMaxPops] = {nd.Vr[0], nd.Vr[1], nd.Vr[2], nd.Vr[3]};
-  const float al[kMaxPops] = {nd.alpha[0], nd.alpha[1], nd.alpha[2], nd.alpha[3]};
-  const int na[kMaxPops] = {nd.n_arp[0], nd.n_arp[1], nd.n_arp[2], nd.n_arp[3]};
+  // per-population constants: uniform loads, selected per lane.  NP = 3:
+  // up to four populations whose constants form two classes (entry 1 holds
+  // those of population cls_rep, where class 1 begins), selected two-way
+  constexpr int NS = NP == 3 ? 2 : NP;
+  const int r1 = NP == 3 ? nd.cls_rep : 1;
+  const float Pm[kMaxPops] = {nd.Pm[0], nd.Pm[r1], nd.Pm[2], nd.Pm[3]};
+  const float Pc[kMaxPops] = {nd.Pc[0], nd.Pc[r1], nd.Pc[2], nd.Pc[3]};
+  const float PVc[kMaxPops] = {nd.PVc[0], nd.PVc[r1], nd.PVc[2], nd.PVc[3]};
+  const float It[kMaxPops] = {nd.Iterm[0], nd.Iterm[r1], nd.Iterm[2], nd.Iterm[3]};
+  const float E[kMaxPops] = {nd.E[0], nd.E[r1], nd.E[2], nd.E[3]};
+  const float Vth[kMaxPops] = {nd.Vth[0], nd.Vth[r1], nd.Vth[2], nd.Vth[3]};
+  const float Vr[kMaxPops] = {nd.Vr[0], nd.Vr[r1], nd.Vr[2], nd.Vr[3]};
+  const float al[kMaxPops] = {nd.alpha[0], nd.alpha[r1], nd.alpha[2], nd.alpha[3]};
+  const int na[kMaxPops] = {nd.n_arp[0], nd.n_arp[r1], nd.n_arp[2], nd.n_arp[3]};
   const int h0 = nd.pop_hi[0], h1 = nd.pop_hi[1], h2 = nd.pop_hi[2];
+  const int c_hi = NP == 3 ? nd.cls_hi : 0;
   uint32_t r_out = 0, mask = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int lj = l0 + j;
     if (lj >= nd.K) lj -= nd.K;
     const int qq = pop_index<NP>(lj, h0, h1, h2);
+    const int qs = NP == 3 ? (lj >= c_hi ? 1 : 0) : qq;  // constants' entry
     uint32_t rj = (R.r4 >> (8 * j)) & 0xFFu;
     if ((int64_t)P.il0 + j < nd.N) {
       const float dv = fix_to_f32(R.I[j]) * a.inv2q;
       float Vj = R.V[j], cj = R.c[j];
-      const float Pcq = sel<NP>(Pc, qq), Eq = sel<NP>(E, qq);
+      const float Pcq = sel<NS>(Pc, qs), Eq = sel<NS>(E, qs);
       bool spk = false;
       if (rj > 0) {
         rj -= 1;
         cj = cj * Pcq;
       } else {
         float vv = Vj - Eq;
-        vv = vv * sel<NP>(Pm, qq);
+        vv = vv * sel<NS>(Pm, qs);
         vv = Eq + vv;
-        const float cc = cj * sel<NP>(PVc, qq);
+        const float cc = cj * sel<NS>(PVc, qs);
         vv = vv - cc;
-        vv = vv + sel<NP>(It, qq);
+        vv = vv + sel<NS>(It, qs);
         vv = vv + dv;
         cj = cj * Pcq;
-        if (vv > sel<NP>(Vth, qq)) {
+        if (vv > sel<NS>(Vth, qs)) {
           spk = true;
-          vv = sel<NP>(Vr, qq);
-          cj = cj + sel<NP>(al, qq);
-          rj = (uint32_t)sel<NP>(na, qq);
+          vv = sel<NS>(Vr, qs);
+          cj = cj + sel<NS>(al, qs);
+          rj = (uint32_t)sel<NS>(na, qs);
         }
         Vj = vv;
       }
@@ -1673,6 +1679,8 @@ static void launch_neuron_fmt(const StepArgs& a, uint32_t t_off, hipStream_t st)
   const dim3 tiles((unsigned)a.n_tiles), block(256);
   if (a.P <= 2)
     hipLaunchKernelGGL((k_neuron<Acc, 2, FMT>), tiles, block, 0, st, a, step_off(a, t_off));
+  else if (a.two_cls)
+    hipLaunchKernelGGL((k_neuron<Acc, 3, FMT>), tiles, block, 0, st, a, step_off(a, t_off));
   else
     hipLaunchKernelGGL((k_neuron<Acc, 4, FMT>), tiles, block, 0, st, a, step_off(a, t_off));
 }

@@ -499,6 +499,9 @@ POP_CASES = {
     "fbi_aw88_open_i8_q32": W.fbi(4, 2, "aw88", scale=0.1, weight_dtype="i8",
                                   acc_bits=64, q_frac_bits=32),
     "fbi_swv_open_f16": W.fbi(4, 4, "swv", scale=0.1, weight_dtype="f16", lam=0.6),
+    # F and B share their Eq. 2 constants in the cases above (two classes);
+    # here every population has its own membrane time constant
+    "fbi_three_classes_f32": W.fbi(3, 3, "aw88", scale=0.1, p_tau_m=[20.0, 16.0, 10.0]),
 }
 
 
