@@ -25,7 +25,6 @@ import argparse
 import json
 import os
 import platform
-import subprocess
 import sys
 import time
 
