@@ -173,3 +173,40 @@ def test_batch_beyond_4096_tiles_teacher_forced(L):
         o.step(1)
         assert _check_step(L, net, o, ("batch", k), info["base"], info["n_neurons"], k=k) > 50
     net.close()
+
+
+@pytest.mark.timeout(420)
+@pytest.mark.parametrize("wd", ["f32", "f16", "i8"])
+def test_48x48_swa_aw_batch_in_the_benchmark_configuration(L, wd):
+    """The benchmark's 48x48 groups: SWA and AW networks (2.88M neurons,
+    2.88G synapses each) in one handle, seed 1 for both, split schedule,
+    1024 delivery blocks, appended spike lists with merged reservations,
+    128-step graph replays.  After 300 steps, one step of each network
+    re-run by the oracle from the GPU's state, read back per network."""
+    import torch
+    plist = [dict(W.grid(48, 48, r, weight_dtype=wd), spike_log_cap=1 << 24, rate_bins_cap=256)
+             for r in ("swa", "aw")]
+    seeds = [1, 1]
+    _say("48x48 batch build", wd)
+    stream = torch.cuda.Stream()  # graph replay needs a stream of its own
+    net = L.dpsnn_build_batch(plist, seeds, stream=stream.cuda_stream)
+    L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+    L.dpsnn_set_delivery(net, 1024, 2)
+    L.dpsnn_set_graph_steps(net, 128)
+    st = net.stats()
+    assert st["deliver_blocks"] == 1024 and st["spike_lists"] == 2 and st["queue_cap"] > 0
+    L.dpsnn_step(net, 300)
+    L.dpsnn_read_spikes(net)
+    orcs = []
+    for k, (p, sd) in enumerate(zip(plist, seeds)):
+        info = L.dpsnn_net_info(net, k)
+        orcs.append((_compare_step_from_state(L, net, p, sd, 300, k, info["base"],
+                                              info["n_neurons"]), info))
+    L.dpsnn_step(net, 1)
+    for k, (o, info) in enumerate(orcs):
+        _say("48x48 network", k, wd)
+        o.step(1)
+        assert _check_step(L, net, o, ("48x48", wd, k), info["base"], info["n_neurons"],
+                           k=k) > 100
+        assert o.status == 0
+    net.close()
