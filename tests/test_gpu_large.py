@@ -210,3 +210,38 @@ def test_48x48_swa_aw_batch_in_the_benchmark_configuration(L, wd):
                            k=k) > 100
         assert o.status == 0
     net.close()
+
+
+@pytest.mark.timeout(420)
+def test_48x48_fbi_batch_in_the_benchmark_configuration(L):
+    """The benchmark's 48x48 F/B/I group: the slow-wave state swv and the AW
+    8.8 Hz state (2.88M neurons, 3.24G synapses each, three populations whose
+    Eq. 2 constants form two classes) in one handle, split schedule, 1024
+    delivery blocks, appended lists with one reservation per run, 128-step
+    graph replays.  After 300 steps, one step of each network re-run by the
+    oracle from the GPU's state."""
+    import torch
+    plist = [dict(W.fbi(48, 48, s, lam=0.5), spike_log_cap=1 << 24, rate_bins_cap=256)
+             for s in ("swv", "aw88")]
+    seeds = [1, 1]
+    _say("48x48 F/B/I batch build")
+    stream = torch.cuda.Stream()
+    net = L.dpsnn_build_batch(plist, seeds, stream=stream.cuda_stream)
+    L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+    L.dpsnn_set_delivery(net, 1024, 1)
+    L.dpsnn_set_graph_steps(net, 128)
+    L.dpsnn_step(net, 300)
+    L.dpsnn_read_spikes(net)
+    orcs = []
+    for k, (p, sd) in enumerate(zip(plist, seeds)):
+        info = L.dpsnn_net_info(net, k)
+        orcs.append((_compare_step_from_state(L, net, p, sd, 300, k, info["base"],
+                                              info["n_neurons"]), info))
+    L.dpsnn_step(net, 1)
+    for k, (o, info) in enumerate(orcs):
+        _say("48x48 F/B/I network", k)
+        o.step(1)
+        assert _check_step(L, net, o, ("48x48 F/B/I", k), info["base"], info["n_neurons"],
+                           k=k) > 100
+        assert o.status == 0
+    net.close()
