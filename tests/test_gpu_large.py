@@ -245,3 +245,43 @@ def test_48x48_fbi_batch_in_the_benchmark_configuration(L):
                            k=k) > 100
         assert o.status == 0
     net.close()
+
+
+@pytest.mark.timeout(420)
+def test_sweep64_in_the_benchmark_configuration(L):
+    """The benchmark's batched sweep: 64 networks of 4x4 to 16x16 full-size
+    modules (9.54M neurons, binary16 efficacies, adaptation and lambda drawn
+    per network) in one handle, split schedule, 1024 delivery blocks,
+    appended lists with merged reservations, 128-step graph replays.  After
+    300 steps, one step of six networks (the first, the last, and the
+    largest and smallest of the rest) re-run by the oracle from the GPU's
+    state."""
+    import torch
+    plist, seeds = W.sweep()
+    plist = [dict(p, spike_log_cap=1 << 25, rate_bins_cap=256) for p in plist]
+    _say("sweep64 build")
+    stream = torch.cuda.Stream()
+    net = L.dpsnn_build_batch(plist, seeds, stream=stream.cuda_stream)
+    assert sum(L.dpsnn_net_info(net, k)["n_neurons"] for k in range(len(plist))) == 9_540_000
+    L.dpsnn_set_schedule(net, L.SCHED_SPLIT)
+    L.dpsnn_set_delivery(net, 1024, 2)
+    L.dpsnn_set_graph_steps(net, 128)
+    for _ in range(6):  # the start has bursts: drain the log as it fills
+        L.dpsnn_step(net, 50)
+        L.dpsnn_read_spikes(net)
+    sizes = [p["grid_w"] * p["grid_h"] for p in plist]
+    mid = range(1, len(plist) - 1)
+    pick = sorted({0, len(plist) - 1, max(mid, key=lambda k: sizes[k]),
+                   min(mid, key=lambda k: sizes[k]), 17, 40})
+    orcs = []
+    for k in pick:
+        info = L.dpsnn_net_info(net, k)
+        orcs.append((k, _compare_step_from_state(L, net, plist[k], seeds[k], 300, k,
+                                                 info["base"], info["n_neurons"]), info))
+    L.dpsnn_step(net, 1)
+    for k, o, info in orcs:
+        _say("sweep network", k)
+        o.step(1)
+        assert _check_step(L, net, o, ("sweep", k), info["base"], info["n_neurons"], k=k) > 0
+        assert o.status == 0
+    net.close()
